@@ -1,0 +1,158 @@
+/*
+ * ustd.h -- C ABI of the MI355X (gfx950) library for the uniform-spanning-tree (UST)
+ * estimator of diag(L^+), the diagonal of the pseudoinverse of a graph Laplacian
+ * (Angriman, Predari, van der Grinten, Meyerhenke, "Approximation of the Diagonal of a
+ * Laplacian's Pseudoinverse for Complex Network Analysis", ESA 2020).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named d_* are DEVICE pointers (HIP global memory of the current device);
+ *    the caller allocates and owns them.  Pointers without the prefix are host pointers.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All device
+ *    work is enqueued on it in order; an entry point returns after enqueueing unless it
+ *    says it synchronises (those that must read a scalar back, e.g. ecc to size tau,
+ *    synchronise `stream` once per phase).
+ *  - The library never allocates device memory: every call takes a caller-owned
+ *    workspace of at least ustd_workspace_bytes() bytes (256-byte aligned), which it
+ *    may overwrite freely.  Calls sharing one workspace must not overlap in time.
+ *  - Graph input (Section "Problem Description and Notation"): simple, connected,
+ *    undirected, unit weights, CSR with row_ptr int64[n+1] (row_ptr[0] = 0,
+ *    row_ptr[n] = nnz = 2m), col int32[nnz], every row strictly ascending, every edge
+ *    present in both rows, no self-loops.  With `validate` set the library checks all
+ *    of this on the device and returns USTD_EGRAPH if it fails.
+ *  - Return value: USTD_OK or an error code; ustd_last_error() gives a thread-local
+ *    message.  No C++ exception crosses this boundary.
+ *  - Determinism: for a fixed (graph, pivot, seed, tree range) the sampled trees, the
+ *    walk-step counts and the integer flow counts are bit-identical across runs, batch
+ *    sizes and devices, and equal those of the sequential definition (ascending Wilson
+ *    start order, minimum-ID BFS parents, Philox4x32-10 walk words keyed by
+ *    (seed; step/4, walk start, tree)).
+ */
+#ifndef USTD_H
+#define USTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    USTD_OK = 0,
+    USTD_EINVAL = 1,   /* bad argument (pivot out of range, eps <= 0, delta/kappa not in (0,1), ...) */
+    USTD_EGRAPH = 2,   /* graph fails validation (asymmetric, self-loop, unsorted, disconnected) */
+    USTD_ENOMEM = 3,   /* workspace smaller than ustd_workspace_bytes() */
+    USTD_EHIP = 4,     /* a HIP runtime call failed */
+    USTD_ENOTCONV = 5  /* the pivot-column solve hit its iteration cap; outputs are still written */
+};
+
+enum {
+    USTD_SOLVE_FP64 = 0,  /* FP64 Jacobi-preconditioned CG */
+    USTD_SOLVE_MIXED = 1  /* FP32 Jacobi-PCG inner solves, FP64 residual/refinement/projection */
+};
+
+/* One problem instance: the inputs of ApproxDiagLpinv(G, u, eps, delta) (Algorithm 1)
+ * plus the solver split kappa and the random seed. */
+typedef struct ustd_problem {
+    int64_t n;                /* vertices, >= 2 */
+    int64_t nnz;              /* row_ptr[n] = 2m; must be < 2^31 */
+    const int64_t *d_row_ptr; /* device, n+1 */
+    const int32_t *d_col;     /* device, nnz */
+    int32_t pivot;            /* u in [0, n); -1 selects the maximum-degree vertex (smallest ID on ties) */
+    int32_t solve_mode;       /* USTD_SOLVE_FP64 or USTD_SOLVE_MIXED */
+    double eps;               /* absolute error bound, > 0 */
+    double delta;             /* failure probability in (0,1); <= 0 selects 1/n */
+    double kappa;             /* error split between solve and sampling in (0,1); <= 0 selects 0.3 */
+    uint64_t seed;            /* Philox key */
+    int64_t tau_override;     /* > 0 replaces the sample-size formula */
+    double solve_tol;         /* relative residual target; <= 0 selects min(eta, 1e-12) */
+    int32_t solve_maxit;      /* iteration cap of the solve; <= 0 selects 20000 */
+    int32_t validate;         /* 1 = validate the CSR on the device first */
+    int32_t trees_per_batch;  /* trees resident in the workspace at once; <= 0 = automatic */
+    int32_t reserved;
+} ustd_problem;
+
+/* Filled by the calls that take it (nullable); times from HIP events on `stream`. */
+typedef struct ustd_report {
+    int64_t tau;          /* number of sampled trees */
+    int64_t walk_steps;   /* steps of the sequential definition (equals the CPU oracle's) */
+    int64_t walk_draws;   /* random-walk steps actually executed (includes speculative ones) */
+    int32_t pivot;        /* pivot used */
+    int32_t ecc;          /* eccentricity of the pivot */
+    int32_t solve_iters;  /* total (inner) CG iterations */
+    int32_t solve_outer;  /* FP64 refinement steps (mixed mode), 1 in FP64 mode */
+    int32_t n_batches;    /* tree batches */
+    int32_t trees_per_batch;
+    double solve_relres;  /* ||b - L x||_2 / ||b||_2 of the returned column, in FP64 */
+    double ms_setup, ms_bfs, ms_sample, ms_intervals, ms_aggregate, ms_solve, ms_combine, ms_total;
+} ustd_report;
+
+/* Minimum workspace size for every call below on this problem (host only, no device work).
+ * Depends on n, nnz and trees_per_batch. */
+int ustd_workspace_bytes(const ustd_problem *prob, size_t *bytes);
+
+/* BFS tree B_u of the pivot (Section "Effective Resistance Approximation by UST
+ * Sampling": one shortest path P(v) per vertex, kept as parent pointers).  The parent of
+ * v is the smallest-ID neighbour one level closer to u; d_parB[u] = -1.  d_dist (int32[n])
+ * and d_parB (int32[n]) are nullable outputs; *ecc_out and *pivot_out are host outputs
+ * (nullable).  Synchronises `stream`. */
+int ustd_bfs(const ustd_problem *prob, void *d_ws, size_t ws_bytes, int32_t *d_dist,
+             int32_t *d_parB, int32_t *ecc_out, int32_t *pivot_out, void *stream);
+
+/* Sample trees tree_begin .. tree_begin+tree_count-1 with Wilson's algorithm rooted at the
+ * pivot (Appendix "Wilson's UST Algorithm").  d_parents: int32[tree_count][n], row i is
+ * the parent array of tree tree_begin+i (parent[u] = -1).  d_steps: int64[tree_count]
+ * walk steps of each tree under the sequential definition (nullable).  tree_count <=
+ * trees per batch of the workspace.  Synchronises `stream` (pivot selection). */
+int ustd_sample_trees(const ustd_problem *prob, int64_t tree_begin, int64_t tree_count,
+                      void *d_ws, size_t ws_bytes, int32_t *d_parents, int64_t *d_steps,
+                      void *stream);
+
+/* Flow counts of trees tree_begin .. +tree_count-1 (Algorithm 2, summed over the trees):
+ * d_counts[v] += sum_T c_T(v), where c_T(v) adds +1 for every edge (a,b) of P(v) that T
+ * traverses from a to b on its path from u to v and -1 for every one it traverses from b
+ * to a (Kirchhoff's theorem; Eq. N-values-in-path).  d_counts is int64[n], accumulated
+ * (the caller zeroes it).  Any split of a tree range gives the same final counts.
+ * rep (nullable) receives walk_steps/draws and phase times.  Synchronises `stream`. */
+int ustd_flow_counts(const ustd_problem *prob, int64_t tree_begin, int64_t tree_count,
+                     void *d_ws, size_t ws_bytes, int64_t *d_counts, ustd_report *rep,
+                     void *stream);
+
+/* Flow counts of caller-supplied spanning trees (Algorithm 2 only): d_parents is
+ * int32[tree_count][n] of parent arrays rooted at the pivot (parent[u] = -1); d_counts
+ * (int64[n]) is accumulated.  The trees are not checked.  Synchronises `stream`. */
+int ustd_tree_counts(const ustd_problem *prob, const int32_t *d_parents, int64_t tree_count,
+                     void *d_ws, size_t ws_bytes, int64_t *d_counts, void *stream);
+
+/* Column u of L^+ (Section "Overview", step 1): solves L x = e_u - (1/n) 1 with x
+ * orthogonal to 1 to relative residual solve_tol, by FP64 Jacobi-PCG or by FP32 PCG with
+ * FP64 iterative refinement (solve_mode).  d_x is double[n].  Returns USTD_ENOTCONV (with
+ * d_x written) if the cap is reached.  Synchronises `stream`. */
+int ustd_solve_pivot_column(const ustd_problem *prob, void *d_ws, size_t ws_bytes, double *d_x,
+                            ustd_report *rep, void *stream);
+
+/* ApproxDiagLpinv (Algorithm 1) end to end: BFS, tau, tau trees sampled and aggregated,
+ * the pivot-column solve, and the combination of Eq. diag-comp,
+ *   diag[u] = x[u],  diag[v] = R[v]/tau - x[u] + 2 x[v].
+ * d_diag is double[n]; d_counts (int64[n], nullable) receives R (overwritten, not
+ * accumulated).  Synchronises `stream`. */
+int ustd_diag_lpinv(const ustd_problem *prob, void *d_ws, size_t ws_bytes, double *d_diag,
+                    int64_t *d_counts, ustd_report *rep, void *stream);
+
+/* Test hook for the walk generator: d_out[i] = word ((k0+i) mod 4) of Philox4x32-10 with
+ * key (seed lo, seed hi) and counter ((k0+i)/4, s, t lo, t hi), i < count; uint32[count]. */
+int ustd_philox_words(uint64_t seed, int64_t t, int32_t s, int64_t k0, int64_t count,
+                      uint32_t *d_out, void *stream);
+
+/* Static name of a status code. */
+const char *ustd_status_string(int status);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char *ustd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* USTD_H */

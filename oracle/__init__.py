@@ -1,0 +1,189 @@
+"""CPU oracle for the UST estimator of diag(L^+) -- TEST INFRASTRUCTURE ONLY.
+
+A thin ctypes loader around ``ustd_oracle.c`` (plain sequential FP64 C, built with gcc).
+Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's ``cpu_baseline`` leg
+may import this package; the GPU library never does, and the two share no code.
+
+Every function follows the paper (Angriman et al., ESA 2020) step by step; see the C
+file for the section each one follows and for the readings of ambiguous passages.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ustd_oracle.c")
+_LIB = os.path.join(_HERE, "libustd_oracle.so")
+
+_lib = None
+
+OK, EINVAL, EGRAPH, ENOMEM, ENOTCONV = 0, 1, 2, 3, 5
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no HIP involved)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        i64, i32, u64, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+        P = ctypes.c_void_p
+        L.ustd_oracle_philox4x32_10.argtypes = [P, P, P]
+        L.ustd_oracle_philox4x32_10.restype = None
+        L.ustd_oracle_walk_word.argtypes = [u64, i64, i32, i64]
+        L.ustd_oracle_walk_word.restype = ctypes.c_uint32
+        L.ustd_oracle_validate.argtypes = [i64, P, P]
+        L.ustd_oracle_validate.restype = ctypes.c_int
+        L.ustd_oracle_bfs.argtypes = [i64, P, P, i32, P, P]
+        L.ustd_oracle_bfs.restype = i32
+        L.ustd_oracle_tau.argtypes = [i64, i64, i32, dbl, dbl, dbl]
+        L.ustd_oracle_tau.restype = i64
+        L.ustd_oracle_eta.argtypes = [i64, i64, i32, dbl, dbl]
+        L.ustd_oracle_eta.restype = dbl
+        L.ustd_oracle_wilson.argtypes = [i64, P, P, i32, u64, i64, P, P, P]
+        L.ustd_oracle_wilson.restype = i64
+        L.ustd_oracle_tree_flow.argtypes = [i64, i32, P, P, P]
+        L.ustd_oracle_tree_flow.restype = ctypes.c_int
+        L.ustd_oracle_trees.argtypes = [i64, P, P, i32, P, u64, i64, i64, P, P, P]
+        L.ustd_oracle_trees.restype = ctypes.c_int
+        L.ustd_oracle_solve.argtypes = [i64, P, P, i32, dbl, i64, P, P]
+        L.ustd_oracle_solve.restype = i64
+        L.ustd_oracle_combine.argtypes = [i64, i32, i64, P, P, P]
+        L.ustd_oracle_combine.restype = None
+        L.ustd_oracle_diag_lpinv.argtypes = [i64, P, P, i32, dbl, dbl, dbl, u64, i64, dbl, i64,
+                                             P, P, P, P, P, P]
+        L.ustd_oracle_diag_lpinv.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _csr(row_ptr, col):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    return rp, c
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().ustd_oracle_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def walk_word(seed: int, t: int, s: int, k: int) -> int:
+    return int(lib().ustd_oracle_walk_word(seed, t, s, k))
+
+
+def validate(row_ptr, col) -> int:
+    rp, c = _csr(row_ptr, col)
+    return int(lib().ustd_oracle_validate(len(rp) - 1, _p(rp), _p(c)))
+
+
+def bfs(row_ptr, col, u: int):
+    """Returns (dist int32[n], parB int32[n], ecc)."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    dist = np.zeros(n, dtype=np.int32)
+    parB = np.zeros(n, dtype=np.int32)
+    ecc = int(lib().ustd_oracle_bfs(n, _p(rp), _p(c), u, _p(dist), _p(parB)))
+    return dist, parB, ecc
+
+
+def tau(n: int, m: int, ecc: int, eps: float, delta: float = 0.0, kappa: float = 0.0) -> int:
+    return int(lib().ustd_oracle_tau(n, m, ecc, eps, delta, kappa))
+
+
+def eta(n: int, m: int, ecc: int, eps: float, kappa: float = 0.0) -> float:
+    return float(lib().ustd_oracle_eta(n, m, ecc, eps, kappa))
+
+
+def wilson(row_ptr, col, u: int, seed: int, t: int):
+    """One UST rooted at u.  Returns (parent int32[n], walk steps)."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    parent = np.zeros(n, dtype=np.int32)
+    nxt = np.zeros(n, dtype=np.int32)
+    intree = np.zeros(n, dtype=np.uint8)
+    steps = int(lib().ustd_oracle_wilson(n, _p(rp), _p(c), u, seed, t, _p(parent), _p(nxt), _p(intree)))
+    return parent, steps
+
+
+def tree_flow(u: int, parB, parent) -> np.ndarray:
+    """c_T(v) of one given tree (Algorithm 2), as int64[n]."""
+    pb = np.ascontiguousarray(parB, dtype=np.int32)
+    pt = np.ascontiguousarray(parent, dtype=np.int32)
+    counts = np.zeros(len(pb), dtype=np.int64)
+    rc = lib().ustd_oracle_tree_flow(len(pb), u, _p(pb), _p(pt), _p(counts))
+    if rc != OK:
+        raise RuntimeError("oracle tree_flow failed: %d" % rc)
+    return counts
+
+
+def trees(row_ptr, col, u: int, seed: int, tree_begin: int, tree_count: int,
+          want_parents: bool = True, want_counts: bool = True):
+    """Trees [tree_begin, tree_begin + tree_count).  Returns (parents or None, steps, counts or None)."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    _, parB, _ = bfs(rp, c, u)
+    parents = np.zeros((tree_count, n), dtype=np.int32) if want_parents else None
+    steps = np.zeros(tree_count, dtype=np.int64)
+    counts = np.zeros(n, dtype=np.int64) if want_counts else None
+    rc = lib().ustd_oracle_trees(n, _p(rp), _p(c), u, _p(parB), seed, tree_begin, tree_count,
+                                 _p(parents) if parents is not None else None, _p(steps),
+                                 _p(counts) if counts is not None else None)
+    if rc != OK:
+        raise RuntimeError("oracle trees failed: %d" % rc)
+    return parents, steps, counts
+
+
+def solve(row_ptr, col, u: int, tol: float = 1e-12, maxit: int = 100000):
+    """Column u of L^+ by FP64 Jacobi-PCG + mean-zero projection.  Returns (x, iters, relres)."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    x = np.zeros(n, dtype=np.float64)
+    rr = ctypes.c_double(0.0)
+    it = int(lib().ustd_oracle_solve(n, _p(rp), _p(c), u, tol, maxit, _p(x), ctypes.byref(rr)))
+    return x, it, rr.value
+
+
+def combine(u: int, tau_: int, counts, x) -> np.ndarray:
+    cnt = np.ascontiguousarray(counts, dtype=np.int64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    diag = np.zeros(len(cnt), dtype=np.float64)
+    lib().ustd_oracle_combine(len(cnt), u, tau_, _p(cnt), _p(xx), _p(diag))
+    return diag
+
+
+def diag_lpinv(row_ptr, col, u: int, eps: float, seed: int, delta: float = 0.0, kappa: float = 0.0,
+               tau_override: int = 0, solve_tol: float = 0.0, solve_maxit: int = 0):
+    """Algorithm 1 end to end.  Returns dict(diag, counts, tau, ecc, steps, relres, status)."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    diag = np.zeros(n, dtype=np.float64)
+    counts = np.zeros(n, dtype=np.int64)
+    t = ctypes.c_int64(0)
+    e = ctypes.c_int32(0)
+    s = ctypes.c_int64(0)
+    rr = ctypes.c_double(0.0)
+    rc = lib().ustd_oracle_diag_lpinv(n, _p(rp), _p(c), u, eps, delta, kappa, seed, tau_override,
+                                      solve_tol, solve_maxit, _p(diag), _p(counts), ctypes.byref(t),
+                                      ctypes.byref(e), ctypes.byref(s), ctypes.byref(rr))
+    return dict(diag=diag, counts=counts, tau=t.value, ecc=e.value, steps=s.value,
+                relres=rr.value, status=rc)
