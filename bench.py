@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark of the UST estimator of diag(L^+) on one MI355X.
+
+One step = one full ApproxDiagLpinv run (BFS tree and sample size, all tau trees sampled
+with Wilson's algorithm, tree intervals, Algorithm 2 aggregation, the pivot-column solve
+and the combination) on a graph already resident in HBM.  Default workload: R-MAT scale 16
+(edge factor 16, Graph500 a/b/c/d), largest component, unit weights, max-degree pivot,
+eps = 0.3 (tau = 4576), Philox seed 1.
+
+Prints one JSON line: trees/s end to end (`value`), walk steps/s of the sampler, the
+end-to-end time, a roofline entry for the dominant kernel and the CPU oracle's rate on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+WORKLOADS = {
+    "rmat16": dict(kind="rmat", scale=16, ef=16, seed=1),
+    "grid32": dict(kind="grid", side=32, tau=1000),
+    "rmat18": dict(kind="rmat", scale=18, ef=16, seed=1),
+    "rmat20": dict(kind="rmat", scale=20, ef=16, seed=1),
+    "rmat22": dict(kind="rmat", scale=22, ef=16, seed=1),
+}
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2006_13679_amd", "csrc", f)
+                  for f in ("ustd_kernels.hip", "ustd_kernels.hpp", "ustd_device.hpp")]
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_workload(name: str):
+    from paper_2006_13679_amd import graphgen as gg
+
+    w = WORKLOADS[name]
+    if w["kind"] == "rmat":
+        g = gg.rmat(w["scale"], w["ef"], w["seed"])
+        return g, gg.max_degree_pivot(g), 0, dict(workload="rmat-scale%d-ef%d" % (w["scale"], w["ef"]),
+                                                  generator_seed=w["seed"])
+    g = gg.grid2d(w["side"])
+    return g, gg.grid_center_pivot(w["side"]), w["tau"], dict(workload="grid%dx%d" % (w["side"], w["side"]))
+
+
+def algorithmic_bytes(n: int, tau: int, steps: int, farness: int) -> dict:
+    """Bytes the method must move (per the design notes): 20 B per walk step plus 12 B per
+    vertex and tree for the commit (sampler); 40 B per vertex and tree (intervals);
+    18 B per (vertex, B-path edge) pair plus 12 B per vertex and tree (aggregation)."""
+    return dict(sample=20 * steps + 12 * n * tau, intervals=40 * n * tau, aggregate=(18 * farness + 12 * n) * tau)
+
+
+def load_traffic(kernel: str, workload: str):
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_src_digest") != kernel_source_digest():
+        return None  # counters were taken on an older kernel
+    return t
+
+
+def cpu_baseline(g, u, tau, seed, budget_s: float):
+    """The oracle as it stands on a bounded sample: as many trees as fit in `budget_s`
+    (sampling + DFS + Algorithm 2), plus one full FP64 solve; scaled to the full tau."""
+    import oracle
+
+    oracle.build()
+    t0 = time.perf_counter()
+    x, it, rr = oracle.solve(g.row_ptr, g.col, u, tol=1e-12)
+    t_solve = time.perf_counter() - t0
+    done, t_trees, chunk = 0, 0.0, 16
+    while t_trees < budget_s and done < tau:
+        c = min(chunk, tau - done)
+        t0 = time.perf_counter()
+        oracle.trees(g.row_ptr, g.col, u, seed, done, c, want_parents=False)
+        t_trees += time.perf_counter() - t0
+        done += c
+        chunk = min(chunk * 2, 512)
+    per_tree = t_trees / done
+    full = per_tree * tau + t_solve
+    return {"value": tau / full, "unit": "trees/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of %d trees (%.1f s) + one FP64 Jacobi-PCG solve (%.2f s), single-threaded C; "
+                      "value = tau / (per-tree time * tau + solve time)" % (done, tau, t_trees, t_solve),
+            "ms_per_tree": per_tree * 1e3}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
+    ap.add_argument("--solve", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--trees-per-batch", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (trees would shard by range "
+              "across GPUs with one all-reduce of the integer counts; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2006_13679_amd import api
+
+    g, u, tau_override, cfg = make_workload(args.workload)
+    dev = torch.device("cuda:0")
+    G = api.Graph.from_host(g.row_ptr, g.col, device=dev)
+    mode = api.SOLVE_MIXED if args.solve == "mixed" else api.SOLVE_FP64
+    p = api.problem(G, pivot=u, eps=0.3, seed=1, tau_override=tau_override, solve_mode=mode, solve_tol=1e-12,
+                    trees_per_batch=args.trees_per_batch)
+    ws = api.Workspace(dev)
+    print("bench: %s n=%d m=%d pivot=%d" % (cfg["workload"], g.n, g.m, u), file=sys.stderr, flush=True)
+
+    reps = []
+    for i in range(args.warmup):
+        api.diag_lpinv_p(G, p, ws=ws, want_counts=False)
+        print("bench: warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, _, rep = api.diag_lpinv_p(G, p, ws=ws, want_counts=False)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print("bench: %d timed steps in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
+
+    ms_step = wall * 1e3 / args.steps
+    tau = reps[0]["tau"]
+    steps = reps[0]["walk_steps"]
+    med = lambda k: float(np.median([r[k] for r in reps]))  # noqa: E731
+    ms_sample, ms_iv, ms_ag = med("ms_sample"), med("ms_intervals"), med("ms_aggregate")
+
+    dist, _, _, _ = api.bfs(G, p, ws=ws)  # farness of the pivot, for the algorithmic-byte count
+    farness = int(dist.sum().item())
+    ab = algorithmic_bytes(g.n, tau, steps, farness)
+    phases = {"sample": ms_sample, "intervals": ms_iv, "aggregate": ms_ag}
+    dom = max(phases, key=phases.get)
+    kname = {"sample": "wilson", "intervals": "intervals", "aggregate": "aggregate"}[dom]
+    achieved = ab[dom] / (phases[dom] * 1e-3) / 1e9
+    traffic = load_traffic(kname, cfg["workload"])
+    roof = {"bound": "hbm", "kernel": kname + "_kernel", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": (traffic["bytes_per_launch"] if traffic else None),
+            "algorithmic_bytes_per_launch": ab[dom], "launch_ms": round(phases[dom], 4)}
+
+    out = {
+        "metric": "spanning trees/sec + walk steps/sec; end-to-end diag(L†) time at ε=0.3",
+        "value": round(tau / (ms_step * 1e-3), 2),
+        "unit": "trees/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32+fp64" if mode == api.SOLVE_FP64 else "int32+fp32/fp64",
+        "data": "synthetic",
+        "config": dict(cfg, n=g.n, m=g.m, pivot=u, eps=0.3, tau=tau, seed=1,
+                       solve=args.solve, trees_per_batch=reps[0]["trees_per_batch"]),
+        "walk_steps_per_s": round(steps / (ms_sample * 1e-3), 1),
+        "sampling_trees_per_s": round(tau / (ms_sample * 1e-3), 1),
+        "e2e_ms": round(med("ms_total"), 4),
+        "phase_ms": {"bfs": med("ms_bfs"), "sample": ms_sample, "intervals": ms_iv, "aggregate": ms_ag,
+                     "solve": med("ms_solve"), "combine": med("ms_combine")},
+        "walk_steps": steps, "walk_draws": reps[0]["walk_draws"],
+        "solve_iters": reps[0]["solve_iters"], "solve_relres": reps[0]["solve_relres"],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(g, u, tau, 1, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

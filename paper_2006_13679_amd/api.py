@@ -1,0 +1,251 @@
+"""Python binding of libustd.so (include/ustd.h): argument marshalling only.
+
+Every step of the estimator runs in the library's HIP kernels; torch provides device
+memory (inputs, outputs, the workspace) and the stream.  If the built library is missing
+the calls raise instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libustd.so")
+
+OK, EINVAL, EGRAPH, ENOMEM, EHIP, ENOTCONV = 0, 1, 2, 3, 4, 5
+SOLVE_FP64, SOLVE_MIXED = 0, 1
+
+
+class UstdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+_STATUS = {0: "USTD_OK", 1: "USTD_EINVAL", 2: "USTD_EGRAPH", 3: "USTD_ENOMEM", 4: "USTD_EHIP", 5: "USTD_ENOTCONV"}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("d_row_ptr", ctypes.c_void_p), ("d_col", ctypes.c_void_p),
+        ("pivot", ctypes.c_int32), ("solve_mode", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("delta", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("tau_override", ctypes.c_int64),
+        ("solve_tol", ctypes.c_double), ("solve_maxit", ctypes.c_int32),
+        ("validate", ctypes.c_int32), ("trees_per_batch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("tau", ctypes.c_int64), ("walk_steps", ctypes.c_int64), ("walk_draws", ctypes.c_int64),
+        ("pivot", ctypes.c_int32), ("ecc", ctypes.c_int32), ("solve_iters", ctypes.c_int32),
+        ("solve_outer", ctypes.c_int32), ("n_batches", ctypes.c_int32), ("trees_per_batch", ctypes.c_int32),
+        ("solve_relres", ctypes.c_double),
+        ("ms_setup", ctypes.c_double), ("ms_bfs", ctypes.c_double), ("ms_sample", ctypes.c_double),
+        ("ms_intervals", ctypes.c_double), ("ms_aggregate", ctypes.c_double), ("ms_solve", ctypes.c_double),
+        ("ms_combine", ctypes.c_double), ("ms_total", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+EXPORTS = ["ustd_workspace_bytes", "ustd_bfs", "ustd_sample_trees", "ustd_flow_counts", "ustd_tree_counts",
+           "ustd_solve_pivot_column", "ustd_diag_lpinv", "ustd_philox_words", "ustd_status_string",
+           "ustd_last_error"]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libustd.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        PP = ctypes.POINTER(Problem)
+        PR = ctypes.POINTER(Report)
+        L.ustd_workspace_bytes.argtypes = [PP, ctypes.POINTER(ctypes.c_size_t)]
+        L.ustd_bfs.argtypes = [PP, P, ctypes.c_size_t, P, P, ctypes.POINTER(i32), ctypes.POINTER(i32), P]
+        L.ustd_sample_trees.argtypes = [PP, i64, i64, P, ctypes.c_size_t, P, P, P]
+        L.ustd_flow_counts.argtypes = [PP, i64, i64, P, ctypes.c_size_t, P, PR, P]
+        L.ustd_tree_counts.argtypes = [PP, P, i64, P, ctypes.c_size_t, P, P]
+        L.ustd_solve_pivot_column.argtypes = [PP, P, ctypes.c_size_t, P, PR, P]
+        L.ustd_diag_lpinv.argtypes = [PP, P, ctypes.c_size_t, P, P, PR, P]
+        L.ustd_philox_words.argtypes = [u64, i64, i32, i64, i64, P, P]
+        for name in EXPORTS[:-2]:
+            getattr(L, name).restype = ctypes.c_int
+        L.ustd_status_string.argtypes = [ctypes.c_int]
+        L.ustd_status_string.restype = ctypes.c_char_p
+        L.ustd_last_error.argtypes = []
+        L.ustd_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, allow=(OK,)):
+    if rc not in allow:
+        raise UstdError(rc, lib().ustd_last_error().decode())
+    return rc
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+@dataclass
+class Graph:
+    """A CSR graph resident on the device (int64 row pointers, int32 columns)."""
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return self.row_ptr.numel() - 1
+
+    @property
+    def nnz(self) -> int:
+        return self.col.numel()
+
+    @staticmethod
+    def from_host(row_ptr, col, device="cuda") -> "Graph":
+        rp = torch.as_tensor(row_ptr, dtype=torch.int64).to(device).contiguous()
+        c = torch.as_tensor(col, dtype=torch.int32).to(device).contiguous()
+        return Graph(rp, c)
+
+
+def problem(g: Graph, pivot: int = -1, eps: float = 0.3, seed: int = 1, delta: float = 0.0, kappa: float = 0.0,
+            tau_override: int = 0, solve_mode: int = SOLVE_FP64, solve_tol: float = 0.0, solve_maxit: int = 0,
+            validate: bool = False, trees_per_batch: int = 0) -> Problem:
+    assert g.row_ptr.dtype == torch.int64 and g.col.dtype == torch.int32
+    assert g.row_ptr.is_cuda and g.col.is_cuda and g.row_ptr.is_contiguous() and g.col.is_contiguous()
+    return Problem(n=g.n, nnz=g.nnz, d_row_ptr=g.row_ptr.data_ptr(), d_col=g.col.data_ptr(), pivot=pivot,
+                   solve_mode=solve_mode, eps=eps, delta=delta, kappa=kappa, seed=seed & 0xFFFFFFFFFFFFFFFF,
+                   tau_override=tau_override, solve_tol=solve_tol, solve_maxit=solve_maxit,
+                   validate=1 if validate else 0, trees_per_batch=trees_per_batch, reserved=0)
+
+
+def workspace_bytes(p: Problem) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().ustd_workspace_bytes(ctypes.byref(p), ctypes.byref(b)))
+    return int(b.value)
+
+
+class Workspace:
+    """A reusable device workspace (grown on demand, 256-byte aligned by torch's allocator)."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws: dict = {}
+
+
+def _ws(p: Problem, g: Graph, ws: Workspace | None):
+    if ws is None:
+        key = g.row_ptr.device
+        ws = _default_ws.setdefault(key, Workspace(key))
+    nbytes = workspace_bytes(p)
+    buf = ws.get(nbytes)
+    return buf, buf.numel()
+
+
+def bfs(g: Graph, p: Problem, ws: Workspace | None = None):
+    buf, nb = _ws(p, g, ws)
+    dist = torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
+    parB = torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
+    ecc, piv = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().ustd_bfs(ctypes.byref(p), _ptr(buf), nb, _ptr(dist), _ptr(parB), ctypes.byref(ecc),
+                          ctypes.byref(piv), _stream(g.row_ptr.device)))
+    return dist, parB, int(ecc.value), int(piv.value)
+
+
+def sample_trees(g: Graph, p: Problem, tree_begin: int, tree_count: int, ws: Workspace | None = None):
+    buf, nb = _ws(p, g, ws)
+    dev = g.row_ptr.device
+    parents = torch.empty((tree_count, g.n), dtype=torch.int32, device=dev)
+    steps = torch.empty(tree_count, dtype=torch.int64, device=dev)
+    _check(lib().ustd_sample_trees(ctypes.byref(p), tree_begin, tree_count, _ptr(buf), nb, _ptr(parents),
+                                   _ptr(steps), _stream(dev)))
+    return parents, steps
+
+
+def flow_counts(g: Graph, p: Problem, tree_begin: int, tree_count: int, counts: torch.Tensor | None = None,
+                ws: Workspace | None = None):
+    buf, nb = _ws(p, g, ws)
+    dev = g.row_ptr.device
+    if counts is None:
+        counts = torch.zeros(g.n, dtype=torch.int64, device=dev)
+    rep = Report()
+    _check(lib().ustd_flow_counts(ctypes.byref(p), tree_begin, tree_count, _ptr(buf), nb, _ptr(counts),
+                                  ctypes.byref(rep), _stream(dev)))
+    return counts, rep.as_dict()
+
+
+def tree_counts(g: Graph, p: Problem, parents: torch.Tensor, counts: torch.Tensor | None = None,
+                ws: Workspace | None = None):
+    buf, nb = _ws(p, g, ws)
+    dev = g.row_ptr.device
+    parents = parents.to(device=dev, dtype=torch.int32).contiguous()
+    assert parents.dim() == 2 and parents.shape[1] == g.n
+    if counts is None:
+        counts = torch.zeros(g.n, dtype=torch.int64, device=dev)
+    _check(lib().ustd_tree_counts(ctypes.byref(p), _ptr(parents), parents.shape[0], _ptr(buf), nb, _ptr(counts),
+                                  _stream(dev)))
+    return counts
+
+
+def solve_pivot_column(g: Graph, p: Problem, ws: Workspace | None = None, allow_notconv: bool = False):
+    buf, nb = _ws(p, g, ws)
+    dev = g.row_ptr.device
+    x = torch.empty(g.n, dtype=torch.float64, device=dev)
+    rep = Report()
+    rc = lib().ustd_solve_pivot_column(ctypes.byref(p), _ptr(buf), nb, _ptr(x), ctypes.byref(rep), _stream(dev))
+    _check(rc, (OK, ENOTCONV) if allow_notconv else (OK,))
+    return x, rep.as_dict()
+
+
+def diag_lpinv_p(g: Graph, p: Problem, ws: Workspace | None = None, want_counts: bool = True,
+                 allow_notconv: bool = False):
+    """ApproxDiagLpinv on a prepared problem.  Returns (diag float64[n], counts int64[n] or None, report)."""
+    buf, nb = _ws(p, g, ws)
+    dev = g.row_ptr.device
+    diag = torch.empty(g.n, dtype=torch.float64, device=dev)
+    counts = torch.empty(g.n, dtype=torch.int64, device=dev) if want_counts else None
+    rep = Report()
+    rc = lib().ustd_diag_lpinv(ctypes.byref(p), _ptr(buf), nb, _ptr(diag), _ptr(counts), ctypes.byref(rep),
+                               _stream(dev))
+    _check(rc, (OK, ENOTCONV) if allow_notconv else (OK,))
+    out = rep.as_dict()
+    out["status"] = rc
+    return diag, counts, out
+
+
+def diag_lpinv(row_ptr, col, pivot: int = -1, eps: float = 0.3, seed: int = 1, **kw):
+    """diag(L^+) of a CSR graph (host or device arrays) by the UST estimator."""
+    g = Graph.from_host(row_ptr, col)
+    p = problem(g, pivot=pivot, eps=eps, seed=seed, **kw)
+    return diag_lpinv_p(g, p)
+
+
+def philox_words(seed: int, t: int, s: int, k0: int, count: int, device="cuda") -> torch.Tensor:
+    out = torch.empty(count, dtype=torch.int32, device=device)
+    _check(lib().ustd_philox_words(seed & 0xFFFFFFFFFFFFFFFF, t, s, k0, count, _ptr(out), _stream(torch.device(device))))
+    return out

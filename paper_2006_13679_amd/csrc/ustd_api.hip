@@ -1,0 +1,627 @@
+// ustd_api.hip -- C ABI (include/ustd.h): argument checks, workspace planning and the
+// stream-ordered orchestration of the estimator's phases (Algorithm 1 of Angriman et
+// al., ESA 2020: BFS tree and sample size, tau trees sampled and aggregated, the pivot
+// column solve, and the final combination).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ustd.h"
+#include "ustd_kernels.hpp"
+
+using namespace ustd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(...)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (__VA_ARGS__);                                                             \
+        if (e_ != hipSuccess) return fail(USTD_EHIP, "%s: %s", #__VA_ARGS__, hipGetErrorString(e_)); \
+    } while (0)
+
+#define USTD_TRY(...)                   \
+    do {                                \
+        int rc_ = (__VA_ARGS__);        \
+        if (rc_ != USTD_OK) return rc_; \
+    } while (0)
+
+constexpr long long kAlign = 256;
+constexpr int kLdsBitsMaxWords = 4096;      // tree bitmap in LDS up to 131072 vertices (16 KB)
+constexpr long long kDefaultBudget = 24ll << 30;
+constexpr int kMaxTreesPerBatch = 8192;
+constexpr int kSolveGrid = 1024;
+constexpr int kPathSteps = 63;
+
+inline long long align_up(long long v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Misc {                      // small zero-initialised block at the front of the workspace
+    int err_validate;
+    int bfs_found;
+    int err_interval;
+    int pad0;
+    unsigned long long best_degree;
+    unsigned int counters[8];
+    CgScalars sc64, sc32;
+    double rr_hist64[kRrHist];
+    double rr_hist32[kRrHist];
+    double sums[4];
+    double shift_scale[4];
+};
+
+struct Plan {
+    int n, nnz, K, rob, nwords;
+    bool lds_bits;
+    long long par_stride, scr_stride, pk_stride;
+    long long off_misc, off_rp32, off_dist, off_parB, off_counts, off_steps, off_draws, off_par, off_path,
+        off_bits, off_scr, off_pk, off_part, off_x64, off_r64, off_z64, off_p64, off_q64, off_res64, off_x32,
+        off_r32, off_z32, off_p32, off_q32;
+    long long total;
+};
+
+int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+int check_problem(const ustd_problem *p) {
+    if (!p) return fail(USTD_EINVAL, "problem is NULL");
+    if (p->n < 2 || p->n >= (1ll << 31) - 1) return fail(USTD_EINVAL, "n = %lld out of range [2, 2^31-1)", (long long)p->n);
+    if (p->nnz < 2 || p->nnz >= (1ll << 31)) return fail(USTD_EINVAL, "nnz = %lld out of range [2, 2^31)", (long long)p->nnz);
+    if (!p->d_row_ptr || !p->d_col) return fail(USTD_EINVAL, "row_ptr / col is NULL");
+    if (p->pivot < -1 || p->pivot >= p->n) return fail(USTD_EINVAL, "pivot %d out of range", p->pivot);
+    if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(USTD_EINVAL, "eps must be > 0");
+    if (p->delta > 0.0 && !(p->delta < 1.0)) return fail(USTD_EINVAL, "delta must lie in (0,1)");
+    if (p->kappa > 0.0 && !(p->kappa < 1.0)) return fail(USTD_EINVAL, "kappa must lie in (0,1)");
+    if (p->solve_mode != USTD_SOLVE_FP64 && p->solve_mode != USTD_SOLVE_MIXED)
+        return fail(USTD_EINVAL, "unknown solve_mode %d", p->solve_mode);
+    if (p->trees_per_batch > kMaxTreesPerBatch)
+        return fail(USTD_EINVAL, "trees_per_batch %d exceeds %d", p->trees_per_batch, kMaxTreesPerBatch);
+    return USTD_OK;
+}
+
+Plan make_plan(const ustd_problem *p) {
+    Plan L{};
+    L.n = (int)p->n;
+    L.nnz = (int)p->nnz;
+    L.nwords = (L.n + 31) / 32;
+    L.lds_bits = L.nwords <= kLdsBitsMaxWords;
+    L.rob = std::min(256, next_pow2(std::max(L.n, 2)));
+    L.par_stride = align_up((long long)L.n * 4) / 4;
+    L.scr_stride = align_up(interval_scratch_ints(L.n) * 4) / 4;
+    L.pk_stride = align_up((long long)L.n * 16) / 16;
+    const long long per_tree = L.par_stride * 4 + align_up((long long)L.rob * kPathSteps * 4) +
+                               (L.lds_bits ? 0 : align_up((long long)L.nwords * 4)) + L.scr_stride * 4 +
+                               L.pk_stride * 16 + 16;
+    long long K = p->trees_per_batch > 0 ? p->trees_per_batch : std::max(1ll, kDefaultBudget / per_tree);
+    K = std::min<long long>(K, kMaxTreesPerBatch);
+    if (p->tau_override > 0) K = std::min<long long>(K, p->tau_override);
+    L.K = (int)std::max(1ll, K);
+    long long o = 0;
+    auto take = [&](long long bytes) {
+        long long at = o;
+        o += align_up(bytes);
+        return at;
+    };
+    const long long n = L.n;
+    L.off_misc = take(sizeof(Misc));
+    L.off_rp32 = take((n + 1) * 4);
+    L.off_dist = take(n * 4);
+    L.off_parB = take(n * 4);
+    L.off_counts = take(n * 8);
+    L.off_steps = take((long long)L.K * 8);
+    L.off_draws = take((long long)L.K * 8);
+    L.off_par = take((long long)L.K * L.par_stride * 4);
+    L.off_path = take((long long)L.K * L.rob * kPathSteps * 4);
+    L.off_bits = take(L.lds_bits ? 0 : (long long)L.K * L.nwords * 4);
+    L.off_scr = take((long long)L.K * L.scr_stride * 4);
+    L.off_pk = take((long long)L.K * L.pk_stride * 16);
+    L.off_part = take((long long)kSolveGrid * 3 * 8);
+    L.off_x64 = take(n * 8);
+    L.off_r64 = take(n * 8);
+    L.off_z64 = take(n * 8);
+    L.off_p64 = take(n * 8);
+    L.off_q64 = take(n * 8);
+    L.off_res64 = take(n * 8);
+    L.off_x32 = take(n * 4);
+    L.off_r32 = take(n * 4);
+    L.off_z32 = take(n * 4);
+    L.off_p32 = take(n * 4);
+    L.off_q32 = take(n * 4);
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+T *at(void *ws, long long off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+// tau = ecc^2 * ceil( ln(2m/delta) / (2 (1-kappa)^2 eps^2) ) (Algorithm 1, initialisation)
+long long sample_size(const ustd_problem *p, int ecc) {
+    if (p->tau_override > 0) return p->tau_override;
+    const double n = (double)p->n, m = (double)(p->nnz / 2);
+    const double delta = p->delta > 0.0 ? p->delta : 1.0 / n;
+    const double kappa = p->kappa > 0.0 ? p->kappa : 0.3;
+    const double om = 1.0 - kappa;
+    const double q = std::log(2.0 * m / delta) / (2.0 * om * om * p->eps * p->eps);
+    return (long long)ecc * (long long)ecc * (long long)std::ceil(q);
+}
+
+// eta = kappa eps / (3 sqrt(m n ln n) diam), diam <= 2 ecc (Algorithm 1, solver accuracy)
+double solver_eta(const ustd_problem *p, int ecc) {
+    const double n = (double)p->n, m = (double)(p->nnz / 2);
+    const double kappa = p->kappa > 0.0 ? p->kappa : 0.3;
+    return kappa * p->eps / (3.0 * std::sqrt(m * n * std::log(n)) * (2.0 * std::max(ecc, 1)));
+}
+
+struct Timer {
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    explicit Timer(hipStream_t s) : st(s) {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, st);
+    }
+    double stop_ms() {
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        return (double)ms;
+    }
+    ~Timer() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+};
+
+struct Ctx {
+    const ustd_problem *p;
+    Plan L;
+    void *ws;
+    hipStream_t st;
+    Misc *misc;
+    int *rp32;
+    int pivot = -1, ecc = 0;
+};
+
+int begin(Ctx &c, const ustd_problem *p, void *ws, size_t ws_bytes, void *stream) {
+    USTD_TRY(check_problem(p));
+    c.p = p;
+    c.L = make_plan(p);
+    if (!ws) return fail(USTD_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return fail(USTD_EINVAL, "workspace must be 256-byte aligned");
+    if ((long long)ws_bytes < c.L.total)
+        return fail(USTD_ENOMEM, "workspace %zu bytes < required %lld", ws_bytes, c.L.total);
+    c.ws = ws;
+    c.st = (hipStream_t)stream;
+    c.misc = at<Misc>(ws, c.L.off_misc);
+    c.rp32 = at<int>(ws, c.L.off_rp32);
+    HIP_TRY(hipMemsetAsync(c.misc, 0, sizeof(Misc), c.st));
+    HIP_TRY(launch_rp_to_i32(c.L.n, (const long long *)p->d_row_ptr, c.rp32, c.st));
+    return USTD_OK;
+}
+
+// pivot choice, optional validation and the BFS tree B_u; synchronises the stream
+int setup(Ctx &c, ustd_report *rep) {
+    const ustd_problem *p = c.p;
+    const int n = c.L.n;
+    Timer tm(c.st);
+    if (p->validate) HIP_TRY(launch_validate(n, p->nnz, (const long long *)p->d_row_ptr, p->d_col, &c.misc->err_validate, c.st));
+    if (p->pivot >= 0) {
+        c.pivot = p->pivot;
+    } else {
+        HIP_TRY(launch_argmax_degree(n, c.rp32, &c.misc->best_degree, c.st));
+        unsigned long long best = 0;
+        HIP_TRY(hipMemcpyAsync(&best, &c.misc->best_degree, sizeof(best), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        c.pivot = (int)(0xFFFFFFFFu - (unsigned)(best & 0xFFFFFFFFull));
+    }
+    if (p->validate) {
+        int err = 0;
+        HIP_TRY(hipMemcpyAsync(&err, &c.misc->err_validate, sizeof(int), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        if (err) return fail(USTD_EGRAPH, "graph validation failed (code %d: 1 bounds, 2 unsorted/range, 4 self-loop, 8 asymmetric, 16 isolated)", err);
+    }
+    int *dist = at<int>(c.ws, c.L.off_dist);
+    int *parB = at<int>(c.ws, c.L.off_parB);
+    HIP_TRY(launch_bfs_init(n, c.pivot, dist, parB, c.st));
+    int d = 0;
+    for (;; ++d) {
+        HIP_TRY(hipMemsetAsync(&c.misc->bfs_found, 0, sizeof(int), c.st));
+        HIP_TRY(launch_bfs_level(n, c.rp32, p->d_col, d, dist, parB, &c.misc->bfs_found, c.st));
+        int found = 0;
+        HIP_TRY(hipMemcpyAsync(&found, &c.misc->bfs_found, sizeof(int), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        if (!found) break;
+    }
+    c.ecc = d;
+    HIP_TRY(launch_count_unreached(n, dist, &c.misc->err_validate, c.st));
+    int err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, &c.misc->err_validate, sizeof(int), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    if (err) return fail(USTD_EGRAPH, "graph is not connected");
+    if (rep) {
+        rep->pivot = c.pivot;
+        rep->ecc = c.ecc;
+        rep->ms_bfs += tm.stop_ms();
+    }
+    return USTD_OK;
+}
+
+WilsonArgs wilson_args(const Ctx &c, long long tree_begin, int *par, long long par_stride, long long *steps,
+                       long long *draws) {
+    WilsonArgs a{};
+    a.n = c.L.n;
+    a.u = c.pivot;
+    a.nwords = c.L.nwords;
+    a.rob = c.L.rob;
+    a.rp = c.rp32;
+    a.col = c.p->d_col;
+    a.key0 = (uint32_t)(c.p->seed & 0xFFFFFFFFull);
+    a.key1 = (uint32_t)(c.p->seed >> 32);
+    a.tree_begin = tree_begin;
+    a.par = par;
+    a.par_stride = par_stride;
+    a.path = at<int>(c.ws, c.L.off_path);
+    a.bits = at<uint32_t>(c.ws, c.L.off_bits);
+    a.steps = steps;
+    a.draws = draws;
+    return a;
+}
+
+// intervals + aggregation of `cnt` trees whose parent arrays start at par (stride par_stride)
+int aggregate_trees(Ctx &c, const int *par, long long par_stride, int cnt, long long *counts, double *ms_iv,
+                    double *ms_ag) {
+    IntervalArgs ia{};
+    ia.n = c.L.n;
+    ia.u = c.pivot;
+    ia.par = par;
+    ia.par_stride = par_stride;
+    ia.scratch = at<int>(c.ws, c.L.off_scr);
+    ia.scratch_stride = c.L.scr_stride;
+    ia.pk = at<int4>(c.ws, c.L.off_pk);
+    ia.pk_stride = c.L.pk_stride;
+    ia.err = &c.misc->err_interval;
+    {
+        Timer tm(c.st);
+        HIP_TRY(launch_intervals(ia, cnt, c.st));
+        if (ms_iv) *ms_iv += tm.stop_ms();
+    }
+    AggregateArgs aa{};
+    aa.n = c.L.n;
+    aa.u = c.pivot;
+    aa.ntrees = cnt;
+    aa.trees_per_chunk = 32;
+    aa.parB = at<int>(c.ws, c.L.off_parB);
+    aa.pk = ia.pk;
+    aa.pk_stride = c.L.pk_stride;
+    aa.counts = counts;
+    {
+        Timer tm(c.st);
+        HIP_TRY(launch_aggregate(aa, c.st));
+        if (ms_ag) *ms_ag += tm.stop_ms();
+    }
+    int err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, &c.misc->err_interval, sizeof(int), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    if (err) return fail(USTD_EINVAL, "a parent array is not a spanning tree rooted at the pivot");
+    return USTD_OK;
+}
+
+int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *counts, ustd_report *rep) {
+    long long steps_total = 0, draws_total = 0;
+    int batches = 0;
+    std::vector<long long> hs(c.L.K), hd(c.L.K);
+    long long *steps = at<long long>(c.ws, c.L.off_steps);
+    long long *draws = at<long long>(c.ws, c.L.off_draws);
+    int *par = at<int>(c.ws, c.L.off_par);
+    double ms_s = 0, ms_i = 0, ms_a = 0;
+    for (long long b0 = 0; b0 < tree_count; b0 += c.L.K) {
+        const int cnt = (int)std::min<long long>(c.L.K, tree_count - b0);
+        WilsonArgs wa = wilson_args(c, tree_begin + b0, par, c.L.par_stride, steps, draws);
+        {
+            Timer tm(c.st);
+            HIP_TRY(launch_wilson(wa, cnt, c.L.lds_bits, c.st));
+            ms_s += tm.stop_ms();
+        }
+        USTD_TRY(aggregate_trees(c, par, c.L.par_stride, cnt, counts, &ms_i, &ms_a));
+        HIP_TRY(hipMemcpyAsync(hs.data(), steps, cnt * sizeof(long long), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipMemcpyAsync(hd.data(), draws, cnt * sizeof(long long), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        for (int i = 0; i < cnt; ++i) {
+            steps_total += hs[i];
+            draws_total += hd[i];
+        }
+        ++batches;
+    }
+    if (rep) {
+        rep->walk_steps += steps_total;
+        rep->walk_draws += draws_total;
+        rep->n_batches += batches;
+        rep->trees_per_batch = c.L.K;
+        rep->ms_sample += ms_s;
+        rep->ms_intervals += ms_i;
+        rep->ms_aggregate += ms_a;
+    }
+    return USTD_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// pivot-column solve
+// ---------------------------------------------------------------------------------------
+template <typename T>
+CgArgs<T> cg_args(Ctx &c, T *x, T *r, T *z, T *pp, T *q, CgScalars *sc, double *hist, unsigned int *counter) {
+    CgArgs<T> a{};
+    a.n = c.L.n;
+    a.rp = c.rp32;
+    a.col = c.p->d_col;
+    a.x = x;
+    a.r = r;
+    a.z = z;
+    a.p = pp;
+    a.q = q;
+    a.part = at<double>(c.ws, c.L.off_part);
+    a.counter = counter;
+    a.sc = sc;
+    a.rr_hist = hist;
+    return a;
+}
+
+int solve_grid(int n) { return std::max(1, std::min(kSolveGrid, (n + 255) / 256)); }
+
+// Runs CG iterations until the device flags convergence (rr <= tol2 * rr0) or breakdown,
+// or `maxit` iterations; launches in chunks and polls the device scalars between chunks.
+template <typename T>
+int cg_iterate(Ctx &c, const CgArgs<T> &a, int maxit, int *iters_out, bool *conv) {
+    const int grid = solve_grid(c.L.n);
+    CgScalars sc{};
+    *conv = false;
+    int launched = 0;
+    const int chunk = 16;
+    for (;;) {
+        HIP_TRY(hipMemcpyAsync(&sc, a.sc, sizeof(sc), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        if (sc.done || launched >= maxit) break;
+        const int todo = std::min(chunk, maxit - launched);
+        for (int i = 0; i < todo; ++i) HIP_TRY(launch_cg_iteration<T>(a, grid, c.st));
+        launched += todo;
+    }
+    *conv = sc.done && sc.rr <= sc.tol2 * sc.rr0;
+    *iters_out = sc.iter;
+    return USTD_OK;
+}
+
+int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
+    const ustd_problem *p = c.p;
+    const int n = c.L.n;
+    const int grid = solve_grid(n);
+    const double bnorm = std::sqrt((double)(n - 1) / (double)n);
+    double tol = p->solve_tol;
+    if (!(tol > 0.0)) tol = std::min(solver_eta(p, c.ecc), 1e-12);
+    const int maxit = p->solve_maxit > 0 ? p->solve_maxit : 20000;
+    double *x64 = x_out;
+    double *part = at<double>(c.ws, c.L.off_part);
+    double *sums = c.misc->sums;
+    int total_it = 0, outer = 0;
+    bool conv = false;
+    Timer tm(c.st);
+    if (p->solve_mode == USTD_SOLVE_FP64) {
+        CgArgs<double> a = cg_args<double>(c, x64, at<double>(c.ws, c.L.off_r64), at<double>(c.ws, c.L.off_z64),
+                                           at<double>(c.ws, c.L.off_p64), at<double>(c.ws, c.L.off_q64),
+                                           &c.misc->sc64, c.misc->rr_hist64, &c.misc->counters[0]);
+        HIP_TRY(launch_cg_start<double, double>(a, grid, nullptr, 1, c.pivot, nullptr, tol * tol, c.st));
+        USTD_TRY(cg_iterate<double>(c, a, maxit, &total_it, &conv));
+        outer = 1;
+        HIP_TRY(launch_residual64(n, c.rp32, p->d_col, c.pivot, x64, nullptr, part, &c.misc->counters[2], sums, grid, c.st));
+        HIP_TRY(launch_axpy_project<double>(n, x64, nullptr, nullptr, 0, sums + 2, grid, c.st));
+    } else {
+        double *res = at<double>(c.ws, c.L.off_res64);
+        float *x32 = at<float>(c.ws, c.L.off_x32);
+        CgArgs<float> a = cg_args<float>(c, x32, at<float>(c.ws, c.L.off_r32), at<float>(c.ws, c.L.off_z32),
+                                         at<float>(c.ws, c.L.off_p32), at<float>(c.ws, c.L.off_q32),
+                                         &c.misc->sc32, c.misc->rr_hist32, &c.misc->counters[1]);
+        HIP_TRY(hipMemsetAsync(x64, 0, (size_t)n * 8, c.st));
+        const double inner_tol = 1e-5;
+        double prev = INFINITY;
+        for (outer = 0; outer < 40; ++outer) {
+            HIP_TRY(launch_residual64(n, c.rp32, p->d_col, c.pivot, x64, res, part, &c.misc->counters[2], sums, grid, c.st));
+            HIP_TRY(launch_axpy_project<double>(n, x64, nullptr, nullptr, 0, sums + 2, grid, c.st));
+            HIP_TRY(launch_outer_scalars(n, sums, c.misc->shift_scale, c.st));
+            double hs[4];
+            HIP_TRY(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, c.st));
+            HIP_TRY(hipStreamSynchronize(c.st));
+            const double rnorm = std::sqrt(std::max(hs[1], 0.0));
+            if (rnorm <= tol * bnorm) { conv = true; break; }
+            if (outer > 0 && rnorm > 0.5 * prev) break;  // refinement stagnates at FP64 rounding
+            prev = rnorm;
+            if (total_it >= maxit) break;
+            HIP_TRY(launch_cg_start<double, float>(a, grid, res, 0, c.pivot, c.misc->shift_scale,
+                                                   inner_tol * inner_tol, c.st));
+            int it = 0;
+            bool ic = false;
+            USTD_TRY(cg_iterate<float>(c, a, maxit - total_it, &it, &ic));
+            total_it += it;
+            HIP_TRY(launch_axpy_project<float>(n, x64, x32, c.misc->shift_scale, 2, nullptr, grid, c.st));
+        }
+    }
+    // final residual of the projected solution
+    HIP_TRY(launch_residual64(n, c.rp32, p->d_col, c.pivot, x64, nullptr, part, &c.misc->counters[2], sums, grid, c.st));
+    double hs[4];
+    HIP_TRY(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    const double relres = std::sqrt(std::max(hs[1], 0.0)) / bnorm;
+    if (relres <= tol) conv = true;
+    if (rep) {
+        rep->solve_iters += total_it;
+        rep->solve_outer += outer;
+        rep->solve_relres = relres;
+        rep->ms_solve += tm.stop_ms();
+    }
+    if (!conv && relres > std::max(tol, 1e-9)) return fail(USTD_ENOTCONV, "solve stopped at relative residual %.3e (target %.3e)", relres, tol);
+    return USTD_OK;
+}
+
+}  // namespace
+
+// =========================================================================================
+// C ABI
+// =========================================================================================
+extern "C" {
+
+int ustd_workspace_bytes(const ustd_problem *prob, size_t *bytes) {
+    g_err.clear();
+    USTD_TRY(check_problem(prob));
+    if (!bytes) return fail(USTD_EINVAL, "bytes is NULL");
+    *bytes = (size_t)make_plan(prob).total;
+    return USTD_OK;
+}
+
+int ustd_bfs(const ustd_problem *prob, void *d_ws, size_t ws_bytes, int32_t *d_dist, int32_t *d_parB,
+             int32_t *ecc_out, int32_t *pivot_out, void *stream) {
+    g_err.clear();
+    Ctx c;
+    USTD_TRY(begin(c, prob, d_ws, ws_bytes, stream));
+    USTD_TRY(setup(c, nullptr));
+    const size_t nb = (size_t)c.L.n * 4;
+    if (d_dist) HIP_TRY(hipMemcpyAsync(d_dist, at<int>(c.ws, c.L.off_dist), nb, hipMemcpyDeviceToDevice, c.st));
+    if (d_parB) HIP_TRY(hipMemcpyAsync(d_parB, at<int>(c.ws, c.L.off_parB), nb, hipMemcpyDeviceToDevice, c.st));
+    if (ecc_out) *ecc_out = c.ecc;
+    if (pivot_out) *pivot_out = c.pivot;
+    HIP_TRY(hipStreamSynchronize(c.st));
+    return USTD_OK;
+}
+
+int ustd_sample_trees(const ustd_problem *prob, int64_t tree_begin, int64_t tree_count, void *d_ws,
+                      size_t ws_bytes, int32_t *d_parents, int64_t *d_steps, void *stream) {
+    g_err.clear();
+    Ctx c;
+    USTD_TRY(begin(c, prob, d_ws, ws_bytes, stream));
+    if (tree_begin < 0 || tree_count < 0) return fail(USTD_EINVAL, "negative tree range");
+    if (tree_count > c.L.K) return fail(USTD_EINVAL, "tree_count %lld exceeds trees per batch %d", (long long)tree_count, c.L.K);
+    if (!d_parents) return fail(USTD_EINVAL, "d_parents is NULL");
+    USTD_TRY(setup(c, nullptr));
+    if (tree_count == 0) return USTD_OK;
+    long long *steps = d_steps ? (long long *)d_steps : at<long long>(c.ws, c.L.off_steps);
+    WilsonArgs wa = wilson_args(c, tree_begin, d_parents, c.L.n, steps, at<long long>(c.ws, c.L.off_draws));
+    HIP_TRY(launch_wilson(wa, (int)tree_count, c.L.lds_bits, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    return USTD_OK;
+}
+
+int ustd_flow_counts(const ustd_problem *prob, int64_t tree_begin, int64_t tree_count, void *d_ws,
+                     size_t ws_bytes, int64_t *d_counts, ustd_report *rep, void *stream) {
+    g_err.clear();
+    Ctx c;
+    USTD_TRY(begin(c, prob, d_ws, ws_bytes, stream));
+    if (tree_begin < 0 || tree_count < 0) return fail(USTD_EINVAL, "negative tree range");
+    if (!d_counts) return fail(USTD_EINVAL, "d_counts is NULL");
+    if (rep) memset(rep, 0, sizeof(*rep));
+    Timer total(c.st);
+    USTD_TRY(setup(c, rep));
+    USTD_TRY(run_trees(c, tree_begin, tree_count, (long long *)d_counts, rep));
+    if (rep) {
+        rep->tau = tree_count;
+        rep->ms_total = total.stop_ms();
+    }
+    return USTD_OK;
+}
+
+int ustd_tree_counts(const ustd_problem *prob, const int32_t *d_parents, int64_t tree_count, void *d_ws,
+                     size_t ws_bytes, int64_t *d_counts, void *stream) {
+    g_err.clear();
+    Ctx c;
+    USTD_TRY(begin(c, prob, d_ws, ws_bytes, stream));
+    if (!d_parents || !d_counts) return fail(USTD_EINVAL, "NULL parents / counts");
+    if (tree_count < 0) return fail(USTD_EINVAL, "negative tree count");
+    USTD_TRY(setup(c, nullptr));
+    for (long long b0 = 0; b0 < tree_count; b0 += c.L.K) {
+        const int cnt = (int)std::min<long long>(c.L.K, tree_count - b0);
+        USTD_TRY(aggregate_trees(c, d_parents + b0 * c.L.n, c.L.n, cnt, (long long *)d_counts, nullptr, nullptr));
+    }
+    HIP_TRY(hipStreamSynchronize(c.st));
+    return USTD_OK;
+}
+
+int ustd_solve_pivot_column(const ustd_problem *prob, void *d_ws, size_t ws_bytes, double *d_x, ustd_report *rep,
+                            void *stream) {
+    g_err.clear();
+    Ctx c;
+    USTD_TRY(begin(c, prob, d_ws, ws_bytes, stream));
+    if (!d_x) return fail(USTD_EINVAL, "d_x is NULL");
+    if (rep) memset(rep, 0, sizeof(*rep));
+    USTD_TRY(setup(c, rep));
+    return solve_column(c, d_x, rep);
+}
+
+int ustd_diag_lpinv(const ustd_problem *prob, void *d_ws, size_t ws_bytes, double *d_diag, int64_t *d_counts,
+                    ustd_report *rep, void *stream) {
+    g_err.clear();
+    Ctx c;
+    USTD_TRY(begin(c, prob, d_ws, ws_bytes, stream));
+    if (!d_diag) return fail(USTD_EINVAL, "d_diag is NULL");
+    ustd_report local{};
+    ustd_report *r = rep ? rep : &local;
+    memset(r, 0, sizeof(*r));
+    Timer total(c.st);
+    USTD_TRY(setup(c, r));
+    const long long tau = sample_size(prob, c.ecc);
+    r->tau = tau;
+    long long *counts = d_counts ? (long long *)d_counts : at<long long>(c.ws, c.L.off_counts);
+    HIP_TRY(hipMemsetAsync(counts, 0, (size_t)c.L.n * 8, c.st));
+    USTD_TRY(run_trees(c, 0, tau, counts, r));
+    double *x = at<double>(c.ws, c.L.off_x64);
+    const int src = solve_column(c, x, r);
+    if (src != USTD_OK && src != USTD_ENOTCONV) return src;
+    {
+        Timer tm(c.st);
+        HIP_TRY(launch_combine(c.L.n, c.pivot, tau, counts, x, d_diag, c.st));
+        r->ms_combine += tm.stop_ms();
+    }
+    r->ms_total = total.stop_ms();
+    return src;
+}
+
+int ustd_philox_words(uint64_t seed, int64_t t, int32_t s, int64_t k0, int64_t count, uint32_t *d_out, void *stream) {
+    g_err.clear();
+    if (count < 0 || k0 < 0 || !d_out) return fail(USTD_EINVAL, "bad arguments");
+    if (count == 0) return USTD_OK;
+    HIP_TRY(launch_philox_words((uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32), t, s, k0, count, d_out,
+                                (hipStream_t)stream));
+    return USTD_OK;
+}
+
+const char *ustd_status_string(int status) {
+    switch (status) {
+        case USTD_OK: return "USTD_OK";
+        case USTD_EINVAL: return "USTD_EINVAL";
+        case USTD_EGRAPH: return "USTD_EGRAPH";
+        case USTD_ENOMEM: return "USTD_ENOMEM";
+        case USTD_EHIP: return "USTD_EHIP";
+        case USTD_ENOTCONV: return "USTD_ENOTCONV";
+        default: return "USTD_UNKNOWN";
+    }
+}
+
+const char *ustd_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

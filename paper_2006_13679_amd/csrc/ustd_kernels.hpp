@@ -1,0 +1,89 @@
+// ustd_kernels.hpp -- argument blocks and launchers of the gfx950 kernels (library-internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ustd_device.hpp"
+
+namespace ustd {
+
+struct WilsonArgs {
+    int n, u, nwords, rob;
+    const int *rp, *col;
+    uint32_t key0, key1;
+    long long tree_begin;
+    int *par;               // [ntrees][par_stride]
+    long long par_stride;
+    int *path;              // [ntrees][rob * 63]
+    uint32_t *bits;         // [ntrees][nwords] when the tree bitmap lives in global memory
+    long long *steps;       // [ntrees], nullable
+    long long *draws;       // [ntrees], nullable
+};
+
+struct IntervalArgs {
+    int n, u;
+    const int *par;         // [ntrees][par_stride]
+    long long par_stride;
+    int *scratch;           // [ntrees][scratch_stride], scratch_stride >= 10n + 3
+    long long scratch_stride;
+    int4 *pk;               // [ntrees][pk_stride] {parent, pre, size, 0}
+    long long pk_stride;
+    int *err;
+};
+
+struct AggregateArgs {
+    int n, u, ntrees, trees_per_chunk;
+    const int *parB;
+    const int4 *pk;
+    long long pk_stride;
+    long long *counts;
+};
+
+constexpr int kRrHist = 64;
+
+struct CgScalars {
+    double rz, pq, alpha, beta, rr, rr0, tol2;
+    int iter, done;  // done: converged or broken down; later iterations are no-ops
+};
+
+template <typename T>
+struct CgArgs {
+    int n;
+    const int *rp, *col;
+    T *x, *r, *z, *p, *q;
+    double *part;           // 2 * grid
+    unsigned int *counter;  // zero-initialised, self-resetting
+    CgScalars *sc;
+    double *rr_hist;        // kRrHist
+};
+
+inline long long interval_scratch_ints(long long n) { return 10 * n + 3; }
+
+hipError_t launch_rp_to_i32(int n, const long long *rp64, int *rp32, hipStream_t st);
+hipError_t launch_validate(int n, long long nnz, const long long *rp64, const int *col, int *err, hipStream_t st);
+hipError_t launch_argmax_degree(int n, const int *rp, unsigned long long *best, hipStream_t st);
+hipError_t launch_bfs_init(int n, int u, int *dist, int *parB, hipStream_t st);
+hipError_t launch_bfs_level(int n, const int *rp, const int *col, int d, int *dist, int *parB, int *found,
+                            hipStream_t st);
+hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t st);
+hipError_t launch_wilson(const WilsonArgs &a, int ntrees, bool lds_bits, hipStream_t st);
+hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st);
+hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st);
+template <typename T>
+hipError_t launch_cg_iteration(const CgArgs<T> &a, int grid, hipStream_t st);
+template <typename Tin, typename T>
+hipError_t launch_cg_start(const CgArgs<T> &a, int grid, const Tin *rhs, int rhs_is_pivot, int u,
+                           const double *shift_scale, double tol2, hipStream_t st);
+hipError_t launch_residual64(int n, const int *rp, const int *col, int u, const double *x, double *res,
+                             double *part, unsigned int *counter, double *out, int grid, hipStream_t st);
+template <typename T>
+hipError_t launch_axpy_project(int n, double *x, const T *d, const double *scale_src, int scale_idx,
+                               const double *mean_src, int grid, hipStream_t st);
+hipError_t launch_outer_scalars(int n, const double *sums, double *ss, hipStream_t st);
+hipError_t launch_combine(int n, int u, long long tau, const long long *counts, const double *x, double *diag,
+                          hipStream_t st);
+hipError_t launch_philox_words(uint32_t key0, uint32_t key1, long long t, int s, long long k0, long long count,
+                               uint32_t *out, hipStream_t st);
+
+}  // namespace ustd

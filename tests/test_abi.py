@@ -1,0 +1,60 @@
+"""Host-only checks of the C-ABI library: it loads, exports every entry point that
+include/ustd.h declares, and its argument checks and workspace planner work without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2006_13679_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "ustd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ustd_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_expected_entry_points():
+    assert declared_symbols() == sorted(api.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = api.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+        assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+
+
+def _prob(**kw):
+    base = dict(n=1024, nnz=3968, d_row_ptr=0x1000, d_col=0x2000, pivot=495, solve_mode=0, eps=0.3, delta=0.0,
+                kappa=0.0, seed=1, tau_override=0, solve_tol=0.0, solve_maxit=0, validate=0, trees_per_batch=0,
+                reserved=0)
+    base.update(kw)
+    return api.Problem(**base)
+
+
+def test_workspace_bytes_host_only():
+    b = api.workspace_bytes(_prob())
+    assert b > 1024 * 16
+    b2 = api.workspace_bytes(_prob(trees_per_batch=10))
+    b3 = api.workspace_bytes(_prob(trees_per_batch=20))
+    assert b2 < b3
+
+
+@pytest.mark.parametrize("kw", [dict(pivot=1024), dict(pivot=-2), dict(eps=0.0), dict(eps=-1.0), dict(delta=1.5),
+                                dict(kappa=1.0), dict(solve_mode=7), dict(n=1), dict(nnz=1), dict(d_col=0),
+                                dict(trees_per_batch=100000)])
+def test_invalid_arguments_rejected(kw):
+    with pytest.raises(api.UstdError) as e:
+        api.workspace_bytes(_prob(**kw))
+    assert e.value.status == api.EINVAL
+
+
+def test_status_strings():
+    L = api.lib()
+    assert L.ustd_status_string(0) == b"USTD_OK"
+    assert L.ustd_status_string(5) == b"USTD_ENOTCONV"
+    assert L.ustd_status_string(99) == b"USTD_UNKNOWN"

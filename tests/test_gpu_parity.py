@@ -1,0 +1,217 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on the same
+seeded inputs.  Integer outputs (BFS tree, sampled parent arrays, walk-step counts, flow
+counts) must match bit for bit; FP64 outputs within the tolerances stated per test."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2006_13679_amd import api
+from paper_2006_13679_amd import graphgen as gg
+from tests import brute
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev_graph(g):
+    return api.Graph.from_host(g.row_ptr, g.col)
+
+
+def cases_small():
+    return [
+        ("K4", gg.complete(4), 3),
+        ("P2", gg.path(2), 0),
+        ("C5", gg.cycle(5), 0),
+        ("star9-centre", gg.star(9), 0),
+        ("star9-leaf", gg.star(9), 5),
+        ("path40-end", gg.path(40), 0),
+        ("path40-mid", gg.path(40), 20),
+        ("grid3", gg.grid2d(3), 4),
+        ("K23", gg.complete_bipartite(2, 3), 0),
+        ("tree50", gg.random_tree(50, 3), 7),
+        ("gnp200", gg.random_connected(200, 0.03, 5), -1),
+        ("grid32", gg.grid2d(32), 495),
+        ("grid17x9", gg.grid2d(17, 9), 0),
+        ("rmat10", gg.rmat(10, 8, 3), -1),
+        ("rmat12", gg.rmat(12, 16, 1), -1),
+    ]
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    api.lib()
+    return torch.device("cuda:0")
+
+
+# ---------------------------------------------------------------------------------------
+def test_philox_words_match_oracle(gpu):
+    for seed, t, s in [(0, 0, 0), (1, 7, 123), (0xDEADBEEFCAFE, 2**33 + 5, 2**31 - 1)]:
+        say("philox", seed, t, s)
+        got = api.philox_words(seed, t, s, 0, 37).cpu().numpy().view(np.uint32)
+        want = np.array([oracle.walk_word(seed, t, s, k) for k in range(37)], dtype=np.uint32)
+        assert (got == want).all()
+    got = api.philox_words(0, 0, 0, 0, 4).cpu().numpy().view(np.uint32)
+    assert list(got) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+
+
+@pytest.mark.parametrize("idx", range(15))
+def test_bfs_matches_oracle(gpu, idx):
+    name, g, piv = cases_small()[idx]
+    say("bfs", name)
+    G = dev_graph(g)
+    p = api.problem(G, pivot=piv, validate=True)
+    dist, parB, ecc, pivot = api.bfs(G, p)
+    want_piv = piv if piv >= 0 else gg.max_degree_pivot(g)
+    assert pivot == want_piv
+    d0, pb0, e0 = oracle.bfs(g.row_ptr, g.col, want_piv)
+    assert ecc == e0
+    assert (dist.cpu().numpy() == d0).all()
+    assert (parB.cpu().numpy() == pb0).all()
+
+
+@pytest.mark.parametrize("idx", range(15))
+def test_sampled_trees_bit_exact(gpu, idx):
+    name, g, piv = cases_small()[idx]
+    u = piv if piv >= 0 else gg.max_degree_pivot(g)
+    T = 24 if g.n > 2000 else 48
+    t0 = 5
+    say("trees", name, g.n, T)
+    G = dev_graph(g)
+    p = api.problem(G, pivot=u, seed=12345)
+    parents, steps = api.sample_trees(G, p, t0, T)
+    want_par, want_steps, _ = oracle.trees(g.row_ptr, g.col, u, 12345, t0, T, want_counts=False)
+    assert (steps.cpu().numpy() == want_steps).all()
+    assert (parents.cpu().numpy() == want_par).all()
+
+
+@pytest.mark.parametrize("idx", range(15))
+def test_flow_counts_bit_exact(gpu, idx):
+    name, g, piv = cases_small()[idx]
+    u = piv if piv >= 0 else gg.max_degree_pivot(g)
+    T = 40 if g.n > 2000 else 120
+    say("counts", name, g.n, T)
+    G = dev_graph(g)
+    p = api.problem(G, pivot=u, seed=99, trees_per_batch=32)
+    counts, rep = api.flow_counts(G, p, 3, T)
+    _, steps, want = oracle.trees(g.row_ptr, g.col, u, 99, 3, T, want_parents=False)
+    assert (counts.cpu().numpy() == want).all()
+    assert rep["walk_steps"] == int(steps.sum())
+    assert rep["walk_draws"] >= rep["walk_steps"]
+
+
+def test_tree_counts_on_enumerated_trees(gpu):
+    """Algorithm 2 alone, on every spanning tree of tiny graphs: the GPU's summed counts
+    equal the oracle's, and their mean is the effective resistance (Kirchhoff)."""
+    for name, g, u in [("K4", gg.complete(4), 0), ("grid3", gg.grid2d(3), 4), ("K23", gg.complete_bipartite(2, 3), 1)]:
+        say("enumerated", name)
+        trees = np.stack(brute.spanning_trees(g, u))
+        G = dev_graph(g)
+        p = api.problem(G, pivot=u, trees_per_batch=64)
+        got = api.tree_counts(G, p, torch.from_numpy(trees)).cpu().numpy()
+        _, parB, _ = oracle.bfs(g.row_ptr, g.col, u)
+        want = sum(oracle.tree_flow(u, parB, t) for t in trees)
+        assert (got == want).all()
+        np.testing.assert_allclose(got / len(trees), brute.effective_resistance_from(g, u), atol=1e-12)
+
+
+def test_counts_additive_and_deterministic(gpu):
+    g = gg.rmat(11, 12, 4)
+    u = gg.max_degree_pivot(g)
+    G = dev_graph(g)
+    p = api.problem(G, pivot=u, seed=3, trees_per_batch=50)
+    say("additivity")
+    a, _ = api.flow_counts(G, p, 0, 130)
+    b, _ = api.flow_counts(G, p, 0, 130)
+    c, _ = api.flow_counts(G, p, 0, 77)
+    c, _ = api.flow_counts(G, p, 77, 53, counts=c)
+    assert torch.equal(a, b) and torch.equal(a, c)
+
+
+# ---------------------------------------------------------------------------------------
+def test_solve_matches_pinv(gpu):
+    for g, u in [(gg.grid2d(12), 66), (gg.rmat(9, 8, 2), -1), (gg.random_connected(300, 0.02, 8), 5)]:
+        for mode in (api.SOLVE_FP64, api.SOLVE_MIXED):
+            say("solve", g.name, mode)
+            G = dev_graph(g)
+            p = api.problem(G, pivot=u, solve_mode=mode, solve_tol=1e-12)
+            x, rep = api.solve_pivot_column(G, p)
+            uu = rep["pivot"]
+            P = brute.pinv(g)
+            ref = P[:, uu]
+            err = np.abs(x.cpu().numpy() - ref).max() / np.abs(ref).max()
+            assert err < 1e-9, (g.name, mode, err, rep)
+            assert rep["solve_relres"] < 1e-11
+
+
+def test_diag_grid32_config(gpu):
+    """2-D grid 32x32, pivot 495, tau = 1000: counts identical to the oracle's, diagonal
+    within 1e-10 relative of the oracle's FP64 result (same counts, both solves converged
+    to 1e-12), for the FP64 and the mixed-precision solve."""
+    g = gg.grid2d(32)
+    ref = oracle.diag_lpinv(g.row_ptr, g.col, 495, eps=0.3, seed=1, tau_override=1000, solve_tol=1e-12)
+    G = dev_graph(g)
+    for mode in (api.SOLVE_FP64, api.SOLVE_MIXED):
+        say("grid32 diag", mode)
+        p = api.problem(G, pivot=495, eps=0.3, seed=1, tau_override=1000, solve_mode=mode, solve_tol=1e-12)
+        diag, counts, rep = api.diag_lpinv_p(G, p)
+        assert rep["tau"] == 1000 and rep["ecc"] == 32
+        assert (counts.cpu().numpy() == ref["counts"]).all()
+        assert rep["walk_steps"] == ref["steps"]
+        d = diag.cpu().numpy()
+        rel = np.abs(d - ref["diag"]).max() / np.abs(ref["diag"]).max()
+        assert rel <= 1e-10, (mode, rel, rep)
+
+
+def test_diag_small_graphs_within_eps(gpu):
+    for g, u in [(gg.complete(6), 0), (gg.cycle(9), 0), (gg.grid2d(4), 5), (gg.complete_bipartite(3, 4), 0)]:
+        say("eps", g.name)
+        G = dev_graph(g)
+        p = api.problem(G, pivot=u, eps=0.3, seed=8)
+        diag, counts, rep = api.diag_lpinv_p(G, p)
+        exact = np.diag(brute.pinv(g))
+        assert np.abs(diag.cpu().numpy() - exact).max() <= 0.3
+        ref = oracle.diag_lpinv(g.row_ptr, g.col, u, eps=0.3, seed=8)
+        assert rep["tau"] == ref["tau"]
+        assert (counts.cpu().numpy() == ref["counts"]).all()
+
+
+# ---------------------------------------------------------------------------------------
+def test_error_paths(gpu):
+    g = gg.grid2d(5)
+    G = dev_graph(g)
+    # asymmetric graph -> EGRAPH with validation on
+    col = g.col.copy()
+    col[g.row_ptr[0] + 1] = 24
+    Gb = api.Graph.from_host(g.row_ptr, col)
+    say("error EGRAPH")
+    with pytest.raises(api.UstdError) as e:
+        api.bfs(Gb, api.problem(Gb, pivot=0, validate=True))
+    assert e.value.status == api.EGRAPH
+    # disconnected graph -> EGRAPH even without full validation
+    rp6 = np.array([0, 2, 4, 6, 8, 10, 12], dtype=np.int64)
+    col6 = np.array([1, 2, 0, 2, 0, 1, 4, 5, 3, 5, 3, 4], dtype=np.int32)
+    Gd = api.Graph.from_host(rp6, col6)
+    say("error disconnected")
+    with pytest.raises(api.UstdError) as e:
+        api.bfs(Gd, api.problem(Gd, pivot=0))
+    assert e.value.status == api.EGRAPH
+    # workspace too small -> ENOMEM
+    p = api.problem(G, pivot=0)
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    diag = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    say("error ENOMEM")
+    rc = api.lib().ustd_diag_lpinv(api.ctypes.byref(p), api._ptr(small), 1024, api._ptr(diag), None, None, None)
+    assert rc == api.ENOMEM
+    # iteration cap -> ENOTCONV, outputs still written
+    say("error ENOTCONV")
+    p = api.problem(G, pivot=0, solve_maxit=1, solve_tol=1e-14)
+    x, rep = api.solve_pivot_column(G, p, allow_notconv=True)
+    assert torch.isfinite(x).all()
+    rc = api.lib().ustd_solve_pivot_column(api.ctypes.byref(p), api._ptr(api._default_ws[G.row_ptr.device].buf),
+                                           api._default_ws[G.row_ptr.device].buf.numel(), api._ptr(x), None, None)
+    assert rc == api.ENOTCONV
