@@ -57,9 +57,9 @@ def make_workload(name: str):
 
 def algorithmic_bytes(n: int, tau: int, steps: int, farness: int) -> dict:
     """Bytes the method must move (per the design notes): 20 B per walk step plus 12 B per
-    vertex and tree for the commit (sampler); 40 B per vertex and tree (intervals);
-    18 B per (vertex, B-path edge) pair plus 12 B per vertex and tree (aggregation)."""
-    return dict(sample=20 * steps + 12 * n * tau, intervals=40 * n * tau, aggregate=(18 * farness + 12 * n) * tau)
+    vertex and tree for the commit (sampler); 18 B per (vertex, B-path edge) pair plus 12 B
+    per vertex and tree for Algorithm 2 (aggregation)."""
+    return dict(sample=20 * steps + 12 * n * tau, aggregate=(18 * farness + 12 * n) * tau)
 
 
 def load_traffic(kernel: str, workload: str):
@@ -151,9 +151,9 @@ def main():
     dist, _, _, _ = api.bfs(G, p, ws=ws)  # farness of the pivot, for the algorithmic-byte count
     farness = int(dist.sum().item())
     ab = algorithmic_bytes(g.n, tau, steps, farness)
-    phases = {"sample": ms_sample, "intervals": ms_iv, "aggregate": ms_ag}
+    phases = {"sample": ms_sample, "aggregate": ms_ag}
     dom = max(phases, key=phases.get)
-    kname = {"sample": "wilson", "intervals": "intervals", "aggregate": "aggregate"}[dom]
+    kname = {"sample": "wilson", "aggregate": "aggregate"}[dom]
     achieved = ab[dom] / (phases[dom] * 1e-3) / 1e9
     traffic = load_traffic(kname, cfg["workload"])
     roof = {"bound": "hbm", "kernel": kname + "_kernel", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
@@ -175,7 +175,7 @@ def main():
         "walk_steps_per_s": round(steps / (ms_sample * 1e-3), 1),
         "sampling_trees_per_s": round(tau / (ms_sample * 1e-3), 1),
         "e2e_ms": round(med("ms_total"), 4),
-        "phase_ms": {"bfs": med("ms_bfs"), "sample": ms_sample, "intervals": ms_iv, "aggregate": ms_ag,
+        "phase_ms": {"setup_bfs": med("ms_bfs"), "sample": ms_sample, "aggregate": ms_ag,
                      "solve": med("ms_solve"), "combine": med("ms_combine")},
         "walk_steps": steps, "walk_draws": reps[0]["walk_draws"],
         "solve_iters": reps[0]["solve_iters"], "solve_relres": reps[0]["solve_relres"],

@@ -47,8 +47,6 @@ constexpr long long kAlign = 256;
 constexpr int kLdsBitsMaxWords = 4096;      // tree bitmap in LDS up to 131072 vertices (16 KB)
 constexpr long long kDefaultBudget = 24ll << 30;
 constexpr int kMaxTreesPerBatch = 8192;
-constexpr int kSolveGrid = 1024;
-constexpr int kPathSteps = 63;
 
 inline long long align_up(long long v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -56,7 +54,7 @@ struct Misc {                      // small zero-initialised block at the front 
     int err_validate;
     int bfs_found;
     int err_interval;
-    int pad0;
+    int nheavy;
     unsigned long long best_degree;
     unsigned int counters[8];
     CgScalars sc64, sc32;
@@ -67,12 +65,12 @@ struct Misc {                      // small zero-initialised block at the front 
 };
 
 struct Plan {
-    int n, nnz, K, rob, nwords;
+    int n, nnz, K, Kiv, rob, nwords, G, heavy_thresh;
     bool lds_bits;
-    long long par_stride, scr_stride, pk_stride;
-    long long off_misc, off_rp32, off_dist, off_parB, off_counts, off_steps, off_draws, off_par, off_path,
-        off_bits, off_scr, off_pk, off_part, off_x64, off_r64, off_z64, off_p64, off_q64, off_res64, off_x32,
-        off_r32, off_z32, off_p32, off_q32;
+    long long rec_stride, scr_stride;
+    long long off_misc, off_rp32, off_dist, off_parB, off_bnode, off_bflag, off_heavy, off_bcount, off_counts, off_steps,
+        off_draws, off_rec, off_path, off_bits, off_scr, off_part, off_x64, off_r64, off_z64, off_p64, off_q64,
+        off_res64, off_x32, off_r32, off_z32, off_p32, off_q32;
     long long total;
 };
 
@@ -104,17 +102,19 @@ Plan make_plan(const ustd_problem *p) {
     L.nnz = (int)p->nnz;
     L.nwords = (L.n + 31) / 32;
     L.lds_bits = L.nwords <= kLdsBitsMaxWords;
-    L.rob = std::min(256, next_pow2(std::max(L.n, 2)));
-    L.par_stride = align_up((long long)L.n * 4) / 4;
+    L.rob = std::min(kSamplerRobMax, next_pow2(std::max(L.n, 2)));
+    const double avg = (double)L.nnz / (double)L.n;
+    L.G = avg <= 6.0 ? 4 : (avg <= 16.0 ? 8 : (avg <= 48.0 ? 16 : 32));
+    L.heavy_thresh = 32 * L.G;
+    L.rec_stride = align_up((long long)L.n * 16) / 16;
     L.scr_stride = align_up(interval_scratch_ints(L.n) * 4) / 4;
-    L.pk_stride = align_up((long long)L.n * 16) / 16;
-    const long long per_tree = L.par_stride * 4 + align_up((long long)L.rob * kPathSteps * 4) +
-                               (L.lds_bits ? 0 : align_up((long long)L.nwords * 4)) + L.scr_stride * 4 +
-                               L.pk_stride * 16 + 16;
+    const long long per_tree = L.rec_stride * 16 + align_up((long long)L.rob * kSamplerPathGlobal * 8) +
+                               (L.lds_bits ? 0 : align_up((long long)L.nwords * 4)) + 16;
     long long K = p->trees_per_batch > 0 ? p->trees_per_batch : std::max(1ll, kDefaultBudget / per_tree);
     K = std::min<long long>(K, kMaxTreesPerBatch);
     if (p->tau_override > 0) K = std::min<long long>(K, p->tau_override);
     L.K = (int)std::max(1ll, K);
+    L.Kiv = std::min(L.K, 16);
     long long o = 0;
     auto take = [&](long long bytes) {
         long long at = o;
@@ -126,15 +126,18 @@ Plan make_plan(const ustd_problem *p) {
     L.off_rp32 = take((n + 1) * 4);
     L.off_dist = take(n * 4);
     L.off_parB = take(n * 4);
+    L.off_bnode = take(n * 16);
+    L.off_bflag = take(n * 4);
+    L.off_heavy = take(n * 4);
+    L.off_bcount = take((n / 256 + 2) * 4);
     L.off_counts = take(n * 8);
     L.off_steps = take((long long)L.K * 8);
     L.off_draws = take((long long)L.K * 8);
-    L.off_par = take((long long)L.K * L.par_stride * 4);
-    L.off_path = take((long long)L.K * L.rob * kPathSteps * 4);
+    L.off_rec = take((long long)L.K * L.rec_stride * 16);
+    L.off_path = take((long long)L.K * L.rob * kSamplerPathGlobal * 8);
     L.off_bits = take(L.lds_bits ? 0 : (long long)L.K * L.nwords * 4);
-    L.off_scr = take((long long)L.K * L.scr_stride * 4);
-    L.off_pk = take((long long)L.K * L.pk_stride * 16);
-    L.off_part = take((long long)kSolveGrid * 3 * 8);
+    L.off_scr = take((long long)L.Kiv * L.scr_stride * 4);
+    L.off_part = take((long long)kMaxSolveGrid * 3 * 8);
     L.off_x64 = take(n * 8);
     L.off_r64 = take(n * 8);
     L.off_z64 = take(n * 8);
@@ -201,6 +204,7 @@ struct Ctx {
     hipStream_t st;
     Misc *misc;
     int *rp32;
+    RowMap rows;
     int pivot = -1, ecc = 0;
 };
 
@@ -218,6 +222,14 @@ int begin(Ctx &c, const ustd_problem *p, void *ws, size_t ws_bytes, void *stream
     c.rp32 = at<int>(ws, c.L.off_rp32);
     HIP_TRY(hipMemsetAsync(c.misc, 0, sizeof(Misc), c.st));
     HIP_TRY(launch_rp_to_i32(c.L.n, (const long long *)p->d_row_ptr, c.rp32, c.st));
+    c.rows.rp = c.rp32;
+    c.rows.col = p->d_col;
+    c.rows.n = c.L.n;
+    c.rows.heavy_thresh = c.L.heavy_thresh;
+    c.rows.heavy = at<int>(ws, c.L.off_heavy);
+    c.rows.nheavy = &c.misc->nheavy;
+    HIP_TRY(launch_heavy_list(c.L.n, c.rp32, c.L.heavy_thresh, at<int>(ws, c.L.off_bcount), at<int>(ws, c.L.off_heavy),
+                              &c.misc->nheavy, c.st));
     return USTD_OK;
 }
 
@@ -248,7 +260,7 @@ int setup(Ctx &c, ustd_report *rep) {
     int d = 0;
     for (;; ++d) {
         HIP_TRY(hipMemsetAsync(&c.misc->bfs_found, 0, sizeof(int), c.st));
-        HIP_TRY(launch_bfs_level(n, c.rp32, p->d_col, d, dist, parB, &c.misc->bfs_found, c.st));
+        HIP_TRY(launch_bfs_level(c.rows, c.L.G, d, dist, parB, &c.misc->bfs_found, c.st));
         int found = 0;
         HIP_TRY(hipMemcpyAsync(&found, &c.misc->bfs_found, sizeof(int), hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipStreamSynchronize(c.st));
@@ -260,6 +272,21 @@ int setup(Ctx &c, ustd_report *rep) {
     HIP_TRY(hipMemcpyAsync(&err, &c.misc->err_validate, sizeof(int), hipMemcpyDeviceToHost, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
     if (err) return fail(USTD_EGRAPH, "graph is not connected");
+    // subtree intervals of B_u (fixed for every tree): bnode[x] = {parB, pre_B, size_B, 0}
+    {
+        IntervalArgs ia{};
+        ia.n = n;
+        ia.u = c.pivot;
+        ia.par = parB;
+        ia.par_stride = n;
+        ia.scratch = at<int>(c.ws, c.L.off_scr);
+        ia.scratch_stride = c.L.scr_stride;
+        ia.pk = at<int4>(c.ws, c.L.off_bnode);
+        ia.pk_stride = n;
+        ia.err = &c.misc->err_interval;
+        HIP_TRY(launch_intervals(ia, 1, c.st));
+        HIP_TRY(launch_bflag(n, at<int4>(c.ws, c.L.off_bnode), at<int>(c.ws, c.L.off_bflag), c.st));
+    }
     if (rep) {
         rep->pivot = c.pivot;
         rep->ecc = c.ecc;
@@ -268,8 +295,7 @@ int setup(Ctx &c, ustd_report *rep) {
     return USTD_OK;
 }
 
-WilsonArgs wilson_args(const Ctx &c, long long tree_begin, int *par, long long par_stride, long long *steps,
-                       long long *draws) {
+WilsonArgs wilson_args(const Ctx &c, long long tree_begin, long long *steps, long long *draws) {
     WilsonArgs a{};
     a.n = c.L.n;
     a.u = c.pivot;
@@ -280,51 +306,30 @@ WilsonArgs wilson_args(const Ctx &c, long long tree_begin, int *par, long long p
     a.key0 = (uint32_t)(c.p->seed & 0xFFFFFFFFull);
     a.key1 = (uint32_t)(c.p->seed >> 32);
     a.tree_begin = tree_begin;
-    a.par = par;
-    a.par_stride = par_stride;
-    a.path = at<int>(c.ws, c.L.off_path);
+    a.rec = at<int4>(c.ws, c.L.off_rec);
+    a.rec_stride = c.L.rec_stride;
+    a.bflag = at<int>(c.ws, c.L.off_bflag);
+    a.path = at<int2>(c.ws, c.L.off_path);
     a.bits = at<uint32_t>(c.ws, c.L.off_bits);
     a.steps = steps;
     a.draws = draws;
     return a;
 }
 
-// intervals + aggregation of `cnt` trees whose parent arrays start at par (stride par_stride)
-int aggregate_trees(Ctx &c, const int *par, long long par_stride, int cnt, long long *counts, double *ms_iv,
-                    double *ms_ag) {
-    IntervalArgs ia{};
-    ia.n = c.L.n;
-    ia.u = c.pivot;
-    ia.par = par;
-    ia.par_stride = par_stride;
-    ia.scratch = at<int>(c.ws, c.L.off_scr);
-    ia.scratch_stride = c.L.scr_stride;
-    ia.pk = at<int4>(c.ws, c.L.off_pk);
-    ia.pk_stride = c.L.pk_stride;
-    ia.err = &c.misc->err_interval;
-    {
-        Timer tm(c.st);
-        HIP_TRY(launch_intervals(ia, cnt, c.st));
-        if (ms_iv) *ms_iv += tm.stop_ms();
-    }
+// Algorithm 2 over `cnt` resident trees (records in the workspace)
+int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag) {
     AggregateArgs aa{};
     aa.n = c.L.n;
     aa.u = c.pivot;
     aa.ntrees = cnt;
     aa.trees_per_chunk = 32;
-    aa.parB = at<int>(c.ws, c.L.off_parB);
-    aa.pk = ia.pk;
-    aa.pk_stride = c.L.pk_stride;
+    aa.bnode = at<int4>(c.ws, c.L.off_bnode);
+    aa.rec = at<int4>(c.ws, c.L.off_rec);
+    aa.rec_stride = c.L.rec_stride;
     aa.counts = counts;
-    {
-        Timer tm(c.st);
-        HIP_TRY(launch_aggregate(aa, c.st));
-        if (ms_ag) *ms_ag += tm.stop_ms();
-    }
-    int err = 0;
-    HIP_TRY(hipMemcpyAsync(&err, &c.misc->err_interval, sizeof(int), hipMemcpyDeviceToHost, c.st));
-    HIP_TRY(hipStreamSynchronize(c.st));
-    if (err) return fail(USTD_EINVAL, "a parent array is not a spanning tree rooted at the pivot");
+    Timer tm(c.st);
+    HIP_TRY(launch_aggregate(aa, c.st));
+    if (ms_ag) *ms_ag += tm.stop_ms();
     return USTD_OK;
 }
 
@@ -334,17 +339,16 @@ int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *cou
     std::vector<long long> hs(c.L.K), hd(c.L.K);
     long long *steps = at<long long>(c.ws, c.L.off_steps);
     long long *draws = at<long long>(c.ws, c.L.off_draws);
-    int *par = at<int>(c.ws, c.L.off_par);
-    double ms_s = 0, ms_i = 0, ms_a = 0;
+    double ms_s = 0, ms_a = 0;
     for (long long b0 = 0; b0 < tree_count; b0 += c.L.K) {
         const int cnt = (int)std::min<long long>(c.L.K, tree_count - b0);
-        WilsonArgs wa = wilson_args(c, tree_begin + b0, par, c.L.par_stride, steps, draws);
+        WilsonArgs wa = wilson_args(c, tree_begin + b0, steps, draws);
         {
             Timer tm(c.st);
             HIP_TRY(launch_wilson(wa, cnt, c.L.lds_bits, c.st));
             ms_s += tm.stop_ms();
         }
-        USTD_TRY(aggregate_trees(c, par, c.L.par_stride, cnt, counts, &ms_i, &ms_a));
+        USTD_TRY(aggregate_trees(c, cnt, counts, &ms_a));
         HIP_TRY(hipMemcpyAsync(hs.data(), steps, cnt * sizeof(long long), hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipMemcpyAsync(hd.data(), draws, cnt * sizeof(long long), hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipStreamSynchronize(c.st));
@@ -360,7 +364,6 @@ int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *cou
         rep->n_batches += batches;
         rep->trees_per_batch = c.L.K;
         rep->ms_sample += ms_s;
-        rep->ms_intervals += ms_i;
         rep->ms_aggregate += ms_a;
     }
     return USTD_OK;
@@ -387,13 +390,10 @@ CgArgs<T> cg_args(Ctx &c, T *x, T *r, T *z, T *pp, T *q, CgScalars *sc, double *
     return a;
 }
 
-int solve_grid(int n) { return std::max(1, std::min(kSolveGrid, (n + 255) / 256)); }
-
 // Runs CG iterations until the device flags convergence (rr <= tol2 * rr0) or breakdown,
 // or `maxit` iterations; launches in chunks and polls the device scalars between chunks.
 template <typename T>
 int cg_iterate(Ctx &c, const CgArgs<T> &a, int maxit, int *iters_out, bool *conv) {
-    const int grid = solve_grid(c.L.n);
     CgScalars sc{};
     *conv = false;
     int launched = 0;
@@ -403,7 +403,7 @@ int cg_iterate(Ctx &c, const CgArgs<T> &a, int maxit, int *iters_out, bool *conv
         HIP_TRY(hipStreamSynchronize(c.st));
         if (sc.done || launched >= maxit) break;
         const int todo = std::min(chunk, maxit - launched);
-        for (int i = 0; i < todo; ++i) HIP_TRY(launch_cg_iteration<T>(a, grid, c.st));
+        for (int i = 0; i < todo; ++i) HIP_TRY(launch_cg_iteration<T>(a, c.rows, c.L.G, c.st));
         launched += todo;
     }
     *conv = sc.done && sc.rr <= sc.tol2 * sc.rr0;
@@ -414,7 +414,7 @@ int cg_iterate(Ctx &c, const CgArgs<T> &a, int maxit, int *iters_out, bool *conv
 int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
     const ustd_problem *p = c.p;
     const int n = c.L.n;
-    const int grid = solve_grid(n);
+    const int grid = solve_grid(c.rows, c.L.G);
     const double bnorm = std::sqrt((double)(n - 1) / (double)n);
     double tol = p->solve_tol;
     if (!(tol > 0.0)) tol = std::min(solver_eta(p, c.ecc), 1e-12);
@@ -432,7 +432,7 @@ int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
         HIP_TRY(launch_cg_start<double, double>(a, grid, nullptr, 1, c.pivot, nullptr, tol * tol, c.st));
         USTD_TRY(cg_iterate<double>(c, a, maxit, &total_it, &conv));
         outer = 1;
-        HIP_TRY(launch_residual64(n, c.rp32, p->d_col, c.pivot, x64, nullptr, part, &c.misc->counters[2], sums, grid, c.st));
+        HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, &c.misc->counters[2], sums, c.st));
         HIP_TRY(launch_axpy_project<double>(n, x64, nullptr, nullptr, 0, sums + 2, grid, c.st));
     } else {
         double *res = at<double>(c.ws, c.L.off_res64);
@@ -444,7 +444,7 @@ int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
         const double inner_tol = 1e-5;
         double prev = INFINITY;
         for (outer = 0; outer < 40; ++outer) {
-            HIP_TRY(launch_residual64(n, c.rp32, p->d_col, c.pivot, x64, res, part, &c.misc->counters[2], sums, grid, c.st));
+            HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, res, part, &c.misc->counters[2], sums, c.st));
             HIP_TRY(launch_axpy_project<double>(n, x64, nullptr, nullptr, 0, sums + 2, grid, c.st));
             HIP_TRY(launch_outer_scalars(n, sums, c.misc->shift_scale, c.st));
             double hs[4];
@@ -465,7 +465,7 @@ int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
         }
     }
     // final residual of the projected solution
-    HIP_TRY(launch_residual64(n, c.rp32, p->d_col, c.pivot, x64, nullptr, part, &c.misc->counters[2], sums, grid, c.st));
+    HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, &c.misc->counters[2], sums, c.st));
     double hs[4];
     HIP_TRY(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
@@ -522,8 +522,9 @@ int ustd_sample_trees(const ustd_problem *prob, int64_t tree_begin, int64_t tree
     USTD_TRY(setup(c, nullptr));
     if (tree_count == 0) return USTD_OK;
     long long *steps = d_steps ? (long long *)d_steps : at<long long>(c.ws, c.L.off_steps);
-    WilsonArgs wa = wilson_args(c, tree_begin, d_parents, c.L.n, steps, at<long long>(c.ws, c.L.off_draws));
+    WilsonArgs wa = wilson_args(c, tree_begin, steps, at<long long>(c.ws, c.L.off_draws));
     HIP_TRY(launch_wilson(wa, (int)tree_count, c.L.lds_bits, c.st));
+    HIP_TRY(launch_extract_parents(c.L.n, (int)tree_count, at<int4>(c.ws, c.L.off_rec), c.L.rec_stride, d_parents, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
     return USTD_OK;
 }
@@ -554,9 +555,25 @@ int ustd_tree_counts(const ustd_problem *prob, const int32_t *d_parents, int64_t
     if (!d_parents || !d_counts) return fail(USTD_EINVAL, "NULL parents / counts");
     if (tree_count < 0) return fail(USTD_EINVAL, "negative tree count");
     USTD_TRY(setup(c, nullptr));
-    for (long long b0 = 0; b0 < tree_count; b0 += c.L.K) {
-        const int cnt = (int)std::min<long long>(c.L.K, tree_count - b0);
-        USTD_TRY(aggregate_trees(c, d_parents + b0 * c.L.n, c.L.n, cnt, (long long *)d_counts, nullptr, nullptr));
+    for (long long b0 = 0; b0 < tree_count; b0 += c.L.Kiv) {
+        const int cnt = (int)std::min<long long>(c.L.Kiv, tree_count - b0);
+        IntervalArgs ia{};
+        ia.n = c.L.n;
+        ia.u = c.pivot;
+        ia.par = d_parents + b0 * c.L.n;
+        ia.par_stride = c.L.n;
+        ia.scratch = at<int>(c.ws, c.L.off_scr);
+        ia.scratch_stride = c.L.scr_stride;
+        ia.rec = at<int4>(c.ws, c.L.off_rec);
+        ia.rec_stride = c.L.rec_stride;
+        ia.bflag = at<int>(c.ws, c.L.off_bflag);
+        ia.err = &c.misc->err_interval;
+        HIP_TRY(launch_intervals(ia, cnt, c.st));
+        USTD_TRY(aggregate_trees(c, cnt, (long long *)d_counts, nullptr));
+        int err = 0;
+        HIP_TRY(hipMemcpyAsync(&err, &c.misc->err_interval, sizeof(int), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        if (err) return fail(USTD_EINVAL, "a parent array is not a spanning tree rooted at the pivot");
     }
     HIP_TRY(hipStreamSynchronize(c.st));
     return USTD_OK;

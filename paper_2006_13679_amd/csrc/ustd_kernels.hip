@@ -12,6 +12,7 @@
 //   combine        : Eq. diag-comp in FP64
 #include "ustd_kernels.hpp"
 
+#include <algorithm>
 #include <climits>
 
 namespace ustd {
@@ -76,24 +77,83 @@ __global__ void bfs_init_kernel(int n, int u, int *__restrict__ dist, int *__res
     }
 }
 
+// Rows are processed in a degree-balanced way: rows of degree <= heavy_thresh by groups of
+// G lanes (one row per group), heavier rows (listed once per graph in ascending order) by a
+// whole 256-thread block each.  Grid-stride over a fixed grid, so every reduction order
+// depends only on the graph.
+
 // One BFS level: every vertex at distance d offers itself as parent to its unvisited
 // neighbours; atomicMin keeps the smallest-ID one among all of them, which is the
-// minimum-ID neighbour one level closer to u.  `found` counts vertices reached.
-__global__ void bfs_level_kernel(int n, const int *__restrict__ rp, const int *__restrict__ col, int d,
-                                 int *__restrict__ dist, int *__restrict__ parB, int *__restrict__ found) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n || dist[v] != d) return;
+// minimum-ID neighbour one level closer to u.  `found` is set if any vertex is reached.
+template <int G>
+__global__ __launch_bounds__(256) void bfs_level_kernel(RowMap m, int d, int *__restrict__ dist,
+                                                        int *__restrict__ parB, int *__restrict__ found) {
     int any = 0;
-    for (int e = rp[v]; e < rp[v + 1]; ++e) {
-        const int y = col[e];
-        const int dy = dist[y];
-        if (dy > d) {
-            atomicMin(&parB[y], v);
-            if (dy != d + 1) dist[y] = d + 1;
-            any = 1;
+    const int nh = *m.nheavy;
+    for (int h = blockIdx.x; h < nh; h += gridDim.x) {
+        const int v = m.heavy[h];
+        if (dist[v] != d) continue;  // uniform in the block
+        for (int e = m.rp[v] + threadIdx.x; e < m.rp[v + 1]; e += blockDim.x) {
+            const int y = m.col[e];
+            const int dy = dist[y];
+            if (dy > d) {
+                atomicMin(&parB[y], v);
+                if (dy != d + 1) dist[y] = d + 1;
+                any = 1;
+            }
         }
     }
-    if (any) atomicOr(found, 1);
+    const int rows_per_tile = 256 / G;
+    const int g = threadIdx.x / G, l = threadIdx.x % G;
+    for (int tile = blockIdx.x; tile * rows_per_tile < m.n; tile += gridDim.x) {
+        const int v = tile * rows_per_tile + g;
+        if (v >= m.n || dist[v] != d) continue;
+        const int lo = m.rp[v], hi = m.rp[v + 1];
+        if (hi - lo > m.heavy_thresh) continue;
+        for (int e = lo + l; e < hi; e += G) {
+            const int y = m.col[e];
+            const int dy = dist[y];
+            if (dy > d) {
+                atomicMin(&parB[y], v);
+                if (dy != d + 1) dist[y] = d + 1;
+                any = 1;
+            }
+        }
+    }
+    if (__any(any) && lane_id() == 0) atomicOr(found, 1);
+}
+
+// heavy-row list, deterministic: per-block counts, one-block scan, ordered writes
+__global__ __launch_bounds__(256) void heavy_count_kernel(int n, const int *__restrict__ rp, int thresh,
+                                                          int *__restrict__ bcount) {
+    __shared__ int sh[5];
+    const int v = blockIdx.x * 256 + threadIdx.x;
+    const int hv = (v < n && rp[v + 1] - rp[v] > thresh) ? 1 : 0;
+    int tot;
+    block_incl_scan(hv, &tot, sh);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
+}
+__global__ __launch_bounds__(256) void heavy_scan_kernel(int nb, int *__restrict__ bcount, int *__restrict__ nheavy) {
+    __shared__ int sh[5];
+    int carry = 0;
+    for (int base = 0; base < nb; base += 256) {
+        const int i = base + threadIdx.x;
+        const int c = i < nb ? bcount[i] : 0;
+        int tot;
+        const int incl = block_incl_scan(c, &tot, sh);
+        if (i < nb) bcount[i] = carry + incl - c;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *nheavy = carry;
+}
+__global__ __launch_bounds__(256) void heavy_write_kernel(int n, const int *__restrict__ rp, int thresh,
+                                                          const int *__restrict__ boff, int *__restrict__ heavy) {
+    __shared__ int sh[5];
+    const int v = blockIdx.x * 256 + threadIdx.x;
+    const int hv = (v < n && rp[v + 1] - rp[v] > thresh) ? 1 : 0;
+    int tot;
+    const int incl = block_incl_scan(hv, &tot, sh);
+    if (hv) heavy[boff[blockIdx.x] + incl - 1] = v;
 }
 
 __global__ void count_unreached_kernel(int n, const int *__restrict__ dist, int *__restrict__ err) {
@@ -119,15 +179,23 @@ __global__ void count_unreached_kernel(int n, const int *__restrict__ dist, int 
 // last visit).  A recorded walk is always long enough: it stopped at a vertex of an older
 // tree, which is still in T.  Three commit paths:
 //   - runs of one-step walks (s -> y) commit in parallel, one lane each;
-//   - recorded walks of 2..63 steps commit cooperatively with ballots (one ballot finds
-//     the truncation point, one per branch vertex finds its last visit);
+//   - recorded walks of 2..255 steps commit cooperatively with ballots (one ballot per
+//     64-step chunk finds the truncation point, one per chunk and branch vertex finds the
+//     vertex's last visit);
 //   - walks longer than the record are re-walked from s by one lane against the current
-//     tree (the sequential algorithm for that start, Next pointers in the parent array).
+//     tree (the sequential algorithm for that start, Next pointers in the record array).
+// Everything a commit needs is prefetched into LDS while walking (the B_u flag word of
+// every recorded vertex, the chain value of the vertex a walk ends on), so the in-order
+// commit path does no dependent global loads in the common cases.
+//
+// Output per vertex x: rec[x] = {parent_T(x), nba(x), cv(x), 0} (see "Marked vertices").
 // ======================================================================================
 namespace {
 
-constexpr int kRobMax = 256;   // reorder-buffer entries (LDS)
-constexpr int kPath = 63;      // recorded steps per speculative walk (x_1..x_63)
+constexpr int kRobMax = kSamplerRobMax;  // reorder-buffer entries (LDS)
+constexpr int kPathLds = 7;              // recorded steps kept in LDS per entry (x_1..x_7)
+constexpr int kPath = 255;               // recorded steps per speculative walk (x_1..x_255)
+static_assert(kPath - kPathLds == kSamplerPathGlobal, "path split");
 constexpr int kWalking = -1, kOverflow = -2;
 
 template <bool LDS>
@@ -141,13 +209,61 @@ struct TreeBits {
     __device__ __forceinline__ void set(int v) const { atomicOr(w + (v >> 5), 1u << (v & 31)); }
 };
 
+// Marked vertices.  Algorithm 2 adds, for v and each edge (a, b) of P(v), +1 when T
+// contains a -> b above v and -1 when it contains b -> a above v.  Written per T-ancestor x
+// of v (x != u), x contributes only if x lies on P(v) and its tree edge x -> parent_T(x) is
+// a B_u edge: +1 when parent_T(x) = parB(x) (that edge of P(v) is traversed forward), -1
+// when parB(parent_T(x)) = x and parent_T(x) is on P(v) too (traversed backward).  A
+// strict T-ancestor of v on P(v) has a child in B_u, so only vertices that are internal in
+// B_u and whose tree edge is a B_u edge ("marked") can contribute.  Each vertex x stores
+// nba(x) = nearest marked strict T-ancestor (u if none) and cv(x) = x if x is marked,
+// else nba(x) (the nba value of x's children).  Algorithm 2 then follows the nba chain and
+// decides "on P(v)" with the fixed subtree intervals of B_u.
+//
+// bflag[x] = (parB(x) + 1) | (1 << 31 if x is internal in B_u), so parB(u) = -1.
+__device__ __forceinline__ int bf_parent(int f) { return (int)((unsigned)f & 0x7FFFFFFFu) - 1; }
+__device__ __forceinline__ bool bf_internal(int f) { return (unsigned)f >> 31; }
+__device__ __forceinline__ bool marked_f(int x, int fx, int px, int fpx) {
+    return bf_internal(fx) && (px == bf_parent(fx) || bf_parent(fpx) == x);
+}
+
+// The sampler's block is one wavefront.  Its LDS operations execute in issue order, so
+// lanes exchange data through LDS with compiler ordering only; a workgroup barrier would
+// also wait for every outstanding global load and store.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+// Force loaded values into registers here.  A load still in flight when its register is
+// reused later makes the compiler wait for the whole in-order memory counter, i.e. for
+// every store issued since (the commit phase's record stores).
+__device__ __forceinline__ void consume(int a, int b, int c, int d) {
+    asm volatile("" ::"v"(a), "v"(b), "v"(c), "v"(d));
+}
+// wait until all of this wavefront's global loads and stores have completed
+__device__ __forceinline__ void wait_global() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt/lgkmcnt unconstrained
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+constexpr int kHashBits = 11;  // batch-commit conflict table: 2048 minimum-writer slots
+__device__ __forceinline__ int hash_slot(int v) { return (int)(((unsigned)v * 2654435761u) >> (32 - kHashBits)); }
+
+template <typename T>
+__device__ __forceinline__ T sel4(int c, T a0, T a1, T a2, T a3) {
+    return c == 0 ? a0 : (c == 1 ? a1 : (c == 2 ? a2 : a3));
+}
+
 }  // namespace
 
 template <bool LDS>
 __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     extern __shared__ uint32_t lds_bits[];
-    __shared__ int rob_s[kRobMax], rob_k[kRobMax], rob_y[kRobMax];
+    __shared__ int rob_s[kRobMax], rob_k[kRobMax], rob_fs[kRobMax], rob_cv[kRobMax];
+    __shared__ int2 rob_p[kRobMax][kPathLds];
     __shared__ int cand[kWave];
+    __shared__ int br[kPath + 1], brf[kPath + 1];
+    __shared__ int hslot[1 << kHashBits];
 
     const int lane = threadIdx.x;
     const int n = a.n;
@@ -155,8 +271,11 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     const int robm = rob - 1;
     const long long t = a.tree_begin + blockIdx.x;
     const uint32_t tlo = (uint32_t)(unsigned long long)t, thi = (uint32_t)((unsigned long long)t >> 32);
-    int *__restrict__ par = a.par + (long long)blockIdx.x * a.par_stride;
-    int *__restrict__ path = a.path + (long long)blockIdx.x * ((long long)rob * kPath);
+    int4 *rec = a.rec + (long long)blockIdx.x * a.rec_stride;
+    int *recw = reinterpret_cast<int *>(rec);  // recw[4x] = parent (Next while walking)
+    const int *__restrict__ bflag = a.bflag;
+    const int u = a.u;
+    int2 *__restrict__ gpath = a.path + (long long)blockIdx.x * ((long long)rob * (kPath - kPathLds));
     TreeBits<LDS> bits{LDS ? lds_bits : a.bits + (long long)blockIdx.x * a.nwords};
     const int *__restrict__ rp = a.rp;
     const int *__restrict__ col = a.col;
@@ -165,17 +284,18 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
         if (LDS) bits.w[i] = 0u;
         else __hip_atomic_store(bits.w + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
+    for (int i = lane; i < (1 << kHashBits); i += kWave) hslot[i] = kWave;
+    wave_sync();
     if (lane == 0) {
-        bits.set(a.u);
-        par[a.u] = -1;
+        bits.set(u);
+        rec[u] = make_int4(-1, u, u, 0);
     }
-    __syncthreads();
+    wave_sync();
 
     int head = 0, tail = 0, cursor = 0;  // wave-uniform
     int seq_lane = -1;                   // wave-uniform: lane re-walking the head entry
     int mode = 0;                        // 0 idle, 1 speculative walk, 2 re-walk, 3 re-walk done
-    int my_e = 0, x = 0, s = 0, k = 0;
+    int my_e = 0, x = 0, s = 0, k = 0, r0 = 0, r1 = 0, fs = 0;
     uint4 ph = make_uint4(0, 0, 0, 0);
     long long steps = 0, draws = 0;
 
@@ -203,7 +323,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 ++r;
                 fb &= fb - 1u;
             }
-            __syncthreads();
+            wave_sync();
             if (total >= need) {
                 got = want;
                 cursor = cand[want - 1] + 1;
@@ -220,48 +340,77 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 x = s;
                 k = 0;
                 mode = 1;
-                rob_s[my_e & robm] = s;
-                rob_k[my_e & robm] = kWalking;
+                r0 = rp[s];
+                r1 = rp[s + 1];
+                fs = bflag[s];  // stored to the entry with the first step, once loaded
+                const int sl = my_e & robm;
+                rob_s[sl] = s;
+                rob_k[sl] = kWalking;
             }
             tail += got;
         }
         if (head == tail && cursor >= n) break;
-        __syncthreads();
+        wave_sync();
 
         // ---------------------------------------------------------------- one walk step
         if (mode == 1 || mode == 2) {
             if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s, tlo, thi), a.key0, a.key1);
             const int q = k & 3;
             const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-            const int rs = rp[x];
-            const int deg = rp[x + 1] - rs;
-            const int y = col[rs + (int)__umulhi(w, (uint32_t)deg)];
+            const int y = col[r0 + (int)__umulhi(w, (uint32_t)(r1 - r0))];
+            // independent loads for y: tree bit, B_u flag, chain value, next row bounds
+            const bool in = bits.test(y);
+            const int fy = bflag[y];
+            const int cvy = recw[4 * y + 2];
+            const int ny0 = rp[y], ny1 = rp[y + 1];
+            consume(fy, cvy, ny0, ny1);  // no load may stay in flight into the commit phase
             ++k;
             ++draws;
-            const bool in = bits.test(y);
             if (mode == 1) {
                 const int sl = my_e & robm;
-                if (k == 1) rob_y[sl] = y;
-                path[sl * kPath + k - 1] = y;
-                if (in) { rob_k[sl] = k; mode = 0; }
+                if (k == 1) rob_fs[sl] = fs;
+                if (k <= kPathLds) rob_p[sl][k - 1] = make_int2(y, fy);
+                else gpath[sl * (kPath - kPathLds) + (k - 1 - kPathLds)] = make_int2(y, fy);
+                if (in) { rob_k[sl] = k; rob_cv[sl] = cvy; mode = 0; }
                 else if (k == kPath) { rob_k[sl] = kOverflow; mode = 0; }
                 else if (bits.test(s)) { rob_k[sl] = 0; mode = 0; }  // s absorbed: never walks
-                else x = y;
+                else { x = y; r0 = ny0; r1 = ny1; }
             } else {
-                par[x] = y;  // Next pointer; becomes the parent when x joins T
+                recw[4 * x] = y;  // Next pointer; becomes the parent when x joins T
                 if (in) {
+                    // retrace the loop erasure from s to the tree vertex ya it reaches
                     int z = s;
                     while (!bits.test(z)) {
                         bits.set(z);
-                        z = par[z];
+                        z = recw[4 * z];
+                    }
+                    const int ya = z;
+                    const int cva = recw[4 * ya + 2];
+                    // nba: nearest marked vertex strictly closer to ya; cv: z itself if marked
+                    int run = s;
+                    z = s;
+                    while (z != ya) {
+                        const int nz = recw[4 * z];
+                        if (marked_f(z, bflag[z], nz, bflag[nz])) {
+                            for (int w2 = run; w2 != z; w2 = recw[4 * w2]) recw[4 * w2 + 1] = z;
+                            run = z;
+                        }
+                        z = nz;
+                    }
+                    for (int w2 = run; w2 != ya; w2 = recw[4 * w2]) recw[4 * w2 + 1] = cva;
+                    for (z = s; z != ya; z = recw[4 * z]) {
+                        const int nz = recw[4 * z];
+                        recw[4 * z + 2] = marked_f(z, bflag[z], nz, bflag[nz]) ? z : recw[4 * z + 1];
                     }
                     mode = 3;
                 } else {
                     x = y;
+                    r0 = ny0;
+                    r1 = ny1;
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
         if (seq_lane >= 0) {
             if (__shfl(mode, seq_lane, kWave) == 3) {
                 if (lane == seq_lane) {
@@ -282,61 +431,223 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 if (bits.test(s0)) { ++head; continue; }
                 const uint64_t idl = __ballot(mode == 0);
                 if (idl == 0) break;
-                const int L = __ffsll((unsigned long long)idl) - 1;
-                if (lane == L) { mode = 2; s = s0; x = s0; k = 0; }
+                const int L = __builtin_ctzll(idl);
+                if (lane == L) { mode = 2; s = s0; x = s0; k = 0; r0 = rp[s0]; r1 = rp[s0 + 1]; }
                 seq_lane = L;
                 break;
             }
             const int idx = head + lane;
             const int sk = idx < tail ? rob_k[idx & robm] : kWalking;
-            const uint64_t fm = __ballot(sk == 0 || sk == 1);
-            const int r = (~fm == 0ull) ? kWave : __builtin_ctzll(~fm);
+            const uint64_t okm = __ballot(sk >= 0 && sk <= kPathLds);
+            const int r = (~okm == 0ull) ? kWave : __builtin_ctzll(~okm);
             if (r > 0) {
-                if (lane < r && sk == 1) {
-                    const int sl = idx & robm;
-                    const int ss = rob_s[sl];
-                    if (!bits.test(ss)) {
-                        bits.set(ss);
-                        par[ss] = rob_y[sl];
-                        steps += 1;
+                // Batch commit of the done entries head .. head+r-1 (walks of <= 7 steps), one
+                // lane each, all planned against the current tree T0.  Entry j's plan is what
+                // the sequential algorithm does unless an earlier entry of the batch adds a
+                // vertex j has read (its start or a vertex before its truncation point); the
+                // plan's written vertices go into a small hash of minimum writer lanes, and the
+                // batch commits up to the first lane that reads a slot written by a smaller
+                // lane (hash collisions only shorten the batch).  The head never conflicts.
+                const bool act = lane < r;
+                const int sl = idx & robm;
+                const int K = act ? sk : 0;
+                int xv[kPathLds + 1], xf[kPathLds + 1];
+                xv[0] = act ? rob_s[sl] : -1;
+                xf[0] = act ? rob_fs[sl] : 0;
+#pragma unroll
+                for (int j = 1; j <= kPathLds; ++j) {
+                    const int2 e = (j <= K) ? rob_p[sl][j - 1] : make_int2(-1, 0);
+                    xv[j] = e.x;
+                    xf[j] = e.y;
+                }
+                const bool live = K > 0 && !bits.test(act ? xv[0] : 0);
+                int istar = kPathLds + 1;
+#pragma unroll
+                for (int j = kPathLds; j >= 1; --j)
+                    if (live && j <= K && bits.test(xv[j])) istar = j;
+                const bool bad = live && istar > K;  // cannot happen for a recorded walk
+                // loop erasure in registers: keep = positions on the erased branch
+                unsigned keep = 0u;
+                if (live && !bad) {
+                    int b = xv[0];
+#pragma unroll
+                    for (int step = 0; step <= kPathLds; ++step) {
+                        int q = -1;
+#pragma unroll
+                        for (int j = 0; j <= kPathLds; ++j)
+                            if (j < istar && xv[j] == b) q = j;
+                        if (q < 0) break;
+                        keep |= 1u << q;
+                        if (q + 1 >= istar) break;
+                        int nb = -1;
+#pragma unroll
+                        for (int j = 1; j <= kPathLds; ++j)
+                            if (j == q + 1) nb = xv[j];
+                        b = nb;
                     }
                 }
-                head += r;
-                __syncthreads();
+                const uint64_t badm = __ballot(bad);
+                if (badm & 1ull) {  // never expected: fall back to the exact re-walk
+                    rob_k[head & robm] = kOverflow;
+                    wave_sync();
+                    continue;
+                }
+                if (live && !bad) {
+#pragma unroll
+                    for (int j = 0; j <= kPathLds; ++j)
+                        if ((keep >> j) & 1u) atomicMin(&hslot[hash_slot(xv[j])], lane);
+                }
+                wave_sync();
+                bool conflict = bad;
+                if (live && !bad) {
+#pragma unroll
+                    for (int j = 0; j <= kPathLds; ++j)
+                        if (j < istar && hslot[hash_slot(xv[j])] < lane) conflict = true;
+                }
+                wave_sync();
+                if (live && !bad) {
+#pragma unroll
+                    for (int j = 0; j <= kPathLds; ++j)
+                        if ((keep >> j) & 1u) hslot[hash_slot(xv[j])] = kWave;
+                }
+                const uint64_t cm = __ballot(conflict);
+                const int jstar = cm ? __builtin_ctzll(cm) : r;
+                const bool commit = live && !bad && lane < jstar;
+                int ya = -1, yaf = 0;
+#pragma unroll
+                for (int j = 1; j <= kPathLds; ++j)
+                    if (j == istar) {
+                        ya = xv[j];
+                        yaf = xf[j];
+                    }
+                int carry = commit ? rob_cv[sl] : 0;
+                const bool need = commit && istar < K;  // ya joined T after the walk passed it
+                if (__ballot(need)) {
+                    wait_global();
+                    if (need) carry = recw[4 * ya + 2];
+                }
+                if (commit) {
+                    int pv = ya, pf = yaf;
+#pragma unroll
+                    for (int j = kPathLds; j >= 0; --j) {
+                        if ((keep >> j) & 1u) {
+                            const int v = xv[j], fv = xf[j];
+                            const bool mk = marked_f(v, fv, pv, pf);
+                            const int cv = mk ? v : carry;
+                            rec[v] = make_int4(pv, carry, cv, 0);
+                            bits.set(v);
+                            carry = cv;
+                            pv = v;
+                            pf = fv;
+                        }
+                    }
+                    steps += istar;
+                }
+                head += jstar;
+                wave_sync();
                 continue;
             }
-            // recorded walk x_0..x_K, 2 <= K <= 63: truncate at the first vertex in T, then
-            // follow successors after last visits
+            // head: recorded walk x_0..x_K, 7 < K <= 255, committed cooperatively; lane j holds
+            // x_{j+64c}, c = 0..3
             const int sl = head & robm;
             const int s0 = rob_s[sl];
             if (!bits.test(s0)) {
-                const bool valid = lane >= 1 && lane <= hs;
-                const int xj = lane == 0 ? s0 : (valid ? path[sl * kPath + lane - 1] : -1);
-                const uint64_t im = __ballot(valid && bits.test(valid ? xj : 0));
-                if (im == 0ull) {
+                const int K = hs;
+                int xv[4] = {-1, -1, -1, -1}, xf[4] = {0, 0, 0, 0};
+                {
+                    int2 e = make_int2(-1, 0);
+                    if (lane == 0) e = make_int2(s0, rob_fs[sl]);
+                    else if (lane <= min(K, kPathLds)) e = rob_p[sl][lane - 1];
+                    xv[0] = e.x;
+                    xf[0] = e.y;
+                }
+                if (K > kPathLds) {
+                    wait_global();  // steps beyond the LDS part were stored by other lanes
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int j = c * kWave + lane;
+                        if (j > kPathLds && j <= K) {
+                            const int2 e = gpath[sl * (kPath - kPathLds) + (j - 1 - kPathLds)];
+                            xv[c] = e.x;
+                            xf[c] = e.y;
+                        }
+                    }
+                    consume(xv[0], xv[1], xv[2], xv[3]);
+                    consume(xf[0], xf[1], xf[2], xf[3]);
+                }
+                int istar = -1;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (istar < 0 && c * kWave <= K) {
+                        const int j = c * kWave + lane;
+                        const bool valid = j >= 1 && j <= K;
+                        const uint64_t im = __ballot(valid && bits.test(valid ? xv[c] : 0));
+                        if (im) istar = c * kWave + __builtin_ctzll(im);
+                    }
+                }
+                if (istar < 0) {
                     // cannot happen for a correctly recorded walk; re-walk to stay exact
                     rob_k[sl] = kOverflow;
-                    __syncthreads();
+                    wave_sync();
                     continue;
                 }
-                const int istar = __builtin_ctzll(im);
-                int b = s0;
+                // loop erasure: from b, jump past b's last visit before istar
+                int b = s0, bfl = rob_fs[sl], blen = 0, ya = -1, yaf = 0;
                 for (;;) {
-                    const uint64_t mm = __ballot(lane < istar && xj == b);
-                    if (mm == 0ull) break;  // unreachable for a recorded walk; never spin
-                    const int qlast = 63 - __builtin_clzll(mm);
-                    const int nx = __shfl(xj, qlast + 1, kWave);
+                    int qlast = -1;
+#pragma unroll
+                    for (int c = 3; c >= 0; --c) {
+                        if (qlast < 0 && c * kWave < istar) {
+                            const uint64_t mm = __ballot(c * kWave + lane < istar && xv[c] == b);
+                            if (mm) qlast = c * kWave + 63 - __builtin_clzll(mm);
+                        }
+                    }
+                    if (qlast < 0) break;  // unreachable for a recorded walk; never spin
+                    const int nq = qlast + 1, cq = nq >> 6, lq = nq & 63;
+                    const int nx = __shfl(sel4(cq, xv[0], xv[1], xv[2], xv[3]), lq, kWave);
+                    const int nf = __shfl(sel4(cq, xf[0], xf[1], xf[2], xf[3]), lq, kWave);
                     if (lane == 0) {
-                        par[b] = nx;
+                        br[blen] = b;
+                        brf[blen] = bfl;
                         bits.set(b);
                     }
-                    if (qlast + 1 == istar) break;
+                    ++blen;
+                    if (nq == istar) {
+                        ya = nx;
+                        yaf = nf;
+                        break;
+                    }
                     b = nx;
+                    bfl = nf;
                 }
-                if (lane == 0) steps += istar;
+                wave_sync();
+                if (ya >= 0) {
+                    // records of the branch b_0 = s .. b_{blen-1}, attached to ya
+                    int carry;
+                    if (istar == K) {
+                        carry = rob_cv[sl];
+                    } else {  // ya joined T after the walk passed it: its record was written since
+                        wait_global();
+                        carry = recw[4 * ya + 2];
+                    }
+                    for (int c = (blen - 1) >> 6; c >= 0; --c) {
+                        const int i = c * kWave + lane;
+                        const bool mine = i < blen;
+                        const int bi = mine ? br[i] : 0, bfi = mine ? brf[i] : 0;
+                        const int nexti = mine ? (i + 1 < blen ? br[i + 1] : ya) : 0;
+                        const int nextf = mine ? (i + 1 < blen ? brf[i + 1] : yaf) : 0;
+                        const bool mk = mine && marked_f(bi, bfi, nexti, nextf);
+                        const uint64_t m = __ballot(mk);
+                        const uint64_t above = lane < kWave - 1 ? (m & (~0ull << (lane + 1))) : 0ull;
+                        const int nba = above ? br[c * kWave + __builtin_ctzll(above)] : carry;
+                        if (mine) rec[bi] = make_int4(nexti, nba, mk ? bi : nba, 0);
+                        carry = m ? br[c * kWave + __builtin_ctzll(m)] : carry;
+                    }
+                    if (lane == 0) steps += istar;
+                }
             }
             ++head;
-            __syncthreads();
+            wave_sync();
         }
     }
 
@@ -470,6 +781,24 @@ __global__ __launch_bounds__(kIvThreads) void intervals_kernel(IntervalArgs a) {
     if (tid == 0 && ls != n) atomicOr(a.err, 64);  // not a spanning tree rooted at u
     if (ls != n) return;
 
+    if (a.rec) {
+        // {parent, nba, cv, 0} top-down along the BFS order of T
+        int4 *rec = a.rec + (long long)blockIdx.x * a.rec_stride;
+        if (tid == 0) rec[u] = make_int4(-1, u, u, 0);
+        __syncthreads();
+        for (int L = 1; L < nlev; ++L) {
+            for (int j = lv[L] + tid; j < lv[L + 1]; j += kIvThreads) {
+                const int xv = ord[j];
+                const int pv = par[xv];
+                const int nba = rec[pv].z;
+                const bool mk = marked_f(xv, a.bflag[xv], pv, a.bflag[pv]);
+                rec[xv] = make_int4(pv, nba, mk ? xv : nba, 0);
+            }
+            __syncthreads();
+        }
+        return;
+    }
+
     // subtree sizes, deepest level first; ps holds the inclusive prefix of the level below
     for (int L = nlev - 1; L >= 0; --L) {
         const int lb = lv[L], le2 = lv[L + 1];
@@ -515,11 +844,13 @@ __global__ __launch_bounds__(kIvThreads) void intervals_kernel(IntervalArgs a) {
 }
 
 // ======================================================================================
-// Aggregation (Algorithm 2).  For v != u and each edge (a, b) of P(v), a = parB(b):
-//   +1 if parent_T(b) = a and v lies in the subtree of b (b = v included),
-//   -1 if parent_T(a) = b and v lies in the subtree of a.
-// Thread per vertex, looping over a chunk of resident trees; one int64 atomic per vertex
-// and chunk, skipped when the chunk's sum is zero.
+// Aggregation (Algorithm 2), on the {parent, chain} records: for v != u,
+//   c_T(v) = [parent_T(v) = parB(v)]
+//          + sum over marked strict T-ancestors x of v lying on P(v) of
+//              +1 if parent_T(x) = parB(x),  -1 if parB(parent_T(x)) = x and parent_T(x) on P(v),
+// which equals Algorithm 2's signed count term by term.  "On P(v)" is the B_u subtree test
+// pre_B(x) <= pre_B(v) < pre_B(x) + size_B(x).  Thread per vertex, looping over a chunk of
+// resident trees; one int64 atomic per vertex and chunk, skipped when the sum is zero.
 // ======================================================================================
 __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -527,23 +858,47 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
     const int t0 = blockIdx.y * a.trees_per_chunk;
     const int t1 = min(a.ntrees, t0 + a.trees_per_chunk);
     const int u = a.u;
-    const int *__restrict__ parB = a.parB;
+    const int4 *__restrict__ bnode = a.bnode;
+    const int4 bv = bnode[v];
+    const int pv = bv.y;
     int sum = 0;
     for (int t = t0; t < t1; ++t) {
-        const int4 *__restrict__ pk = a.pk + (long long)t * a.pk_stride;
-        int4 pb = pk[v];
-        const int pv = pb.y;
-        int b = v;
-        while (b != u) {
-            const int av = parB[b];
-            const int4 pa = pk[av];
-            if (pb.x == av) sum += (pb.y <= pv && pv < pb.y + pb.z) ? 1 : 0;
-            else if (pa.x == b) sum -= (pa.y <= pv && pv < pa.y + pa.z) ? 1 : 0;
-            b = av;
-            pb = pa;
+        const int4 *__restrict__ rec = a.rec + (long long)t * a.rec_stride;
+        const int4 rv = rec[v];
+        sum += (rv.x == bv.x) ? 1 : 0;
+        int x = rv.y;
+        while (x != u) {
+            const int4 rx = rec[x];
+            const int4 bx = bnode[x];
+            if (bx.y <= pv && pv < bx.y + bx.z) {
+                if (rx.x == bx.x) {
+                    ++sum;
+                } else {
+                    const int4 bp = bnode[rx.x];
+                    if (bp.x == x && bp.y <= pv && pv < bp.y + bp.z) --sum;
+                }
+            }
+            x = rx.y;
         }
     }
     if (sum != 0) atomicAdd((unsigned long long *)&a.counts[v], (unsigned long long)(long long)sum);
+}
+
+// bflag[x] = (parB(x) + 1) | (1 << 31 if x has a child in B_u)
+__global__ void bflag_kernel(int n, const int4 *__restrict__ bnode, int *__restrict__ bflag) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int4 b = bnode[v];
+    bflag[v] = (int)((unsigned)(b.x + 1) | (b.z > 1 ? 0x80000000u : 0u));
+}
+
+// parents[i][v] = rec_i[v].parent
+__global__ void extract_parents_kernel(int n, int ntrees, const int4 *__restrict__ rec, long long rec_stride,
+                                       int *__restrict__ out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * ntrees) return;
+    const long long t = i / n, v = i - t * n;
+    out[i] = rec[t * rec_stride + v].x;
 }
 
 // ======================================================================================
@@ -553,12 +908,45 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
 // finish sums the partials in index order.
 // ======================================================================================
 template <typename T>
-__device__ __forceinline__ T lap_row(int v, const int *__restrict__ rp, const int *__restrict__ col,
-                                     const T *__restrict__ p) {
-    const int lo = rp[v], hi = rp[v + 1];
-    T s = (T)(hi - lo) * p[v];
-    for (int e = lo; e < hi; ++e) s -= p[col[e]];
+__device__ __forceinline__ T block_sum_t(T v, T *sh) {
+    const int l = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    v = wave_sum(v);
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    T s = (T)0;
+    for (int i = 0; i < nw; ++i) s += sh[i];
+    __syncthreads();
     return s;
+}
+
+// y = L p over all rows, degree-balanced; calls emit(v, (L p)_v) once per row from one
+// thread.  Fixed grid and fixed per-row reduction trees: deterministic.
+template <typename T, int G, typename Emit>
+__device__ __forceinline__ void lap_apply_rows(const RowMap &m, const T *__restrict__ p, Emit emit) {
+    __shared__ T shr[4];
+    const int nh = *m.nheavy;
+    for (int h = blockIdx.x; h < nh; h += gridDim.x) {
+        const int v = m.heavy[h];
+        const int lo = m.rp[v], hi = m.rp[v + 1];
+        T acc = (T)0;
+        for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) acc += p[m.col[e]];
+        acc = block_sum_t<T>(acc, shr);
+        if (threadIdx.x == 0) emit(v, (T)(hi - lo) * p[v] - acc);
+    }
+    const int rows_per_tile = 256 / G;
+    const int g = threadIdx.x / G, l = threadIdx.x % G;
+    for (int tile = blockIdx.x; tile * rows_per_tile < m.n; tile += gridDim.x) {
+        const int v = tile * rows_per_tile + g;
+        const bool ok = v < m.n;
+        const int lo = ok ? m.rp[v] : 0, hi = ok ? m.rp[v + 1] : 0;
+        const bool light = ok && (hi - lo <= m.heavy_thresh);
+        T acc = (T)0;
+        if (light)
+            for (int e = lo + l; e < hi; e += G) acc += p[m.col[e]];
+#pragma unroll
+        for (int dd = G / 2; dd > 0; dd >>= 1) acc += __shfl_xor(acc, dd, G);
+        if (light && l == 0) emit(v, (T)(hi - lo) * p[v] - acc);
+    }
 }
 
 // last block of the grid sums `nparts` partials of width `w` into out[0..w)
@@ -586,16 +974,17 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
 }
 
 // q = L p and alpha = rz / (p . q)
-template <typename T>
-__global__ __launch_bounds__(256) void cg_spmv_kernel(CgArgs<T> a) {
+template <typename T, int G>
+__global__ __launch_bounds__(256) void cg_spmv_kernel(CgArgs<T> a, RowMap m) {
     __shared__ double sh[4];
     if (a.sc->done) return;  // uniform: written by an earlier kernel
     double acc = 0.0;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
-        const T qv = lap_row<T>(v, a.rp, a.col, a.p);
-        a.q[v] = qv;
-        acc += (double)a.p[v] * (double)qv;
-    }
+    T *__restrict__ q = a.q;
+    const T *__restrict__ p = a.p;
+    lap_apply_rows<T, G>(m, p, [&](int v, T qv) {
+        q[v] = qv;
+        acc += (double)p[v] * (double)qv;
+    });
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) __hip_atomic_store(a.part + blockIdx.x * 2, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (last_block(a.counter)) {
@@ -707,23 +1096,22 @@ __global__ __launch_bounds__(256) void cg_start_kernel(CgArgs<T> a, const Tin *_
     }
 }
 
-// FP64 residual of the current x64: res = b - L x, sums (res, res.res, x) for the outer
-// loop of the mixed solve and for the final relative residual.  out: [sum res, |res|^2, sum x]
-__global__ __launch_bounds__(256) void residual64_kernel(int n, const int *__restrict__ rp, const int *__restrict__ col,
-                                                         int u, const double *__restrict__ x, double *__restrict__ res,
-                                                         double *__restrict__ part, unsigned int *counter,
-                                                         double *__restrict__ out) {
+// FP64 residual of the current x64: res = b - L x with b = e_u - 1/n; sums
+// [sum res, |res|^2, sum x] for the outer loop of the mixed solve and the final residual
+template <int G>
+__global__ __launch_bounds__(256) void residual64_kernel(RowMap m, int u, const double *__restrict__ x,
+                                                         double *__restrict__ res, double *__restrict__ part,
+                                                         unsigned int *counter, double *__restrict__ out) {
     __shared__ double sh[4];
-    const double inv_n = 1.0 / (double)n;
+    const double inv_n = 1.0 / (double)m.n;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        const double b = (v == u ? 1.0 : 0.0) - inv_n;
-        const double rv = b - lap_row<double>(v, rp, col, x);
+    lap_apply_rows<double, G>(m, x, [&](int v, double lx) {
+        const double rv = ((v == u ? 1.0 : 0.0) - inv_n) - lx;
         if (res) res[v] = rv;
         s0 += rv;
         s1 += rv * rv;
         s2 += x[v];
-    }
+    });
     s0 = block_sum(s0, sh);
     s1 = block_sum(s1, sh);
     s2 = block_sum(s2, sh);
@@ -809,9 +1197,29 @@ hipError_t launch_bfs_init(int n, int u, int *dist, int *parB, hipStream_t st) {
     bfs_init_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, u, dist, parB);
     return hipGetLastError();
 }
-hipError_t launch_bfs_level(int n, const int *rp, const int *col, int d, int *dist, int *parB, int *found,
-                            hipStream_t st) {
-    bfs_level_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, rp, col, d, dist, parB, found);
+#define USTD_DISPATCH_G(G, ...)                            \
+    switch (G) {                                           \
+        case 4: { constexpr int GG = 4; __VA_ARGS__; break; }   \
+        case 8: { constexpr int GG = 8; __VA_ARGS__; break; }   \
+        case 16: { constexpr int GG = 16; __VA_ARGS__; break; } \
+        default: { constexpr int GG = 32; __VA_ARGS__; break; } \
+    }
+
+static inline int row_grid(const RowMap &m, int G) {
+    const long long tiles = ((long long)m.n + (256 / G) - 1) / (256 / G);
+    return (int)std::min<long long>(std::max<long long>(tiles, 1), 4096);
+}
+
+hipError_t launch_bfs_level(const RowMap &m, int G, int d, int *dist, int *parB, int *found, hipStream_t st) {
+    const int grid = row_grid(m, G);
+    USTD_DISPATCH_G(G, bfs_level_kernel<GG><<<grid, 256, 0, st>>>(m, d, dist, parB, found));
+    return hipGetLastError();
+}
+hipError_t launch_heavy_list(int n, const int *rp, int thresh, int *bcount, int *heavy, int *nheavy, hipStream_t st) {
+    const int nb = blocks_for(n, 256);
+    heavy_count_kernel<<<nb, 256, 0, st>>>(n, rp, thresh, bcount);
+    heavy_scan_kernel<<<1, 256, 0, st>>>(nb, bcount, nheavy);
+    heavy_write_kernel<<<nb, 256, 0, st>>>(n, rp, thresh, bcount, heavy);
     return hipGetLastError();
 }
 hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t st) {
@@ -830,20 +1238,31 @@ hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st) {
     intervals_kernel<<<ntrees, kIvThreads, 0, st>>>(a);
     return hipGetLastError();
 }
+hipError_t launch_extract_parents(int n, int ntrees, const int4 *rec, long long rec_stride, int *out, hipStream_t st) {
+    extract_parents_kernel<<<blocks_for((long long)n * ntrees, 256), 256, 0, st>>>(n, ntrees, rec, rec_stride, out);
+    return hipGetLastError();
+}
+hipError_t launch_bflag(int n, const int4 *bnode, int *bflag, hipStream_t st) {
+    bflag_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, bnode, bflag);
+    return hipGetLastError();
+}
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st) {
     dim3 grid(blocks_for(a.n, 256), (a.ntrees + a.trees_per_chunk - 1) / a.trees_per_chunk);
     aggregate_kernel<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
+int solve_grid(const RowMap &m, int G) { return std::min(row_grid(m, G), kMaxSolveGrid); }
+
 template <typename T>
-hipError_t launch_cg_iteration(const CgArgs<T> &a, int grid, hipStream_t st) {
-    cg_spmv_kernel<T><<<grid, 256, 0, st>>>(a);
+hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, hipStream_t st) {
+    const int grid = solve_grid(m, G);
+    USTD_DISPATCH_G(G, cg_spmv_kernel<T, GG><<<grid, 256, 0, st>>>(a, m));
     cg_update_kernel<T><<<grid, 256, 0, st>>>(a);
     cg_pdir_kernel<T><<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
-template hipError_t launch_cg_iteration<double>(const CgArgs<double> &, int, hipStream_t);
-template hipError_t launch_cg_iteration<float>(const CgArgs<float> &, int, hipStream_t);
+template hipError_t launch_cg_iteration<double>(const CgArgs<double> &, const RowMap &, int, hipStream_t);
+template hipError_t launch_cg_iteration<float>(const CgArgs<float> &, const RowMap &, int, hipStream_t);
 
 template <typename Tin, typename T>
 hipError_t launch_cg_start(const CgArgs<T> &a, int grid, const Tin *rhs, int rhs_is_pivot, int u,
@@ -856,9 +1275,10 @@ template hipError_t launch_cg_start<double, double>(const CgArgs<double> &, int,
 template hipError_t launch_cg_start<double, float>(const CgArgs<float> &, int, const double *, int, int,
                                                    const double *, double, hipStream_t);
 
-hipError_t launch_residual64(int n, const int *rp, const int *col, int u, const double *x, double *res,
-                             double *part, unsigned int *counter, double *out, int grid, hipStream_t st) {
-    residual64_kernel<<<grid, 256, 0, st>>>(n, rp, col, u, x, res, part, counter, out);
+hipError_t launch_residual64(const RowMap &m, int G, int u, const double *x, double *res, double *part,
+                             unsigned int *counter, double *out, hipStream_t st) {
+    const int grid = solve_grid(m, G);
+    USTD_DISPATCH_G(G, residual64_kernel<GG><<<grid, 256, 0, st>>>(m, u, x, res, part, counter, out));
     return hipGetLastError();
 }
 template <typename T>

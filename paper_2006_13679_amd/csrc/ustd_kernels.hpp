@@ -13,9 +13,10 @@ struct WilsonArgs {
     const int *rp, *col;
     uint32_t key0, key1;
     long long tree_begin;
-    int *par;               // [ntrees][par_stride]
-    long long par_stride;
-    int *path;              // [ntrees][rob * 63]
+    int4 *rec;              // [ntrees][rec_stride] {parent, nba, cv, 0}
+    long long rec_stride;
+    const int *bflag;       // [n] (parB + 1) | (internal in B_u) << 31
+    int2 *path;             // [ntrees][rob * kSamplerPathGlobal] recorded steps beyond the LDS part
     uint32_t *bits;         // [ntrees][nwords] when the tree bitmap lives in global memory
     long long *steps;       // [ntrees], nullable
     long long *draws;       // [ntrees], nullable
@@ -27,20 +28,35 @@ struct IntervalArgs {
     long long par_stride;
     int *scratch;           // [ntrees][scratch_stride], scratch_stride >= 10n + 3
     long long scratch_stride;
-    int4 *pk;               // [ntrees][pk_stride] {parent, pre, size, 0}
+    int4 *pk;               // [ntrees][pk_stride] {parent, pre, size, 0} (when rec is null)
     long long pk_stride;
+    int4 *rec;              // nullable: [ntrees][rec_stride] {parent, nba, cv, 0} instead of pk
+    long long rec_stride;
+    const int *bflag;       // needed with rec
     int *err;
 };
 
 struct AggregateArgs {
     int n, u, ntrees, trees_per_chunk;
-    const int *parB;
-    const int4 *pk;
-    long long pk_stride;
+    const int4 *bnode;
+    const int4 *rec;
+    long long rec_stride;
     long long *counts;
 };
 
 constexpr int kRrHist = 64;
+constexpr int kSamplerRobMax = 128;      // reorder-buffer entries of the sampler
+constexpr int kSamplerPathGlobal = 248;  // recorded steps per entry kept in global memory
+constexpr int kMaxSolveGrid = 1024;
+
+// degree-balanced row mapping (see the BFS / SpMV kernels)
+struct RowMap {
+    const int *rp, *col;
+    int n;
+    int heavy_thresh;
+    const int *heavy;   // ascending IDs of rows with degree > heavy_thresh
+    const int *nheavy;  // device count
+};
 
 struct CgScalars {
     double rz, pq, alpha, beta, rr, rr0, tol2;
@@ -64,19 +80,22 @@ hipError_t launch_rp_to_i32(int n, const long long *rp64, int *rp32, hipStream_t
 hipError_t launch_validate(int n, long long nnz, const long long *rp64, const int *col, int *err, hipStream_t st);
 hipError_t launch_argmax_degree(int n, const int *rp, unsigned long long *best, hipStream_t st);
 hipError_t launch_bfs_init(int n, int u, int *dist, int *parB, hipStream_t st);
-hipError_t launch_bfs_level(int n, const int *rp, const int *col, int d, int *dist, int *parB, int *found,
-                            hipStream_t st);
+hipError_t launch_bfs_level(const RowMap &m, int G, int d, int *dist, int *parB, int *found, hipStream_t st);
+hipError_t launch_heavy_list(int n, const int *rp, int thresh, int *bcount, int *heavy, int *nheavy, hipStream_t st);
+int solve_grid(const RowMap &m, int G);
 hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t st);
 hipError_t launch_wilson(const WilsonArgs &a, int ntrees, bool lds_bits, hipStream_t st);
 hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st);
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st);
+hipError_t launch_extract_parents(int n, int ntrees, const int4 *rec, long long rec_stride, int *out, hipStream_t st);
+hipError_t launch_bflag(int n, const int4 *bnode, int *bflag, hipStream_t st);
 template <typename T>
-hipError_t launch_cg_iteration(const CgArgs<T> &a, int grid, hipStream_t st);
+hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, hipStream_t st);
 template <typename Tin, typename T>
 hipError_t launch_cg_start(const CgArgs<T> &a, int grid, const Tin *rhs, int rhs_is_pivot, int u,
                            const double *shift_scale, double tol2, hipStream_t st);
-hipError_t launch_residual64(int n, const int *rp, const int *col, int u, const double *x, double *res,
-                             double *part, unsigned int *counter, double *out, int grid, hipStream_t st);
+hipError_t launch_residual64(const RowMap &m, int G, int u, const double *x, double *res, double *part,
+                             unsigned int *counter, double *out, hipStream_t st);
 template <typename T>
 hipError_t launch_axpy_project(int n, double *x, const T *d, const double *scale_src, int scale_idx,
                                const double *mean_src, int grid, hipStream_t st);
