@@ -56,7 +56,6 @@ struct Misc {                      // small zero-initialised block at the front 
     int err_interval;
     int nheavy;
     unsigned long long best_degree;
-    unsigned int counters[8];
     CgScalars sc64, sc32;
     double rr_hist64[kRrHist];
     double rr_hist32[kRrHist];
@@ -136,8 +135,8 @@ Plan make_plan(const ustd_problem *p) {
     L.off_rec = take((long long)L.K * L.rec_stride * 16);
     L.off_path = take((long long)L.K * L.rob * kSamplerPathGlobal * 8);
     L.off_bits = take(L.lds_bits ? 0 : (long long)L.K * L.nwords * 4);
-    L.off_scr = take((long long)L.Kiv * L.scr_stride * 4);
-    L.off_part = take((long long)kMaxSolveGrid * 3 * 8);
+    L.off_scr = take(std::max((long long)L.Kiv * L.scr_stride, 3 * n) * 4);
+    L.off_part = take((long long)kMaxSolveGrid * 6 * 8);
     L.off_x64 = take(n * 8);
     L.off_r64 = take(n * 8);
     L.off_z64 = take(n * 8);
@@ -273,20 +272,8 @@ int setup(Ctx &c, ustd_report *rep) {
     HIP_TRY(hipStreamSynchronize(c.st));
     if (err) return fail(USTD_EGRAPH, "graph is not connected");
     // subtree intervals of B_u (fixed for every tree): bnode[x] = {parB, pre_B, size_B, 0}
-    {
-        IntervalArgs ia{};
-        ia.n = n;
-        ia.u = c.pivot;
-        ia.par = parB;
-        ia.par_stride = n;
-        ia.scratch = at<int>(c.ws, c.L.off_scr);
-        ia.scratch_stride = c.L.scr_stride;
-        ia.pk = at<int4>(c.ws, c.L.off_bnode);
-        ia.pk_stride = n;
-        ia.err = &c.misc->err_interval;
-        HIP_TRY(launch_intervals(ia, 1, c.st));
-        HIP_TRY(launch_bflag(n, at<int4>(c.ws, c.L.off_bnode), at<int>(c.ws, c.L.off_bflag), c.st));
-    }
+    HIP_TRY(launch_b_intervals(n, c.pivot, c.ecc, dist, parB, at<int>(c.ws, c.L.off_scr), at<int4>(c.ws, c.L.off_bnode),
+                               at<int>(c.ws, c.L.off_bflag), c.st));
     if (rep) {
         rep->pivot = c.pivot;
         rep->ecc = c.ecc;
@@ -373,7 +360,7 @@ int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *cou
 // pivot-column solve
 // ---------------------------------------------------------------------------------------
 template <typename T>
-CgArgs<T> cg_args(Ctx &c, T *x, T *r, T *z, T *pp, T *q, CgScalars *sc, double *hist, unsigned int *counter) {
+CgArgs<T> cg_args(Ctx &c, T *x, T *r, T *z, T *pp, T *q, CgScalars *sc, double *hist) {
     CgArgs<T> a{};
     a.n = c.L.n;
     a.rp = c.rp32;
@@ -383,8 +370,10 @@ CgArgs<T> cg_args(Ctx &c, T *x, T *r, T *z, T *pp, T *q, CgScalars *sc, double *
     a.z = z;
     a.p = pp;
     a.q = q;
-    a.part = at<double>(c.ws, c.L.off_part);
-    a.counter = counter;
+    a.part_pq = at<double>(c.ws, c.L.off_part);
+    a.part_rz = a.part_pq + kMaxSolveGrid;
+    a.grid_spmv = solve_grid(c.rows, c.L.G);
+    a.grid_vec = vec_grid(c.L.n);
     a.sc = sc;
     a.rr_hist = hist;
     return a;
@@ -403,7 +392,7 @@ int cg_iterate(Ctx &c, const CgArgs<T> &a, int maxit, int *iters_out, bool *conv
         HIP_TRY(hipStreamSynchronize(c.st));
         if (sc.done || launched >= maxit) break;
         const int todo = std::min(chunk, maxit - launched);
-        for (int i = 0; i < todo; ++i) HIP_TRY(launch_cg_iteration<T>(a, c.rows, c.L.G, c.st));
+        for (int i = 0; i < todo; ++i) HIP_TRY(launch_cg_iteration<T>(a, c.rows, c.L.G, launched + i, c.st));
         launched += todo;
     }
     *conv = sc.done && sc.rr <= sc.tol2 * sc.rr0;
@@ -414,13 +403,13 @@ int cg_iterate(Ctx &c, const CgArgs<T> &a, int maxit, int *iters_out, bool *conv
 int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
     const ustd_problem *p = c.p;
     const int n = c.L.n;
-    const int grid = solve_grid(c.rows, c.L.G);
+    const int grid = vec_grid(n);
     const double bnorm = std::sqrt((double)(n - 1) / (double)n);
     double tol = p->solve_tol;
     if (!(tol > 0.0)) tol = std::min(solver_eta(p, c.ecc), 1e-12);
     const int maxit = p->solve_maxit > 0 ? p->solve_maxit : 20000;
     double *x64 = x_out;
-    double *part = at<double>(c.ws, c.L.off_part);
+    double *part = at<double>(c.ws, c.L.off_part) + 3 * kMaxSolveGrid;  // residual partials
     double *sums = c.misc->sums;
     int total_it = 0, outer = 0;
     bool conv = false;
@@ -428,23 +417,23 @@ int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
     if (p->solve_mode == USTD_SOLVE_FP64) {
         CgArgs<double> a = cg_args<double>(c, x64, at<double>(c.ws, c.L.off_r64), at<double>(c.ws, c.L.off_z64),
                                            at<double>(c.ws, c.L.off_p64), at<double>(c.ws, c.L.off_q64),
-                                           &c.misc->sc64, c.misc->rr_hist64, &c.misc->counters[0]);
-        HIP_TRY(launch_cg_start<double, double>(a, grid, nullptr, 1, c.pivot, nullptr, tol * tol, c.st));
+                                           &c.misc->sc64, c.misc->rr_hist64);
+        HIP_TRY(launch_cg_start<double, double>(a, nullptr, 1, c.pivot, nullptr, tol * tol, c.st));
         USTD_TRY(cg_iterate<double>(c, a, maxit, &total_it, &conv));
         outer = 1;
-        HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, &c.misc->counters[2], sums, c.st));
+        HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, sums, c.st));
         HIP_TRY(launch_axpy_project<double>(n, x64, nullptr, nullptr, 0, sums + 2, grid, c.st));
     } else {
         double *res = at<double>(c.ws, c.L.off_res64);
         float *x32 = at<float>(c.ws, c.L.off_x32);
         CgArgs<float> a = cg_args<float>(c, x32, at<float>(c.ws, c.L.off_r32), at<float>(c.ws, c.L.off_z32),
                                          at<float>(c.ws, c.L.off_p32), at<float>(c.ws, c.L.off_q32),
-                                         &c.misc->sc32, c.misc->rr_hist32, &c.misc->counters[1]);
+                                         &c.misc->sc32, c.misc->rr_hist32);
         HIP_TRY(hipMemsetAsync(x64, 0, (size_t)n * 8, c.st));
         const double inner_tol = 1e-5;
         double prev = INFINITY;
         for (outer = 0; outer < 40; ++outer) {
-            HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, res, part, &c.misc->counters[2], sums, c.st));
+            HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, res, part, sums, c.st));
             HIP_TRY(launch_axpy_project<double>(n, x64, nullptr, nullptr, 0, sums + 2, grid, c.st));
             HIP_TRY(launch_outer_scalars(n, sums, c.misc->shift_scale, c.st));
             double hs[4];
@@ -455,8 +444,8 @@ int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
             if (outer > 0 && rnorm > 0.5 * prev) break;  // refinement stagnates at FP64 rounding
             prev = rnorm;
             if (total_it >= maxit) break;
-            HIP_TRY(launch_cg_start<double, float>(a, grid, res, 0, c.pivot, c.misc->shift_scale,
-                                                   inner_tol * inner_tol, c.st));
+            HIP_TRY(launch_cg_start<double, float>(a, res, 0, c.pivot, c.misc->shift_scale, inner_tol * inner_tol,
+                                                   c.st));
             int it = 0;
             bool ic = false;
             USTD_TRY(cg_iterate<float>(c, a, maxit - total_it, &it, &ic));
@@ -465,7 +454,7 @@ int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
         }
     }
     // final residual of the projected solution
-    HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, &c.misc->counters[2], sums, c.st));
+    HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, sums, c.st));
     double hs[4];
     HIP_TRY(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));

@@ -183,7 +183,8 @@ __global__ void count_unreached_kernel(int n, const int *__restrict__ dist, int 
 //     64-step chunk finds the truncation point, one per chunk and branch vertex finds the
 //     vertex's last visit);
 //   - walks longer than the record are re-walked from s by one lane against the current
-//     tree (the sequential algorithm for that start, Next pointers in the record array).
+//     tree in a tight loop (the sequential algorithm for that start, Next pointers in the
+//     parent field of the record array).
 // Everything a commit needs is prefetched into LDS while walking (the B_u flag word of
 // every recorded vertex, the chain value of the vertex a walk ends on), so the in-order
 // commit path does no dependent global loads in the common cases.
@@ -246,8 +247,70 @@ __device__ __forceinline__ void wait_global() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-constexpr int kHashBits = 11;  // batch-commit conflict table: 2048 minimum-writer slots
+constexpr int kHashBits = 10;  // batch-commit conflict table: 1024 minimum-writer slots
+
+// inclusive prefix sum over the 64 lanes with DPP row shifts and row broadcasts
+__device__ __forceinline__ int wave_scan_dpp(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
 __device__ __forceinline__ int hash_slot(int v) { return (int)(((unsigned)v * 2654435761u) >> (32 - kHashBits)); }
+
+// The sequential algorithm for one start s0 against the current tree: walk with Next
+// pointers (in the parent field), retrace the loop erasure, and write the branch's records
+// {parent, nba, cv}.  One lane; returns the walk's step count.
+template <bool LDS>
+__device__ long long rewalk_commit(const TreeBits<LDS> &bits, int *recw, const int *__restrict__ rp,
+                                   const int *__restrict__ col, const int *__restrict__ bflag, int s0,
+                                   uint32_t tlo, uint32_t thi, uint32_t key0, uint32_t key1) {
+    int xw = s0;
+    int r0 = rp[s0], r1 = rp[s0 + 1];
+    long long k = 0;
+    uint4 ph = make_uint4(0, 0, 0, 0);
+    for (;;) {
+        if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
+        const int q = (int)(k & 3);
+        const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
+        const int y = col[r0 + (int)__umulhi(w, (uint32_t)(r1 - r0))];
+        const int ny0 = rp[y], ny1 = rp[y + 1];
+        ++k;
+        recw[4 * xw] = y;  // Next pointer; becomes the parent when xw joins T
+        if (bits.test(y)) break;
+        xw = y;
+        r0 = ny0;
+        r1 = ny1;
+    }
+    // retrace the loop erasure from s0 to the tree vertex ya it reaches
+    int z = s0;
+    while (!bits.test(z)) {
+        bits.set(z);
+        z = recw[4 * z];
+    }
+    const int ya = z;
+    const int cva = recw[4 * ya + 2];
+    // nba: nearest marked vertex strictly closer to ya; cv: the vertex itself if marked
+    int run = s0;
+    z = s0;
+    while (z != ya) {
+        const int nz = recw[4 * z];
+        if (marked_f(z, bflag[z], nz, bflag[nz])) {
+            for (int w2 = run; w2 != z; w2 = recw[4 * w2]) recw[4 * w2 + 1] = z;
+            run = z;
+        }
+        z = nz;
+    }
+    for (int w2 = run; w2 != ya; w2 = recw[4 * w2]) recw[4 * w2 + 1] = cva;
+    for (z = s0; z != ya; z = recw[4 * z]) {
+        const int nz = recw[4 * z];
+        recw[4 * z + 2] = marked_f(z, bflag[z], nz, bflag[nz]) ? z : recw[4 * z + 1];
+    }
+    return k;
+}
 
 template <typename T>
 __device__ __forceinline__ T sel4(int c, T a0, T a1, T a2, T a3) {
@@ -262,8 +325,10 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     __shared__ int rob_s[kRobMax], rob_k[kRobMax], rob_fs[kRobMax], rob_cv[kRobMax];
     __shared__ int2 rob_p[kRobMax][kPathLds];
     __shared__ int cand[kWave];
-    __shared__ int br[kPath + 1], brf[kPath + 1];
     __shared__ int hslot[1 << kHashBits];
+    int *const br = hslot;               // long-walk branch buffers share the hash table's
+    int *const brf = hslot + kPath + 1;  // storage; the slots are cleared again afterwards
+    static_assert(2 * (kPath + 1) <= (1 << kHashBits), "branch buffers fit the hash table");
 
     const int lane = threadIdx.x;
     const int n = a.n;
@@ -293,8 +358,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     wave_sync();
 
     int head = 0, tail = 0, cursor = 0;  // wave-uniform
-    int seq_lane = -1;                   // wave-uniform: lane re-walking the head entry
-    int mode = 0;                        // 0 idle, 1 speculative walk, 2 re-walk, 3 re-walk done
+    int mode = 0;                        // 0 idle, 1 speculative walk
     int my_e = 0, x = 0, s = 0, k = 0, r0 = 0, r1 = 0, fs = 0;
     uint4 ph = make_uint4(0, 0, 0, 0);
     long long steps = 0, draws = 0;
@@ -314,7 +378,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 if (wi == a.nwords - 1 && (n & 31)) fb &= (1u << (n & 31)) - 1u;
             }
             const int c = __popc(fb);
-            const int incl = wave_incl_scan(c);
+            const int incl = wave_scan_dpp(c);
             const int total = __shfl(incl, kWave - 1, kWave);
             const int need = want - got;
             int r = incl - c;
@@ -353,7 +417,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
         wave_sync();
 
         // ---------------------------------------------------------------- one walk step
-        if (mode == 1 || mode == 2) {
+        if (mode == 1) {
             if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s, tlo, thi), a.key0, a.key1);
             const int q = k & 3;
             const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
@@ -366,75 +430,33 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             consume(fy, cvy, ny0, ny1);  // no load may stay in flight into the commit phase
             ++k;
             ++draws;
-            if (mode == 1) {
-                const int sl = my_e & robm;
-                if (k == 1) rob_fs[sl] = fs;
-                if (k <= kPathLds) rob_p[sl][k - 1] = make_int2(y, fy);
-                else gpath[sl * (kPath - kPathLds) + (k - 1 - kPathLds)] = make_int2(y, fy);
-                if (in) { rob_k[sl] = k; rob_cv[sl] = cvy; mode = 0; }
-                else if (k == kPath) { rob_k[sl] = kOverflow; mode = 0; }
-                else if (bits.test(s)) { rob_k[sl] = 0; mode = 0; }  // s absorbed: never walks
-                else { x = y; r0 = ny0; r1 = ny1; }
-            } else {
-                recw[4 * x] = y;  // Next pointer; becomes the parent when x joins T
-                if (in) {
-                    // retrace the loop erasure from s to the tree vertex ya it reaches
-                    int z = s;
-                    while (!bits.test(z)) {
-                        bits.set(z);
-                        z = recw[4 * z];
-                    }
-                    const int ya = z;
-                    const int cva = recw[4 * ya + 2];
-                    // nba: nearest marked vertex strictly closer to ya; cv: z itself if marked
-                    int run = s;
-                    z = s;
-                    while (z != ya) {
-                        const int nz = recw[4 * z];
-                        if (marked_f(z, bflag[z], nz, bflag[nz])) {
-                            for (int w2 = run; w2 != z; w2 = recw[4 * w2]) recw[4 * w2 + 1] = z;
-                            run = z;
-                        }
-                        z = nz;
-                    }
-                    for (int w2 = run; w2 != ya; w2 = recw[4 * w2]) recw[4 * w2 + 1] = cva;
-                    for (z = s; z != ya; z = recw[4 * z]) {
-                        const int nz = recw[4 * z];
-                        recw[4 * z + 2] = marked_f(z, bflag[z], nz, bflag[nz]) ? z : recw[4 * z + 1];
-                    }
-                    mode = 3;
-                } else {
-                    x = y;
-                    r0 = ny0;
-                    r1 = ny1;
-                }
-            }
+            const int sl = my_e & robm;
+            if (k == 1) rob_fs[sl] = fs;
+            if (k <= kPathLds) rob_p[sl][k - 1] = make_int2(y, fy);
+            else gpath[sl * (kPath - kPathLds) + (k - 1 - kPathLds)] = make_int2(y, fy);
+            if (in) { rob_k[sl] = k; rob_cv[sl] = cvy; mode = 0; }
+            else if (k == kPath) { rob_k[sl] = kOverflow; mode = 0; }
+            else if (bits.test(s)) { rob_k[sl] = 0; mode = 0; }  // s absorbed: never walks
+            else { x = y; r0 = ny0; r1 = ny1; }
         }
         wave_sync();
-        if (seq_lane >= 0) {
-            if (__shfl(mode, seq_lane, kWave) == 3) {
-                if (lane == seq_lane) {
-                    steps += k;
-                    mode = 0;
-                }
-                ++head;
-                seq_lane = -1;
-            }
-        }
 
         // ---------------------------------------------------------------- in-order commit
-        while (head < tail && seq_lane < 0) {
+        while (head < tail) {
             const int hs = rob_k[head & robm];
             if (hs == kWalking) break;
             if (hs == kOverflow) {
+                // walk longer than the record: lane 0 runs the sequential algorithm for this
+                // start against the current tree (all earlier starts are committed)
                 const int s0 = rob_s[head & robm];
-                if (bits.test(s0)) { ++head; continue; }
-                const uint64_t idl = __ballot(mode == 0);
-                if (idl == 0) break;
-                const int L = __builtin_ctzll(idl);
-                if (lane == L) { mode = 2; s = s0; x = s0; k = 0; r0 = rp[s0]; r1 = rp[s0 + 1]; }
-                seq_lane = L;
-                break;
+                if (!bits.test(s0) && lane == 0) {
+                    const long long kk = rewalk_commit(bits, recw, rp, col, bflag, s0, tlo, thi, a.key0, a.key1);
+                    steps += kk;
+                    draws += kk;
+                }
+                ++head;
+                wave_sync();
+                continue;
             }
             const int idx = head + lane;
             const int sk = idx < tail ? rob_k[idx & robm] : kWalking;
@@ -646,6 +668,8 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                     if (lane == 0) steps += istar;
                 }
             }
+            wave_sync();
+            for (int i = lane; i < 2 * (kPath + 1); i += kWave) hslot[i] = kWave;
             ++head;
             wave_sync();
         }
@@ -884,6 +908,41 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
     if (sum != 0) atomicAdd((unsigned long long *)&a.counts[v], (unsigned long long)(long long)sum);
 }
 
+// Subtree intervals of B_u, level by level over the whole grid (B_u has ecc(u) + 1 levels):
+// sizes bottom-up (each vertex adds its finished size to its parent), then pre-order
+// numbers top-down (each vertex takes the next free range under its parent; the order of
+// siblings is whatever the atomics give, and any order is a valid nesting).
+__global__ void bsub_init_kernel(int n, int u, int *__restrict__ sz, int *__restrict__ cur, int *__restrict__ pre) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    sz[v] = 1;
+    if (v == u) {
+        pre[v] = 0;
+        cur[v] = 1;
+    }
+}
+__global__ void bsub_size_kernel(int n, int d, const int *__restrict__ dist, const int *__restrict__ parB,
+                                 int *__restrict__ sz) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && dist[v] == d) atomicAdd(&sz[parB[v]], sz[v]);
+}
+__global__ void bsub_pre_kernel(int n, int d, const int *__restrict__ dist, const int *__restrict__ parB,
+                                const int *__restrict__ sz, int *__restrict__ cur, int *__restrict__ pre) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n || dist[v] != d) return;
+    const int pv = atomicAdd(&cur[parB[v]], sz[v]);
+    pre[v] = pv;
+    cur[v] = pv + 1;
+}
+__global__ void bsub_pack_kernel(int n, const int *__restrict__ parB, const int *__restrict__ pre,
+                                 const int *__restrict__ sz, int4 *__restrict__ bnode, int *__restrict__ bflag) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int pb = parB[v], z = sz[v];
+    bnode[v] = make_int4(pb, pre[v], z, 0);
+    bflag[v] = (int)((unsigned)(pb + 1) | (z > 1 ? 0x80000000u : 0u));
+}
+
 // bflag[x] = (parB(x) + 1) | (1 << 31 if x has a child in B_u)
 __global__ void bflag_kernel(int n, const int4 *__restrict__ bnode, int *__restrict__ bflag) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -949,31 +1008,21 @@ __device__ __forceinline__ void lap_apply_rows(const RowMap &m, const T *__restr
     }
 }
 
-// last block of the grid sums `nparts` partials of width `w` into out[0..w)
-__device__ __forceinline__ bool last_block(unsigned int *counter) {
-    __shared__ bool am_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned int prev = atomicAdd(counter, 1u);
-        am_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (am_last) {
-        __threadfence();
-        if (threadIdx.x == 0) *counter = 0u;
-    }
-    return am_last;
-}
-
+// Sum of per-block partials, computed redundantly by every consumer block in index order
+// (deterministic; no atomics).  The partials were written by an earlier kernel.
 __device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nparts, int stride,
                                                double *sh) {
     double v = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += __hip_atomic_load(part + (long long)i * stride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += part[(long long)i * stride];
     return block_sum(v, sh);
 }
 
-// q = L p and alpha = rz / (p . q)
+// Conjugate gradients, one iteration = three kernels:
+//   spmv  : q = L p, partial p.q per block
+//   update: alpha = rz_i / p.q; x += alpha p; r -= alpha q; z = r / deg; partial r.z, r.r
+//   pdir  : beta = rz_{i+1} / rz_i; p = z + beta p; convergence (r.r <= tol^2 r0.r0)
+// rz is double-buffered by iteration parity so no block overwrites a value another block
+// of the same kernel still reads.
 template <typename T, int G>
 __global__ __launch_bounds__(256) void cg_spmv_kernel(CgArgs<T> a, RowMap m) {
     __shared__ double sh[4];
@@ -986,29 +1035,16 @@ __global__ __launch_bounds__(256) void cg_spmv_kernel(CgArgs<T> a, RowMap m) {
         acc += (double)p[v] * (double)qv;
     });
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) __hip_atomic_store(a.part + blockIdx.x * 2, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (last_block(a.counter)) {
-        const double pq = sum_partials(a.part, gridDim.x, 2, sh);
-        if (threadIdx.x == 0) {
-            CgScalars *S = a.sc;
-            S->pq = pq;
-            if (pq > 0.0 && pq == pq) {
-                S->alpha = S->rz / pq;
-            } else {  // breakdown (p = 0 or non-finite): stop with the current x
-                S->alpha = 0.0;
-                S->done = 1;
-            }
-        }
-    }
+    if (threadIdx.x == 0) a.part_pq[blockIdx.x] = acc;
 }
 
-// x += alpha p; r -= alpha q; z = r / deg; beta = (r . z) / rz_old; rr = r . r
 template <typename T>
-__global__ __launch_bounds__(256) void cg_update_kernel(CgArgs<T> a) {
+__global__ __launch_bounds__(256) void cg_update_kernel(CgArgs<T> a, int it) {
     __shared__ double sh[4];
     if (a.sc->done) return;
-    const double alpha = a.sc->alpha;
-    const T al = (T)alpha;
+    const double pq = sum_partials(a.part_pq, a.grid_spmv, 1, sh);
+    if (!(pq > 0.0 && pq == pq)) return;  // breakdown: cg_pdir sees the same sum and stops
+    const T al = (T)(a.sc->rz[it & 1] / pq);
     double rz = 0.0, rr = 0.0;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
         a.x[v] += al * a.p[v];
@@ -1022,38 +1058,43 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgArgs<T> a) {
     rz = block_sum(rz, sh);
     rr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        __hip_atomic_store(a.part + blockIdx.x * 2, rz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(a.part + blockIdx.x * 2 + 1, rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (last_block(a.counter)) {
-        const double rzn = sum_partials(a.part, gridDim.x, 2, sh);
-        const double rrn = sum_partials(a.part + 1, gridDim.x, 2, sh);
-        if (threadIdx.x == 0) {
-            CgScalars *S = a.sc;
-            S->beta = (S->rz != 0.0) ? rzn / S->rz : 0.0;
-            S->rz = rzn;
-            S->rr = rrn;
-            a.rr_hist[S->iter & (kRrHist - 1)] = rrn;
-            S->iter += 1;
-            if (!(rrn > S->tol2 * S->rr0)) S->done = 1;  // converged (or NaN)
-        }
+        a.part_rz[2 * blockIdx.x] = rz;
+        a.part_rz[2 * blockIdx.x + 1] = rr;
     }
 }
 
-// p = z + beta p
 template <typename T>
-__global__ __launch_bounds__(256) void cg_pdir_kernel(CgArgs<T> a) {
-    if (a.sc->done) return;
-    const T be = (T)a.sc->beta;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x)
-        a.p[v] = a.z[v] + be * a.p[v];
+__global__ __launch_bounds__(256) void cg_pdir_kernel(CgArgs<T> a, int it) {
+    __shared__ double sh[4];
+    CgScalars *S = a.sc;
+    if (S->done) return;
+    const double pq = sum_partials(a.part_pq, a.grid_spmv, 1, sh);
+    const bool breakdown = !(pq > 0.0 && pq == pq);
+    const double rzn = breakdown ? 0.0 : sum_partials(a.part_rz, a.grid_vec, 2, sh);
+    const double rr = breakdown ? S->rr : sum_partials(a.part_rz + 1, a.grid_vec, 2, sh);
+    const bool conv = breakdown || !(rr > S->tol2 * S->rr0);
+    if (!conv) {
+        const double rzo = S->rz[it & 1];
+        const T be = (T)(rzo != 0.0 ? rzn / rzo : 0.0);
+        for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x)
+            a.p[v] = a.z[v] + be * a.p[v];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S->rz[(it + 1) & 1] = rzn;
+        if (!breakdown) {
+            S->rr = rr;
+            S->iter = it + 1;
+            a.rr_hist[it & (kRrHist - 1)] = rr;
+        }
+        if (conv) S->done = 1;
+    }
 }
 
-// start of a CG solve of L d = rhs: d = 0, r = rhs (optionally scaled and shifted to mean
-// zero), z = r/deg, p = z, rz = r . z
+// start of a CG solve of L d = rhs: d = 0, r = rhs (optionally shifted to mean zero and
+// scaled), z = r/deg, p = z; partial r.z, r.r per block (cg_start_finish sums them)
 template <typename Tin, typename T>
 __global__ __launch_bounds__(256) void cg_start_kernel(CgArgs<T> a, const Tin *__restrict__ rhs, int rhs_is_pivot,
-                                                      int u, const double *__restrict__ shift_scale, double tol2) {
+                                                      int u, const double *__restrict__ shift_scale) {
     __shared__ double sh[4];
     double rz = 0.0, rr = 0.0;
     const double shift = shift_scale ? shift_scale[0] : 0.0;
@@ -1075,33 +1116,34 @@ __global__ __launch_bounds__(256) void cg_start_kernel(CgArgs<T> a, const Tin *_
     rz = block_sum(rz, sh);
     rr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        __hip_atomic_store(a.part + blockIdx.x * 2, rz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(a.part + blockIdx.x * 2 + 1, rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (last_block(a.counter)) {
-        const double rzn = sum_partials(a.part, gridDim.x, 2, sh);
-        const double rrn = sum_partials(a.part + 1, gridDim.x, 2, sh);
-        if (threadIdx.x == 0) {
-            CgScalars *S = a.sc;
-            S->rz = rzn;
-            S->rr = rrn;
-            S->rr0 = rrn;
-            S->beta = 0.0;
-            S->alpha = 0.0;
-            S->iter = 0;
-            S->tol2 = tol2;
-            S->done = (rrn > 0.0) ? 0 : 1;
-            a.rr_hist[kRrHist - 1] = rrn;
-        }
+        a.part_rz[2 * blockIdx.x] = rz;
+        a.part_rz[2 * blockIdx.x + 1] = rr;
     }
 }
 
-// FP64 residual of the current x64: res = b - L x with b = e_u - 1/n; sums
-// [sum res, |res|^2, sum x] for the outer loop of the mixed solve and the final residual
+template <typename T>
+__global__ __launch_bounds__(256) void cg_start_finish_kernel(CgArgs<T> a, double tol2) {
+    __shared__ double sh[4];
+    const double rz = sum_partials(a.part_rz, a.grid_vec, 2, sh);
+    const double rr = sum_partials(a.part_rz + 1, a.grid_vec, 2, sh);
+    if (threadIdx.x == 0) {
+        CgScalars *S = a.sc;
+        S->rz[0] = rz;
+        S->rz[1] = 0.0;
+        S->rr = rr;
+        S->rr0 = rr;
+        S->tol2 = tol2;
+        S->iter = 0;
+        S->done = (rr > 0.0) ? 0 : 1;
+        a.rr_hist[kRrHist - 1] = rr;
+    }
+}
+
+// FP64 residual of the current x64: res = b - L x with b = e_u - 1/n; per-block partials of
+// [sum res, |res|^2, sum x]; reduce3_kernel sums them into out[0..3)
 template <int G>
 __global__ __launch_bounds__(256) void residual64_kernel(RowMap m, int u, const double *__restrict__ x,
-                                                         double *__restrict__ res, double *__restrict__ part,
-                                                         unsigned int *counter, double *__restrict__ out) {
+                                                         double *__restrict__ res, double *__restrict__ part) {
     __shared__ double sh[4];
     const double inv_n = 1.0 / (double)m.n;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -1116,19 +1158,22 @@ __global__ __launch_bounds__(256) void residual64_kernel(RowMap m, int u, const 
     s1 = block_sum(s1, sh);
     s2 = block_sum(s2, sh);
     if (threadIdx.x == 0) {
-        __hip_atomic_store(part + blockIdx.x * 3, s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(part + blockIdx.x * 3 + 1, s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(part + blockIdx.x * 3 + 2, s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        part[blockIdx.x * 3] = s0;
+        part[blockIdx.x * 3 + 1] = s1;
+        part[blockIdx.x * 3 + 2] = s2;
     }
-    if (last_block(counter)) {
-        const double a0 = sum_partials(part, gridDim.x, 3, sh);
-        const double a1 = sum_partials(part + 1, gridDim.x, 3, sh);
-        const double a2 = sum_partials(part + 2, gridDim.x, 3, sh);
-        if (threadIdx.x == 0) {
-            out[0] = a0;
-            out[1] = a1;
-            out[2] = a2;
-        }
+}
+
+__global__ __launch_bounds__(256) void reduce3_kernel(const double *__restrict__ part, int nparts,
+                                                      double *__restrict__ out) {
+    __shared__ double sh[4];
+    const double a0 = sum_partials(part, nparts, 3, sh);
+    const double a1 = sum_partials(part + 1, nparts, 3, sh);
+    const double a2 = sum_partials(part + 2, nparts, 3, sh);
+    if (threadIdx.x == 0) {
+        out[0] = a0;
+        out[1] = a1;
+        out[2] = a2;
     }
 }
 
@@ -1242,6 +1287,16 @@ hipError_t launch_extract_parents(int n, int ntrees, const int4 *rec, long long 
     extract_parents_kernel<<<blocks_for((long long)n * ntrees, 256), 256, 0, st>>>(n, ntrees, rec, rec_stride, out);
     return hipGetLastError();
 }
+hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int *parB, int *scratch, int4 *bnode,
+                              int *bflag, hipStream_t st) {
+    int *sz = scratch, *cur = scratch + n, *pre = scratch + 2 * n;
+    const int nb = blocks_for(n, 256);
+    bsub_init_kernel<<<nb, 256, 0, st>>>(n, u, sz, cur, pre);
+    for (int d = ecc; d >= 1; --d) bsub_size_kernel<<<nb, 256, 0, st>>>(n, d, dist, parB, sz);
+    for (int d = 1; d <= ecc; ++d) bsub_pre_kernel<<<nb, 256, 0, st>>>(n, d, dist, parB, sz, cur, pre);
+    bsub_pack_kernel<<<nb, 256, 0, st>>>(n, parB, pre, sz, bnode, bflag);
+    return hipGetLastError();
+}
 hipError_t launch_bflag(int n, const int4 *bnode, int *bflag, hipStream_t st) {
     bflag_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, bnode, bflag);
     return hipGetLastError();
@@ -1252,33 +1307,35 @@ hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 int solve_grid(const RowMap &m, int G) { return std::min(row_grid(m, G), kMaxSolveGrid); }
+int vec_grid(int n) { return std::max(1, std::min((n + 255) / 256, kMaxSolveGrid)); }
 
 template <typename T>
-hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, hipStream_t st) {
-    const int grid = solve_grid(m, G);
-    USTD_DISPATCH_G(G, cg_spmv_kernel<T, GG><<<grid, 256, 0, st>>>(a, m));
-    cg_update_kernel<T><<<grid, 256, 0, st>>>(a);
-    cg_pdir_kernel<T><<<grid, 256, 0, st>>>(a);
+hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, int it, hipStream_t st) {
+    USTD_DISPATCH_G(G, cg_spmv_kernel<T, GG><<<a.grid_spmv, 256, 0, st>>>(a, m));
+    cg_update_kernel<T><<<a.grid_vec, 256, 0, st>>>(a, it);
+    cg_pdir_kernel<T><<<a.grid_vec, 256, 0, st>>>(a, it);
     return hipGetLastError();
 }
-template hipError_t launch_cg_iteration<double>(const CgArgs<double> &, const RowMap &, int, hipStream_t);
-template hipError_t launch_cg_iteration<float>(const CgArgs<float> &, const RowMap &, int, hipStream_t);
+template hipError_t launch_cg_iteration<double>(const CgArgs<double> &, const RowMap &, int, int, hipStream_t);
+template hipError_t launch_cg_iteration<float>(const CgArgs<float> &, const RowMap &, int, int, hipStream_t);
 
 template <typename Tin, typename T>
-hipError_t launch_cg_start(const CgArgs<T> &a, int grid, const Tin *rhs, int rhs_is_pivot, int u,
-                           const double *shift_scale, double tol2, hipStream_t st) {
-    cg_start_kernel<Tin, T><<<grid, 256, 0, st>>>(a, rhs, rhs_is_pivot, u, shift_scale, tol2);
+hipError_t launch_cg_start(const CgArgs<T> &a, const Tin *rhs, int rhs_is_pivot, int u, const double *shift_scale,
+                           double tol2, hipStream_t st) {
+    cg_start_kernel<Tin, T><<<a.grid_vec, 256, 0, st>>>(a, rhs, rhs_is_pivot, u, shift_scale);
+    cg_start_finish_kernel<T><<<1, 256, 0, st>>>(a, tol2);
     return hipGetLastError();
 }
-template hipError_t launch_cg_start<double, double>(const CgArgs<double> &, int, const double *, int, int,
-                                                    const double *, double, hipStream_t);
-template hipError_t launch_cg_start<double, float>(const CgArgs<float> &, int, const double *, int, int,
-                                                   const double *, double, hipStream_t);
+template hipError_t launch_cg_start<double, double>(const CgArgs<double> &, const double *, int, int, const double *,
+                                                    double, hipStream_t);
+template hipError_t launch_cg_start<double, float>(const CgArgs<float> &, const double *, int, int, const double *,
+                                                   double, hipStream_t);
 
-hipError_t launch_residual64(const RowMap &m, int G, int u, const double *x, double *res, double *part,
-                             unsigned int *counter, double *out, hipStream_t st) {
+hipError_t launch_residual64(const RowMap &m, int G, int u, const double *x, double *res, double *part, double *out,
+                             hipStream_t st) {
     const int grid = solve_grid(m, G);
-    USTD_DISPATCH_G(G, residual64_kernel<GG><<<grid, 256, 0, st>>>(m, u, x, res, part, counter, out));
+    USTD_DISPATCH_G(G, residual64_kernel<GG><<<grid, 256, 0, st>>>(m, u, x, res, part));
+    reduce3_kernel<<<1, 256, 0, st>>>(part, grid, out);
     return hipGetLastError();
 }
 template <typename T>

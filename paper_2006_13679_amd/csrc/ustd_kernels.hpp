@@ -59,7 +59,8 @@ struct RowMap {
 };
 
 struct CgScalars {
-    double rz, pq, alpha, beta, rr, rr0, tol2;
+    double rz[2];    // r.z of the current iteration, double-buffered by iteration parity
+    double rr, rr0, tol2;
     int iter, done;  // done: converged or broken down; later iterations are no-ops
 };
 
@@ -68,8 +69,9 @@ struct CgArgs {
     int n;
     const int *rp, *col;
     T *x, *r, *z, *p, *q;
-    double *part;           // 2 * grid
-    unsigned int *counter;  // zero-initialised, self-resetting
+    double *part_pq;        // [grid_spmv] partial p.q
+    double *part_rz;        // [2 * grid_vec] partial r.z, r.r
+    int grid_spmv, grid_vec;
     CgScalars *sc;
     double *rr_hist;        // kRrHist
 };
@@ -83,19 +85,22 @@ hipError_t launch_bfs_init(int n, int u, int *dist, int *parB, hipStream_t st);
 hipError_t launch_bfs_level(const RowMap &m, int G, int d, int *dist, int *parB, int *found, hipStream_t st);
 hipError_t launch_heavy_list(int n, const int *rp, int thresh, int *bcount, int *heavy, int *nheavy, hipStream_t st);
 int solve_grid(const RowMap &m, int G);
+int vec_grid(int n);
 hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t st);
 hipError_t launch_wilson(const WilsonArgs &a, int ntrees, bool lds_bits, hipStream_t st);
 hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st);
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st);
 hipError_t launch_extract_parents(int n, int ntrees, const int4 *rec, long long rec_stride, int *out, hipStream_t st);
 hipError_t launch_bflag(int n, const int4 *bnode, int *bflag, hipStream_t st);
+hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int *parB, int *scratch, int4 *bnode,
+                              int *bflag, hipStream_t st);
 template <typename T>
-hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, hipStream_t st);
+hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, int it, hipStream_t st);
 template <typename Tin, typename T>
-hipError_t launch_cg_start(const CgArgs<T> &a, int grid, const Tin *rhs, int rhs_is_pivot, int u,
-                           const double *shift_scale, double tol2, hipStream_t st);
-hipError_t launch_residual64(const RowMap &m, int G, int u, const double *x, double *res, double *part,
-                             unsigned int *counter, double *out, hipStream_t st);
+hipError_t launch_cg_start(const CgArgs<T> &a, const Tin *rhs, int rhs_is_pivot, int u, const double *shift_scale,
+                           double tol2, hipStream_t st);
+hipError_t launch_residual64(const RowMap &m, int G, int u, const double *x, double *res, double *part, double *out,
+                             hipStream_t st);
 template <typename T>
 hipError_t launch_axpy_project(int n, double *x, const T *d, const double *scale_src, int scale_idx,
                                const double *mean_src, int grid, hipStream_t st);
