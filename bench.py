@@ -108,7 +108,21 @@ def main():
     ap.add_argument("--trees-per-batch", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB mebibytes device to device (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+
+        nbytes = args.copy_probe << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes}), flush=True)
+        return
 
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (trees would shard by range "

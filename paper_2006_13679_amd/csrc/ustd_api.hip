@@ -65,9 +65,9 @@ struct Misc {                      // small zero-initialised block at the front 
 
 struct Plan {
     int n, nnz, K, Kiv, rob, nwords, G, heavy_thresh;
-    bool lds_bits;
+    bool lds_bits, col16;
     long long rec_stride, scr_stride;
-    long long off_misc, off_rp32, off_dist, off_parB, off_bnode, off_bflag, off_heavy, off_bcount, off_counts, off_steps,
+    long long off_misc, off_rp32, off_col16, off_dist, off_parB, off_bnode, off_bflag, off_heavy, off_bcount, off_counts, off_steps,
         off_draws, off_rec, off_path, off_bits, off_scr, off_part, off_x64, off_r64, off_z64, off_p64, off_q64,
         off_res64, off_x32, off_r32, off_z32, off_p32, off_q32;
     long long total;
@@ -101,6 +101,7 @@ Plan make_plan(const ustd_problem *p) {
     L.nnz = (int)p->nnz;
     L.nwords = (L.n + 31) / 32;
     L.lds_bits = L.nwords <= kLdsBitsMaxWords;
+    L.col16 = L.n <= 65536;  // 16-bit column copy for the sampler (half the cache footprint)
     L.rob = std::min(kSamplerRobMax, next_pow2(std::max(L.n, 2)));
     const double avg = (double)L.nnz / (double)L.n;
     L.G = avg <= 6.0 ? 4 : (avg <= 16.0 ? 8 : (avg <= 48.0 ? 16 : 32));
@@ -123,6 +124,7 @@ Plan make_plan(const ustd_problem *p) {
     const long long n = L.n;
     L.off_misc = take(sizeof(Misc));
     L.off_rp32 = take((n + 1) * 4);
+    L.off_col16 = take(L.col16 ? (long long)L.nnz * 2 : 0);
     L.off_dist = take(n * 4);
     L.off_parB = take(n * 4);
     L.off_bnode = take(n * 16);
@@ -221,6 +223,7 @@ int begin(Ctx &c, const ustd_problem *p, void *ws, size_t ws_bytes, void *stream
     c.rp32 = at<int>(ws, c.L.off_rp32);
     HIP_TRY(hipMemsetAsync(c.misc, 0, sizeof(Misc), c.st));
     HIP_TRY(launch_rp_to_i32(c.L.n, (const long long *)p->d_row_ptr, c.rp32, c.st));
+    if (c.L.col16) HIP_TRY(launch_col_to_u16(c.L.nnz, p->d_col, at<unsigned short>(ws, c.L.off_col16), c.st));
     c.rows.rp = c.rp32;
     c.rows.col = p->d_col;
     c.rows.n = c.L.n;
@@ -289,7 +292,7 @@ WilsonArgs wilson_args(const Ctx &c, long long tree_begin, long long *steps, lon
     a.nwords = c.L.nwords;
     a.rob = c.L.rob;
     a.rp = c.rp32;
-    a.col = c.p->d_col;
+    a.colv = c.L.col16 ? (const void *)at<unsigned short>(c.ws, c.L.off_col16) : (const void *)c.p->d_col;
     a.key0 = (uint32_t)(c.p->seed & 0xFFFFFFFFull);
     a.key1 = (uint32_t)(c.p->seed >> 32);
     a.tree_begin = tree_begin;
@@ -332,7 +335,7 @@ int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *cou
         WilsonArgs wa = wilson_args(c, tree_begin + b0, steps, draws);
         {
             Timer tm(c.st);
-            HIP_TRY(launch_wilson(wa, cnt, c.L.lds_bits, c.st));
+            HIP_TRY(launch_wilson(wa, cnt, c.L.lds_bits, c.L.col16, c.st));
             ms_s += tm.stop_ms();
         }
         USTD_TRY(aggregate_trees(c, cnt, counts, &ms_a));
@@ -512,7 +515,7 @@ int ustd_sample_trees(const ustd_problem *prob, int64_t tree_begin, int64_t tree
     if (tree_count == 0) return USTD_OK;
     long long *steps = d_steps ? (long long *)d_steps : at<long long>(c.ws, c.L.off_steps);
     WilsonArgs wa = wilson_args(c, tree_begin, steps, at<long long>(c.ws, c.L.off_draws));
-    HIP_TRY(launch_wilson(wa, (int)tree_count, c.L.lds_bits, c.st));
+    HIP_TRY(launch_wilson(wa, (int)tree_count, c.L.lds_bits, c.L.col16, c.st));
     HIP_TRY(launch_extract_parents(c.L.n, (int)tree_count, at<int4>(c.ws, c.L.off_rec), c.L.rec_stride, d_parents, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
     return USTD_OK;

@@ -20,6 +20,11 @@ namespace ustd {
 // ======================================================================================
 // graph set-up
 // ======================================================================================
+__global__ void col_to_u16_kernel(long long nnz, const int *__restrict__ col, unsigned short *__restrict__ col16) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) col16[e] = (unsigned short)col[e];
+}
+
 __global__ void rp_to_i32_kernel(int n, const long long *__restrict__ rp64, int *__restrict__ rp32) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v <= n) rp32[v] = (int)rp64[v];
@@ -264,9 +269,9 @@ __device__ __forceinline__ int hash_slot(int v) { return (int)(((unsigned)v * 26
 // The sequential algorithm for one start s0 against the current tree: walk with Next
 // pointers (in the parent field), retrace the loop erasure, and write the branch's records
 // {parent, nba, cv}.  One lane; returns the walk's step count.
-template <bool LDS>
+template <bool LDS, typename CT>
 __device__ long long rewalk_commit(const TreeBits<LDS> &bits, int *recw, const int *__restrict__ rp,
-                                   const int *__restrict__ col, const int *__restrict__ bflag, int s0,
+                                   const CT *__restrict__ col, const int *__restrict__ bflag, int s0,
                                    uint32_t tlo, uint32_t thi, uint32_t key0, uint32_t key1) {
     int xw = s0;
     int r0 = rp[s0], r1 = rp[s0 + 1];
@@ -276,7 +281,7 @@ __device__ long long rewalk_commit(const TreeBits<LDS> &bits, int *recw, const i
         if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
         const int q = (int)(k & 3);
         const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-        const int y = col[r0 + (int)__umulhi(w, (uint32_t)(r1 - r0))];
+        const int y = (int)col[r0 + (int)__umulhi(w, (uint32_t)(r1 - r0))];
         const int ny0 = rp[y], ny1 = rp[y + 1];
         ++k;
         recw[4 * xw] = y;  // Next pointer; becomes the parent when xw joins T
@@ -319,7 +324,7 @@ __device__ __forceinline__ T sel4(int c, T a0, T a1, T a2, T a3) {
 
 }  // namespace
 
-template <bool LDS>
+template <bool LDS, typename CT>
 __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     extern __shared__ uint32_t lds_bits[];
     __shared__ int rob_s[kRobMax], rob_k[kRobMax], rob_fs[kRobMax], rob_cv[kRobMax];
@@ -343,7 +348,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     int2 *__restrict__ gpath = a.path + (long long)blockIdx.x * ((long long)rob * (kPath - kPathLds));
     TreeBits<LDS> bits{LDS ? lds_bits : a.bits + (long long)blockIdx.x * a.nwords};
     const int *__restrict__ rp = a.rp;
-    const int *__restrict__ col = a.col;
+    const CT *__restrict__ col = reinterpret_cast<const CT *>(a.colv);  // int32, or uint16 when n <= 65536
 
     for (int i = lane; i < a.nwords; i += kWave) {
         if (LDS) bits.w[i] = 0u;
@@ -421,12 +426,18 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s, tlo, thi), a.key0, a.key1);
             const int q = k & 3;
             const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-            const int y = col[r0 + (int)__umulhi(w, (uint32_t)(r1 - r0))];
-            // independent loads for y: tree bit, B_u flag, chain value, next row bounds
+            const int y = (int)col[r0 + (int)__umulhi(w, (uint32_t)(r1 - r0))];
+            // loads for y: tree bit and B_u flag; then either the chain value (the walk ends
+            // here) or the next row bounds (it continues)
             const bool in = bits.test(y);
             const int fy = bflag[y];
-            const int cvy = recw[4 * y + 2];
-            const int ny0 = rp[y], ny1 = rp[y + 1];
+            int cvy = 0, ny0 = 0, ny1 = 0;
+            if (in) {
+                cvy = recw[4 * y + 2];
+            } else {
+                ny0 = rp[y];
+                ny1 = rp[y + 1];
+            }
             consume(fy, cvy, ny0, ny1);  // no load may stay in flight into the commit phase
             ++k;
             ++draws;
@@ -1226,6 +1237,10 @@ __global__ void philox_words_kernel(uint32_t key0, uint32_t key1, long long t, i
 // ======================================================================================
 static inline int blocks_for(long long n, int bs) { return (int)((n + bs - 1) / bs); }
 
+hipError_t launch_col_to_u16(long long nnz, const int *col, unsigned short *col16, hipStream_t st) {
+    col_to_u16_kernel<<<blocks_for(nnz, 256), 256, 0, st>>>(nnz, col, col16);
+    return hipGetLastError();
+}
 hipError_t launch_rp_to_i32(int n, const long long *rp64, int *rp32, hipStream_t st) {
     rp_to_i32_kernel<<<blocks_for(n + 1, 256), 256, 0, st>>>(n, rp64, rp32);
     return hipGetLastError();
@@ -1271,11 +1286,13 @@ hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t 
     count_unreached_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, dist, err);
     return hipGetLastError();
 }
-hipError_t launch_wilson(const WilsonArgs &a, int ntrees, bool lds_bits, hipStream_t st) {
+hipError_t launch_wilson(const WilsonArgs &a, int ntrees, bool lds_bits, bool col16, hipStream_t st) {
     if (lds_bits) {
-        wilson_kernel<true><<<ntrees, 64, (size_t)a.nwords * 4, st>>>(a);
+        if (col16) wilson_kernel<true, unsigned short><<<ntrees, 64, (size_t)a.nwords * 4, st>>>(a);
+        else wilson_kernel<true, int><<<ntrees, 64, (size_t)a.nwords * 4, st>>>(a);
     } else {
-        wilson_kernel<false><<<ntrees, 64, 0, st>>>(a);
+        if (col16) wilson_kernel<false, unsigned short><<<ntrees, 64, 0, st>>>(a);
+        else wilson_kernel<false, int><<<ntrees, 64, 0, st>>>(a);
     }
     return hipGetLastError();
 }

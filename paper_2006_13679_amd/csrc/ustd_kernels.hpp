@@ -10,7 +10,8 @@ namespace ustd {
 
 struct WilsonArgs {
     int n, u, nwords, rob;
-    const int *rp, *col;
+    const int *rp;
+    const void *colv;       // column indices: int32, or uint16 when the launch says so
     uint32_t key0, key1;
     long long tree_begin;
     int4 *rec;              // [ntrees][rec_stride] {parent, nba, cv, 0}
@@ -87,7 +88,8 @@ hipError_t launch_heavy_list(int n, const int *rp, int thresh, int *bcount, int 
 int solve_grid(const RowMap &m, int G);
 int vec_grid(int n);
 hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t st);
-hipError_t launch_wilson(const WilsonArgs &a, int ntrees, bool lds_bits, hipStream_t st);
+hipError_t launch_wilson(const WilsonArgs &a, int ntrees, bool lds_bits, bool col16, hipStream_t st);
+hipError_t launch_col_to_u16(long long nnz, const int *col, unsigned short *col16, hipStream_t st);
 hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st);
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st);
 hipError_t launch_extract_parents(int n, int ntrees, const int4 *rec, long long rec_stride, int *out, hipStream_t st);

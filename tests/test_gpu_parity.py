@@ -215,3 +215,22 @@ def test_error_paths(gpu):
     rc = api.lib().ustd_solve_pivot_column(api.ctypes.byref(p), api._ptr(api._default_ws[G.row_ptr.device].buf),
                                            api._default_ws[G.row_ptr.device].buf.numel(), api._ptr(x), None, None)
     assert rc == api.ENOTCONV
+
+
+@pytest.mark.parametrize("scale", [17, 18])
+def test_large_graph_paths_bit_exact(gpu, scale):
+    """Graphs past the 16-bit column copy (n > 65536) and past the LDS tree bitmap
+    (n > 131072): parents, steps and counts still match the oracle bit for bit."""
+    g = gg.rmat(scale, 8, 3)
+    assert g.n > (65536 if scale == 17 else 131072)
+    u = gg.max_degree_pivot(g)
+    G = dev_graph(g)
+    p = api.problem(G, pivot=u, seed=5, trees_per_batch=16)
+    say("large", scale, g.n)
+    parents, steps = api.sample_trees(G, p, 2, 6)
+    want_par, want_steps, _ = oracle.trees(g.row_ptr, g.col, u, 5, 2, 6, want_counts=False)
+    assert (steps.cpu().numpy() == want_steps).all()
+    assert (parents.cpu().numpy() == want_par).all()
+    counts, rep = api.flow_counts(G, p, 0, 12)
+    _, st, want = oracle.trees(g.row_ptr, g.col, u, 5, 0, 12, want_parents=False)
+    assert (counts.cpu().numpy() == want).all() and rep["walk_steps"] == int(st.sum())
