@@ -30,6 +30,8 @@ WORKLOADS = {
     "rmat18": dict(kind="rmat", scale=18, ef=16, seed=1),
     "rmat20": dict(kind="rmat", scale=20, ef=16, seed=1),
     "rmat22": dict(kind="rmat", scale=22, ef=16, seed=1),
+    "rhg1m": dict(kind="rhg", n=1_000_000, deg=20.0, gamma=3.0, seed=1),
+    "batch64": dict(kind="batch", count=64, tau_cap=4096),
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2006_13679_amd", "csrc", f)
                   for f in ("ustd_kernels.hip", "ustd_kernels.hpp", "ustd_device.hpp")]
@@ -50,6 +52,10 @@ def make_workload(name: str):
     if w["kind"] == "rmat":
         g = gg.rmat(w["scale"], w["ef"], w["seed"])
         return g, gg.max_degree_pivot(g), 0, dict(workload="rmat-scale%d-ef%d" % (w["scale"], w["ef"]),
+                                                  generator_seed=w["seed"])
+    if w["kind"] == "rhg":
+        g = gg.hyperbolic(w["n"], w["deg"], w["gamma"], seed=w["seed"])
+        return g, gg.max_degree_pivot(g), 0, dict(workload="rhg-n%d-deg%g-gamma%g" % (w["n"], w["deg"], w["gamma"]),
                                                   generator_seed=w["seed"])
     g = gg.grid2d(w["side"])
     return g, gg.grid_center_pivot(w["side"]), w["tau"], dict(workload="grid%dx%d" % (w["side"], w["side"]))
@@ -98,6 +104,110 @@ def cpu_baseline(g, u, tau, seed, budget_s: float):
             "ms_per_tree": per_tree * 1e3}
 
 
+def run_batch(args):
+    """Config of 64 mixed graphs (32 R-MAT, 32 grids) with tau capped at 4096, through the
+    batched entry point; one step = one ustd_batch_diag_lpinv call over all members."""
+    import numpy as np
+    import torch
+
+    from paper_2006_13679_amd import api
+    from paper_2006_13679_amd import graphgen as gg
+
+    w = WORKLOADS[args.workload]
+    members = gg.batch_members(w["count"], w["tau_cap"])
+    dev = torch.device("cuda:0")
+    mode = api.SOLVE_MIXED if args.solve == "mixed" else api.SOLVE_FP64
+    graphs = [api.Graph.from_host(m["graph"].row_ptr, m["graph"].col, device=dev) for m in members]
+    probs = [api.problem(G, pivot=m["pivot"], eps=0.3, seed=m["seed"], tau_cap=m["tau_cap"], solve_mode=mode,
+                         solve_tol=1e-12) for G, m in zip(graphs, members)]
+    ws = api.Workspace(dev)
+    print("bench: batch of %d graphs, n total %d" % (len(members), sum(m["graph"].n for m in members)),
+          file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        api.batch_diag_lpinv(graphs, probs, ws=ws, want_counts=False)
+        print("bench: warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = None
+    for i in range(args.steps):
+        _, _, reps = api.batch_diag_lpinv(graphs, probs, ws=ws, want_counts=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    print("bench: %d timed steps in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
+    tau = sum(r["tau"] for r in reps)
+    steps = sum(r["walk_steps"] for r in reps)
+    ms_sample, ms_ag = reps[0]["ms_sample"], reps[0]["ms_aggregate"]
+    ms_solve = sum(r["ms_solve"] for r in reps)
+    ms_bfs = sum(r["ms_bfs"] for r in reps)
+    # the same members one call each, FP64 solve (the plain per-graph form), one pass
+    pws = api.Workspace(dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for G, p in zip(graphs, probs):
+        q = api.Problem.from_buffer_copy(p)
+        q.solve_mode = api.SOLVE_FP64
+        api.diag_lpinv_p(G, q, ws=pws, want_counts=False)
+    torch.cuda.synchronize()
+    ms_single = (time.perf_counter() - t1) * 1e3
+    ab = 0
+    for i, (m, r) in enumerate(zip(members, reps)):
+        dist, _, _, _ = api.bfs(graphs[i], probs[i], ws=pws)
+        ab += algorithmic_bytes(m["graph"].n, r["tau"], r["walk_steps"], int(dist.sum().item()))["sample"]
+    achieved = ab / (ms_sample * 1e-3) / 1e9
+    out = {
+        "metric": "spanning trees/sec + walk steps/sec; end-to-end diag(L\u2020) time at \u03b5=0.3",
+        "value": round(tau / (ms_step * 1e-3), 2), "unit": "trees/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32+fp64" if mode == api.SOLVE_FP64 else "int32+fp32/fp64", "data": "synthetic",
+        "config": {"workload": "batch-%d-mixed-rmat10to16-grid16to256-taucap%d" % (w["count"], w["tau_cap"]),
+                   "members": w["count"], "tau_total": tau, "n_total": sum(m["graph"].n for m in members),
+                   "eps": 0.3, "solve": args.solve},
+        "walk_steps_per_s": round(steps / (ms_sample * 1e-3), 1),
+        "sampling_trees_per_s": round(tau / (ms_sample * 1e-3), 1),
+        "e2e_ms": round(reps[0]["ms_total"], 4),
+        "phase_ms": {"setup_bfs": ms_bfs, "sample": ms_sample, "aggregate": ms_ag, "solve": ms_solve},
+        "pool_fills": reps[0]["n_batches"], "walk_steps": steps,
+        "per_graph_fp64_ms": round(ms_single, 3), "batched_speedup_vs_per_graph_fp64": round(ms_single / ms_step, 3),
+        "roofline": {"bound": "hbm", "kernel": "wilson_kernel", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "algorithmic_bytes_per_launch": ab, "launch_ms": round(ms_sample, 4)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(members, reps, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batch(members, reps, budget_s: float):
+    """The oracle on a bounded sample of the batch: two trees of every member (scaled to its
+    tau) and the solve of every eighth member (scaled by eight)."""
+    import oracle
+
+    oracle.build()
+    est, t_used, trees_done = 0.0, 0.0, 0
+    for i, (m, r) in enumerate(zip(members, reps)):
+        g = m["graph"]
+        c = 2 if t_used < budget_s else 1
+        t0 = time.perf_counter()
+        oracle.trees(g.row_ptr, g.col, r["pivot"], m["seed"], 0, c, want_parents=False)
+        dt = time.perf_counter() - t0
+        t_used += dt
+        trees_done += c
+        est += dt / c * r["tau"]
+        if i % 8 == 0:
+            t0 = time.perf_counter()
+            oracle.solve(g.row_ptr, g.col, r["pivot"], tol=1e-12)
+            dt = time.perf_counter() - t0
+            t_used += dt
+            est += 8 * dt
+    tau = sum(r["tau"] for r in reps)
+    return {"value": tau / est, "unit": "trees/s", "cores": 1, "kind": "oracle",
+            "sample": "%d trees over the 64 members (each scaled to its tau) + the FP64 solves of 8 members "
+                      "(each scaled by 8), %.1f s of single-threaded C; value = total tau / estimated time"
+                      % (trees_done, t_used)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +238,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (trees would shard by range "
               "across GPUs with one all-reduce of the integer counts; see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if WORKLOADS[args.workload]["kind"] == "batch":
+        run_batch(args)
+        return
 
     import numpy as np
     import torch

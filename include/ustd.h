@@ -70,7 +70,7 @@ typedef struct ustd_problem {
     int32_t solve_maxit;      /* iteration cap of the solve; <= 0 selects 20000 */
     int32_t validate;         /* 1 = validate the CSR on the device first */
     int32_t trees_per_batch;  /* trees resident in the workspace at once; <= 0 = automatic */
-    int32_t reserved;
+    int32_t tau_cap;          /* > 0: tau = min(formula, tau_cap) (ignored with tau_override) */
 } ustd_problem;
 
 /* Filled by the calls that take it (nullable); times from HIP events on `stream`. */
@@ -139,6 +139,25 @@ int ustd_solve_pivot_column(const ustd_problem *prob, void *d_ws, size_t ws_byte
  * accumulated).  Synchronises `stream`. */
 int ustd_diag_lpinv(const ustd_problem *prob, void *d_ws, size_t ws_bytes, double *d_diag,
                     int64_t *d_counts, ustd_report *rep, void *stream);
+
+/* Workspace size for ustd_batch_diag_lpinv over probs[0 .. count-1] (host only). */
+int ustd_batch_workspace_bytes(const ustd_problem *probs, int32_t count, size_t *bytes);
+
+/* ApproxDiagLpinv (Algorithm 1) for `count` independent problems (different graphs,
+ * pivots, seeds, tau_cap ...) in one call.  d_diags: host array of `count` device
+ * pointers, d_diags[i] double[n_i].  d_counts: nullable host array of nullable device
+ * pointers (int64[n_i], overwritten with R of problem i).  reps: nullable, `count`
+ * entries; ms_sample, ms_aggregate and ms_total there are those of the whole batch
+ * (members share launches), the other fields are per member.  Each member's trees,
+ * counts and diagonal are bit-identical to those of ustd_diag_lpinv on that problem alone.
+ * The members' trees share one pool of records in the workspace and are sampled by
+ * persistent launches that take (member, tree) tiles, larger graphs first.
+ * A member's trees_per_batch (> 0) bounds its trees per pool fill.  A member error returns its code with "problem i: ..." in
+ * ustd_last_error(); USTD_ENOTCONV of a member solve is returned after all members are
+ * written.  Synchronises `stream`. */
+int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, size_t ws_bytes,
+                          double *const *d_diags, int64_t *const *d_counts, ustd_report *reps,
+                          void *stream);
 
 /* Test hook for the walk generator: d_out[i] = word ((k0+i) mod 4) of Philox4x32-10 with
  * key (seed lo, seed hi) and counter ((k0+i)/4, s, t lo, t hi), i < count; uint32[count]. */

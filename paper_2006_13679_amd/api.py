@@ -36,7 +36,7 @@ class Problem(ctypes.Structure):
         ("eps", ctypes.c_double), ("delta", ctypes.c_double), ("kappa", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("tau_override", ctypes.c_int64),
         ("solve_tol", ctypes.c_double), ("solve_maxit", ctypes.c_int32),
-        ("validate", ctypes.c_int32), ("trees_per_batch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("validate", ctypes.c_int32), ("trees_per_batch", ctypes.c_int32), ("tau_cap", ctypes.c_int32),
     ]
 
 
@@ -56,8 +56,8 @@ class Report(ctypes.Structure):
 
 
 EXPORTS = ["ustd_workspace_bytes", "ustd_bfs", "ustd_sample_trees", "ustd_flow_counts", "ustd_tree_counts",
-           "ustd_solve_pivot_column", "ustd_diag_lpinv", "ustd_philox_words", "ustd_status_string",
-           "ustd_last_error"]
+           "ustd_solve_pivot_column", "ustd_diag_lpinv", "ustd_batch_workspace_bytes", "ustd_batch_diag_lpinv",
+           "ustd_philox_words", "ustd_status_string", "ustd_last_error"]
 
 _lib = None
 
@@ -78,6 +78,8 @@ def lib() -> ctypes.CDLL:
         L.ustd_tree_counts.argtypes = [PP, P, i64, P, ctypes.c_size_t, P, P]
         L.ustd_solve_pivot_column.argtypes = [PP, P, ctypes.c_size_t, P, PR, P]
         L.ustd_diag_lpinv.argtypes = [PP, P, ctypes.c_size_t, P, P, PR, P]
+        L.ustd_batch_workspace_bytes.argtypes = [PP, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.ustd_batch_diag_lpinv.argtypes = [PP, i32, P, ctypes.c_size_t, P, P, PR, P]
         L.ustd_philox_words.argtypes = [u64, i64, i32, i64, i64, P, P]
         for name in EXPORTS[:-2]:
             getattr(L, name).restype = ctypes.c_int
@@ -126,13 +128,13 @@ class Graph:
 
 def problem(g: Graph, pivot: int = -1, eps: float = 0.3, seed: int = 1, delta: float = 0.0, kappa: float = 0.0,
             tau_override: int = 0, solve_mode: int = SOLVE_FP64, solve_tol: float = 0.0, solve_maxit: int = 0,
-            validate: bool = False, trees_per_batch: int = 0) -> Problem:
+            validate: bool = False, trees_per_batch: int = 0, tau_cap: int = 0) -> Problem:
     assert g.row_ptr.dtype == torch.int64 and g.col.dtype == torch.int32
     assert g.row_ptr.is_cuda and g.col.is_cuda and g.row_ptr.is_contiguous() and g.col.is_contiguous()
     return Problem(n=g.n, nnz=g.nnz, d_row_ptr=g.row_ptr.data_ptr(), d_col=g.col.data_ptr(), pivot=pivot,
                    solve_mode=solve_mode, eps=eps, delta=delta, kappa=kappa, seed=seed & 0xFFFFFFFFFFFFFFFF,
                    tau_override=tau_override, solve_tol=solve_tol, solve_maxit=solve_maxit,
-                   validate=1 if validate else 0, trees_per_batch=trees_per_batch, reserved=0)
+                   validate=1 if validate else 0, trees_per_batch=trees_per_batch, tau_cap=tau_cap)
 
 
 def workspace_bytes(p: Problem) -> int:
@@ -243,6 +245,29 @@ def diag_lpinv(row_ptr, col, pivot: int = -1, eps: float = 0.3, seed: int = 1, *
     g = Graph.from_host(row_ptr, col)
     p = problem(g, pivot=pivot, eps=eps, seed=seed, **kw)
     return diag_lpinv_p(g, p)
+
+
+def batch_diag_lpinv(graphs: list, probs: list, ws: Workspace | None = None, want_counts: bool = True,
+                     allow_notconv: bool = False):
+    """ApproxDiagLpinv for several prepared problems in one call (ustd_batch_diag_lpinv).
+    Returns (list of diag float64[n_i], list of counts int64[n_i] or None, list of reports)."""
+    count = len(probs)
+    assert count == len(graphs) and count > 0
+    dev = graphs[0].row_ptr.device
+    arr = (Problem * count)(*probs)
+    b = ctypes.c_size_t(0)
+    _check(lib().ustd_batch_workspace_bytes(arr, count, ctypes.byref(b)))
+    if ws is None:
+        ws = _default_ws.setdefault(dev, Workspace(dev))
+    buf = ws.get(int(b.value))
+    diags = [torch.empty(g.n, dtype=torch.float64, device=dev) for g in graphs]
+    counts = [torch.empty(g.n, dtype=torch.int64, device=dev) for g in graphs] if want_counts else None
+    dptr = (ctypes.c_void_p * count)(*[d.data_ptr() for d in diags])
+    cptr = (ctypes.c_void_p * count)(*[c.data_ptr() for c in counts]) if want_counts else None
+    reps = (Report * count)()
+    rc = lib().ustd_batch_diag_lpinv(arr, count, _ptr(buf), buf.numel(), dptr, cptr, reps, _stream(dev))
+    _check(rc, (OK, ENOTCONV) if allow_notconv else (OK,))
+    return diags, counts, [r.as_dict() for r in reps]
 
 
 def philox_words(seed: int, t: int, s: int, k0: int, count: int, device="cuda") -> torch.Tensor:

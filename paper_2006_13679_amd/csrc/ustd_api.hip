@@ -45,7 +45,7 @@ int fail(int code, const char *fmt, ...) {
 
 constexpr long long kAlign = 256;
 constexpr int kLdsBitsMaxWords = 4096;      // tree bitmap in LDS up to 131072 vertices (16 KB)
-constexpr long long kDefaultBudget = 24ll << 30;
+constexpr long long kDefaultBudget = 64ll << 30;  // tree records + sampler scratch, of 288 GB HBM
 constexpr int kMaxTreesPerBatch = 8192;
 
 inline long long align_up(long long v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -55,6 +55,8 @@ struct Misc {                      // small zero-initialised block at the front 
     int bfs_found;
     int err_interval;
     int nheavy;
+    int queue;                     // sampler tile counter
+    int pad_;
     unsigned long long best_degree;
     CgScalars sc64, sc32;
     double rr_hist64[kRrHist];
@@ -64,9 +66,9 @@ struct Misc {                      // small zero-initialised block at the front 
 };
 
 struct Plan {
-    int n, nnz, K, Kiv, rob, nwords, G, heavy_thresh;
+    int n, nnz, K, Kiv, slots, rob, nwords, G, heavy_thresh;
     bool lds_bits, col16;
-    long long rec_stride, scr_stride;
+    long long rec_stride, scr_stride, bits_stride;
     long long off_misc, off_rp32, off_col16, off_dist, off_parB, off_bnode, off_bflag, off_heavy, off_bcount, off_counts, off_steps,
         off_draws, off_rec, off_path, off_bits, off_scr, off_part, off_x64, off_r64, off_z64, off_p64, off_q64,
         off_res64, off_x32, off_r32, off_z32, off_p32, off_q32;
@@ -95,7 +97,9 @@ int check_problem(const ustd_problem *p) {
     return USTD_OK;
 }
 
-Plan make_plan(const ustd_problem *p) {
+// Workspace layout of one problem.  Without trees (a batch member's own region) the tree
+// records and sampler slots are left out: a batch keeps them in a shared pool.
+Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     Plan L{};
     L.n = (int)p->n;
     L.nnz = (int)p->nnz;
@@ -106,15 +110,19 @@ Plan make_plan(const ustd_problem *p) {
     const double avg = (double)L.nnz / (double)L.n;
     L.G = avg <= 6.0 ? 4 : (avg <= 16.0 ? 8 : (avg <= 48.0 ? 16 : 32));
     L.heavy_thresh = 32 * L.G;
-    L.rec_stride = align_up((long long)L.n * 16) / 16;
+    L.rec_stride = align_up((long long)L.n * 8) / 8;  // int2 records
     L.scr_stride = align_up(interval_scratch_ints(L.n) * 4) / 4;
-    const long long per_tree = L.rec_stride * 16 + align_up((long long)L.rob * kSamplerPathGlobal * 8) +
-                               (L.lds_bits ? 0 : align_up((long long)L.nwords * 4)) + 16;
-    long long K = p->trees_per_batch > 0 ? p->trees_per_batch : std::max(1ll, kDefaultBudget / per_tree);
+    L.bits_stride = L.lds_bits ? 0 : align_up((long long)L.nwords * 4) / 4;
+    // trees resident at once (records), and sampler blocks resident at once (scratch slots)
+    const long long per_tree = L.rec_stride * 8 + 16;
+    const long long per_slot = kSamplerPathSlot * 8 + L.bits_stride * 4;
+    long long K = p->trees_per_batch > 0 ? p->trees_per_batch : std::max(1ll, kDefaultBudget / (per_tree + per_slot));
     K = std::min<long long>(K, kMaxTreesPerBatch);
     if (p->tau_override > 0) K = std::min<long long>(K, p->tau_override);
-    L.K = (int)std::max(1ll, K);
+    if (p->tau_cap > 0) K = std::min<long long>(K, p->tau_cap);
+    L.K = with_trees ? (int)std::max(1ll, K) : 0;
     L.Kiv = std::min(L.K, 16);
+    L.slots = std::min(L.K, kSamplerMaxBlocks);
     long long o = 0;
     auto take = [&](long long bytes) {
         long long at = o;
@@ -134,9 +142,9 @@ Plan make_plan(const ustd_problem *p) {
     L.off_counts = take(n * 8);
     L.off_steps = take((long long)L.K * 8);
     L.off_draws = take((long long)L.K * 8);
-    L.off_rec = take((long long)L.K * L.rec_stride * 16);
-    L.off_path = take((long long)L.K * L.rob * kSamplerPathGlobal * 8);
-    L.off_bits = take(L.lds_bits ? 0 : (long long)L.K * L.nwords * 4);
+    L.off_rec = take((long long)L.K * L.rec_stride * 8);
+    L.off_path = take((long long)L.slots * kSamplerPathSlot * 8);
+    L.off_bits = take((long long)L.slots * L.bits_stride * 4);
     L.off_scr = take(std::max((long long)L.Kiv * L.scr_stride, 3 * n) * 4);
     L.off_part = take((long long)kMaxSolveGrid * 6 * 8);
     L.off_x64 = take(n * 8);
@@ -159,7 +167,8 @@ T *at(void *ws, long long off) {
     return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
 }
 
-// tau = ecc^2 * ceil( ln(2m/delta) / (2 (1-kappa)^2 eps^2) ) (Algorithm 1, initialisation)
+// tau = ecc^2 * ceil( ln(2m/delta) / (2 (1-kappa)^2 eps^2) ) (Algorithm 1, initialisation),
+// then at most tau_cap when one is set; tau_override replaces the formula
 long long sample_size(const ustd_problem *p, int ecc) {
     if (p->tau_override > 0) return p->tau_override;
     const double n = (double)p->n, m = (double)(p->nnz / 2);
@@ -167,7 +176,8 @@ long long sample_size(const ustd_problem *p, int ecc) {
     const double kappa = p->kappa > 0.0 ? p->kappa : 0.3;
     const double om = 1.0 - kappa;
     const double q = std::log(2.0 * m / delta) / (2.0 * om * om * p->eps * p->eps);
-    return (long long)ecc * (long long)ecc * (long long)std::ceil(q);
+    const long long tau = (long long)ecc * (long long)ecc * (long long)std::ceil(q);
+    return p->tau_cap > 0 ? std::min<long long>(tau, p->tau_cap) : tau;
 }
 
 // eta = kappa eps / (3 sqrt(m n ln n) diam), diam <= 2 ecc (Algorithm 1, solver accuracy)
@@ -209,14 +219,18 @@ struct Ctx {
     int pivot = -1, ecc = 0;
 };
 
-int begin(Ctx &c, const ustd_problem *p, void *ws, size_t ws_bytes, void *stream) {
-    USTD_TRY(check_problem(p));
-    c.p = p;
-    c.L = make_plan(p);
+int check_ws(void *ws, size_t ws_bytes, long long need) {
     if (!ws) return fail(USTD_EINVAL, "workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return fail(USTD_EINVAL, "workspace must be 256-byte aligned");
-    if ((long long)ws_bytes < c.L.total)
-        return fail(USTD_ENOMEM, "workspace %zu bytes < required %lld", ws_bytes, c.L.total);
+    if ((long long)ws_bytes < need) return fail(USTD_ENOMEM, "workspace %zu bytes < required %lld", ws_bytes, need);
+    return USTD_OK;
+}
+
+// per-problem preparation on the stream: 32-bit row pointers, the 16-bit column copy and
+// the list of heavy rows, in the workspace region `ws` laid out by `L`
+int begin_with(Ctx &c, const ustd_problem *p, const Plan &L, void *ws, void *stream) {
+    c.p = p;
+    c.L = L;
     c.ws = ws;
     c.st = (hipStream_t)stream;
     c.misc = at<Misc>(ws, c.L.off_misc);
@@ -233,6 +247,13 @@ int begin(Ctx &c, const ustd_problem *p, void *ws, size_t ws_bytes, void *stream
     HIP_TRY(launch_heavy_list(c.L.n, c.rp32, c.L.heavy_thresh, at<int>(ws, c.L.off_bcount), at<int>(ws, c.L.off_heavy),
                               &c.misc->nheavy, c.st));
     return USTD_OK;
+}
+
+int begin(Ctx &c, const ustd_problem *p, void *ws, size_t ws_bytes, void *stream) {
+    USTD_TRY(check_problem(p));
+    const Plan L = make_plan(p);
+    USTD_TRY(check_ws(ws, ws_bytes, L.total));
+    return begin_with(c, p, L, ws, stream);
 }
 
 // pivot choice, optional validation and the BFS tree B_u; synchronises the stream
@@ -285,25 +306,40 @@ int setup(Ctx &c, ustd_report *rep) {
     return USTD_OK;
 }
 
-WilsonArgs wilson_args(const Ctx &c, long long tree_begin, long long *steps, long long *draws) {
+WilsonGraph wilson_graph(const Ctx &c) {
+    WilsonGraph g{};
+    g.n = c.L.n;
+    g.u = c.pivot;
+    g.nwords = c.L.nwords;
+    g.rob = c.L.rob;
+    g.rp = c.rp32;
+    g.colv = c.L.col16 ? (const void *)at<unsigned short>(c.ws, c.L.off_col16) : (const void *)c.p->d_col;
+    g.bflag = at<int>(c.ws, c.L.off_bflag);
+    g.key0 = (uint32_t)(c.p->seed & 0xFFFFFFFFull);
+    g.key1 = (uint32_t)(c.p->seed >> 32);
+    return g;
+}
+
+// trees tree_begin .. +ntrees-1 into the record slots 0 .. ntrees-1 (ntrees <= K)
+int sample_batch(Ctx &c, long long tree_begin, int ntrees, long long *steps, long long *draws) {
     WilsonArgs a{};
-    a.n = c.L.n;
-    a.u = c.pivot;
-    a.nwords = c.L.nwords;
-    a.rob = c.L.rob;
-    a.rp = c.rp32;
-    a.colv = c.L.col16 ? (const void *)at<unsigned short>(c.ws, c.L.off_col16) : (const void *)c.p->d_col;
-    a.key0 = (uint32_t)(c.p->seed & 0xFFFFFFFFull);
-    a.key1 = (uint32_t)(c.p->seed >> 32);
+    a.g = wilson_graph(c);
+    a.ntiles = ntrees;
     a.tree_begin = tree_begin;
-    a.rec = at<int4>(c.ws, c.L.off_rec);
+    a.rec = at<int2>(c.ws, c.L.off_rec);
     a.rec_stride = c.L.rec_stride;
-    a.bflag = at<int>(c.ws, c.L.off_bflag);
     a.path = at<int2>(c.ws, c.L.off_path);
     a.bits = at<uint32_t>(c.ws, c.L.off_bits);
+    a.bits_stride = c.L.bits_stride;
+    a.queue = &c.misc->queue;
     a.steps = steps;
     a.draws = draws;
-    return a;
+    int blocks = std::min(ntrees, c.L.slots);
+    const int resident = wilson_resident_blocks(c.L.lds_bits, c.L.col16, c.L.nwords);
+    if (resident > 0) blocks = std::min(blocks, resident);
+    HIP_TRY(hipMemsetAsync(&c.misc->queue, 0, sizeof(int), c.st));
+    HIP_TRY(launch_wilson(a, blocks, c.L.lds_bits, c.L.col16, c.L.nwords, c.st));
+    return USTD_OK;
 }
 
 // Algorithm 2 over `cnt` resident trees (records in the workspace)
@@ -314,7 +350,7 @@ int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag) {
     aa.ntrees = cnt;
     aa.trees_per_chunk = 32;
     aa.bnode = at<int4>(c.ws, c.L.off_bnode);
-    aa.rec = at<int4>(c.ws, c.L.off_rec);
+    aa.rec = at<int2>(c.ws, c.L.off_rec);
     aa.rec_stride = c.L.rec_stride;
     aa.counts = counts;
     Timer tm(c.st);
@@ -330,12 +366,14 @@ int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *cou
     long long *steps = at<long long>(c.ws, c.L.off_steps);
     long long *draws = at<long long>(c.ws, c.L.off_draws);
     double ms_s = 0, ms_a = 0;
-    for (long long b0 = 0; b0 < tree_count; b0 += c.L.K) {
-        const int cnt = (int)std::min<long long>(c.L.K, tree_count - b0);
-        WilsonArgs wa = wilson_args(c, tree_begin + b0, steps, draws);
+    // equal batches: ceil(count / K) of them, none larger than K
+    const long long nb = (tree_count + c.L.K - 1) / c.L.K;
+    const long long per = nb > 0 ? (tree_count + nb - 1) / nb : 0;
+    for (long long b0 = 0; b0 < tree_count; b0 += per) {
+        const int cnt = (int)std::min<long long>(per, tree_count - b0);
         {
             Timer tm(c.st);
-            HIP_TRY(launch_wilson(wa, cnt, c.L.lds_bits, c.L.col16, c.st));
+            USTD_TRY(sample_batch(c, tree_begin + b0, cnt, steps, draws));
             ms_s += tm.stop_ms();
         }
         USTD_TRY(aggregate_trees(c, cnt, counts, &ms_a));
@@ -473,6 +511,83 @@ int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
     return USTD_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// batches of problems: every member keeps its own region (CSR copies, B_u, counts, solve
+// vectors); the trees of all members share one pool of records and sampler slots, filled
+// with (graph, tree) tiles, larger graphs first, and sampled by one persistent launch per
+// pool fill.
+// ---------------------------------------------------------------------------------------
+constexpr long long kMaxBatchTiles = 1ll << 20;
+
+struct BatchPlan {
+    std::vector<Plan> g;
+    std::vector<long long> base;  // byte offset of each member's region
+    bool lds_bits = true, col16 = true;
+    int nwords_max = 0, slots = 0;
+    long long bits_stride = 0, rec_pool = 0, max_tiles = 0;
+    long long off_queue = 0, off_rec = 0, off_path = 0, off_bits = 0, off_steps = 0, off_draws = 0, off_tiles = 0,
+              off_graphs = 0, total = 0;
+};
+
+int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
+    if (!probs || count <= 0) return fail(USTD_EINVAL, "empty batch");
+    long long o = 0, want_rec = 0, min_rec = 0, want_tiles = 0;
+    bool bounded = true;
+    for (int i = 0; i < count; ++i) {
+        const int rc = check_problem(&probs[i]);
+        if (rc != USTD_OK) {
+            const std::string m = g_err;
+            return fail(rc, "problem %d: %s", i, m.c_str());
+        }
+        const Plan L = make_plan(&probs[i], false);
+        B.g.push_back(L);
+        B.base.push_back(o);
+        o += align_up(L.total);
+        B.lds_bits = B.lds_bits && L.lds_bits;
+        B.col16 = B.col16 && L.col16;
+        B.nwords_max = std::max(B.nwords_max, L.nwords);
+        const long long rb = L.rec_stride * 8;
+        min_rec = std::max(min_rec, rb);
+        long long cap = probs[i].tau_override > 0 ? probs[i].tau_override : probs[i].tau_cap;
+        if (probs[i].trees_per_batch > 0) cap = cap > 0 ? std::min<long long>(cap, probs[i].trees_per_batch)
+                                                        : probs[i].trees_per_batch;
+        if (cap > 0) {
+            want_rec += cap * rb;
+            want_tiles += cap;
+        } else {
+            bounded = false;
+        }
+    }
+    B.bits_stride = B.lds_bits ? 0 : align_up((long long)B.nwords_max * 4) / 4;
+    B.max_tiles = std::max(1ll, std::min(bounded ? want_tiles : kMaxBatchTiles, kMaxBatchTiles));
+    B.slots = (int)std::min<long long>(kSamplerMaxBlocks, B.max_tiles);
+    const long long slot_bytes = (long long)B.slots * (kSamplerPathSlot * 8 + B.bits_stride * 4);
+    long long pool = std::max(kDefaultBudget - slot_bytes, min_rec);
+    if (bounded) pool = std::min(pool, std::max(want_rec, min_rec));
+    B.rec_pool = align_up(pool);
+    auto take = [&](long long bytes) {
+        const long long at = o;
+        o += align_up(bytes);
+        return at;
+    };
+    B.off_queue = take(sizeof(int));
+    B.off_rec = take(B.rec_pool);
+    B.off_path = take((long long)B.slots * kSamplerPathSlot * 8);
+    B.off_bits = take((long long)B.slots * B.bits_stride * 4);
+    B.off_steps = take(B.max_tiles * 8);
+    B.off_draws = take(B.max_tiles * 8);
+    B.off_tiles = take(B.max_tiles * (long long)sizeof(WilsonTile));
+    B.off_graphs = take((long long)count * (long long)sizeof(WilsonGraph));
+    B.total = o;
+    return USTD_OK;
+}
+
+int member(int i, int rc) {
+    if (rc == USTD_OK) return rc;
+    const std::string m = g_err;
+    return fail(rc, "problem %d: %s", i, m.c_str());
+}
+
 }  // namespace
 
 // =========================================================================================
@@ -514,9 +629,8 @@ int ustd_sample_trees(const ustd_problem *prob, int64_t tree_begin, int64_t tree
     USTD_TRY(setup(c, nullptr));
     if (tree_count == 0) return USTD_OK;
     long long *steps = d_steps ? (long long *)d_steps : at<long long>(c.ws, c.L.off_steps);
-    WilsonArgs wa = wilson_args(c, tree_begin, steps, at<long long>(c.ws, c.L.off_draws));
-    HIP_TRY(launch_wilson(wa, (int)tree_count, c.L.lds_bits, c.L.col16, c.st));
-    HIP_TRY(launch_extract_parents(c.L.n, (int)tree_count, at<int4>(c.ws, c.L.off_rec), c.L.rec_stride, d_parents, c.st));
+    USTD_TRY(sample_batch(c, tree_begin, (int)tree_count, steps, at<long long>(c.ws, c.L.off_draws)));
+    HIP_TRY(launch_extract_parents(c.L.n, (int)tree_count, at<int2>(c.ws, c.L.off_rec), c.L.rec_stride, d_parents, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
     return USTD_OK;
 }
@@ -556,7 +670,7 @@ int ustd_tree_counts(const ustd_problem *prob, const int32_t *d_parents, int64_t
         ia.par_stride = c.L.n;
         ia.scratch = at<int>(c.ws, c.L.off_scr);
         ia.scratch_stride = c.L.scr_stride;
-        ia.rec = at<int4>(c.ws, c.L.off_rec);
+        ia.rec = at<int2>(c.ws, c.L.off_rec);
         ia.rec_stride = c.L.rec_stride;
         ia.bflag = at<int>(c.ws, c.L.off_bflag);
         ia.err = &c.misc->err_interval;
@@ -608,6 +722,157 @@ int ustd_diag_lpinv(const ustd_problem *prob, void *d_ws, size_t ws_bytes, doubl
     }
     r->ms_total = total.stop_ms();
     return src;
+}
+
+int ustd_batch_workspace_bytes(const ustd_problem *probs, int32_t count, size_t *bytes) {
+    g_err.clear();
+    if (!bytes) return fail(USTD_EINVAL, "bytes is NULL");
+    BatchPlan B;
+    USTD_TRY(make_batch_plan(probs, count, B));
+    *bytes = (size_t)B.total;
+    return USTD_OK;
+}
+
+int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, size_t ws_bytes,
+                          double *const *d_diags, int64_t *const *d_counts, ustd_report *reps, void *stream) {
+    g_err.clear();
+    BatchPlan B;
+    USTD_TRY(make_batch_plan(probs, count, B));
+    USTD_TRY(check_ws(d_ws, ws_bytes, B.total));
+    if (!d_diags) return fail(USTD_EINVAL, "d_diags is NULL");
+    for (int i = 0; i < count; ++i)
+        if (!d_diags[i]) return fail(USTD_EINVAL, "d_diags[%d] is NULL", i);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<ustd_report> local(count);
+    ustd_report *R = reps ? reps : local.data();
+    memset(R, 0, sizeof(ustd_report) * (size_t)count);
+    Timer total(st);
+
+    // per member: preparation, BFS tree B_u, tau, zeroed counts
+    std::vector<Ctx> cs(count);
+    std::vector<long long> tau(count), next(count, 0);
+    std::vector<long long *> counts(count);
+    std::vector<WilsonGraph> gt(count);
+    for (int i = 0; i < count; ++i) {
+        void *wsi = static_cast<char *>(d_ws) + B.base[i];
+        USTD_TRY(member(i, begin_with(cs[i], &probs[i], B.g[i], wsi, stream)));
+        USTD_TRY(member(i, setup(cs[i], &R[i])));
+        tau[i] = sample_size(&probs[i], cs[i].ecc);
+        R[i].tau = tau[i];
+        counts[i] = (d_counts && d_counts[i]) ? (long long *)d_counts[i] : at<long long>(wsi, B.g[i].off_counts);
+        HIP_TRY(hipMemsetAsync(counts[i], 0, (size_t)B.g[i].n * 8, st));
+        gt[i] = wilson_graph(cs[i]);
+        gt[i].colv = B.col16 ? (const void *)at<unsigned short>(wsi, B.g[i].off_col16) : (const void *)probs[i].d_col;
+    }
+    WilsonGraph *d_graphs = at<WilsonGraph>(d_ws, B.off_graphs);
+    WilsonTile *d_tiles = at<WilsonTile>(d_ws, B.off_tiles);
+    int2 *pool = at<int2>(d_ws, B.off_rec);
+    long long *steps = at<long long>(d_ws, B.off_steps), *draws = at<long long>(d_ws, B.off_draws);
+    int *queue = at<int>(d_ws, B.off_queue);
+    HIP_TRY(hipMemcpyAsync(d_graphs, gt.data(), sizeof(WilsonGraph) * (size_t)count, hipMemcpyHostToDevice, st));
+
+    // tiles: members by decreasing size (longest trees start first), each member's trees in order
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B.g[a].n > B.g[b].n; });
+    struct Seg {
+        int graph;
+        long long ntrees, rec_off;
+    };
+    std::vector<WilsonTile> tiles;
+    std::vector<Seg> segs;
+    std::vector<long long> hs, hd;
+    double ms_s = 0, ms_a = 0;
+    int fills = 0;
+    long long largest = 0;
+    const int resident = wilson_resident_blocks(B.lds_bits, B.col16, B.nwords_max);
+    for (;;) {
+        tiles.clear();
+        segs.clear();
+        long long used = 0;  // bytes of the record pool
+        for (int gi : order) {
+            const long long left = tau[gi] - next[gi];
+            if (left <= 0) continue;
+            const long long rb = B.g[gi].rec_stride * 8;
+            const long long fit = std::min((B.rec_pool - used) / rb, B.max_tiles - (long long)tiles.size());
+            const long long lim = probs[gi].trees_per_batch > 0 ? probs[gi].trees_per_batch : left;
+            const long long take = std::min(std::min(left, fit), lim);
+            if (take <= 0) break;
+            segs.push_back(Seg{gi, take, used / 8});
+            for (long long j = 0; j < take; ++j)
+                tiles.push_back(WilsonTile{next[gi] + j, used / 8 + j * B.g[gi].rec_stride, gi, 0});
+            used += take * rb;
+            next[gi] += take;
+        }
+        if (tiles.empty()) break;
+        const int nt = (int)tiles.size();
+        largest = std::max<long long>(largest, nt);
+        HIP_TRY(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(WilsonTile) * tiles.size(), hipMemcpyHostToDevice, st));
+        WilsonArgs a{};
+        a.graphs = d_graphs;
+        a.tiles = d_tiles;
+        a.ntiles = nt;
+        a.rec = pool;
+        a.path = at<int2>(d_ws, B.off_path);
+        a.bits = at<uint32_t>(d_ws, B.off_bits);
+        a.bits_stride = B.bits_stride;
+        a.queue = queue;
+        a.steps = steps;
+        a.draws = draws;
+        int blocks = std::min(nt, B.slots);
+        if (resident > 0) blocks = std::min(blocks, resident);
+        {
+            Timer tm(st);
+            HIP_TRY(hipMemsetAsync(queue, 0, sizeof(int), st));
+            HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, B.nwords_max, st));
+            ms_s += tm.stop_ms();
+        }
+        {
+            Timer tm(st);
+            for (const Seg &sg : segs) {
+                AggregateArgs aa{};
+                aa.n = B.g[sg.graph].n;
+                aa.u = cs[sg.graph].pivot;
+                aa.ntrees = (int)sg.ntrees;
+                aa.trees_per_chunk = 32;
+                aa.bnode = at<int4>(cs[sg.graph].ws, B.g[sg.graph].off_bnode);
+                aa.rec = pool + sg.rec_off;
+                aa.rec_stride = B.g[sg.graph].rec_stride;
+                aa.counts = counts[sg.graph];
+                HIP_TRY(launch_aggregate(aa, st));
+            }
+            ms_a += tm.stop_ms();
+        }
+        hs.resize(nt);
+        hd.resize(nt);
+        HIP_TRY(hipMemcpyAsync(hs.data(), steps, sizeof(long long) * (size_t)nt, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hd.data(), draws, sizeof(long long) * (size_t)nt, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int j = 0; j < nt; ++j) {
+            R[tiles[j].graph].walk_steps += hs[j];
+            R[tiles[j].graph].walk_draws += hd[j];
+        }
+        ++fills;
+    }
+
+    // per member: pivot-column solve and combination
+    int status = USTD_OK;
+    for (int i = 0; i < count; ++i) {
+        R[i].n_batches = fills;
+        R[i].trees_per_batch = (int32_t)largest;
+        R[i].ms_sample = ms_s;
+        R[i].ms_aggregate = ms_a;
+        double *x = at<double>(cs[i].ws, B.g[i].off_x64);
+        const int src = solve_column(cs[i], x, &R[i]);
+        if (src != USTD_OK && src != USTD_ENOTCONV) return member(i, src);
+        if (src == USTD_ENOTCONV) status = member(i, src);
+        Timer tm(st);
+        HIP_TRY(launch_combine(B.g[i].n, cs[i].pivot, tau[i], counts[i], x, d_diags[i], st));
+        R[i].ms_combine += tm.stop_ms();
+    }
+    const double ms = total.stop_ms();
+    for (int i = 0; i < count; ++i) R[i].ms_total = ms;
+    return status;
 }
 
 int ustd_philox_words(uint64_t seed, int64_t t, int32_t s, int64_t k0, int64_t count, uint32_t *d_out, void *stream) {

@@ -194,7 +194,8 @@ __global__ void count_unreached_kernel(int n, const int *__restrict__ dist, int 
 // every recorded vertex, the chain value of the vertex a walk ends on), so the in-order
 // commit path does no dependent global loads in the common cases.
 //
-// Output per vertex x: rec[x] = {parent_T(x), nba(x), cv(x), 0} (see "Marked vertices").
+// Output per vertex x: rec[x] = {parent_T(x), nba(x) | marked(x) << 31} (see "Marked
+// vertices").  Launches are persistent: each block takes tree after tree from a queue.
 // ======================================================================================
 namespace {
 
@@ -222,8 +223,8 @@ struct TreeBits {
 // when parB(parent_T(x)) = x and parent_T(x) is on P(v) too (traversed backward).  A
 // strict T-ancestor of v on P(v) has a child in B_u, so only vertices that are internal in
 // B_u and whose tree edge is a B_u edge ("marked") can contribute.  Each vertex x stores
-// nba(x) = nearest marked strict T-ancestor (u if none) and cv(x) = x if x is marked,
-// else nba(x) (the nba value of x's children).  Algorithm 2 then follows the nba chain and
+// nba(x) = nearest marked strict T-ancestor (u if none) and its mark bit; cv(x) = x if x is
+// marked, else nba(x), is the nba value of x's children.  Algorithm 2 then follows the nba chain and
 // decides "on P(v)" with the fixed subtree intervals of B_u.
 //
 // bflag[x] = (parB(x) + 1) | (1 << 31 if x is internal in B_u), so parB(u) = -1.
@@ -232,6 +233,10 @@ __device__ __forceinline__ bool bf_internal(int f) { return (unsigned)f >> 31; }
 __device__ __forceinline__ bool marked_f(int x, int fx, int px, int fpx) {
     return bf_internal(fx) && (px == bf_parent(fx) || bf_parent(fpx) == x);
 }
+// A record is {parent_T(x), nba(x) | marked(x) << 31}; cv(x) follows from it.
+constexpr int kMarkBit = (int)0x80000000u;
+__device__ __forceinline__ int cv_of(int x, int nbx) { return nbx < 0 ? x : nbx; }
+__device__ __forceinline__ int nba_of(int nbx) { return nbx & 0x7FFFFFFF; }
 
 // The sampler's block is one wavefront.  Its LDS operations execute in issue order, so
 // lanes exchange data through LDS with compiler ordering only; a workgroup barrier would
@@ -268,7 +273,7 @@ __device__ __forceinline__ int hash_slot(int v) { return (int)(((unsigned)v * 26
 
 // The sequential algorithm for one start s0 against the current tree: walk with Next
 // pointers (in the parent field), retrace the loop erasure, and write the branch's records
-// {parent, nba, cv}.  One lane; returns the walk's step count.
+// {parent, nba | marked << 31}.  One lane; returns the walk's step count.
 template <bool LDS, typename CT>
 __device__ long long rewalk_commit(const TreeBits<LDS> &bits, int *recw, const int *__restrict__ rp,
                                    const CT *__restrict__ col, const int *__restrict__ bflag, int s0,
@@ -284,7 +289,7 @@ __device__ long long rewalk_commit(const TreeBits<LDS> &bits, int *recw, const i
         const int y = (int)col[r0 + (int)__umulhi(w, (uint32_t)(r1 - r0))];
         const int ny0 = rp[y], ny1 = rp[y + 1];
         ++k;
-        recw[4 * xw] = y;  // Next pointer; becomes the parent when xw joins T
+        recw[2 * xw] = y;  // Next pointer; becomes the parent when xw joins T
         if (bits.test(y)) break;
         xw = y;
         r0 = ny0;
@@ -294,25 +299,25 @@ __device__ long long rewalk_commit(const TreeBits<LDS> &bits, int *recw, const i
     int z = s0;
     while (!bits.test(z)) {
         bits.set(z);
-        z = recw[4 * z];
+        z = recw[2 * z];
     }
     const int ya = z;
-    const int cva = recw[4 * ya + 2];
-    // nba: nearest marked vertex strictly closer to ya; cv: the vertex itself if marked
+    const int cva = cv_of(ya, recw[2 * ya + 1]);
+    // nba: the nearest marked vertex strictly closer to ya on the branch, else cv(ya)
     int run = s0;
     z = s0;
     while (z != ya) {
-        const int nz = recw[4 * z];
+        const int nz = recw[2 * z];
         if (marked_f(z, bflag[z], nz, bflag[nz])) {
-            for (int w2 = run; w2 != z; w2 = recw[4 * w2]) recw[4 * w2 + 1] = z;
+            for (int w2 = run; w2 != z; w2 = recw[2 * w2]) recw[2 * w2 + 1] = z;
             run = z;
         }
         z = nz;
     }
-    for (int w2 = run; w2 != ya; w2 = recw[4 * w2]) recw[4 * w2 + 1] = cva;
-    for (z = s0; z != ya; z = recw[4 * z]) {
-        const int nz = recw[4 * z];
-        recw[4 * z + 2] = marked_f(z, bflag[z], nz, bflag[nz]) ? z : recw[4 * z + 1];
+    for (int w2 = run; w2 != ya; w2 = recw[2 * w2]) recw[2 * w2 + 1] = cva;
+    for (z = s0; z != ya; z = recw[2 * z]) {
+        const int nz = recw[2 * z];
+        if (marked_f(z, bflag[z], nz, bflag[nz])) recw[2 * z + 1] |= kMarkBit;
     }
     return k;
 }
@@ -336,21 +341,41 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     static_assert(2 * (kPath + 1) <= (1 << kHashBits), "branch buffers fit the hash table");
 
     const int lane = threadIdx.x;
-    const int n = a.n;
-    const int rob = a.rob;  // power of two <= kRobMax
-    const int robm = rob - 1;
-    const long long t = a.tree_begin + blockIdx.x;
-    const uint32_t tlo = (uint32_t)(unsigned long long)t, thi = (uint32_t)((unsigned long long)t >> 32);
-    int4 *rec = a.rec + (long long)blockIdx.x * a.rec_stride;
-    int *recw = reinterpret_cast<int *>(rec);  // recw[4x] = parent (Next while walking)
-    const int *__restrict__ bflag = a.bflag;
-    const int u = a.u;
-    int2 *__restrict__ gpath = a.path + (long long)blockIdx.x * ((long long)rob * (kPath - kPathLds));
-    TreeBits<LDS> bits{LDS ? lds_bits : a.bits + (long long)blockIdx.x * a.nwords};
-    const int *__restrict__ rp = a.rp;
-    const CT *__restrict__ col = reinterpret_cast<const CT *>(a.colv);  // int32, or uint16 when n <= 65536
+    int2 *__restrict__ gpath = a.path + (long long)blockIdx.x * kSamplerPathSlot;
+    const TreeBits<LDS> bits{LDS ? lds_bits : a.bits + (long long)blockIdx.x * a.bits_stride};
 
-    for (int i = lane; i < a.nwords; i += kWave) {
+    for (;;) {
+    // ---------------------------------------------------------------- next tile
+    int tile = 0;
+    if (lane == 0) tile = atomicAdd(a.queue, 1);
+    tile = __builtin_amdgcn_readfirstlane(tile);
+    if (tile >= a.ntiles) break;
+    WilsonGraph g;
+    long long t;
+    int2 *rec;
+    if (a.tiles) {
+        const WilsonTile tl = a.tiles[tile];
+        g = a.graphs[tl.graph];
+        t = tl.tree;
+        rec = a.rec + tl.rec_off;
+    } else {
+        g = a.g;
+        t = a.tree_begin + tile;
+        rec = a.rec + (long long)tile * a.rec_stride;
+    }
+    const int n = g.n;
+    const int nwords = g.nwords;
+    const int rob = g.rob;  // power of two <= kRobMax
+    const int robm = rob - 1;
+    const uint32_t tlo = (uint32_t)(unsigned long long)t, thi = (uint32_t)((unsigned long long)t >> 32);
+    int *recw = reinterpret_cast<int *>(rec);  // recw[2x] = parent (Next while walking)
+    const int *__restrict__ bflag = g.bflag;
+    const int u = g.u;
+    const int *__restrict__ rp = g.rp;
+    const CT *__restrict__ col = reinterpret_cast<const CT *>(g.colv);  // int32, or uint16 when n <= 65536
+
+    wait_global();  // the previous tree's bitmap updates have landed
+    for (int i = lane; i < nwords; i += kWave) {
         if (LDS) bits.w[i] = 0u;
         else __hip_atomic_store(bits.w + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -358,7 +383,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     wave_sync();
     if (lane == 0) {
         bits.set(u);
-        rec[u] = make_int4(-1, u, u, 0);
+        rec[u] = make_int2(-1, u);
     }
     wave_sync();
 
@@ -377,10 +402,10 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             const int wbase = cursor >> 5;
             const int wi = wbase + lane;
             uint32_t fb = 0u;
-            if (wi < a.nwords) {
+            if (wi < nwords) {
                 fb = ~bits.word(wi);
                 if (lane == 0) fb &= ~0u << (cursor & 31);
-                if (wi == a.nwords - 1 && (n & 31)) fb &= (1u << (n & 31)) - 1u;
+                if (wi == nwords - 1 && (n & 31)) fb &= (1u << (n & 31)) - 1u;
             }
             const int c = __popc(fb);
             const int incl = wave_scan_dpp(c);
@@ -423,7 +448,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
 
         // ---------------------------------------------------------------- one walk step
         if (mode == 1) {
-            if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s, tlo, thi), a.key0, a.key1);
+            if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s, tlo, thi), g.key0, g.key1);
             const int q = k & 3;
             const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
             const int y = (int)col[r0 + (int)__umulhi(w, (uint32_t)(r1 - r0))];
@@ -433,12 +458,13 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             const int fy = bflag[y];
             int cvy = 0, ny0 = 0, ny1 = 0;
             if (in) {
-                cvy = recw[4 * y + 2];
+                cvy = recw[2 * y + 1];
             } else {
                 ny0 = rp[y];
                 ny1 = rp[y + 1];
             }
             consume(fy, cvy, ny0, ny1);  // no load may stay in flight into the commit phase
+            if (in) cvy = cv_of(y, cvy);
             ++k;
             ++draws;
             const int sl = my_e & robm;
@@ -461,7 +487,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 // start against the current tree (all earlier starts are committed)
                 const int s0 = rob_s[head & robm];
                 if (!bits.test(s0) && lane == 0) {
-                    const long long kk = rewalk_commit(bits, recw, rp, col, bflag, s0, tlo, thi, a.key0, a.key1);
+                    const long long kk = rewalk_commit(bits, recw, rp, col, bflag, s0, tlo, thi, g.key0, g.key1);
                     steps += kk;
                     draws += kk;
                 }
@@ -557,7 +583,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 const bool need = commit && istar < K;  // ya joined T after the walk passed it
                 if (__ballot(need)) {
                     wait_global();
-                    if (need) carry = recw[4 * ya + 2];
+                    if (need) carry = cv_of(ya, recw[2 * ya + 1]);
                 }
                 if (commit) {
                     int pv = ya, pf = yaf;
@@ -567,7 +593,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                             const int v = xv[j], fv = xf[j];
                             const bool mk = marked_f(v, fv, pv, pf);
                             const int cv = mk ? v : carry;
-                            rec[v] = make_int4(pv, carry, cv, 0);
+                            rec[v] = make_int2(pv, mk ? (carry | kMarkBit) : carry);
                             bits.set(v);
                             carry = cv;
                             pv = v;
@@ -661,7 +687,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                         carry = rob_cv[sl];
                     } else {  // ya joined T after the walk passed it: its record was written since
                         wait_global();
-                        carry = recw[4 * ya + 2];
+                        carry = cv_of(ya, recw[2 * ya + 1]);
                     }
                     for (int c = (blen - 1) >> 6; c >= 0; --c) {
                         const int i = c * kWave + lane;
@@ -673,7 +699,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                         const uint64_t m = __ballot(mk);
                         const uint64_t above = lane < kWave - 1 ? (m & (~0ull << (lane + 1))) : 0ull;
                         const int nba = above ? br[c * kWave + __builtin_ctzll(above)] : carry;
-                        if (mine) rec[bi] = make_int4(nexti, nba, mk ? bi : nba, 0);
+                        if (mine) rec[bi] = make_int2(nexti, mk ? (nba | kMarkBit) : nba);
                         carry = m ? br[c * kWave + __builtin_ctzll(m)] : carry;
                     }
                     if (lane == 0) steps += istar;
@@ -689,9 +715,10 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     steps = wave_sum(steps);
     draws = wave_sum(draws);
     if (lane == 0) {
-        if (a.steps) a.steps[blockIdx.x] = steps;
-        if (a.draws) a.draws[blockIdx.x] = draws;
+        if (a.steps) a.steps[tile] = steps;
+        if (a.draws) a.draws[tile] = draws;
     }
+    }  // next tile
 }
 
 // ======================================================================================
@@ -817,17 +844,17 @@ __global__ __launch_bounds__(kIvThreads) void intervals_kernel(IntervalArgs a) {
     if (ls != n) return;
 
     if (a.rec) {
-        // {parent, nba, cv, 0} top-down along the BFS order of T
-        int4 *rec = a.rec + (long long)blockIdx.x * a.rec_stride;
-        if (tid == 0) rec[u] = make_int4(-1, u, u, 0);
+        // {parent, nba | marked << 31} top-down along the BFS order of T
+        int2 *rec = a.rec + (long long)blockIdx.x * a.rec_stride;
+        if (tid == 0) rec[u] = make_int2(-1, u);
         __syncthreads();
         for (int L = 1; L < nlev; ++L) {
             for (int j = lv[L] + tid; j < lv[L + 1]; j += kIvThreads) {
                 const int xv = ord[j];
                 const int pv = par[xv];
-                const int nba = rec[pv].z;
+                const int nba = cv_of(pv, rec[pv].y);
                 const bool mk = marked_f(xv, a.bflag[xv], pv, a.bflag[pv]);
-                rec[xv] = make_int4(pv, nba, mk ? xv : nba, 0);
+                rec[xv] = make_int2(pv, mk ? (nba | kMarkBit) : nba);
             }
             __syncthreads();
         }
@@ -898,12 +925,12 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
     const int pv = bv.y;
     int sum = 0;
     for (int t = t0; t < t1; ++t) {
-        const int4 *__restrict__ rec = a.rec + (long long)t * a.rec_stride;
-        const int4 rv = rec[v];
+        const int2 *__restrict__ rec = a.rec + (long long)t * a.rec_stride;
+        const int2 rv = rec[v];
         sum += (rv.x == bv.x) ? 1 : 0;
-        int x = rv.y;
+        int x = nba_of(rv.y);
         while (x != u) {
-            const int4 rx = rec[x];
+            const int2 rx = rec[x];
             const int4 bx = bnode[x];
             if (bx.y <= pv && pv < bx.y + bx.z) {
                 if (rx.x == bx.x) {
@@ -913,7 +940,7 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
                     if (bp.x == x && bp.y <= pv && pv < bp.y + bp.z) --sum;
                 }
             }
-            x = rx.y;
+            x = nba_of(rx.y);
         }
     }
     if (sum != 0) atomicAdd((unsigned long long *)&a.counts[v], (unsigned long long)(long long)sum);
@@ -963,7 +990,7 @@ __global__ void bflag_kernel(int n, const int4 *__restrict__ bnode, int *__restr
 }
 
 // parents[i][v] = rec_i[v].parent
-__global__ void extract_parents_kernel(int n, int ntrees, const int4 *__restrict__ rec, long long rec_stride,
+__global__ void extract_parents_kernel(int n, int ntrees, const int2 *__restrict__ rec, long long rec_stride,
                                        int *__restrict__ out) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (long long)n * ntrees) return;
@@ -1286,13 +1313,28 @@ hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t 
     count_unreached_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, dist, err);
     return hipGetLastError();
 }
-hipError_t launch_wilson(const WilsonArgs &a, int ntrees, bool lds_bits, bool col16, hipStream_t st) {
+int wilson_resident_blocks(bool lds_bits, bool col16, int nwords) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const size_t dyn = lds_bits ? (size_t)nwords * 4 : 0;
+    hipError_t e;
+    if (lds_bits)
+        e = col16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wilson_kernel<true, unsigned short>, 64, dyn)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wilson_kernel<true, int>, 64, dyn);
+    else
+        e = col16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wilson_kernel<false, unsigned short>, 64, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wilson_kernel<false, int>, 64, 0);
+    if (e != hipSuccess) return 0;
+    return std::max(1, per_cu) * std::max(1, cus);
+}
+hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool col16, int nwords, hipStream_t st) {
     if (lds_bits) {
-        if (col16) wilson_kernel<true, unsigned short><<<ntrees, 64, (size_t)a.nwords * 4, st>>>(a);
-        else wilson_kernel<true, int><<<ntrees, 64, (size_t)a.nwords * 4, st>>>(a);
+        if (col16) wilson_kernel<true, unsigned short><<<blocks, 64, (size_t)nwords * 4, st>>>(a);
+        else wilson_kernel<true, int><<<blocks, 64, (size_t)nwords * 4, st>>>(a);
     } else {
-        if (col16) wilson_kernel<false, unsigned short><<<ntrees, 64, 0, st>>>(a);
-        else wilson_kernel<false, int><<<ntrees, 64, 0, st>>>(a);
+        if (col16) wilson_kernel<false, unsigned short><<<blocks, 64, 0, st>>>(a);
+        else wilson_kernel<false, int><<<blocks, 64, 0, st>>>(a);
     }
     return hipGetLastError();
 }
@@ -1300,7 +1342,7 @@ hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st) {
     intervals_kernel<<<ntrees, kIvThreads, 0, st>>>(a);
     return hipGetLastError();
 }
-hipError_t launch_extract_parents(int n, int ntrees, const int4 *rec, long long rec_stride, int *out, hipStream_t st) {
+hipError_t launch_extract_parents(int n, int ntrees, const int2 *rec, long long rec_stride, int *out, hipStream_t st) {
     extract_parents_kernel<<<blocks_for((long long)n * ntrees, 256), 256, 0, st>>>(n, ntrees, rec, rec_stride, out);
     return hipGetLastError();
 }

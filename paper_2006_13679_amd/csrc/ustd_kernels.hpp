@@ -8,19 +8,39 @@
 
 namespace ustd {
 
-struct WilsonArgs {
+// One graph as the sampler sees it (read-only while sampling).
+struct WilsonGraph {
     int n, u, nwords, rob;
     const int *rp;
     const void *colv;       // column indices: int32, or uint16 when the launch says so
-    uint32_t key0, key1;
-    long long tree_begin;
-    int4 *rec;              // [ntrees][rec_stride] {parent, nba, cv, 0}
-    long long rec_stride;
     const int *bflag;       // [n] (parB + 1) | (internal in B_u) << 31
-    int2 *path;             // [ntrees][rob * kSamplerPathGlobal] recorded steps beyond the LDS part
-    uint32_t *bits;         // [ntrees][nwords] when the tree bitmap lives in global memory
-    long long *steps;       // [ntrees], nullable
-    long long *draws;       // [ntrees], nullable
+    uint32_t key0, key1;    // Philox key (seed)
+};
+
+// One unit of sampler work in a batched launch: tree `tree` of graph `graph`, whose
+// records go to rec + rec_off.
+struct WilsonTile {
+    long long tree, rec_off;
+    int graph, pad;
+};
+
+// Persistent sampler launch: every block repeatedly takes the next tile index from
+// *queue until all `ntiles` are taken.  Tile i is tree tree_begin + i of `g` with
+// records at rec + i * rec_stride, or tiles[i] of the graph table when `tiles` is set.
+struct WilsonArgs {
+    WilsonGraph g;
+    const WilsonGraph *graphs;  // batched launches: graph table (device)
+    const WilsonTile *tiles;    // batched launches: tile table (device); null = single graph
+    int ntiles;
+    long long tree_begin;
+    int2 *rec;                  // records {parent_T, nba | marked << 31}
+    long long rec_stride;
+    int2 *path;                 // [blocks][kSamplerPathSlot] recorded steps beyond the LDS part
+    uint32_t *bits;             // [blocks][bits_stride] when the tree bitmap lives in global memory
+    long long bits_stride;
+    int *queue;                 // tile counter, zero at launch
+    long long *steps;           // [ntiles], nullable
+    long long *draws;           // [ntiles], nullable
 };
 
 struct IntervalArgs {
@@ -31,7 +51,7 @@ struct IntervalArgs {
     long long scratch_stride;
     int4 *pk;               // [ntrees][pk_stride] {parent, pre, size, 0} (when rec is null)
     long long pk_stride;
-    int4 *rec;              // nullable: [ntrees][rec_stride] {parent, nba, cv, 0} instead of pk
+    int2 *rec;              // nullable: [ntrees][rec_stride] {parent, nba | marked << 31} instead of pk
     long long rec_stride;
     const int *bflag;       // needed with rec
     int *err;
@@ -40,7 +60,7 @@ struct IntervalArgs {
 struct AggregateArgs {
     int n, u, ntrees, trees_per_chunk;
     const int4 *bnode;
-    const int4 *rec;
+    const int2 *rec;
     long long rec_stride;
     long long *counts;
 };
@@ -48,6 +68,8 @@ struct AggregateArgs {
 constexpr int kRrHist = 64;
 constexpr int kSamplerRobMax = 128;      // reorder-buffer entries of the sampler
 constexpr int kSamplerPathGlobal = 248;  // recorded steps per entry kept in global memory
+constexpr long long kSamplerPathSlot = (long long)kSamplerRobMax * kSamplerPathGlobal;  // int2 per block
+constexpr int kSamplerMaxBlocks = 4096;  // resident sampler blocks (path / bitmap slots)
 constexpr int kMaxSolveGrid = 1024;
 
 // degree-balanced row mapping (see the BFS / SpMV kernels)
@@ -88,11 +110,13 @@ hipError_t launch_heavy_list(int n, const int *rp, int thresh, int *bcount, int 
 int solve_grid(const RowMap &m, int G);
 int vec_grid(int n);
 hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t st);
-hipError_t launch_wilson(const WilsonArgs &a, int ntrees, bool lds_bits, bool col16, hipStream_t st);
+// resident blocks of one sampler launch on the current device (occupancy x compute units)
+int wilson_resident_blocks(bool lds_bits, bool col16, int nwords);
+hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool col16, int nwords, hipStream_t st);
 hipError_t launch_col_to_u16(long long nnz, const int *col, unsigned short *col16, hipStream_t st);
 hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st);
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st);
-hipError_t launch_extract_parents(int n, int ntrees, const int4 *rec, long long rec_stride, int *out, hipStream_t st);
+hipError_t launch_extract_parents(int n, int ntrees, const int2 *rec, long long rec_stride, int *out, hipStream_t st);
 hipError_t launch_bflag(int n, const int4 *bnode, int *bflag, hipStream_t st);
 hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int *parB, int *scratch, int4 *bnode,
                               int *bflag, hipStream_t st);

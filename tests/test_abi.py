@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 def _prob(**kw):
     base = dict(n=1024, nnz=3968, d_row_ptr=0x1000, d_col=0x2000, pivot=495, solve_mode=0, eps=0.3, delta=0.0,
                 kappa=0.0, seed=1, tau_override=0, solve_tol=0.0, solve_maxit=0, validate=0, trees_per_batch=0,
-                reserved=0)
+                tau_cap=0)
     base.update(kw)
     return api.Problem(**base)
 

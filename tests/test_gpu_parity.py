@@ -234,3 +234,81 @@ def test_large_graph_paths_bit_exact(gpu, scale):
     counts, rep = api.flow_counts(G, p, 0, 12)
     _, st, want = oracle.trees(g.row_ptr, g.col, u, 5, 0, 12, want_parents=False)
     assert (counts.cpu().numpy() == want).all() and rep["walk_steps"] == int(st.sum())
+
+
+# ---------------------------------------------------------------------------------------
+def _batch_case(members):
+    graphs, probs = [], []
+    for g, piv, seed, kw in members:
+        G = dev_graph(g)
+        graphs.append(G)
+        probs.append(api.problem(G, pivot=piv, seed=seed, solve_mode=api.SOLVE_MIXED, solve_tol=1e-12, **kw))
+    return graphs, probs
+
+
+def _check_batch_against_single(members, oracle_idx=()):
+    graphs, probs = _batch_case(members)
+    diags, counts, reps = api.batch_diag_lpinv(graphs, probs)
+    for i, (G, p) in enumerate(zip(graphs, probs)):
+        say("batch member", i, members[i][0].name)
+        d1, c1, r1 = api.diag_lpinv_p(G, p, ws=api.Workspace(G.row_ptr.device))
+        assert reps[i]["tau"] == r1["tau"] and reps[i]["pivot"] == r1["pivot"] and reps[i]["ecc"] == r1["ecc"]
+        assert reps[i]["walk_steps"] == r1["walk_steps"]
+        assert torch.equal(counts[i], c1)
+        assert torch.equal(diags[i], d1)  # same counts, same solve: bit-identical
+        if i in oracle_idx:
+            g = members[i][0]
+            _, st, want = oracle.trees(g.row_ptr, g.col, r1["pivot"], members[i][2], 0, r1["tau"], want_parents=False)
+            assert (counts[i].cpu().numpy() == want).all() and reps[i]["walk_steps"] == int(st.sum())
+    return reps
+
+
+def test_batch_bit_identical_to_single(gpu):
+    """ustd_batch_diag_lpinv on a mixed batch equals ustd_diag_lpinv per member, bit for bit
+    (diag, counts, steps), and the counts equal the oracle's; one member's trees_per_batch
+    forces several pool fills."""
+    members = [
+        (gg.rmat(9, 8, 1), -1, 3, dict(tau_cap=150)),
+        (gg.grid2d(12), 78, 4, dict(tau_override=90)),
+        (gg.rmat(11, 12, 2), -1, 5, dict(tau_cap=120, trees_per_batch=50)),
+        (gg.path(30), 0, 6, dict(tau_cap=40)),
+        (gg.complete(5), 2, 7, dict(tau_cap=64)),
+        (gg.star(20), 3, 8, dict(tau_cap=33)),
+        (gg.grid2d(24, 7), 0, 9, dict(tau_cap=70)),
+    ]
+    reps = _check_batch_against_single(members, oracle_idx=(0, 1, 3, 6))
+    assert reps[0]["n_batches"] >= 3  # 120 trees of member 2 at 50 per fill
+
+
+def test_batch_large_member(gpu):
+    """A member beyond the 16-bit columns and the LDS bitmap switches the whole launch to
+    32-bit columns and global bitmaps; results still match per-member runs and the oracle."""
+    g18 = gg.rmat(18, 8, 3)
+    assert g18.n > 131072
+    members = [
+        (g18, -1, 11, dict(tau_cap=4)),
+        (gg.grid2d(10), 55, 12, dict(tau_override=20)),
+        (gg.rmat(10, 8, 5), -1, 13, dict(tau_cap=30)),
+    ]
+    _check_batch_against_single(members, oracle_idx=(0, 1, 2))
+
+
+def test_batch_member_error(gpu):
+    graphs, probs = _batch_case([(gg.grid2d(5), 0, 1, {}), (gg.cycle(7), 0, 2, {})])
+    probs[1].eps = 0.0
+    say("batch error")
+    with pytest.raises(api.UstdError) as e:
+        api.batch_diag_lpinv(graphs, probs)
+    assert e.value.status == api.EINVAL and "problem 1" in str(e.value)
+
+
+def test_tau_cap(gpu):
+    g = gg.rmat(10, 8, 3)
+    G = dev_graph(g)
+    p = api.problem(G, pivot=-1, seed=2, tau_cap=77)
+    say("tau_cap")
+    _, counts, rep = api.diag_lpinv_p(G, p)
+    full = oracle.tau(g.n, g.m, rep["ecc"], 0.3)
+    assert full > 77 and rep["tau"] == 77
+    _, _, want = oracle.trees(g.row_ptr, g.col, rep["pivot"], 2, 0, 77, want_parents=False)
+    assert (counts.cpu().numpy() == want).all()
