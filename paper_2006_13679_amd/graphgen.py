@@ -113,27 +113,45 @@ def grid_center_pivot(rows: int, cols: int | None = None) -> int:
     return ((rows - 1) // 2) * cols + (cols - 1) // 2
 
 
+def _even_bits(x: np.ndarray) -> np.ndarray:
+    """Bits 0, 2, 4, ... of each uint64, packed into bits 0, 1, 2, ..."""
+    x = x & np.uint64(0x5555555555555555)
+    x = (x | (x >> np.uint64(1))) & np.uint64(0x3333333333333333)
+    x = (x | (x >> np.uint64(2))) & np.uint64(0x0F0F0F0F0F0F0F0F)
+    x = (x | (x >> np.uint64(4))) & np.uint64(0x00FF00FF00FF00FF)
+    x = (x | (x >> np.uint64(8))) & np.uint64(0x0000FFFF0000FFFF)
+    x = (x | (x >> np.uint64(16))) & np.uint64(0x00000000FFFFFFFF)
+    return x
+
+
 def rmat_edges(scale: int, edge_factor: int, seed: int, a=0.57, b=0.19, c=0.19,
                chunk: int = 1 << 22):
     """Raw R-MAT edge list: edge_factor * 2^scale edges; at every one of the `scale`
-    levels each edge picks a quadrant with probabilities (a, b, c, d)."""
+    levels each edge draws r uniform in [0,1) and picks quadrant q = [r >= a] + [r >= a+b]
+    + [r >= a+b+c] (probabilities a, b, c, d); bit `level` of the source is q >> 1 and of
+    the destination q & 1.  Draws are consumed chunk by chunk, level by level."""
     rng = np.random.default_rng(seed)
     M = edge_factor << scale
     src = np.empty(M, dtype=np.int64)
     dst = np.empty(M, dtype=np.int64)
     ab, abc = a + b, a + b + c
+    r = np.empty(min(chunk, M), dtype=np.float64)
+    q = np.empty(len(r), dtype=np.uint8)
+    t = np.empty(len(r), dtype=np.uint8)
     for lo in range(0, M, chunk):
-        hi = min(M, lo + chunk)
-        s = np.zeros(hi - lo, dtype=np.int64)
-        d = np.zeros(hi - lo, dtype=np.int64)
+        L = min(M, lo + chunk) - lo
+        code = np.zeros(L, dtype=np.uint64)  # quadrant of level l in bits 2l, 2l+1
+        rr, qq, tt = r[:L], q[:L], t[:L]
         for level in range(scale):
-            r = rng.random(hi - lo)
-            sbit = r >= ab
-            dbit = ((r >= a) & (r < ab)) | (r >= abc)
-            s |= sbit.astype(np.int64) << level
-            d |= dbit.astype(np.int64) << level
-        src[lo:hi] = s
-        dst[lo:hi] = d
+            rng.random(out=rr)
+            np.greater_equal(rr, a, out=qq.view(bool))
+            np.greater_equal(rr, ab, out=tt.view(bool))
+            qq += tt
+            np.greater_equal(rr, abc, out=tt.view(bool))
+            qq += tt
+            code |= qq.astype(np.uint64) << np.uint64(2 * level)
+        dst[lo:lo + L] = _even_bits(code).astype(np.int64)
+        src[lo:lo + L] = _even_bits(code >> np.uint64(1)).astype(np.int64)
     return src, dst
 
 
@@ -209,8 +227,9 @@ def _rhg_edges(r: np.ndarray, theta: np.ndarray, R: float, bands: int | None = N
         with np.errstate(divide="ignore", invalid="ignore"):
             cosg = (ch * ch_b - coshR) / (sh * sh_b)
         cosg = np.where(np.isfinite(cosg), cosg, -1.0)
+        # the admissible gap shrinks as r2 grows, so the one at the inner radius bounds the
+        # band; an argument below -1 admits every angle
         gap = np.arccos(np.clip(cosg, -1.0, 1.0))
-        gap = np.where(ch * ch_b - sh * sh_b <= coshR, np.pi, gap)  # dtheta = 0 qualifies
         # query only points with band >= bi to count each pair once (then filter by id)
         q = np.nonzero(band_of >= bi)[0]
         if len(q) == 0:
