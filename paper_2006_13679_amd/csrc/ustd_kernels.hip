@@ -183,8 +183,10 @@ __global__ void count_unreached_kernel(int n, const int *__restrict__ dist, int 
 // been absorbed meanwhile, and adds the loop erasure (each vertex's successor after its
 // last visit).  A recorded walk is always long enough: it stopped at a vertex of an older
 // tree, which is still in T.  Three commit paths:
-//   - runs of one-step walks (s -> y) commit in parallel, one lane each;
-//   - recorded walks of 2..255 steps commit cooperatively with ballots (one ballot per
+//   - runs of short walks (at most kPathLds steps, kept in LDS) commit as one batch, one
+//     lane each, up to the first entry that reads a vertex an earlier entry of the batch
+//     writes (detected through two minimum-writer tables under independent hashes);
+//   - longer recorded walks (up to 255 steps) commit cooperatively with ballots (one ballot per
 //     64-step chunk finds the truncation point, one per chunk and branch vertex finds the
 //     vertex's last visit);
 //   - walks longer than the record are re-walked from s by one lane against the current
@@ -200,7 +202,7 @@ __global__ void count_unreached_kernel(int n, const int *__restrict__ dist, int 
 namespace {
 
 constexpr int kRobMax = kSamplerRobMax;  // reorder-buffer entries (LDS)
-constexpr int kPathLds = 7;              // recorded steps kept in LDS per entry (x_1..x_7)
+constexpr int kPathLds = 5;              // recorded steps kept in LDS per entry (x_1..x_5)
 constexpr int kPath = 255;               // recorded steps per speculative walk (x_1..x_255)
 static_assert(kPath - kPathLds == kSamplerPathGlobal, "path split");
 constexpr int kWalking = -1, kOverflow = -2;
@@ -257,7 +259,10 @@ __device__ __forceinline__ void wait_global() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-constexpr int kHashBits = 10;  // batch-commit conflict table: 1024 minimum-writer slots
+// Batch-commit conflict tables: two tables of minimum-writer lanes under independent
+// hashes; a read conflicts only if both of its slots hold a smaller lane, so collisions
+// rarely cut a batch short and a real conflict is never missed.
+constexpr int kHashBits = 8;
 
 // inclusive prefix sum over the 64 lanes with DPP row shifts and row broadcasts
 __device__ __forceinline__ int wave_scan_dpp(int x) {
@@ -270,6 +275,24 @@ __device__ __forceinline__ int wave_scan_dpp(int x) {
     return x;
 }
 __device__ __forceinline__ int hash_slot(int v) { return (int)(((unsigned)v * 2654435761u) >> (32 - kHashBits)); }
+__device__ __forceinline__ int hash_slot2(int v) { return (int)(((unsigned)v * 2246822519u + 3266489917u) >> (32 - kHashBits)); }
+
+// position of the k-th set bit of x (k < popc(x)), by halving
+__device__ __forceinline__ int select_bit(uint32_t x, int k) {
+    int pos = 0, c = __popc(x & 0xFFFFu);
+    if (k >= c) { k -= c; pos += 16; x >>= 16; }
+    c = __popc(x & 0xFFu);
+    if (k >= c) { k -= c; pos += 8; x >>= 8; }
+    c = __popc(x & 0xFu);
+    if (k >= c) { k -= c; pos += 4; x >>= 4; }
+    c = __popc(x & 0x3u);
+    if (k >= c) { k -= c; pos += 2; x >>= 2; }
+    return pos + (k >= (int)(x & 1u) ? 1 : 0);
+}
+__device__ __forceinline__ int select_bit64(uint64_t x, int k) {
+    const int c = __popc((uint32_t)x);
+    return k >= c ? 32 + select_bit((uint32_t)(x >> 32), k - c) : select_bit((uint32_t)x, k);
+}
 
 // The sequential algorithm for one start s0 against the current tree: walk with Next
 // pointers (in the parent field), retrace the loop erasure, and write the branch's records
@@ -334,11 +357,12 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     extern __shared__ uint32_t lds_bits[];
     __shared__ int rob_s[kRobMax], rob_k[kRobMax], rob_fs[kRobMax], rob_cv[kRobMax];
     __shared__ int2 rob_p[kRobMax][kPathLds];
-    __shared__ int cand[kWave];
-    __shared__ int hslot[1 << kHashBits];
-    int *const br = hslot;               // long-walk branch buffers share the hash table's
-    int *const brf = hslot + kPath + 1;  // storage; the slots are cleared again afterwards
-    static_assert(2 * (kPath + 1) <= (1 << kHashBits), "branch buffers fit the hash table");
+    __shared__ int htab[2 << kHashBits];
+    int *const hslot = htab;                        // first conflict table
+    int *const hslot2 = htab + (1 << kHashBits);    // second conflict table
+    int *const br = htab;                // long-walk branch buffers share the tables'
+    int *const brf = htab + kPath + 1;   // storage; the slots are cleared again afterwards
+    static_assert(2 * (kPath + 1) <= (2 << kHashBits), "branch buffers fit the conflict tables");
 
     const int lane = threadIdx.x;
     int2 *__restrict__ gpath = a.path + (long long)blockIdx.x * kSamplerPathSlot;
@@ -379,7 +403,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
         if (LDS) bits.w[i] = 0u;
         else __hip_atomic_store(bits.w + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    for (int i = lane; i < (1 << kHashBits); i += kWave) hslot[i] = kWave;
+    for (int i = lane; i < (2 << kHashBits); i += kWave) htab[i] = kWave;
     wave_sync();
     if (lane == 0) {
         bits.set(u);
@@ -395,9 +419,14 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
 
     for (;;) {
         // ---------------------------------------------------------------- allocate
+        // The idle lane of rank r takes the r-th not-in-tree vertex at or after `cursor`
+        // (ascending start order).  A window of 64 bitmap words is scanned at once: every
+        // lane finds its own start by a binary search over the lanes' prefix counts and a
+        // select of the bit within that word, with no per-bit loop.
         const uint64_t idle = __ballot(mode == 0);
         const int want = min(__popcll(idle), rob - (tail - head));
-        int got = 0;
+        const int rank = __popcll(idle & lanemask_lt());
+        int got = 0, mys = 0;
         while (got < want && cursor < n) {
             const int wbase = cursor >> 5;
             const int wi = wbase + lane;
@@ -409,28 +438,29 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             }
             const int c = __popc(fb);
             const int incl = wave_scan_dpp(c);
+            const int excl = incl - c;
             const int total = __shfl(incl, kWave - 1, kWave);
             const int need = want - got;
-            int r = incl - c;
-            while (fb && r < need) {
-                cand[got + r] = wi * 32 + (__ffs(fb) - 1);
-                ++r;
-                fb &= fb - 1u;
-            }
-            wave_sync();
+            const int j = rank - got;  // this lane's index among the window's free vertices
+            int L = 0;                 // the lane whose word holds free vertex j
+#pragma unroll
+            for (int st = kWave / 2; st >= 1; st >>= 1)
+                if (__shfl(excl, L + st, kWave) <= j) L += st;
+            const uint32_t wL = (uint32_t)__shfl((int)fb, L, kWave);
+            const int eL = __shfl(excl, L, kWave);
+            if (mode == 0 && j >= 0 && j < min(total, need)) mys = (wbase + L) * 32 + select_bit(wL, j - eL);
             if (total >= need) {
                 got = want;
-                cursor = cand[want - 1] + 1;
+                cursor = __shfl(mys, select_bit64(idle, want - 1), kWave) + 1;
             } else {
                 got += total;
                 cursor = (wbase + kWave) * 32;
             }
         }
         if (got > 0) {
-            const int rank = __popcll(idle & lanemask_lt());
             if (mode == 0 && rank < got) {
                 my_e = tail + rank;
-                s = cand[rank];
+                s = mys;
                 x = s;
                 k = 0;
                 mode = 1;
@@ -500,13 +530,13 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             const uint64_t okm = __ballot(sk >= 0 && sk <= kPathLds);
             const int r = (~okm == 0ull) ? kWave : __builtin_ctzll(~okm);
             if (r > 0) {
-                // Batch commit of the done entries head .. head+r-1 (walks of <= 7 steps), one
+                // Batch commit of the done entries head .. head+r-1 (walks of <= kPathLds steps), one
                 // lane each, all planned against the current tree T0.  Entry j's plan is what
                 // the sequential algorithm does unless an earlier entry of the batch adds a
                 // vertex j has read (its start or a vertex before its truncation point); the
-                // plan's written vertices go into a small hash of minimum writer lanes, and the
-                // batch commits up to the first lane that reads a slot written by a smaller
-                // lane (hash collisions only shorten the batch).  The head never conflicts.
+                // plan's written vertices go into the two minimum-writer tables, and the batch
+                // commits up to the first lane that reads a vertex whose two slots both hold a
+                // smaller lane (collisions only shorten the batch).  The head never conflicts.
                 const bool act = lane < r;
                 const int sl = idx & robm;
                 const int K = act ? sk : 0;
@@ -554,20 +584,27 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 if (live && !bad) {
 #pragma unroll
                     for (int j = 0; j <= kPathLds; ++j)
-                        if ((keep >> j) & 1u) atomicMin(&hslot[hash_slot(xv[j])], lane);
+                        if ((keep >> j) & 1u) {
+                            atomicMin(&hslot[hash_slot(xv[j])], lane);
+                            atomicMin(&hslot2[hash_slot2(xv[j])], lane);
+                        }
                 }
                 wave_sync();
                 bool conflict = bad;
                 if (live && !bad) {
 #pragma unroll
                     for (int j = 0; j <= kPathLds; ++j)
-                        if (j < istar && hslot[hash_slot(xv[j])] < lane) conflict = true;
+                        if (j < istar && hslot[hash_slot(xv[j])] < lane && hslot2[hash_slot2(xv[j])] < lane)
+                            conflict = true;
                 }
                 wave_sync();
                 if (live && !bad) {
 #pragma unroll
                     for (int j = 0; j <= kPathLds; ++j)
-                        if ((keep >> j) & 1u) hslot[hash_slot(xv[j])] = kWave;
+                        if ((keep >> j) & 1u) {
+                            hslot[hash_slot(xv[j])] = kWave;
+                            hslot2[hash_slot2(xv[j])] = kWave;
+                        }
                 }
                 const uint64_t cm = __ballot(conflict);
                 const int jstar = cm ? __builtin_ctzll(cm) : r;
@@ -606,7 +643,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 wave_sync();
                 continue;
             }
-            // head: recorded walk x_0..x_K, 7 < K <= 255, committed cooperatively; lane j holds
+            // head: recorded walk x_0..x_K, kPathLds < K <= 255, committed cooperatively; lane j holds
             // x_{j+64c}, c = 0..3
             const int sl = head & robm;
             const int s0 = rob_s[sl];
@@ -706,7 +743,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 }
             }
             wave_sync();
-            for (int i = lane; i < 2 * (kPath + 1); i += kWave) hslot[i] = kWave;
+            for (int i = lane; i < 2 * (kPath + 1); i += kWave) htab[i] = kWave;
             ++head;
             wave_sync();
         }

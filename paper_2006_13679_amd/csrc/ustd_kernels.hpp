@@ -66,8 +66,8 @@ struct AggregateArgs {
 };
 
 constexpr int kRrHist = 64;
-constexpr int kSamplerRobMax = 128;      // reorder-buffer entries of the sampler
-constexpr int kSamplerPathGlobal = 248;  // recorded steps per entry kept in global memory
+constexpr int kSamplerRobMax = 64;       // reorder-buffer entries of the sampler
+constexpr int kSamplerPathGlobal = 250;  // recorded steps per entry kept in global memory
 constexpr long long kSamplerPathSlot = (long long)kSamplerRobMax * kSamplerPathGlobal;  // int2 per block
 constexpr int kSamplerMaxBlocks = 4096;  // resident sampler blocks (path / bitmap slots)
 constexpr int kMaxSolveGrid = 1024;
