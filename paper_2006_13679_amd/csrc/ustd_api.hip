@@ -441,6 +441,25 @@ int cg_iterate(Ctx &c, const CgArgs<T> &a, int maxit, int *iters_out, bool *conv
     return USTD_OK;
 }
 
+// One CG solve of L d = rhs (or the pivot right-hand side): in one workgroup for small
+// graphs, else by iteration kernels polled in chunks.
+template <typename T>
+int cg_solve(Ctx &c, const CgArgs<T> &a, const double *rhs, int rhs_is_pivot, const double *shift_scale, double tol2,
+             int maxit, int *iters, bool *conv) {
+    if (c.L.n <= kSmallSolveMaxN) {
+        HIP_TRY(launch_cg_small<double, T>(a, c.rows, c.L.G, rhs, rhs_is_pivot, c.pivot, shift_scale, tol2, maxit,
+                                           c.st));
+        CgScalars sc{};
+        HIP_TRY(hipMemcpyAsync(&sc, a.sc, sizeof(sc), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        *iters = sc.iter;
+        *conv = sc.done && sc.rr <= sc.tol2 * sc.rr0;
+        return USTD_OK;
+    }
+    HIP_TRY(launch_cg_start<double, T>(a, rhs, rhs_is_pivot, c.pivot, shift_scale, tol2, c.st));
+    return cg_iterate<T>(c, a, maxit, iters, conv);
+}
+
 int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
     const ustd_problem *p = c.p;
     const int n = c.L.n;
@@ -459,8 +478,7 @@ int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
         CgArgs<double> a = cg_args<double>(c, x64, at<double>(c.ws, c.L.off_r64), at<double>(c.ws, c.L.off_z64),
                                            at<double>(c.ws, c.L.off_p64), at<double>(c.ws, c.L.off_q64),
                                            &c.misc->sc64, c.misc->rr_hist64);
-        HIP_TRY(launch_cg_start<double, double>(a, nullptr, 1, c.pivot, nullptr, tol * tol, c.st));
-        USTD_TRY(cg_iterate<double>(c, a, maxit, &total_it, &conv));
+        USTD_TRY(cg_solve<double>(c, a, nullptr, 1, nullptr, tol * tol, maxit, &total_it, &conv));
         outer = 1;
         HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, sums, c.st));
         HIP_TRY(launch_axpy_project<double>(n, x64, nullptr, nullptr, 0, sums + 2, grid, c.st));
@@ -485,11 +503,10 @@ int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
             if (outer > 0 && rnorm > 0.5 * prev) break;  // refinement stagnates at FP64 rounding
             prev = rnorm;
             if (total_it >= maxit) break;
-            HIP_TRY(launch_cg_start<double, float>(a, res, 0, c.pivot, c.misc->shift_scale, inner_tol * inner_tol,
-                                                   c.st));
             int it = 0;
             bool ic = false;
-            USTD_TRY(cg_iterate<float>(c, a, maxit - total_it, &it, &ic));
+            USTD_TRY(cg_solve<float>(c, a, res, 0, c.misc->shift_scale, inner_tol * inner_tol, maxit - total_it, &it,
+                                     &ic));
             total_it += it;
             HIP_TRY(launch_axpy_project<float>(n, x64, x32, c.misc->shift_scale, 2, nullptr, grid, c.st));
         }

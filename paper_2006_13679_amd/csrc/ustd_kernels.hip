@@ -1054,10 +1054,10 @@ __device__ __forceinline__ T block_sum_t(T v, T *sh) {
 }
 
 // y = L p over all rows, degree-balanced; calls emit(v, (L p)_v) once per row from one
-// thread.  Fixed grid and fixed per-row reduction trees: deterministic.
-template <typename T, int G, typename Emit>
+// thread.  Fixed grid and fixed per-row reduction trees: deterministic.  BS = block size.
+template <typename T, int G, int BS = 256, typename Emit>
 __device__ __forceinline__ void lap_apply_rows(const RowMap &m, const T *__restrict__ p, Emit emit) {
-    __shared__ T shr[4];
+    __shared__ T shr[BS / kWave];
     const int nh = *m.nheavy;
     for (int h = blockIdx.x; h < nh; h += gridDim.x) {
         const int v = m.heavy[h];
@@ -1067,7 +1067,7 @@ __device__ __forceinline__ void lap_apply_rows(const RowMap &m, const T *__restr
         acc = block_sum_t<T>(acc, shr);
         if (threadIdx.x == 0) emit(v, (T)(hi - lo) * p[v] - acc);
     }
-    const int rows_per_tile = 256 / G;
+    constexpr int rows_per_tile = BS / G;
     const int g = threadIdx.x / G, l = threadIdx.x % G;
     for (int tile = blockIdx.x; tile * rows_per_tile < m.n; tile += gridDim.x) {
         const int v = tile * rows_per_tile + g;
@@ -1211,6 +1211,88 @@ __global__ __launch_bounds__(256) void cg_start_finish_kernel(CgArgs<T> a, doubl
         S->iter = 0;
         S->done = (rr > 0.0) ? 0 : 1;
         a.rr_hist[kRrHist - 1] = rr;
+    }
+}
+
+// Whole CG solve in one workgroup, for small graphs: the same start, iteration, Jacobi
+// preconditioner and stopping rule as the kernels above (dot products in FP64, vectors in
+// T), with no kernel boundary or host poll between iterations.  Ends with the scalars
+// the multi-kernel path leaves (iter, rr, rr0, tol2, done).
+constexpr int kSmallThreads = 1024;
+
+template <typename Tin, typename T, int G>
+__global__ __launch_bounds__(kSmallThreads) void cg_small_kernel(CgArgs<T> a, RowMap m, const Tin *__restrict__ rhs,
+                                                                 int rhs_is_pivot, int u,
+                                                                 const double *__restrict__ shift_scale, double tol2,
+                                                                 int maxit) {
+    __shared__ double sh[kSmallThreads / kWave];
+    const int n = a.n, tid = threadIdx.x;
+    const double shift = shift_scale ? shift_scale[0] : 0.0;
+    const double scale = shift_scale ? shift_scale[1] : 1.0;
+    const double inv_n = 1.0 / (double)n;
+    double rz = 0.0, rr = 0.0;
+    for (int v = tid; v < n; v += kSmallThreads) {
+        double b;
+        if (rhs_is_pivot) b = (v == u ? 1.0 : 0.0) - inv_n;
+        else b = ((double)rhs[v] - shift) * scale;
+        const T rv = (T)b;
+        const T zv = rv / (T)(a.rp[v + 1] - a.rp[v]);
+        a.x[v] = (T)0;
+        a.r[v] = rv;
+        a.z[v] = zv;
+        a.p[v] = zv;
+        rz += (double)rv * (double)zv;
+        rr += (double)rv * (double)rv;
+    }
+    rz = block_sum_t<double>(rz, sh);
+    rr = block_sum_t<double>(rr, sh);  // the barriers also publish p before the first product
+    const double rr0 = rr;
+    int it = 0;
+    bool done = !(rr > 0.0);
+    while (!done && it < maxit) {
+        double pq = 0.0;
+        lap_apply_rows<T, G, kSmallThreads>(m, a.p, [&](int v, T qv) {
+            a.q[v] = qv;
+            pq += (double)a.p[v] * (double)qv;
+        });
+        pq = block_sum_t<double>(pq, sh);
+        if (!(pq > 0.0 && pq == pq)) {  // breakdown
+            done = true;
+            break;
+        }
+        const T al = (T)(rz / pq);
+        double rzn = 0.0, rrn = 0.0;
+        for (int v = tid; v < n; v += kSmallThreads) {
+            a.x[v] += al * a.p[v];
+            const T rv = a.r[v] - al * a.q[v];
+            a.r[v] = rv;
+            const T zv = rv / (T)(a.rp[v + 1] - a.rp[v]);
+            a.z[v] = zv;
+            rzn += (double)rv * (double)zv;
+            rrn += (double)rv * (double)rv;
+        }
+        rzn = block_sum_t<double>(rzn, sh);
+        rrn = block_sum_t<double>(rrn, sh);
+        ++it;
+        rr = rrn;
+        if (!(rrn > tol2 * rr0)) {
+            done = true;
+            break;
+        }
+        const T be = (T)(rz != 0.0 ? rzn / rz : 0.0);
+        rz = rzn;
+        for (int v = tid; v < n; v += kSmallThreads) a.p[v] = a.z[v] + be * a.p[v];
+        __syncthreads();  // p complete before the next product gathers it
+    }
+    if (tid == 0) {
+        CgScalars *S = a.sc;
+        S->rz[0] = rz;
+        S->rz[1] = 0.0;
+        S->rr = rr;
+        S->rr0 = rr0;
+        S->tol2 = tol2;
+        S->iter = it;
+        S->done = done ? 1 : 0;
     }
 }
 
@@ -1404,6 +1486,18 @@ hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st) {
 }
 int solve_grid(const RowMap &m, int G) { return std::min(row_grid(m, G), kMaxSolveGrid); }
 int vec_grid(int n) { return std::max(1, std::min((n + 255) / 256, kMaxSolveGrid)); }
+
+template <typename Tin, typename T>
+hipError_t launch_cg_small(const CgArgs<T> &a, const RowMap &m, int G, const Tin *rhs, int rhs_is_pivot, int u,
+                           const double *shift_scale, double tol2, int maxit, hipStream_t st) {
+    USTD_DISPATCH_G(G, (cg_small_kernel<Tin, T, GG><<<1, kSmallThreads, 0, st>>>(a, m, rhs, rhs_is_pivot, u, shift_scale,
+                                                                               tol2, maxit)));
+    return hipGetLastError();
+}
+template hipError_t launch_cg_small<double, double>(const CgArgs<double> &, const RowMap &, int, const double *, int,
+                                                    int, const double *, double, int, hipStream_t);
+template hipError_t launch_cg_small<double, float>(const CgArgs<float> &, const RowMap &, int, const double *, int,
+                                                   int, const double *, double, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, int it, hipStream_t st) {

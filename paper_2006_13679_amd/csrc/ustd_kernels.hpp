@@ -122,6 +122,11 @@ hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int 
                               int *bflag, hipStream_t st);
 template <typename T>
 hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, int it, hipStream_t st);
+// whole CG solve in one workgroup (small graphs); leaves the same scalars as the iteration kernels
+constexpr int kSmallSolveMaxN = 16384;
+template <typename Tin, typename T>
+hipError_t launch_cg_small(const CgArgs<T> &a, const RowMap &m, int G, const Tin *rhs, int rhs_is_pivot, int u,
+                           const double *shift_scale, double tol2, int maxit, hipStream_t st);
 template <typename Tin, typename T>
 hipError_t launch_cg_start(const CgArgs<T> &a, const Tin *rhs, int rhs_is_pivot, int u, const double *shift_scale,
                            double tol2, hipStream_t st);
