@@ -214,7 +214,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
-    ap.add_argument("--solve", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--solve", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--trees-per-batch", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
