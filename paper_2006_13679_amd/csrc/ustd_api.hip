@@ -47,6 +47,7 @@ constexpr long long kAlign = 256;
 constexpr int kLdsBitsMaxWords = 4096;      // tree bitmap in LDS up to 131072 vertices (16 KB)
 constexpr long long kDefaultBudget = 64ll << 30;  // tree records + sampler scratch, of 288 GB HBM
 constexpr int kMaxTreesPerBatch = 8192;
+constexpr int kAggTreesPerChunk = 8;   // trees one aggregation thread sums before its atomic
 
 inline long long align_up(long long v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -348,7 +349,7 @@ int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag) {
     aa.n = c.L.n;
     aa.u = c.pivot;
     aa.ntrees = cnt;
-    aa.trees_per_chunk = 32;
+    aa.trees_per_chunk = kAggTreesPerChunk;
     aa.bnode = at<int4>(c.ws, c.L.off_bnode);
     aa.rec = at<int2>(c.ws, c.L.off_rec);
     aa.rec_stride = c.L.rec_stride;
@@ -851,7 +852,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
                 aa.n = B.g[sg.graph].n;
                 aa.u = cs[sg.graph].pivot;
                 aa.ntrees = (int)sg.ntrees;
-                aa.trees_per_chunk = 32;
+                aa.trees_per_chunk = kAggTreesPerChunk;
                 aa.bnode = at<int4>(cs[sg.graph].ws, B.g[sg.graph].off_bnode);
                 aa.rec = pool + sg.rec_off;
                 aa.rec_stride = B.g[sg.graph].rec_stride;

@@ -188,10 +188,12 @@ __global__ void count_unreached_kernel(int n, const int *__restrict__ dist, int 
 //     writes (detected through two minimum-writer tables under independent hashes);
 //   - longer recorded walks (up to 255 steps) commit cooperatively with ballots (one ballot per
 //     64-step chunk finds the truncation point, one per chunk and branch vertex finds the
-//     vertex's last visit);
-//   - walks longer than the record are re-walked from s by one lane against the current
-//     tree in a tight loop (the sequential algorithm for that start, Next pointers in the
-//     parent field of the record array).
+//     vertex's last visit).  A walk that filled its 255-step record without reaching the
+//     tree it saw takes this path too: the tree has usually grown since, so the record
+//     mostly does reach it;
+//   - if no recorded vertex is in the tree, one lane turns the record into Next pointers (in
+//     the parent field of the record array) and continues the walk from its last vertex in
+//     a tight loop (the sequential algorithm for that start).
 // Everything a commit needs is prefetched into LDS while walking (the B_u flag word of
 // every recorded vertex, the chain value of the vertex a walk ends on), so the in-order
 // commit path does no dependent global loads in the common cases.
@@ -205,7 +207,12 @@ constexpr int kRobMax = kSamplerRobMax;  // reorder-buffer entries (LDS)
 constexpr int kPathLds = 5;              // recorded steps kept in LDS per entry (x_1..x_5)
 constexpr int kPath = 255;               // recorded steps per speculative walk (x_1..x_255)
 static_assert(kPath - kPathLds == kSamplerPathGlobal, "path split");
-constexpr int kWalking = -1, kOverflow = -2;
+// reorder-buffer entry states besides a finished walk's step count (>= 0):
+//   kWalking  - still walking
+//   kOverflow - recorded kPath steps without reaching the tree it saw
+//   kContinue - an overflowed walk none of whose recorded vertices is in the tree at commit
+//   kRewalk   - re-walk from the start (never expected; keeps the commit exact regardless)
+constexpr int kWalking = -1, kOverflow = -2, kContinue = -3, kRewalk = -4;
 
 template <bool LDS>
 struct TreeBits {
@@ -296,15 +303,17 @@ __device__ __forceinline__ int select_bit64(uint64_t x, int k) {
 
 // The sequential algorithm for one start s0 against the current tree: walk with Next
 // pointers (in the parent field), retrace the loop erasure, and write the branch's records
-// {parent, nba | marked << 31}.  One lane; returns the walk's step count.
+// {parent, nba | marked << 31}.  The walk resumes at step k0 from vertex x0 (k0 = 0, x0 = s0
+// for a whole walk; otherwise the Next pointers of steps 0..k0-1 are already written).  One
+// lane; returns the walk's total step count.
 template <bool LDS, typename CT>
 __device__ long long rewalk_commit(const TreeBits<LDS> &bits, int *recw, const int *__restrict__ rp,
-                                   const CT *__restrict__ col, const int *__restrict__ bflag, int s0,
-                                   uint32_t tlo, uint32_t thi, uint32_t key0, uint32_t key1) {
-    int xw = s0;
-    int r0 = rp[s0], r1 = rp[s0 + 1];
-    long long k = 0;
-    uint4 ph = make_uint4(0, 0, 0, 0);
+                                   const CT *__restrict__ col, const int *__restrict__ bflag, int s0, int x0,
+                                   long long k0, uint32_t tlo, uint32_t thi, uint32_t key0, uint32_t key1) {
+    int xw = x0;
+    int r0 = rp[x0], r1 = rp[x0 + 1];
+    long long k = k0;
+    uint4 ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
     for (;;) {
         if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
         const int q = (int)(k & 3);
@@ -512,14 +521,32 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
         while (head < tail) {
             const int hs = rob_k[head & robm];
             if (hs == kWalking) break;
-            if (hs == kOverflow) {
-                // walk longer than the record: lane 0 runs the sequential algorithm for this
-                // start against the current tree (all earlier starts are committed)
-                const int s0 = rob_s[head & robm];
-                if (!bits.test(s0) && lane == 0) {
-                    const long long kk = rewalk_commit(bits, recw, rp, col, bflag, s0, tlo, thi, g.key0, g.key1);
-                    steps += kk;
-                    draws += kk;
+            if (hs == kContinue || hs == kRewalk) {
+                // lane 0 runs the sequential algorithm for this start against the current tree
+                // (all earlier starts are committed).  An overflowed walk whose record misses
+                // the tree resumes after its record: the recorded steps become Next pointers.
+                const int sl = head & robm;
+                const int s0 = rob_s[sl];
+                if (!bits.test(s0)) {
+                    if (hs == kContinue) wait_global();  // recorded steps stored by another lane
+                    if (lane == 0) {
+                        int xs = s0;
+                        long long k0 = 0;
+                        if (hs == kContinue) {
+#pragma unroll 8
+                            for (int j = 1; j <= kPath; ++j) {
+                                const int xj = j <= kPathLds ? rob_p[sl][j - 1].x
+                                                             : gpath[sl * (kPath - kPathLds) + (j - 1 - kPathLds)].x;
+                                recw[2 * xs] = xj;
+                                xs = xj;
+                            }
+                            k0 = kPath;
+                        }
+                        const long long kk =
+                            rewalk_commit(bits, recw, rp, col, bflag, s0, xs, k0, tlo, thi, g.key0, g.key1);
+                        steps += kk;
+                        draws += kk - k0;
+                    }
                 }
                 ++head;
                 wave_sync();
@@ -577,7 +604,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 }
                 const uint64_t badm = __ballot(bad);
                 if (badm & 1ull) {  // never expected: fall back to the exact re-walk
-                    rob_k[head & robm] = kOverflow;
+                    rob_k[head & robm] = kRewalk;
                     wave_sync();
                     continue;
                 }
@@ -643,12 +670,13 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 wave_sync();
                 continue;
             }
-            // head: recorded walk x_0..x_K, kPathLds < K <= 255, committed cooperatively; lane j holds
-            // x_{j+64c}, c = 0..3
+            // head: recorded walk x_0..x_K, kPathLds < K <= 255 (an overflowed walk: its whole
+            // record, K = 255), committed cooperatively; lane j holds x_{j+64c}, c = 0..3
             const int sl = head & robm;
             const int s0 = rob_s[sl];
             if (!bits.test(s0)) {
-                const int K = hs;
+                const bool ended = hs >= 0;  // the walk reached the tree it saw
+                const int K = ended ? hs : kPath;
                 int xv[4] = {-1, -1, -1, -1}, xf[4] = {0, 0, 0, 0};
                 {
                     int2 e = make_int2(-1, 0);
@@ -682,8 +710,9 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                     }
                 }
                 if (istar < 0) {
-                    // cannot happen for a correctly recorded walk; re-walk to stay exact
-                    rob_k[sl] = kOverflow;
+                    // an overflowed walk that still misses the tree resumes after its record; for
+                    // a finished walk this cannot happen, and the re-walk keeps the commit exact
+                    rob_k[sl] = ended ? kRewalk : kContinue;
                     wave_sync();
                     continue;
                 }
@@ -720,7 +749,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 if (ya >= 0) {
                     // records of the branch b_0 = s .. b_{blen-1}, attached to ya
                     int carry;
-                    if (istar == K) {
+                    if (ended && istar == K) {
                         carry = rob_cv[sl];
                     } else {  // ya joined T after the walk passed it: its record was written since
                         wait_global();
