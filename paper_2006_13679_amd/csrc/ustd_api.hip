@@ -57,7 +57,8 @@ struct Misc {                      // small zero-initialised block at the front 
     int err_interval;
     int nheavy;
     int queue;                     // sampler tile counter
-    int pad_;
+    int setup_out[2];              // small-graph set-up: ecc, unreached flag
+    int pad_[3];
     unsigned long long best_degree;
     CgScalars sc64, sc32;
     double rr_hist64[kRrHist];
@@ -280,6 +281,23 @@ int setup(Ctx &c, ustd_report *rep) {
     }
     int *dist = at<int>(c.ws, c.L.off_dist);
     int *parB = at<int>(c.ws, c.L.off_parB);
+    if (n <= kSmallSolveMaxN) {
+        // BFS tree, connectivity and B_u intervals in one workgroup, one readback
+        HIP_TRY(launch_setup_small(c.rows, c.L.G, c.pivot, dist, parB, at<int>(c.ws, c.L.off_scr),
+                                   at<int4>(c.ws, c.L.off_bnode), at<int>(c.ws, c.L.off_bflag), c.misc->setup_out,
+                                   c.st));
+        int out[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(out, c.misc->setup_out, sizeof(out), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        if (out[1]) return fail(USTD_EGRAPH, "graph is not connected");
+        c.ecc = out[0];
+        if (rep) {
+            rep->pivot = c.pivot;
+            rep->ecc = c.ecc;
+            rep->ms_bfs += tm.stop_ms();
+        }
+        return USTD_OK;
+    }
     HIP_TRY(launch_bfs_init(n, c.pivot, dist, parB, c.st));
     int d = 0;
     for (;; ++d) {

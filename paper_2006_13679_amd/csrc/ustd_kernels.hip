@@ -1025,18 +1025,45 @@ __global__ void bsub_init_kernel(int n, int u, int *__restrict__ sz, int *__rest
         cur[v] = 1;
     }
 }
-__global__ void bsub_size_kernel(int n, int d, const int *__restrict__ dist, const int *__restrict__ parB,
-                                 int *__restrict__ sz) {
+// Children of one hub make up most of a level in small-world graphs; the lanes of a wave
+// that share the parent of the wave's first active lane combine into one atomic.
+__global__ __launch_bounds__(256) void bsub_size_kernel(int n, int d, const int *__restrict__ dist,
+                                                        const int *__restrict__ parB, int *__restrict__ sz) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n && dist[v] == d) atomicAdd(&sz[parB[v]], sz[v]);
+    const bool act = v < n && dist[v] == d;
+    const int p = act ? parB[v] : -1, val = act ? sz[v] : 0;
+    const uint64_t am = __ballot(act);
+    if (!am) return;
+    const int leader = __builtin_ctzll(am);
+    const int lp = __shfl(p, leader, kWave);
+    const bool same = act && p == lp;
+    const int tot = wave_sum(same ? val : 0);
+    if (lane_id() == leader) atomicAdd(&sz[lp], tot);
+    if (act && !same) atomicAdd(&sz[p], val);
 }
-__global__ void bsub_pre_kernel(int n, int d, const int *__restrict__ dist, const int *__restrict__ parB,
-                                const int *__restrict__ sz, int *__restrict__ cur, int *__restrict__ pre) {
+__global__ __launch_bounds__(256) void bsub_pre_kernel(int n, int d, const int *__restrict__ dist,
+                                                       const int *__restrict__ parB, const int *__restrict__ sz,
+                                                       int *__restrict__ cur, int *__restrict__ pre) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n || dist[v] != d) return;
-    const int pv = atomicAdd(&cur[parB[v]], sz[v]);
-    pre[v] = pv;
-    cur[v] = pv + 1;
+    const bool act = v < n && dist[v] == d;
+    const int p = act ? parB[v] : -1, val = act ? sz[v] : 0;
+    const uint64_t am = __ballot(act);
+    if (!am) return;
+    const int leader = __builtin_ctzll(am);
+    const int lp = __shfl(p, leader, kWave);
+    const bool same = act && p == lp;
+    const int incl = wave_incl_scan(same ? val : 0);
+    const int tot = __shfl(incl, kWave - 1, kWave);
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(&cur[lp], tot);
+    base = __shfl(base, leader, kWave);
+    int pv = 0;
+    if (same) pv = base + incl - val;
+    else if (act) pv = atomicAdd(&cur[p], val);
+    if (act) {
+        pre[v] = pv;
+        cur[v] = pv + 1;
+    }
 }
 __global__ void bsub_pack_kernel(int n, const int *__restrict__ parB, const int *__restrict__ pre,
                                  const int *__restrict__ sz, int4 *__restrict__ bnode, int *__restrict__ bflag) {
@@ -1045,6 +1072,113 @@ __global__ void bsub_pack_kernel(int n, const int *__restrict__ parB, const int 
     const int pb = parB[v], z = sz[v];
     bnode[v] = make_int4(pb, pre[v], z, 0);
     bflag[v] = (int)((unsigned)(pb + 1) | (z > 1 ? 0x80000000u : 0u));
+}
+
+// Set-up of a small graph in one workgroup: the BFS levels (the same minimum-ID parent
+// rule as bfs_level_kernel), the connectivity check, and the subtree intervals and flag
+// words of B_u (as the bsub_* kernels).  out[0] = ecc(u), out[1] = 1 if a vertex is
+// unreached.  scratch holds 3n ints.
+constexpr int kSetupThreads = 1024;
+
+template <int G>
+__global__ __launch_bounds__(kSetupThreads) void setup_small_kernel(RowMap m, int u, int *__restrict__ dist,
+                                                                    int *__restrict__ parB, int *__restrict__ scratch,
+                                                                    int4 *__restrict__ bnode, int *__restrict__ bflag,
+                                                                    int *__restrict__ out) {
+    __shared__ int found, unreached;
+    const int n = m.n, tid = threadIdx.x;
+    int *__restrict__ sz = scratch;
+    int *__restrict__ cur = scratch + n;
+    int *__restrict__ pre = scratch + 2 * n;
+    for (int v = tid; v < n; v += kSetupThreads) {
+        dist[v] = (v == u) ? 0 : INT_MAX;
+        parB[v] = (v == u) ? -1 : INT_MAX;
+        sz[v] = 1;
+    }
+    if (tid == 0) unreached = 0;
+    const int nh = *m.nheavy;
+    int d = 0;
+    for (;; ++d) {
+        if (tid == 0) found = 0;
+        __syncthreads();
+        int any = 0;
+        for (int h = 0; h < nh; ++h) {
+            const int v = m.heavy[h];
+            if (dist[v] != d) continue;  // uniform in the block
+            for (int e = m.rp[v] + tid; e < m.rp[v + 1]; e += kSetupThreads) {
+                const int y = m.col[e];
+                const int dy = dist[y];
+                if (dy > d) {
+                    atomicMin(&parB[y], v);
+                    if (dy != d + 1) dist[y] = d + 1;
+                    any = 1;
+                }
+            }
+        }
+        constexpr int rows_per_tile = kSetupThreads / G;
+        const int g = tid / G, l = tid % G;
+        for (int base = 0; base < n; base += rows_per_tile) {
+            const int v = base + g;
+            if (v >= n || dist[v] != d) continue;
+            const int lo = m.rp[v], hi = m.rp[v + 1];
+            if (hi - lo > m.heavy_thresh) continue;
+            for (int e = lo + l; e < hi; e += G) {
+                const int y = m.col[e];
+                const int dy = dist[y];
+                if (dy > d) {
+                    atomicMin(&parB[y], v);
+                    if (dy != d + 1) dist[y] = d + 1;
+                    any = 1;
+                }
+            }
+        }
+        if (any) found = 1;
+        __syncthreads();
+        const int f = found;
+        __syncthreads();  // every thread has read `found` before it is reset
+        if (!f) break;
+    }
+    const int ecc = d;
+    for (int v = tid; v < n; v += kSetupThreads)
+        if (dist[v] == INT_MAX) unreached = 1;
+    __syncthreads();
+    if (unreached) {
+        if (tid == 0) {
+            out[0] = ecc;
+            out[1] = 1;
+        }
+        return;
+    }
+    // subtree sizes bottom-up, then pre-order ranges top-down, level by level
+    for (int dd = ecc; dd >= 1; --dd) {
+        for (int v = tid; v < n; v += kSetupThreads)
+            if (dist[v] == dd) atomicAdd(&sz[parB[v]], sz[v]);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        pre[u] = 0;
+        cur[u] = 1;
+    }
+    __syncthreads();
+    for (int dd = 1; dd <= ecc; ++dd) {
+        for (int v = tid; v < n; v += kSetupThreads) {
+            if (dist[v] == dd) {
+                const int pv = atomicAdd(&cur[parB[v]], sz[v]);
+                pre[v] = pv;
+                cur[v] = pv + 1;
+            }
+        }
+        __syncthreads();
+    }
+    for (int v = tid; v < n; v += kSetupThreads) {
+        const int pb = parB[v], z = sz[v];
+        bnode[v] = make_int4(pb, pre[v], z, 0);
+        bflag[v] = (int)((unsigned)(pb + 1) | (z > 1 ? 0x80000000u : 0u));
+    }
+    if (tid == 0) {
+        out[0] = ecc;
+        out[1] = 0;
+    }
 }
 
 // bflag[x] = (parB(x) + 1) | (1 << 31 if x has a child in B_u)
@@ -1502,6 +1636,12 @@ hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int 
     for (int d = ecc; d >= 1; --d) bsub_size_kernel<<<nb, 256, 0, st>>>(n, d, dist, parB, sz);
     for (int d = 1; d <= ecc; ++d) bsub_pre_kernel<<<nb, 256, 0, st>>>(n, d, dist, parB, sz, cur, pre);
     bsub_pack_kernel<<<nb, 256, 0, st>>>(n, parB, pre, sz, bnode, bflag);
+    return hipGetLastError();
+}
+hipError_t launch_setup_small(const RowMap &m, int G, int u, int *dist, int *parB, int *scratch, int4 *bnode,
+                              int *bflag, int *out, hipStream_t st) {
+    USTD_DISPATCH_G(G, (setup_small_kernel<GG><<<1, kSetupThreads, 0, st>>>(m, u, dist, parB, scratch, bnode, bflag,
+                                                                             out)));
     return hipGetLastError();
 }
 hipError_t launch_bflag(int n, const int4 *bnode, int *bflag, hipStream_t st) {

@@ -118,6 +118,10 @@ hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st);
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st);
 hipError_t launch_extract_parents(int n, int ntrees, const int2 *rec, long long rec_stride, int *out, hipStream_t st);
 hipError_t launch_bflag(int n, const int4 *bnode, int *bflag, hipStream_t st);
+// BFS tree, connectivity check and B_u intervals of a small graph (n <= kSmallSolveMaxN) in
+// one workgroup; out[0] = ecc, out[1] = 1 if a vertex is unreached; scratch holds 3n ints
+hipError_t launch_setup_small(const RowMap &m, int G, int u, int *dist, int *parB, int *scratch, int4 *bnode,
+                              int *bflag, int *out, hipStream_t st);
 hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int *parB, int *scratch, int4 *bnode,
                               int *bflag, hipStream_t st);
 template <typename T>
