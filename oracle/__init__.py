@@ -187,3 +187,49 @@ def diag_lpinv(row_ptr, col, u: int, eps: float, seed: int, delta: float = 0.0, 
                                       ctypes.byref(e), ctypes.byref(s), ctypes.byref(rr))
     return dict(diag=diag, counts=counts, tau=t.value, ecc=e.value, steps=s.value,
                 relres=rr.value, status=rc)
+
+
+# ---------------------------------------------------------------------------------------
+# Measures derived from the estimator's outputs (plain numpy; the paper's formulas)
+# ---------------------------------------------------------------------------------------
+def centralities(diag) -> dict:
+    """Vertex measures that depend only on diag(L^+):
+    trace tr(L^+); electrical farness n L^+_vv + tr (Eq. elec-farness, section on electrical
+    closeness); electrical closeness (n-1)/farness; normalized random-walk betweenness
+    1/n + tr/((n-1) farness) (Lemma on NRWB); Kirchhoff index n tr (Kirchhoff appendix)."""
+    d = np.asarray(diag, dtype=np.float64)
+    n = len(d)
+    tr = float(np.sum(d))
+    far = n * d + tr
+    return dict(trace=tr, kirchhoff=n * tr, farness=far, closeness=(n - 1) / far,
+                nrwb=1.0 / n + tr / ((n - 1) * far))
+
+
+def edge_sample_size(n: int, m: int, eps: float, delta: float = 0.0) -> int:
+    """q = ceil(2 eps^-2 ln(2m/delta)) trees for every edge's effective resistance within eps
+    (Kirchhoff appendix, after Hayashi et al.); delta <= 0 selects 1/n."""
+    import math
+
+    d = delta if delta > 0 else 1.0 / n
+    return int(math.ceil(2.0 * math.log(2.0 * m / d) / (eps * eps)))
+
+
+def edge_counts(row_ptr, col, parents, u: int) -> np.ndarray:
+    """Spanning-edge counts (Kirchhoff appendix: for each edge the number of sampled USTs it
+    appears in) of the given parent arrays.  The edge {v, parent(v)} is counted at the CSR
+    position of (min, max) of its endpoints; entries (a, b) with a > b stay 0."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    key = rows * n + c  # ascending: rows in order, each row ascending
+    counts = np.zeros(len(c), dtype=np.int64)
+    par = np.asarray(parents, dtype=np.int64).reshape(-1, n)
+    v = np.arange(n, dtype=np.int64)
+    for p in par:
+        keep = v != u
+        a = np.minimum(v[keep], p[keep])
+        b = np.maximum(v[keep], p[keep])
+        slot = np.searchsorted(key, a * n + b)
+        assert (key[slot] == a * n + b).all(), "a parent is not a neighbour"
+        np.add.at(counts, slot, 1)
+    return counts

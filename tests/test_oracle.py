@@ -373,3 +373,88 @@ def test_wilson_worked_example_k4():
     par, steps = oracle.wilson(g.row_ptr, g.col, 3, 0, 0)
     assert list(par) == [2, 2, 3, -1]
     assert steps == 3
+
+
+# ---------------------------------------------------------------------------------------
+# Measures derived from diag(L^+) and spanning-edge counts
+# ---------------------------------------------------------------------------------------
+def _resistances(P):
+    d = np.diag(P)
+    return d[:, None] + d[None, :] - 2 * P
+
+
+@pytest.mark.parametrize("g", [gg.grid2d(4), gg.rmat(7, 6, 2), gg.cycle(9), gg.complete_bipartite(3, 5)])
+def test_centralities_match_definitions(g):
+    """Farness, closeness and the Kirchhoff index against sums of effective resistances from
+    the dense pseudoinverse; NRWB against its original definition with M = L + P."""
+    P = brute.pinv(g)
+    n = g.n
+    R = _resistances(P)
+    c = oracle.centralities(np.diag(P))
+    np.testing.assert_allclose(c["farness"], R.sum(axis=1), rtol=1e-10)
+    np.testing.assert_allclose(c["closeness"], (n - 1) / R.sum(axis=1), rtol=1e-10)
+    assert c["kirchhoff"] == pytest.approx(R[np.triu_indices(n, 1)].sum(), rel=1e-10)
+    # NRWB: the Lemma's closed form is 1/n + (sum over t != v of the definition's numerators) /
+    # ((n-1) * sum of its denominators), with M = L + P inverted densely (the reading taken;
+    # the definition as printed sums the per-t ratios instead, which the Lemma's proof does not)
+    Minv = np.linalg.inv(brute.laplacian(g) + np.full((n, n), 1.0 / n))
+    nrwb = np.empty(n)
+    for v in range(n):
+        num = den = 0.0
+        for t in range(n):
+            if t != v:
+                num += Minv[t, t] - Minv[t, v]
+                den += Minv[t, t] + Minv[v, v] - 2 * Minv[t, v]
+        nrwb[v] = 1.0 / n + num / ((n - 1) * den)
+    np.testing.assert_allclose(c["nrwb"], nrwb, rtol=1e-10)
+
+
+def test_centralities_complete_graph_closed_form():
+    n = 7
+    P = brute.pinv(gg.complete(n))  # r(u,v) = 2/n
+    c = oracle.centralities(np.diag(P))
+    np.testing.assert_allclose(c["farness"], 2.0 * (n - 1) / n, rtol=1e-12)
+    np.testing.assert_allclose(c["closeness"], n / 2.0, rtol=1e-12)
+    assert c["kirchhoff"] == pytest.approx(n * (n - 1) / 2 * 2.0 / n, rel=1e-12)
+
+
+@pytest.mark.parametrize("name,g,u", [("grid3", gg.grid2d(3), 4), ("K4", gg.complete(4), 0),
+                                      ("K23", gg.complete_bipartite(2, 3), 1), ("C6", gg.cycle(6), 2)])
+def test_edge_counts_over_all_trees_give_resistances(name, g, u):
+    """Over every spanning tree once, count(e)/#trees = r(e) (Kirchhoff's theorem); the
+    counts sum to (n-1) #trees and sit only at entries (a, b) with a < b."""
+    trees = np.stack(brute.spanning_trees(g, u))
+    cnt = oracle.edge_counts(g.row_ptr, g.col, trees, u)
+    P = brute.pinv(g)
+    R = _resistances(P)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    assert (cnt[rows > g.col] == 0).all()
+    assert cnt.sum() == (g.n - 1) * len(trees)
+    for e in range(len(g.col)):
+        a, b = rows[e], g.col[e]
+        if a < b:
+            assert cnt[e] / len(trees) == pytest.approx(R[a, b], abs=1e-12)
+
+
+def test_edge_counts_on_tree_graph_and_sampled_trees():
+    g = gg.random_tree(40, 5)
+    par, _ = oracle.wilson(g.row_ptr, g.col, 3, 9, 0)
+    cnt = oracle.edge_counts(g.row_ptr, g.col, np.stack([par, par]), 3)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    assert (cnt[rows < g.col] == 2).all()  # a tree graph's only spanning tree holds every edge
+    h = gg.grid2d(6)
+    parents, _, _ = oracle.trees(h.row_ptr, h.col, 14, 3, 0, 4000, want_counts=False)
+    cnt = oracle.edge_counts(h.row_ptr, h.col, parents, 14)
+    R = _resistances(brute.pinv(h))
+    rows = np.repeat(np.arange(h.n), np.diff(h.row_ptr))
+    sel = rows < h.col
+    est = cnt[sel] / 4000.0
+    # Hoeffding: P(|est - r| > 0.05) <= 2 exp(-2 * 4000 * 0.05^2) ~ 4e-9 per edge
+    assert np.abs(est - R[rows[sel], h.col[sel]]).max() <= 0.05
+
+
+def test_edge_sample_size_worked_example():
+    # n = 100, m = 250, eps = 0.5, delta = 1/n: ln(2*250*100) = ln(50000) = 10.8198; 2/0.25 = 8 -> 86.56 -> 87
+    assert oracle.edge_sample_size(100, 250, 0.5) == 87
+    assert oracle.edge_sample_size(100, 250, 0.5, 0.01) == 87
+    assert oracle.edge_sample_size(1000, 250, 0.5, 0.5) == 56  # ln(1000) = 6.9078 * 8 = 55.26
