@@ -179,6 +179,69 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_edges(args):
+    """Spanning-edge counts of q trees on the workload (effective resistance of every edge to
+    +-eps w.h.p.); one step = sampling the q trees and counting their edges."""
+    import numpy as np
+    import torch
+
+    from paper_2006_13679_amd import api
+
+    g, u, _, cfg = make_workload(args.workload)
+    dev = torch.device("cuda:0")
+    G = api.Graph.from_host(g.row_ptr, g.col, device=dev)
+    q = api.edge_sample_size(g.n, g.m, 0.3, 0.0)
+    p = api.problem(G, pivot=u, eps=0.3, seed=1, trees_per_batch=args.trees_per_batch)
+    ws = api.Workspace(dev)
+    counts = torch.zeros(G.nnz, dtype=torch.int64, device=dev)
+    for _ in range(args.warmup):
+        counts.zero_()
+        api.edge_counts(G, p, 0, q, counts=counts, ws=ws)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        counts.zero_()
+        _, r = api.edge_counts(G, p, 0, q, counts=counts, ws=ws)
+        reps.append(r)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    med = lambda k: float(np.median([r[k] for r in reps]))  # noqa: E731
+    steps = reps[0]["walk_steps"]
+    ms_sample, ms_count = med("ms_sample"), med("ms_aggregate")
+    ab = 20 * steps + 12 * g.n * q
+    achieved = ab / (ms_sample * 1e-3) / 1e9
+    out = {
+        "metric": "spanning trees/sec for all-edge effective resistances (spanning-edge counts) at eps=0.3",
+        "value": round(q / (ms_step * 1e-3), 2), "unit": "trees/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": dict(cfg, n=g.n, m=g.m, pivot=u, eps=0.3, q=q, seed=1, task="edges"),
+        "walk_steps_per_s": round(steps / (ms_sample * 1e-3), 1),
+        "phase_ms": {"setup_bfs": med("ms_bfs"), "sample": ms_sample, "edge_count": ms_count},
+        "roofline": {"bound": "hbm", "kernel": "wilson_kernel", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "algorithmic_bytes_per_launch": ab, "launch_ms": round(ms_sample, 4)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        done, t_used, chunk = 0, 0.0, 8
+        while t_used < args.cpu_budget and done < q:
+            c = min(chunk, q - done)
+            t1 = time.perf_counter()
+            par, _, _ = oracle.trees(g.row_ptr, g.col, u, 1, done, c, want_counts=False)
+            oracle.edge_counts(g.row_ptr, g.col, par, u)
+            t_used += time.perf_counter() - t1
+            done += c
+            chunk = min(chunk * 2, 256)
+        out["cpu_baseline"] = {"value": done / t_used, "unit": "trees/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d of %d trees with their edge counts (%.1f s), single-threaded" %
+                                         (done, q, t_used)}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline_batch(members, reps, budget_s: float):
     """The oracle on a bounded sample of the batch: two trees of every member (scaled to its
     tau) and the solve of every eighth member (scaled by eight)."""
@@ -218,6 +281,9 @@ def main():
     ap.add_argument("--trees-per-batch", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--task", default="diag", choices=["diag", "edges"],
+                    help="diag: diag(L+) (default); edges: spanning-edge counts of q = ceil(2 eps^-2 ln(2m/delta)) "
+                         "trees, the effective resistance of every edge")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device to device (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -240,6 +306,9 @@ def main():
         sys.exit(2)
     if WORKLOADS[args.workload]["kind"] == "batch":
         run_batch(args)
+        return
+    if args.task == "edges":
+        run_edges(args)
         return
 
     import numpy as np
@@ -275,6 +344,13 @@ def main():
     med = lambda k: float(np.median([r[k] for r in reps]))  # noqa: E731
     ms_sample, ms_iv, ms_ag = med("ms_sample"), med("ms_intervals"), med("ms_aggregate")
 
+    diag_t, _, _ = api.diag_lpinv_p(G, p, ws=ws, want_counts=False)
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    for _ in range(10):
+        api.centralities(diag_t)
+    torch.cuda.synchronize()
+    ms_central = (time.perf_counter() - tc) * 1e3 / 10
     dist, _, _, _ = api.bfs(G, p, ws=ws)  # farness of the pivot, for the algorithmic-byte count
     farness = int(dist.sum().item())
     ab = algorithmic_bytes(g.n, tau, steps, farness)
@@ -307,6 +383,7 @@ def main():
         "walk_steps": steps, "walk_draws": reps[0]["walk_draws"],
         "solve_iters": reps[0]["solve_iters"], "solve_relres": reps[0]["solve_relres"],
         "roofline": roof,
+        "centralities_ms": round(ms_central, 4),
     }
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -159,6 +159,34 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
                           double *const *d_diags, int64_t *const *d_counts, ustd_report *reps,
                           void *stream);
 
+/* Spanning-edge counts (Kirchhoff index appendix: counting, for each edge, the sampled USTs
+ * it appears in; count / #trees estimates the edge's effective resistance r(e), which is
+ * also the probability that a uniform spanning tree contains e).  Trees tree_begin ..
+ * +tree_count-1 are the ones ustd_sample_trees returns.  For each tree and each v != u the
+ * edge {v, parent_T(v)} adds 1 at the CSR position of the entry (a, b), a = min and b = max
+ * of its endpoints (row a); entries with a > b end at 0 (a value there is moved to the
+ * entry (b, a)).  d_counts is int64[nnz], accumulated (the caller zeroes it); any split of a
+ * tree range gives the same counts.
+ * rep (nullable): walk steps/draws and times (the counting in ms_aggregate).  Synchronises
+ * `stream`. */
+int ustd_edge_counts(const ustd_problem *prob, int64_t tree_begin, int64_t tree_count,
+                     void *d_ws, size_t ws_bytes, int64_t *d_counts, ustd_report *rep, void *stream);
+
+/* Number of trees for every edge's effective resistance within +-eps with probability
+ * 1 - delta (Kirchhoff index appendix, after Hayashi et al.): *q = ceil(2 eps^-2 ln(2m/delta)),
+ * delta <= 0 selecting 1/n.  Host only. */
+int ustd_edge_sample_size(int64_t n, int64_t m, double eps, double delta, int64_t *q);
+
+/* Vertex measures that depend only on the diagonal d = diag(L^+) (section on electrical
+ * closeness, Eq. elec-farness; Lemma on normalized random-walk betweenness; Kirchhoff
+ * index appendix): tr = sum_v d[v]; farness[v] = n d[v] + tr; closeness[v] = (n-1) /
+ * farness[v]; nrwb[v] = 1/n + tr / ((n-1) farness[v]); Kirchhoff index n tr.  d_diag
+ * double[n] (device, e.g. from ustd_diag_lpinv); d_farness, d_closeness, d_nrwb double[n]
+ * (device, nullable); d_scalars double[2] (device) receives {tr, Kirchhoff index}.  The
+ * trace is summed in a fixed order.  Enqueued on `stream`; does not synchronise. */
+int ustd_centralities(int64_t n, const double *d_diag, double *d_farness, double *d_closeness,
+                      double *d_nrwb, double *d_scalars, void *stream);
+
 /* Test hook for the walk generator: d_out[i] = word ((k0+i) mod 4) of Philox4x32-10 with
  * key (seed lo, seed hi) and counter ((k0+i)/4, s, t lo, t hi), i < count; uint32[count]. */
 int ustd_philox_words(uint64_t seed, int64_t t, int32_t s, int64_t k0, int64_t count,

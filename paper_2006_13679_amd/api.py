@@ -57,6 +57,7 @@ class Report(ctypes.Structure):
 
 EXPORTS = ["ustd_workspace_bytes", "ustd_bfs", "ustd_sample_trees", "ustd_flow_counts", "ustd_tree_counts",
            "ustd_solve_pivot_column", "ustd_diag_lpinv", "ustd_batch_workspace_bytes", "ustd_batch_diag_lpinv",
+           "ustd_edge_counts", "ustd_edge_sample_size", "ustd_centralities",
            "ustd_philox_words", "ustd_status_string", "ustd_last_error"]
 
 _lib = None
@@ -80,6 +81,9 @@ def lib() -> ctypes.CDLL:
         L.ustd_diag_lpinv.argtypes = [PP, P, ctypes.c_size_t, P, P, PR, P]
         L.ustd_batch_workspace_bytes.argtypes = [PP, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.ustd_batch_diag_lpinv.argtypes = [PP, i32, P, ctypes.c_size_t, P, P, PR, P]
+        L.ustd_edge_counts.argtypes = [PP, i64, i64, P, ctypes.c_size_t, P, PR, P]
+        L.ustd_edge_sample_size.argtypes = [i64, i64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(i64)]
+        L.ustd_centralities.argtypes = [i64, P, P, P, P, P, P]
         L.ustd_philox_words.argtypes = [u64, i64, i32, i64, i64, P, P]
         for name in EXPORTS[:-2]:
             getattr(L, name).restype = ctypes.c_int
@@ -268,6 +272,41 @@ def batch_diag_lpinv(graphs: list, probs: list, ws: Workspace | None = None, wan
     rc = lib().ustd_batch_diag_lpinv(arr, count, _ptr(buf), buf.numel(), dptr, cptr, reps, _stream(dev))
     _check(rc, (OK, ENOTCONV) if allow_notconv else (OK,))
     return diags, counts, [r.as_dict() for r in reps]
+
+
+def edge_counts(g: Graph, p: Problem, tree_begin: int, tree_count: int, counts: torch.Tensor | None = None,
+                ws: Workspace | None = None):
+    """Spanning-edge counts of trees [tree_begin, tree_begin + tree_count) at the CSR entries
+    (a, b), a < b (ustd_edge_counts).  Returns (counts int64[nnz], report)."""
+    buf, nb = _ws(p, g, ws)
+    dev = g.row_ptr.device
+    if counts is None:
+        counts = torch.zeros(g.nnz, dtype=torch.int64, device=dev)
+    rep = Report()
+    _check(lib().ustd_edge_counts(ctypes.byref(p), tree_begin, tree_count, _ptr(buf), nb, _ptr(counts),
+                                  ctypes.byref(rep), _stream(dev)))
+    return counts, rep.as_dict()
+
+
+def edge_sample_size(n: int, m: int, eps: float, delta: float = 0.0) -> int:
+    q = ctypes.c_int64(0)
+    _check(lib().ustd_edge_sample_size(n, m, eps, delta, ctypes.byref(q)))
+    return int(q.value)
+
+
+def centralities(diag: torch.Tensor) -> dict:
+    """Electrical farness and closeness, normalized random-walk betweenness and the Kirchhoff
+    index from diag(L^+) (ustd_centralities)."""
+    assert diag.dtype == torch.float64 and diag.is_cuda and diag.is_contiguous()
+    n = diag.numel()
+    dev = diag.device
+    far = torch.empty(n, dtype=torch.float64, device=dev)
+    clo = torch.empty_like(far)
+    nrwb = torch.empty_like(far)
+    sc = torch.empty(2, dtype=torch.float64, device=dev)
+    _check(lib().ustd_centralities(n, _ptr(diag), _ptr(far), _ptr(clo), _ptr(nrwb), _ptr(sc), _stream(dev)))
+    h = sc.cpu()
+    return dict(farness=far, closeness=clo, nrwb=nrwb, trace=float(h[0]), kirchhoff=float(h[1]))
 
 
 def philox_words(seed: int, t: int, s: int, k0: int, count: int, device="cuda") -> torch.Tensor:

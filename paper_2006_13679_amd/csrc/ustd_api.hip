@@ -378,7 +378,28 @@ int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag) {
     return USTD_OK;
 }
 
-int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *counts, ustd_report *rep) {
+// Spanning-edge counts over `cnt` resident trees (records in the workspace)
+int edge_count_trees(Ctx &c, int cnt, long long *edge_counts, double *ms) {
+    EdgeCountArgs ea{};
+    ea.n = c.L.n;
+    ea.u = c.pivot;
+    ea.ntrees = cnt;
+    ea.trees_per_chunk = kAggTreesPerChunk;
+    ea.rp = c.rp32;
+    ea.col = c.p->d_col;
+    ea.rec = at<int2>(c.ws, c.L.off_rec);
+    ea.rec_stride = c.L.rec_stride;
+    ea.counts = edge_counts;
+    Timer tm(c.st);
+    HIP_TRY(launch_edge_counts(ea, c.st));
+    if (ms) *ms += tm.stop_ms();
+    return USTD_OK;
+}
+
+// Samples trees tree_begin .. +tree_count-1 in batches of at most K; after each batch,
+// Algorithm 2 adds into `counts` and/or the spanning-edge counts into `edge_counts`.
+int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *counts, ustd_report *rep,
+              long long *edge_counts = nullptr) {
     long long steps_total = 0, draws_total = 0;
     int batches = 0;
     std::vector<long long> hs(c.L.K), hd(c.L.K);
@@ -395,7 +416,8 @@ int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *cou
             USTD_TRY(sample_batch(c, tree_begin + b0, cnt, steps, draws));
             ms_s += tm.stop_ms();
         }
-        USTD_TRY(aggregate_trees(c, cnt, counts, &ms_a));
+        if (counts) USTD_TRY(aggregate_trees(c, cnt, counts, &ms_a));
+        if (edge_counts) USTD_TRY(edge_count_trees(c, cnt, edge_counts, &ms_a));
         HIP_TRY(hipMemcpyAsync(hs.data(), steps, cnt * sizeof(long long), hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipMemcpyAsync(hd.data(), draws, cnt * sizeof(long long), hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipStreamSynchronize(c.st));
@@ -909,6 +931,49 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
     const double ms = total.stop_ms();
     for (int i = 0; i < count; ++i) R[i].ms_total = ms;
     return status;
+}
+
+int ustd_edge_counts(const ustd_problem *prob, int64_t tree_begin, int64_t tree_count, void *d_ws, size_t ws_bytes,
+                     int64_t *d_counts, ustd_report *rep, void *stream) {
+    g_err.clear();
+    Ctx c;
+    USTD_TRY(begin(c, prob, d_ws, ws_bytes, stream));
+    if (tree_begin < 0 || tree_count < 0) return fail(USTD_EINVAL, "negative tree range");
+    if (!d_counts) return fail(USTD_EINVAL, "d_counts is NULL");
+    if (rep) memset(rep, 0, sizeof(*rep));
+    Timer total(c.st);
+    USTD_TRY(setup(c, rep));
+    USTD_TRY(run_trees(c, tree_begin, tree_count, nullptr, rep, (long long *)d_counts));
+    {
+        Timer tm(c.st);
+        HIP_TRY(launch_edge_fold(c.L.n, c.L.nnz, c.rp32, prob->d_col, (long long *)d_counts, c.st));
+        if (rep) rep->ms_aggregate += tm.stop_ms();
+    }
+    if (rep) {
+        rep->tau = tree_count;
+        rep->ms_total = total.stop_ms();
+    }
+    return USTD_OK;
+}
+
+int ustd_edge_sample_size(int64_t n, int64_t m, double eps, double delta, int64_t *q) {
+    g_err.clear();
+    if (!q) return fail(USTD_EINVAL, "q is NULL");
+    if (n < 2 || m < 1) return fail(USTD_EINVAL, "n = %lld, m = %lld out of range", (long long)n, (long long)m);
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(USTD_EINVAL, "eps must be > 0");
+    if (delta > 0.0 && !(delta < 1.0)) return fail(USTD_EINVAL, "delta must lie in (0,1)");
+    const double d = delta > 0.0 ? delta : 1.0 / (double)n;
+    *q = (int64_t)std::ceil(2.0 * std::log(2.0 * (double)m / d) / (eps * eps));
+    return USTD_OK;
+}
+
+int ustd_centralities(int64_t n, const double *d_diag, double *d_farness, double *d_closeness, double *d_nrwb,
+                      double *d_scalars, void *stream) {
+    g_err.clear();
+    if (n < 2) return fail(USTD_EINVAL, "n = %lld out of range", (long long)n);
+    if (!d_diag || !d_scalars) return fail(USTD_EINVAL, "d_diag / d_scalars is NULL");
+    HIP_TRY(launch_centralities(n, d_diag, d_farness, d_closeness, d_nrwb, d_scalars, (hipStream_t)stream));
+    return USTD_OK;
 }
 
 int ustd_philox_words(uint64_t seed, int64_t t, int32_t s, int64_t k0, int64_t count, uint32_t *d_out, void *stream) {

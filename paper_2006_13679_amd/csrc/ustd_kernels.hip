@@ -1459,6 +1459,106 @@ __global__ __launch_bounds__(kSmallThreads) void cg_small_kernel(CgArgs<T> a, Ro
     }
 }
 
+// ======================================================================================
+// Measures that depend only on diag(L^+) (section on electrical closeness, Eq. elec-farness;
+// Lemma on normalized random-walk betweenness; Kirchhoff index appendix):
+//   tr = sum_v diag[v], farness[v] = n diag[v] + tr, closeness[v] = (n-1) / farness[v],
+//   nrwb[v] = 1/n + tr / ((n-1) farness[v]), Kirchhoff index = n tr.
+// The trace is summed by one workgroup in a fixed order (deterministic).
+// ======================================================================================
+constexpr int kTraceThreads = 1024;
+
+__global__ __launch_bounds__(kTraceThreads) void trace_kernel(long long n, const double *__restrict__ diag,
+                                                              double *__restrict__ scalars) {
+    __shared__ double sh[kTraceThreads / kWave];
+    double acc = 0.0;
+    for (long long v = threadIdx.x; v < n; v += kTraceThreads) acc += diag[v];
+    acc = block_sum_t<double>(acc, sh);
+    if (threadIdx.x == 0) {
+        scalars[0] = acc;
+        scalars[1] = (double)n * acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void centrality_kernel(long long n, const double *__restrict__ diag,
+                                                         const double *__restrict__ scalars,
+                                                         double *__restrict__ farness, double *__restrict__ closeness,
+                                                         double *__restrict__ nrwb) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const double tr = scalars[0];
+    const double f = (double)n * diag[v] + tr;
+    if (farness) farness[v] = f;
+    if (closeness) closeness[v] = (double)(n - 1) / f;
+    if (nrwb) nrwb[v] = 1.0 / (double)n + tr / ((double)(n - 1) * f);
+}
+
+// ======================================================================================
+// Spanning-edge counts (Kirchhoff index appendix: for each edge, the number of sampled
+// USTs it appears in).  Thread per vertex v != u over a chunk of resident trees: the edge
+// v -> parent_T(v) is found by binary search in v's own ascending row (short for the
+// children of hubs) and counted at that position; equal positions in a row of trees add
+// with one atomic.  edge_fold_kernel then moves every count at an entry (a, b), a > b, to
+// the entry (b, a), so each undirected edge is counted at (min, max).
+// ======================================================================================
+__global__ __launch_bounds__(256) void edge_count_kernel(EdgeCountArgs a) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= a.n || v == a.u) return;
+    const int t0 = blockIdx.y * a.trees_per_chunk;
+    const int t1 = min(a.ntrees, t0 + a.trees_per_chunk);
+    long long cur = -1;
+    int c = 0;
+    for (int t = t0; t < t1; ++t) {
+        const int p = a.rec[(long long)t * a.rec_stride + v].x;
+        int lo = a.rp[v], hi = a.rp[v + 1];
+        const int end = hi;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (a.col[mid] < p) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo == end || a.col[lo] != p) continue;  // not a neighbour: never for a sampled tree
+        if (lo == cur) {
+            ++c;
+        } else {
+            if (c) atomicAdd((unsigned long long *)&a.counts[cur], (unsigned long long)c);
+            cur = lo;
+            c = 1;
+        }
+    }
+    if (c) atomicAdd((unsigned long long *)&a.counts[cur], (unsigned long long)c);
+}
+
+// Thread per entry e = (a, b) with a > b and a nonzero count: add it to the entry (b, a)
+// (binary search in row b) and clear it.  Entries (b, a) with b < a are never cleared, so
+// each receives from exactly one entry.  The row a of entry e comes from a binary search
+// over the row pointers.
+__global__ __launch_bounds__(256) void edge_fold_kernel(int n, long long nnz, const int *__restrict__ rp,
+                                                        const int *__restrict__ col, long long *__restrict__ counts) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const long long c = counts[e];
+    if (c == 0) return;
+    int lo = 0, hi = n;  // largest a with rp[a] <= e
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rp[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    const int a = lo, b = col[e];
+    if (b >= a) return;
+    int l = rp[b], h = rp[b + 1];
+    const int end = h;
+    while (l < h) {
+        const int mid = (l + h) >> 1;
+        if (col[mid] < a) l = mid + 1;
+        else h = mid;
+    }
+    if (l == end || col[l] != a) return;  // asymmetric input: left where it is
+    atomicAdd((unsigned long long *)&counts[l], (unsigned long long)c);
+    counts[e] = 0;
+}
+
 // FP64 residual of the current x64: res = b - L x with b = e_u - 1/n; per-block partials of
 // [sum res, |res|^2, sum x]; reduce3_kernel sums them into out[0..3)
 template <int G>
@@ -1642,6 +1742,22 @@ hipError_t launch_setup_small(const RowMap &m, int G, int u, int *dist, int *par
                               int *bflag, int *out, hipStream_t st) {
     USTD_DISPATCH_G(G, (setup_small_kernel<GG><<<1, kSetupThreads, 0, st>>>(m, u, dist, parB, scratch, bnode, bflag,
                                                                              out)));
+    return hipGetLastError();
+}
+hipError_t launch_centralities(long long n, const double *diag, double *farness, double *closeness, double *nrwb,
+                               double *scalars, hipStream_t st) {
+    trace_kernel<<<1, kTraceThreads, 0, st>>>(n, diag, scalars);
+    if (farness || closeness || nrwb)
+        centrality_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, diag, scalars, farness, closeness, nrwb);
+    return hipGetLastError();
+}
+hipError_t launch_edge_counts(const EdgeCountArgs &a, hipStream_t st) {
+    dim3 grid(blocks_for(a.n, 256), (a.ntrees + a.trees_per_chunk - 1) / a.trees_per_chunk);
+    edge_count_kernel<<<grid, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+hipError_t launch_edge_fold(int n, long long nnz, const int *rp, const int *col, long long *counts, hipStream_t st) {
+    edge_fold_kernel<<<blocks_for(nnz, 256), 256, 0, st>>>(n, nnz, rp, col, counts);
     return hipGetLastError();
 }
 hipError_t launch_bflag(int n, const int4 *bnode, int *bflag, hipStream_t st) {

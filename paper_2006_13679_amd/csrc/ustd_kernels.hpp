@@ -65,6 +65,14 @@ struct AggregateArgs {
     long long *counts;
 };
 
+struct EdgeCountArgs {
+    int n, u, ntrees, trees_per_chunk;
+    const int *rp, *col;        // int32 row pointers, ascending rows
+    const int2 *rec;            // [ntrees][rec_stride] tree records
+    long long rec_stride;
+    long long *counts;          // [nnz], accumulated
+};
+
 constexpr int kRrHist = 64;
 constexpr int kSamplerRobMax = 64;       // reorder-buffer entries of the sampler
 constexpr int kSamplerPathGlobal = 250;  // recorded steps per entry kept in global memory
@@ -118,6 +126,10 @@ hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st);
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st);
 hipError_t launch_extract_parents(int n, int ntrees, const int2 *rec, long long rec_stride, int *out, hipStream_t st);
 hipError_t launch_bflag(int n, const int4 *bnode, int *bflag, hipStream_t st);
+hipError_t launch_centralities(long long n, const double *diag, double *farness, double *closeness, double *nrwb,
+                               double *scalars, hipStream_t st);
+hipError_t launch_edge_counts(const EdgeCountArgs &a, hipStream_t st);
+hipError_t launch_edge_fold(int n, long long nnz, const int *rp, const int *col, long long *counts, hipStream_t st);
 // BFS tree, connectivity check and B_u intervals of a small graph (n <= kSmallSolveMaxN) in
 // one workgroup; out[0] = ecc, out[1] = 1 if a vertex is unreached; scratch holds 3n ints
 hipError_t launch_setup_small(const RowMap &m, int G, int u, int *dist, int *parB, int *scratch, int4 *bnode,

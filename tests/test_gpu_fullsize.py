@@ -144,3 +144,19 @@ def test_batch64_members(gpu):
     parents, steps = api.sample_trees(graphs[grid_big], probs[grid_big], 4095, 1)
     want_par, want_steps = oracle.wilson(g.row_ptr, g.col, m["pivot"], m["seed"], 4095)
     assert int(steps[0]) == want_steps and (parents[0].cpu().numpy() == want_par).all()
+
+
+def test_rmat16_edge_counts_q_trees(gpu):
+    """Spanning-edge counts of all q = ceil(2 eps^-2 ln(2m n)) trees at eps = 0.3 (the edges
+    workload of the benchmark), bit-exact against the oracle's trees."""
+    g = gg.rmat(16, 16, 1)
+    u = gg.max_degree_pivot(g)
+    q = oracle.edge_sample_size(g.n, g.m, 0.3)
+    G = api.Graph.from_host(g.row_ptr, g.col)
+    assert api.edge_sample_size(g.n, g.m, 0.3) == q
+    say("rmat16 edges gpu", q)
+    got, rep = api.edge_counts(G, api.problem(G, pivot=u, eps=0.3, seed=1), 0, q)
+    say("rmat16 edges oracle")
+    parents, st, _ = oracle.trees(g.row_ptr, g.col, u, 1, 0, q, want_counts=False)
+    want = oracle.edge_counts(g.row_ptr, g.col, parents, u)
+    assert (got.cpu().numpy() == want).all() and rep["walk_steps"] == int(st.sum())

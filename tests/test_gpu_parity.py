@@ -312,3 +312,51 @@ def test_tau_cap(gpu):
     assert full > 77 and rep["tau"] == 77
     _, _, want = oracle.trees(g.row_ptr, g.col, rep["pivot"], 2, 0, 77, want_parents=False)
     assert (counts.cpu().numpy() == want).all()
+
+
+# ---------------------------------------------------------------------------------------
+def test_centralities_match_oracle(gpu):
+    """Farness, closeness, NRWB and the Kirchhoff index from a diagonal the library computed,
+    against the oracle's formulas on the same diagonal."""
+    for g, u in [(gg.grid2d(32), 495), (gg.rmat(12, 16, 1), -1), (gg.path(50), 0)]:
+        say("centralities", g.name)
+        G = dev_graph(g)
+        diag, _, _ = api.diag_lpinv_p(G, api.problem(G, pivot=u, tau_override=64, solve_tol=1e-12))
+        got = api.centralities(diag)
+        want = oracle.centralities(diag.cpu().numpy())
+        assert got["trace"] == pytest.approx(want["trace"], rel=1e-13)
+        assert got["kirchhoff"] == pytest.approx(want["kirchhoff"], rel=1e-13)
+        for k in ("farness", "closeness", "nrwb"):
+            np.testing.assert_allclose(got[k].cpu().numpy(), want[k], rtol=1e-13)
+
+
+@pytest.mark.parametrize("idx", [0, 2, 4, 7, 9, 10, 11, 13, 14])
+def test_edge_counts_bit_exact(gpu, idx):
+    name, g, piv = cases_small()[idx]
+    u = piv if piv >= 0 else gg.max_degree_pivot(g)
+    T = 30 if g.n > 2000 else 90
+    say("edge counts", name, g.n, T)
+    G = dev_graph(g)
+    p = api.problem(G, pivot=u, seed=21, trees_per_batch=40)
+    got, rep = api.edge_counts(G, p, 4, T)
+    parents, steps, _ = oracle.trees(g.row_ptr, g.col, u, 21, 4, T, want_counts=False)
+    want = oracle.edge_counts(g.row_ptr, g.col, parents, u)
+    assert (got.cpu().numpy() == want).all()
+    assert rep["walk_steps"] == int(steps.sum())
+
+
+def test_edge_counts_enumerated_resistances(gpu):
+    """Algorithm-free check of the counting kernel: sampled on the GPU, the counts of a long
+    tree range estimate every edge's effective resistance within the Hoeffding bound."""
+    g = gg.grid2d(6)
+    G = dev_graph(g)
+    q = api.edge_sample_size(g.n, g.m, 0.05, 1e-6)
+    assert q == oracle.edge_sample_size(g.n, g.m, 0.05, 1e-6)
+    say("edge resistances", q)
+    got, _ = api.edge_counts(G, api.problem(G, pivot=14, seed=5), 0, q)
+    P = brute.pinv(g)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    sel = rows < g.col
+    est = got.cpu().numpy()[sel] / q
+    r = np.diag(P)[rows[sel]] + np.diag(P)[g.col[sel]] - 2 * P[rows[sel], g.col[sel]]
+    assert np.abs(est - r).max() <= 0.05
