@@ -55,7 +55,7 @@ enum {
 /* One problem instance: the inputs of ApproxDiagLpinv(G, u, eps, delta) (Algorithm 1)
  * plus the solver split kappa and the random seed. */
 typedef struct ustd_problem {
-    int64_t n;                /* vertices, >= 2 */
+    int64_t n;                /* vertices, 2 .. 2^30 (a connected graph with nnz < 2^31) */
     int64_t nnz;              /* row_ptr[n] = 2m; must be < 2^31 */
     const int64_t *d_row_ptr; /* device, n+1 */
     const int32_t *d_col;     /* device, nnz */

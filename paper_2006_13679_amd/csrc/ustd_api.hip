@@ -47,7 +47,7 @@ constexpr long long kAlign = 256;
 constexpr int kLdsBitsMaxWords = 4096;      // tree bitmap in LDS up to 131072 vertices (16 KB)
 constexpr long long kDefaultBudget = 64ll << 30;  // tree records + sampler scratch, of 288 GB HBM
 constexpr int kMaxTreesPerBatch = 8192;
-constexpr int kAggTreesPerChunk = 8;   // trees one aggregation thread sums before its atomic
+constexpr int kEdgeTreesPerChunk = 8;  // trees one edge-counting thread goes through
 
 inline long long align_up(long long v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -71,7 +71,7 @@ struct Plan {
     int n, nnz, K, Kiv, slots, rob, nwords, G, heavy_thresh;
     bool lds_bits, col16;
     long long rec_stride, scr_stride, bits_stride;
-    long long off_misc, off_rp32, off_col16, off_dist, off_parB, off_bnode, off_bflag, off_heavy, off_bcount, off_counts, off_steps,
+    long long off_misc, off_rp32, off_col16, off_dist, off_parB, off_bint, off_bflag, off_heavy, off_bcount, off_counts, off_steps,
         off_draws, off_rec, off_path, off_bits, off_scr, off_part, off_x64, off_r64, off_z64, off_p64, off_q64,
         off_res64, off_x32, off_r32, off_z32, off_p32, off_q32;
     long long total;
@@ -85,7 +85,7 @@ int next_pow2(int v) {
 
 int check_problem(const ustd_problem *p) {
     if (!p) return fail(USTD_EINVAL, "problem is NULL");
-    if (p->n < 2 || p->n >= (1ll << 31) - 1) return fail(USTD_EINVAL, "n = %lld out of range [2, 2^31-1)", (long long)p->n);
+    if (p->n < 2 || p->n > (1ll << 30)) return fail(USTD_EINVAL, "n = %lld out of range [2, 2^30]", (long long)p->n);
     if (p->nnz < 2 || p->nnz >= (1ll << 31)) return fail(USTD_EINVAL, "nnz = %lld out of range [2, 2^31)", (long long)p->nnz);
     if (!p->d_row_ptr || !p->d_col) return fail(USTD_EINVAL, "row_ptr / col is NULL");
     if (p->pivot < -1 || p->pivot >= p->n) return fail(USTD_EINVAL, "pivot %d out of range", p->pivot);
@@ -137,7 +137,7 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     L.off_col16 = take(L.col16 ? (long long)L.nnz * 2 : 0);
     L.off_dist = take(n * 4);
     L.off_parB = take(n * 4);
-    L.off_bnode = take(n * 16);
+    L.off_bint = take(n * 8);
     L.off_bflag = take(n * 4);
     L.off_heavy = take(n * 4);
     L.off_bcount = take((n / 256 + 2) * 4);
@@ -284,7 +284,7 @@ int setup(Ctx &c, ustd_report *rep) {
     if (n <= kSmallSolveMaxN) {
         // BFS tree, connectivity and B_u intervals in one workgroup, one readback
         HIP_TRY(launch_setup_small(c.rows, c.L.G, c.pivot, dist, parB, at<int>(c.ws, c.L.off_scr),
-                                   at<int4>(c.ws, c.L.off_bnode), at<int>(c.ws, c.L.off_bflag), c.misc->setup_out,
+                                   at<int2>(c.ws, c.L.off_bint), at<int>(c.ws, c.L.off_bflag), c.misc->setup_out,
                                    c.st));
         int out[2] = {0, 0};
         HIP_TRY(hipMemcpyAsync(out, c.misc->setup_out, sizeof(out), hipMemcpyDeviceToHost, c.st));
@@ -314,8 +314,8 @@ int setup(Ctx &c, ustd_report *rep) {
     HIP_TRY(hipMemcpyAsync(&err, &c.misc->err_validate, sizeof(int), hipMemcpyDeviceToHost, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
     if (err) return fail(USTD_EGRAPH, "graph is not connected");
-    // subtree intervals of B_u (fixed for every tree): bnode[x] = {parB, pre_B, size_B, 0}
-    HIP_TRY(launch_b_intervals(n, c.pivot, c.ecc, dist, parB, at<int>(c.ws, c.L.off_scr), at<int4>(c.ws, c.L.off_bnode),
+    // subtree intervals of B_u (fixed for every tree): bint[x] = {pre_B, size_B}
+    HIP_TRY(launch_b_intervals(n, c.pivot, c.ecc, dist, parB, at<int>(c.ws, c.L.off_scr), at<int2>(c.ws, c.L.off_bint),
                                at<int>(c.ws, c.L.off_bflag), c.st));
     if (rep) {
         rep->pivot = c.pivot;
@@ -367,8 +367,8 @@ int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag) {
     aa.n = c.L.n;
     aa.u = c.pivot;
     aa.ntrees = cnt;
-    aa.trees_per_chunk = kAggTreesPerChunk;
-    aa.bnode = at<int4>(c.ws, c.L.off_bnode);
+    aa.parB = at<int>(c.ws, c.L.off_parB);
+    aa.bint = at<int2>(c.ws, c.L.off_bint);
     aa.rec = at<int2>(c.ws, c.L.off_rec);
     aa.rec_stride = c.L.rec_stride;
     aa.counts = counts;
@@ -384,7 +384,7 @@ int edge_count_trees(Ctx &c, int cnt, long long *edge_counts, double *ms) {
     ea.n = c.L.n;
     ea.u = c.pivot;
     ea.ntrees = cnt;
-    ea.trees_per_chunk = kAggTreesPerChunk;
+    ea.trees_per_chunk = kEdgeTreesPerChunk;
     ea.rp = c.rp32;
     ea.col = c.p->d_col;
     ea.rec = at<int2>(c.ws, c.L.off_rec);
@@ -892,8 +892,8 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
                 aa.n = B.g[sg.graph].n;
                 aa.u = cs[sg.graph].pivot;
                 aa.ntrees = (int)sg.ntrees;
-                aa.trees_per_chunk = kAggTreesPerChunk;
-                aa.bnode = at<int4>(cs[sg.graph].ws, B.g[sg.graph].off_bnode);
+                aa.parB = at<int>(cs[sg.graph].ws, B.g[sg.graph].off_parB);
+                aa.bint = at<int2>(cs[sg.graph].ws, B.g[sg.graph].off_bint);
                 aa.rec = pool + sg.rec_off;
                 aa.rec_stride = B.g[sg.graph].rec_stride;
                 aa.counts = counts[sg.graph];

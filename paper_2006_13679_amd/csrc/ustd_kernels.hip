@@ -232,20 +232,28 @@ struct TreeBits {
 // when parB(parent_T(x)) = x and parent_T(x) is on P(v) too (traversed backward).  A
 // strict T-ancestor of v on P(v) has a child in B_u, so only vertices that are internal in
 // B_u and whose tree edge is a B_u edge ("marked") can contribute.  Each vertex x stores
-// nba(x) = nearest marked strict T-ancestor (u if none) and its mark bit; cv(x) = x if x is
-// marked, else nba(x), is the nba value of x's children.  Algorithm 2 then follows the nba chain and
-// decides "on P(v)" with the fixed subtree intervals of B_u.
+// nba(x) = nearest marked strict T-ancestor (u if none) and its flags (marked; forward or
+// backward edge); cv(x) = x if x is marked, else nba(x), is the nba value of x's children.
+// Algorithm 2 then follows the nba chain and decides "on P(v)" with the fixed subtree
+// intervals of B_u: a forward x counts if x is on P(v), a backward x if parent_T(x) is.
 //
 // bflag[x] = (parB(x) + 1) | (1 << 31 if x is internal in B_u), so parB(u) = -1.
 __device__ __forceinline__ int bf_parent(int f) { return (int)((unsigned)f & 0x7FFFFFFFu) - 1; }
 __device__ __forceinline__ bool bf_internal(int f) { return (unsigned)f >> 31; }
-__device__ __forceinline__ bool marked_f(int x, int fx, int px, int fpx) {
-    return bf_internal(fx) && (px == bf_parent(fx) || bf_parent(fpx) == x);
-}
-// A record is {parent_T(x), nba(x) | marked(x) << 31}; cv(x) follows from it.
+// A record is {parent_T(x), nba(x) | flags}: bit 31 = x is marked, bit 30 = its tree edge
+// is a forward B_u edge (parent_T(x) = parB(x)), else it is a backward one
+// (parB(parent_T(x)) = x).  Vertex IDs are < 2^30 (a connected graph with nnz < 2^31).
+// cv(x) follows from the record.
 constexpr int kMarkBit = (int)0x80000000u;
+constexpr int kFwdBit = 0x40000000;
 __device__ __forceinline__ int cv_of(int x, int nbx) { return nbx < 0 ? x : nbx; }
-__device__ __forceinline__ int nba_of(int nbx) { return nbx & 0x7FFFFFFF; }
+__device__ __forceinline__ int nba_of(int nbx) { return nbx & 0x3FFFFFFF; }
+// the flag bits of vertex x (B_u flag word fx) whose tree parent is px (flag word fpx)
+__device__ __forceinline__ int mark_bits(int x, int fx, int px, int fpx) {
+    const unsigned fwd = px == bf_parent(fx), bwd = bf_parent(fpx) == x;
+    const unsigned m = ((unsigned)fx >> 31) & (fwd | bwd);
+    return (int)((m << 31) | ((m & fwd) << 30));
+}
 
 // The sampler's block is one wavefront.  Its LDS operations execute in issue order, so
 // lanes exchange data through LDS with compiler ordering only; a workgroup barrier would
@@ -340,7 +348,7 @@ __device__ long long rewalk_commit(const TreeBits<LDS> &bits, int *recw, const i
     z = s0;
     while (z != ya) {
         const int nz = recw[2 * z];
-        if (marked_f(z, bflag[z], nz, bflag[nz])) {
+        if (mark_bits(z, bflag[z], nz, bflag[nz])) {
             for (int w2 = run; w2 != z; w2 = recw[2 * w2]) recw[2 * w2 + 1] = z;
             run = z;
         }
@@ -349,7 +357,7 @@ __device__ long long rewalk_commit(const TreeBits<LDS> &bits, int *recw, const i
     for (int w2 = run; w2 != ya; w2 = recw[2 * w2]) recw[2 * w2 + 1] = cva;
     for (z = s0; z != ya; z = recw[2 * z]) {
         const int nz = recw[2 * z];
-        if (marked_f(z, bflag[z], nz, bflag[nz])) recw[2 * z + 1] |= kMarkBit;
+        recw[2 * z + 1] |= mark_bits(z, bflag[z], nz, bflag[nz]);
     }
     return k;
 }
@@ -655,9 +663,9 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                     for (int j = kPathLds; j >= 0; --j) {
                         if ((keep >> j) & 1u) {
                             const int v = xv[j], fv = xf[j];
-                            const bool mk = marked_f(v, fv, pv, pf);
-                            const int cv = mk ? v : carry;
-                            rec[v] = make_int2(pv, mk ? (carry | kMarkBit) : carry);
+                            const int mb = mark_bits(v, fv, pv, pf);
+                            const int cv = mb ? v : carry;
+                            rec[v] = make_int2(pv, carry | mb);
                             bits.set(v);
                             carry = cv;
                             pv = v;
@@ -761,11 +769,12 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                         const int bi = mine ? br[i] : 0, bfi = mine ? brf[i] : 0;
                         const int nexti = mine ? (i + 1 < blen ? br[i + 1] : ya) : 0;
                         const int nextf = mine ? (i + 1 < blen ? brf[i + 1] : yaf) : 0;
-                        const bool mk = mine && marked_f(bi, bfi, nexti, nextf);
+                        const int mb = mine ? mark_bits(bi, bfi, nexti, nextf) : 0;
+                        const bool mk = mb != 0;
                         const uint64_t m = __ballot(mk);
                         const uint64_t above = lane < kWave - 1 ? (m & (~0ull << (lane + 1))) : 0ull;
                         const int nba = above ? br[c * kWave + __builtin_ctzll(above)] : carry;
-                        if (mine) rec[bi] = make_int2(nexti, mk ? (nba | kMarkBit) : nba);
+                        if (mine) rec[bi] = make_int2(nexti, nba | mb);
                         carry = m ? br[c * kWave + __builtin_ctzll(m)] : carry;
                     }
                     if (lane == 0) steps += istar;
@@ -919,8 +928,7 @@ __global__ __launch_bounds__(kIvThreads) void intervals_kernel(IntervalArgs a) {
                 const int xv = ord[j];
                 const int pv = par[xv];
                 const int nba = cv_of(pv, rec[pv].y);
-                const bool mk = marked_f(xv, a.bflag[xv], pv, a.bflag[pv]);
-                rec[xv] = make_int2(pv, mk ? (nba | kMarkBit) : nba);
+                rec[xv] = make_int2(pv, nba | mark_bits(xv, a.bflag[xv], pv, a.bflag[pv]));
             }
             __syncthreads();
         }
@@ -977,36 +985,59 @@ __global__ __launch_bounds__(kIvThreads) void intervals_kernel(IntervalArgs a) {
 //          + sum over marked strict T-ancestors x of v lying on P(v) of
 //              +1 if parent_T(x) = parB(x),  -1 if parB(parent_T(x)) = x and parent_T(x) on P(v),
 // which equals Algorithm 2's signed count term by term.  "On P(v)" is the B_u subtree test
-// pre_B(x) <= pre_B(v) < pre_B(x) + size_B(x).  Thread per vertex, looping over a chunk of
-// resident trees; one int64 atomic per vertex and chunk, skipped when the sum is zero.
+// pre_B(x) <= pre_B(v) < pre_B(x) + size_B(x).  Thread per vertex over a chunk of resident
+// trees; one int64 atomic per vertex and chunk, skipped when the sum is zero.
 // ======================================================================================
 __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= a.n || v == a.u) return;
-    const int t0 = blockIdx.y * a.trees_per_chunk;
-    const int t1 = min(a.ntrees, t0 + a.trees_per_chunk);
+    const int t0 = blockIdx.y * kAggChunk;
+    const int nt = min(a.ntrees - t0, kAggChunk);
     const int u = a.u;
-    const int4 *__restrict__ bnode = a.bnode;
-    const int4 bv = bnode[v];
-    const int pv = bv.y;
+    const int2 *__restrict__ bint = a.bint;
+    const int pbv = a.parB[v];
+    const int pv = bint[v].x;
+    const int2 *__restrict__ rec0 = a.rec + (long long)t0 * a.rec_stride;
+    // The chains of the chunk's trees are walked in lockstep, one step of every unfinished
+    // chain per round, so their independent loads are in flight together.
+    int x[kAggChunk];
     int sum = 0;
-    for (int t = t0; t < t1; ++t) {
-        const int2 *__restrict__ rec = a.rec + (long long)t * a.rec_stride;
-        const int2 rv = rec[v];
-        sum += (rv.x == bv.x) ? 1 : 0;
-        int x = nba_of(rv.y);
-        while (x != u) {
-            const int2 rx = rec[x];
-            const int4 bx = bnode[x];
-            if (bx.y <= pv && pv < bx.y + bx.z) {
-                if (rx.x == bx.x) {
-                    ++sum;
-                } else {
-                    const int4 bp = bnode[rx.x];
-                    if (bp.x == x && bp.y <= pv && pv < bp.y + bp.z) --sum;
-                }
+#pragma unroll
+    for (int i = 0; i < kAggChunk; ++i) {
+        x[i] = u;
+        if (i < nt) {
+            const int2 rv = rec0[(long long)i * a.rec_stride + v];
+            sum += (rv.x == pbv) ? 1 : 0;
+            x[i] = nba_of(rv.y);
+        }
+    }
+    for (;;) {
+        int2 rx[kAggChunk], bx[kAggChunk];
+        bool act = false;
+#pragma unroll
+        for (int i = 0; i < kAggChunk; ++i) {
+            if (x[i] != u) {
+                act = true;
+                rx[i] = rec0[(long long)i * a.rec_stride + x[i]];
+                bx[i] = bint[x[i]];
             }
-            x = nba_of(rx.y);
+        }
+        if (!act) break;
+#pragma unroll
+        for (int i = 0; i < kAggChunk; ++i) {
+            if (x[i] != u) {
+                // a forward x counts +1 if x is on P(v); a backward x counts -1 if parent_T(x),
+                // a B_u child of x, is on P(v), which needs x on P(v) first
+                if (bx[i].x <= pv && pv < bx[i].x + bx[i].y) {
+                    if (rx[i].y & kFwdBit) {
+                        ++sum;
+                    } else {
+                        const int2 bp = bint[rx[i].x];
+                        if (bp.x <= pv && pv < bp.x + bp.y) --sum;
+                    }
+                }
+                x[i] = nba_of(rx[i].y);
+            }
         }
     }
     if (sum != 0) atomicAdd((unsigned long long *)&a.counts[v], (unsigned long long)(long long)sum);
@@ -1066,11 +1097,11 @@ __global__ __launch_bounds__(256) void bsub_pre_kernel(int n, int d, const int *
     }
 }
 __global__ void bsub_pack_kernel(int n, const int *__restrict__ parB, const int *__restrict__ pre,
-                                 const int *__restrict__ sz, int4 *__restrict__ bnode, int *__restrict__ bflag) {
+                                 const int *__restrict__ sz, int2 *__restrict__ bint, int *__restrict__ bflag) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int pb = parB[v], z = sz[v];
-    bnode[v] = make_int4(pb, pre[v], z, 0);
+    bint[v] = make_int2(pre[v], z);
     bflag[v] = (int)((unsigned)(pb + 1) | (z > 1 ? 0x80000000u : 0u));
 }
 
@@ -1083,7 +1114,7 @@ constexpr int kSetupThreads = 1024;
 template <int G>
 __global__ __launch_bounds__(kSetupThreads) void setup_small_kernel(RowMap m, int u, int *__restrict__ dist,
                                                                     int *__restrict__ parB, int *__restrict__ scratch,
-                                                                    int4 *__restrict__ bnode, int *__restrict__ bflag,
+                                                                    int2 *__restrict__ bint, int *__restrict__ bflag,
                                                                     int *__restrict__ out) {
     __shared__ int found, unreached;
     const int n = m.n, tid = threadIdx.x;
@@ -1172,7 +1203,7 @@ __global__ __launch_bounds__(kSetupThreads) void setup_small_kernel(RowMap m, in
     }
     for (int v = tid; v < n; v += kSetupThreads) {
         const int pb = parB[v], z = sz[v];
-        bnode[v] = make_int4(pb, pre[v], z, 0);
+        bint[v] = make_int2(pre[v], z);
         bflag[v] = (int)((unsigned)(pb + 1) | (z > 1 ? 0x80000000u : 0u));
     }
     if (tid == 0) {
@@ -1181,13 +1212,6 @@ __global__ __launch_bounds__(kSetupThreads) void setup_small_kernel(RowMap m, in
     }
 }
 
-// bflag[x] = (parB(x) + 1) | (1 << 31 if x has a child in B_u)
-__global__ void bflag_kernel(int n, const int4 *__restrict__ bnode, int *__restrict__ bflag) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    const int4 b = bnode[v];
-    bflag[v] = (int)((unsigned)(b.x + 1) | (b.z > 1 ? 0x80000000u : 0u));
-}
 
 // parents[i][v] = rec_i[v].parent
 __global__ void extract_parents_kernel(int n, int ntrees, const int2 *__restrict__ rec, long long rec_stride,
@@ -1728,19 +1752,19 @@ hipError_t launch_extract_parents(int n, int ntrees, const int2 *rec, long long 
     extract_parents_kernel<<<blocks_for((long long)n * ntrees, 256), 256, 0, st>>>(n, ntrees, rec, rec_stride, out);
     return hipGetLastError();
 }
-hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int *parB, int *scratch, int4 *bnode,
+hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int *parB, int *scratch, int2 *bint,
                               int *bflag, hipStream_t st) {
     int *sz = scratch, *cur = scratch + n, *pre = scratch + 2 * n;
     const int nb = blocks_for(n, 256);
     bsub_init_kernel<<<nb, 256, 0, st>>>(n, u, sz, cur, pre);
     for (int d = ecc; d >= 1; --d) bsub_size_kernel<<<nb, 256, 0, st>>>(n, d, dist, parB, sz);
     for (int d = 1; d <= ecc; ++d) bsub_pre_kernel<<<nb, 256, 0, st>>>(n, d, dist, parB, sz, cur, pre);
-    bsub_pack_kernel<<<nb, 256, 0, st>>>(n, parB, pre, sz, bnode, bflag);
+    bsub_pack_kernel<<<nb, 256, 0, st>>>(n, parB, pre, sz, bint, bflag);
     return hipGetLastError();
 }
-hipError_t launch_setup_small(const RowMap &m, int G, int u, int *dist, int *parB, int *scratch, int4 *bnode,
+hipError_t launch_setup_small(const RowMap &m, int G, int u, int *dist, int *parB, int *scratch, int2 *bint,
                               int *bflag, int *out, hipStream_t st) {
-    USTD_DISPATCH_G(G, (setup_small_kernel<GG><<<1, kSetupThreads, 0, st>>>(m, u, dist, parB, scratch, bnode, bflag,
+    USTD_DISPATCH_G(G, (setup_small_kernel<GG><<<1, kSetupThreads, 0, st>>>(m, u, dist, parB, scratch, bint, bflag,
                                                                              out)));
     return hipGetLastError();
 }
@@ -1760,12 +1784,8 @@ hipError_t launch_edge_fold(int n, long long nnz, const int *rp, const int *col,
     edge_fold_kernel<<<blocks_for(nnz, 256), 256, 0, st>>>(n, nnz, rp, col, counts);
     return hipGetLastError();
 }
-hipError_t launch_bflag(int n, const int4 *bnode, int *bflag, hipStream_t st) {
-    bflag_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, bnode, bflag);
-    return hipGetLastError();
-}
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st) {
-    dim3 grid(blocks_for(a.n, 256), (a.ntrees + a.trees_per_chunk - 1) / a.trees_per_chunk);
+    dim3 grid(blocks_for(a.n, 256), (a.ntrees + kAggChunk - 1) / kAggChunk);
     aggregate_kernel<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }

@@ -57,9 +57,12 @@ struct IntervalArgs {
     int *err;
 };
 
+constexpr int kAggChunk = 8;  // trees one aggregation thread walks together
+
 struct AggregateArgs {
-    int n, u, ntrees, trees_per_chunk;
-    const int4 *bnode;
+    int n, u, ntrees;
+    const int *parB;        // [n] B_u parents
+    const int2 *bint;       // [n] {pre_B, size_B} subtree intervals of B_u
     const int2 *rec;
     long long rec_stride;
     long long *counts;
@@ -125,16 +128,15 @@ hipError_t launch_col_to_u16(long long nnz, const int *col, unsigned short *col1
 hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st);
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st);
 hipError_t launch_extract_parents(int n, int ntrees, const int2 *rec, long long rec_stride, int *out, hipStream_t st);
-hipError_t launch_bflag(int n, const int4 *bnode, int *bflag, hipStream_t st);
 hipError_t launch_centralities(long long n, const double *diag, double *farness, double *closeness, double *nrwb,
                                double *scalars, hipStream_t st);
 hipError_t launch_edge_counts(const EdgeCountArgs &a, hipStream_t st);
 hipError_t launch_edge_fold(int n, long long nnz, const int *rp, const int *col, long long *counts, hipStream_t st);
 // BFS tree, connectivity check and B_u intervals of a small graph (n <= kSmallSolveMaxN) in
 // one workgroup; out[0] = ecc, out[1] = 1 if a vertex is unreached; scratch holds 3n ints
-hipError_t launch_setup_small(const RowMap &m, int G, int u, int *dist, int *parB, int *scratch, int4 *bnode,
+hipError_t launch_setup_small(const RowMap &m, int G, int u, int *dist, int *parB, int *scratch, int2 *bint,
                               int *bflag, int *out, hipStream_t st);
-hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int *parB, int *scratch, int4 *bnode,
+hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int *parB, int *scratch, int2 *bint,
                               int *bflag, hipStream_t st);
 template <typename T>
 hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, int it, hipStream_t st);
