@@ -233,3 +233,23 @@ def edge_counts(row_ptr, col, parents, u: int) -> np.ndarray:
         assert (key[slot] == a * n + b).all(), "a parent is not a neighbour"
         np.add.at(counts, slot, 1)
     return counts
+
+
+def sweep_pivot(row_ptr, col, sweeps: int = 10) -> tuple:
+    """Pivot of low eccentricity by repeated BFS sweeps (engineering appendix, after Magnien et
+    al.'s double sweep): BFS from a first source, then from the vertex farthest from it, and
+    so on, `sweeps` BFS in all; every BFS raises each vertex's lower bound on its
+    eccentricity to its distance from the source; the pivot is the vertex with the lowest
+    bound.  Readings: the first source is the maximum-degree vertex (the paper draws it at
+    random); ties everywhere go to the smallest vertex ID.  Returns (pivot, bounds)."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    deg = np.diff(rp)
+    src = int(np.flatnonzero(deg == deg.max())[0])
+    bound = np.zeros(n, dtype=np.int64)
+    for _ in range(sweeps):
+        dist, _, ecc = bfs(rp, c, src)
+        bound = np.maximum(bound, dist)
+        src = int(np.flatnonzero(dist == ecc)[0])
+    piv = int(np.flatnonzero(bound == bound.min())[0])
+    return piv, bound

@@ -458,3 +458,42 @@ def test_edge_sample_size_worked_example():
     assert oracle.edge_sample_size(100, 250, 0.5) == 87
     assert oracle.edge_sample_size(100, 250, 0.5, 0.01) == 87
     assert oracle.edge_sample_size(1000, 250, 0.5, 0.5) == 56  # ln(1000) = 6.9078 * 8 = 55.26
+
+
+# ---------------------------------------------------------------------------------------
+# Pivot by repeated BFS sweeps
+# ---------------------------------------------------------------------------------------
+def test_sweep_pivot_closed_forms():
+    # path P_n: the sweeps alternate between the two ends, bounds are exact, centre floor((n-1)/2)
+    for n in (2, 7, 10):
+        piv, bound = oracle.sweep_pivot(gg.path(n).row_ptr, gg.path(n).col)
+        assert piv == (n - 1) // 2
+        assert list(bound) == [max(x, n - 1 - x) for x in range(n)]
+    # star: the centre has eccentricity 1
+    assert oracle.sweep_pivot(gg.star(9).row_ptr, gg.star(9).col)[0] == 0
+    # cycle C_12: sources 0 and 6 alternate; bound max(d(0,x), d(6,x)) is smallest (3) at x = 3
+    g = gg.cycle(12)
+    piv, bound = oracle.sweep_pivot(g.row_ptr, g.col)
+    d0 = np.minimum(np.arange(12), 12 - np.arange(12))
+    d6 = np.abs(np.arange(12) - 6)
+    assert piv == 3 and list(bound) == list(np.maximum(d0, d6))
+
+
+def test_sweep_pivot_bounds_are_lower_bounds():
+    """Against all-pairs distances: every bound is <= the true eccentricity and equals the
+    largest distance from the sources the sweeps visited."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import shortest_path
+
+    for g in (gg.grid2d(9, 5), gg.rmat(9, 8, 3), gg.random_tree(60, 2)):
+        A = sp.csr_matrix((np.ones(len(g.col)), g.col, g.row_ptr), shape=(g.n, g.n))
+        D = shortest_path(A, unweighted=True).astype(np.int64)
+        ecc = D.max(axis=1)
+        piv, bound = oracle.sweep_pivot(g.row_ptr, g.col)
+        assert (bound <= ecc).all()
+        src = int(np.argmax(np.diff(g.row_ptr)))
+        want = np.zeros(g.n, dtype=np.int64)
+        for _ in range(10):
+            want = np.maximum(want, D[src])
+            src = int(np.flatnonzero(D[src] == D[src].max())[0])
+        assert (bound == want).all() and piv == int(np.argmin(want))
