@@ -59,7 +59,10 @@ typedef struct ustd_problem {
     int64_t nnz;              /* row_ptr[n] = 2m; must be < 2^31 */
     const int64_t *d_row_ptr; /* device, n+1 */
     const int32_t *d_col;     /* device, nnz */
-    int32_t pivot;            /* u in [0, n); -1 selects the maximum-degree vertex (smallest ID on ties) */
+    int32_t pivot;            /* u in [0, n); -1 selects the maximum-degree vertex (smallest ID on ties);
+                                 -2 the vertex with the smallest eccentricity lower bound after 10 BFS
+                                 sweeps (engineering appendix): first source the maximum-degree vertex,
+                                 each next one the farthest from the last, ties to the smallest ID */
     int32_t solve_mode;       /* USTD_SOLVE_FP64 or USTD_SOLVE_MIXED */
     double eps;               /* absolute error bound, > 0 */
     double delta;             /* failure probability in (0,1); <= 0 selects 1/n */

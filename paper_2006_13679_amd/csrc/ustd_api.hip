@@ -88,7 +88,7 @@ int check_problem(const ustd_problem *p) {
     if (p->n < 2 || p->n > (1ll << 30)) return fail(USTD_EINVAL, "n = %lld out of range [2, 2^30]", (long long)p->n);
     if (p->nnz < 2 || p->nnz >= (1ll << 31)) return fail(USTD_EINVAL, "nnz = %lld out of range [2, 2^31)", (long long)p->nnz);
     if (!p->d_row_ptr || !p->d_col) return fail(USTD_EINVAL, "row_ptr / col is NULL");
-    if (p->pivot < -1 || p->pivot >= p->n) return fail(USTD_EINVAL, "pivot %d out of range", p->pivot);
+    if (p->pivot < -2 || p->pivot >= p->n) return fail(USTD_EINVAL, "pivot %d out of range", p->pivot);
     if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(USTD_EINVAL, "eps must be > 0");
     if (p->delta > 0.0 && !(p->delta < 1.0)) return fail(USTD_EINVAL, "delta must lie in (0,1)");
     if (p->kappa > 0.0 && !(p->kappa < 1.0)) return fail(USTD_EINVAL, "kappa must lie in (0,1)");
@@ -258,6 +258,60 @@ int begin(Ctx &c, const ustd_problem *p, void *ws, size_t ws_bytes, void *stream
     return begin_with(c, p, L, ws, stream);
 }
 
+// level-synchronous BFS from src into dist / parB, one readback per level; *ecc = levels - 1
+int bfs_levels(Ctx &c, int src, int *dist, int *parB, int *ecc) {
+    HIP_TRY(launch_bfs_init(c.L.n, src, dist, parB, c.st));
+    int d = 0;
+    for (;; ++d) {
+        HIP_TRY(hipMemsetAsync(&c.misc->bfs_found, 0, sizeof(int), c.st));
+        HIP_TRY(launch_bfs_level(c.rows, c.L.G, d, dist, parB, &c.misc->bfs_found, c.st));
+        int found = 0;
+        HIP_TRY(hipMemcpyAsync(&found, &c.misc->bfs_found, sizeof(int), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        if (!found) break;
+    }
+    *ecc = d;
+    return USTD_OK;
+}
+
+unsigned packed_id(unsigned long long key) { return 0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull); }
+
+// the packed key a reduction kernel left in misc->best_degree (then cleared for the next)
+int read_key(Ctx &c, unsigned long long *key) {
+    HIP_TRY(hipMemcpyAsync(key, &c.misc->best_degree, sizeof(*key), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipMemsetAsync(&c.misc->best_degree, 0, sizeof(*key), c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    return USTD_OK;
+}
+
+// Pivot of low eccentricity by repeated BFS sweeps (engineering appendix): BFS from the
+// maximum-degree vertex, then from the vertex farthest from the last source (smallest ID
+// among the farthest), kPivotSweeps BFS in all; each raises every vertex's lower bound on
+// its eccentricity to its distance; the pivot has the smallest bound (then smallest ID).
+constexpr int kPivotSweeps = 10;
+int sweep_pivot(Ctx &c, int *pivot) {
+    const int n = c.L.n;
+    int *dist = at<int>(c.ws, c.L.off_dist);
+    int *parB = at<int>(c.ws, c.L.off_parB);
+    int *bound = at<int>(c.ws, c.L.off_scr);
+    unsigned long long key = 0;
+    HIP_TRY(hipMemsetAsync(&c.misc->best_degree, 0, sizeof(key), c.st));
+    HIP_TRY(launch_argmax_degree(n, c.rp32, &c.misc->best_degree, c.st));
+    USTD_TRY(read_key(c, &key));
+    int src = (int)packed_id(key);
+    for (int i = 0; i < kPivotSweeps; ++i) {
+        int ecc = 0;
+        USTD_TRY(bfs_levels(c, src, dist, parB, &ecc));
+        HIP_TRY(launch_sweep_update(n, dist, bound, i == 0 ? 1 : 0, &c.misc->best_degree, c.st));
+        USTD_TRY(read_key(c, &key));
+        src = (int)packed_id(key);
+    }
+    HIP_TRY(launch_argmin_bound(n, bound, &c.misc->best_degree, c.st));
+    USTD_TRY(read_key(c, &key));
+    *pivot = (int)packed_id(key);
+    return USTD_OK;
+}
+
 // pivot choice, optional validation and the BFS tree B_u; synchronises the stream
 int setup(Ctx &c, ustd_report *rep) {
     const ustd_problem *p = c.p;
@@ -266,6 +320,8 @@ int setup(Ctx &c, ustd_report *rep) {
     if (p->validate) HIP_TRY(launch_validate(n, p->nnz, (const long long *)p->d_row_ptr, p->d_col, &c.misc->err_validate, c.st));
     if (p->pivot >= 0) {
         c.pivot = p->pivot;
+    } else if (p->pivot == -2) {
+        USTD_TRY(sweep_pivot(c, &c.pivot));
     } else {
         HIP_TRY(launch_argmax_degree(n, c.rp32, &c.misc->best_degree, c.st));
         unsigned long long best = 0;
@@ -298,17 +354,7 @@ int setup(Ctx &c, ustd_report *rep) {
         }
         return USTD_OK;
     }
-    HIP_TRY(launch_bfs_init(n, c.pivot, dist, parB, c.st));
-    int d = 0;
-    for (;; ++d) {
-        HIP_TRY(hipMemsetAsync(&c.misc->bfs_found, 0, sizeof(int), c.st));
-        HIP_TRY(launch_bfs_level(c.rows, c.L.G, d, dist, parB, &c.misc->bfs_found, c.st));
-        int found = 0;
-        HIP_TRY(hipMemcpyAsync(&found, &c.misc->bfs_found, sizeof(int), hipMemcpyDeviceToHost, c.st));
-        HIP_TRY(hipStreamSynchronize(c.st));
-        if (!found) break;
-    }
-    c.ecc = d;
+    USTD_TRY(bfs_levels(c, c.pivot, dist, parB, &c.ecc));
     HIP_TRY(launch_count_unreached(n, dist, &c.misc->err_validate, c.st));
     int err = 0;
     HIP_TRY(hipMemcpyAsync(&err, &c.misc->err_validate, sizeof(int), hipMemcpyDeviceToHost, c.st));

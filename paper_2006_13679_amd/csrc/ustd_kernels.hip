@@ -74,6 +74,40 @@ __global__ void argmax_degree_kernel(int n, const int *__restrict__ rp, unsigned
     if (lane_id() == 0) atomicMax(best, key);
 }
 
+// Pivot by repeated BFS sweeps (engineering appendix): after each BFS, bound[v] = max(bound[v],
+// dist[v]) (bound = dist after the first) and the farthest vertex, largest distance then
+// smallest ID, as a packed key; at the end the vertex of smallest bound, then smallest ID.
+__global__ void sweep_update_kernel(int n, const int *__restrict__ dist, int *__restrict__ bound, int first,
+                                    unsigned long long *__restrict__ far) {
+    unsigned long long key = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int d = dist[v];
+        bound[v] = first ? d : max(bound[v], d);
+        const unsigned long long k = ((unsigned long long)(unsigned)d << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)v);
+        key = k > key ? k : key;
+    }
+#pragma unroll
+    for (int dd = 32; dd > 0; dd >>= 1) {
+        const unsigned long long o = __shfl_xor(key, dd, 64);
+        key = o > key ? o : key;
+    }
+    if (lane_id() == 0) atomicMax(far, key);
+}
+__global__ void argmin_bound_kernel(int n, const int *__restrict__ bound, unsigned long long *__restrict__ best) {
+    unsigned long long key = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const unsigned long long k = ((unsigned long long)(0x7FFFFFFFu - (unsigned)bound[v]) << 32) |
+                                     (unsigned long long)(0xFFFFFFFFu - (unsigned)v);
+        key = k > key ? k : key;
+    }
+#pragma unroll
+    for (int dd = 32; dd > 0; dd >>= 1) {
+        const unsigned long long o = __shfl_xor(key, dd, 64);
+        key = o > key ? o : key;
+    }
+    if (lane_id() == 0) atomicMax(best, key);
+}
+
 __global__ void bfs_init_kernel(int n, int u, int *__restrict__ dist, int *__restrict__ parB) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n) {
@@ -1684,6 +1718,14 @@ hipError_t launch_validate(int n, long long nnz, const long long *rp64, const in
 }
 hipError_t launch_argmax_degree(int n, const int *rp, unsigned long long *best, hipStream_t st) {
     argmax_degree_kernel<<<min(blocks_for(n, 256), 1024), 256, 0, st>>>(n, rp, best);
+    return hipGetLastError();
+}
+hipError_t launch_sweep_update(int n, const int *dist, int *bound, int first, unsigned long long *far, hipStream_t st) {
+    sweep_update_kernel<<<min(blocks_for(n, 256), 1024), 256, 0, st>>>(n, dist, bound, first, far);
+    return hipGetLastError();
+}
+hipError_t launch_argmin_bound(int n, const int *bound, unsigned long long *best, hipStream_t st) {
+    argmin_bound_kernel<<<min(blocks_for(n, 256), 1024), 256, 0, st>>>(n, bound, best);
     return hipGetLastError();
 }
 hipError_t launch_bfs_init(int n, int u, int *dist, int *parB, hipStream_t st) {

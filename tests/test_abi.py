@@ -44,7 +44,7 @@ def test_workspace_bytes_host_only():
     assert b2 < b3
 
 
-@pytest.mark.parametrize("kw", [dict(pivot=1024), dict(pivot=-2), dict(eps=0.0), dict(eps=-1.0), dict(delta=1.5),
+@pytest.mark.parametrize("kw", [dict(pivot=1024), dict(pivot=-3), dict(eps=0.0), dict(eps=-1.0), dict(delta=1.5),
                                 dict(kappa=1.0), dict(solve_mode=7), dict(n=1), dict(nnz=1), dict(d_col=0),
                                 dict(trees_per_batch=100000)])
 def test_invalid_arguments_rejected(kw):

@@ -360,3 +360,23 @@ def test_edge_counts_enumerated_resistances(gpu):
     est = got.cpu().numpy()[sel] / q
     r = np.diag(P)[rows[sel]] + np.diag(P)[g.col[sel]] - 2 * P[rows[sel], g.col[sel]]
     assert np.abs(est - r).max() <= 0.05
+
+
+@pytest.mark.parametrize("idx", range(15))
+def test_sweep_pivot_matches_oracle(gpu, idx):
+    """pivot = -2: the vertex with the smallest eccentricity lower bound after 10 BFS sweeps."""
+    name, g, _ = cases_small()[idx]
+    say("sweep pivot", name)
+    G = dev_graph(g)
+    _, _, ecc, pivot = api.bfs(G, api.problem(G, pivot=-2))
+    want, bound = oracle.sweep_pivot(g.row_ptr, g.col)
+    assert pivot == want
+    assert ecc == oracle.bfs(g.row_ptr, g.col, want)[2]
+
+
+def test_sweep_pivot_rmat16(gpu):
+    g = gg.rmat(16, 16, 1)
+    G = dev_graph(g)
+    say("sweep pivot rmat16")
+    _, _, ecc, pivot = api.bfs(G, api.problem(G, pivot=-2))
+    assert pivot == oracle.sweep_pivot(g.row_ptr, g.col)[0]
