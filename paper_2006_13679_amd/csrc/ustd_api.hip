@@ -70,9 +70,9 @@ struct Misc {                      // small zero-initialised block at the front 
 struct Plan {
     int n, nnz, K, Kiv, slots, rob, nwords, G, heavy_thresh;
     bool lds_bits, col16;
-    long long rec_stride, scr_stride, bits_stride;
+    long long rec_stride, scr_stride;
     long long off_misc, off_rp32, off_col16, off_dist, off_parB, off_bint, off_bflag, off_heavy, off_bcount, off_counts, off_steps,
-        off_draws, off_rec, off_path, off_bits, off_scr, off_part, off_x64, off_r64, off_z64, off_p64, off_q64,
+        off_draws, off_rec, off_path, off_scr, off_part, off_x64, off_r64, off_z64, off_p64, off_q64,
         off_res64, off_x32, off_r32, off_z32, off_p32, off_q32;
     long long total;
 };
@@ -85,7 +85,7 @@ int next_pow2(int v) {
 
 int check_problem(const ustd_problem *p) {
     if (!p) return fail(USTD_EINVAL, "problem is NULL");
-    if (p->n < 2 || p->n > (1ll << 30)) return fail(USTD_EINVAL, "n = %lld out of range [2, 2^30]", (long long)p->n);
+    if (p->n < 2 || p->n >= (1ll << 30) - 1) return fail(USTD_EINVAL, "n = %lld out of range [2, 2^30 - 1)", (long long)p->n);
     if (p->nnz < 2 || p->nnz >= (1ll << 31)) return fail(USTD_EINVAL, "nnz = %lld out of range [2, 2^31)", (long long)p->nnz);
     if (!p->d_row_ptr || !p->d_col) return fail(USTD_EINVAL, "row_ptr / col is NULL");
     if (p->pivot < -2 || p->pivot >= p->n) return fail(USTD_EINVAL, "pivot %d out of range", p->pivot);
@@ -114,10 +114,9 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     L.heavy_thresh = 32 * L.G;
     L.rec_stride = align_up((long long)L.n * 8) / 8;  // int2 records
     L.scr_stride = align_up(interval_scratch_ints(L.n) * 4) / 4;
-    L.bits_stride = L.lds_bits ? 0 : align_up((long long)L.nwords * 4) / 4;
     // trees resident at once (records), and sampler blocks resident at once (scratch slots)
     const long long per_tree = L.rec_stride * 8 + 16;
-    const long long per_slot = kSamplerPathSlot * 8 + L.bits_stride * 4;
+    const long long per_slot = kSamplerPathSlot * 8;
     long long K = p->trees_per_batch > 0 ? p->trees_per_batch : std::max(1ll, kDefaultBudget / (per_tree + per_slot));
     K = std::min<long long>(K, kMaxTreesPerBatch);
     if (p->tau_override > 0) K = std::min<long long>(K, p->tau_override);
@@ -146,7 +145,6 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     L.off_draws = take((long long)L.K * 8);
     L.off_rec = take((long long)L.K * L.rec_stride * 8);
     L.off_path = take((long long)L.slots * kSamplerPathSlot * 8);
-    L.off_bits = take((long long)L.slots * L.bits_stride * 4);
     L.off_scr = take(std::max((long long)L.Kiv * L.scr_stride, 3 * n) * 4);
     L.off_part = take((long long)kMaxSolveGrid * 6 * 8);
     L.off_x64 = take(n * 8);
@@ -394,8 +392,6 @@ int sample_batch(Ctx &c, long long tree_begin, int ntrees, long long *steps, lon
     a.rec = at<int2>(c.ws, c.L.off_rec);
     a.rec_stride = c.L.rec_stride;
     a.path = at<int2>(c.ws, c.L.off_path);
-    a.bits = at<uint32_t>(c.ws, c.L.off_bits);
-    a.bits_stride = c.L.bits_stride;
     a.queue = &c.misc->queue;
     a.steps = steps;
     a.draws = draws;
@@ -628,8 +624,8 @@ struct BatchPlan {
     std::vector<long long> base;  // byte offset of each member's region
     bool lds_bits = true, col16 = true;
     int nwords_max = 0, slots = 0;
-    long long bits_stride = 0, rec_pool = 0, max_tiles = 0;
-    long long off_queue = 0, off_rec = 0, off_path = 0, off_bits = 0, off_steps = 0, off_draws = 0, off_tiles = 0,
+    long long rec_pool = 0, max_tiles = 0;
+    long long off_queue = 0, off_rec = 0, off_path = 0, off_steps = 0, off_draws = 0, off_tiles = 0,
               off_graphs = 0, total = 0;
 };
 
@@ -662,10 +658,9 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
             bounded = false;
         }
     }
-    B.bits_stride = B.lds_bits ? 0 : align_up((long long)B.nwords_max * 4) / 4;
     B.max_tiles = std::max(1ll, std::min(bounded ? want_tiles : kMaxBatchTiles, kMaxBatchTiles));
     B.slots = (int)std::min<long long>(kSamplerMaxBlocks, B.max_tiles);
-    const long long slot_bytes = (long long)B.slots * (kSamplerPathSlot * 8 + B.bits_stride * 4);
+    const long long slot_bytes = (long long)B.slots * kSamplerPathSlot * 8;
     long long pool = std::max(kDefaultBudget - slot_bytes, min_rec);
     if (bounded) pool = std::min(pool, std::max(want_rec, min_rec));
     B.rec_pool = align_up(pool);
@@ -677,7 +672,6 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
     B.off_queue = take(sizeof(int));
     B.off_rec = take(B.rec_pool);
     B.off_path = take((long long)B.slots * kSamplerPathSlot * 8);
-    B.off_bits = take((long long)B.slots * B.bits_stride * 4);
     B.off_steps = take(B.max_tiles * 8);
     B.off_draws = take(B.max_tiles * 8);
     B.off_tiles = take(B.max_tiles * (long long)sizeof(WilsonTile));
@@ -918,8 +912,6 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         a.ntiles = nt;
         a.rec = pool;
         a.path = at<int2>(d_ws, B.off_path);
-        a.bits = at<uint32_t>(d_ws, B.off_bits);
-        a.bits_stride = B.bits_stride;
         a.queue = queue;
         a.steps = steps;
         a.draws = draws;

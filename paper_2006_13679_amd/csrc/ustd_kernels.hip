@@ -248,15 +248,47 @@ static_assert(kPath - kPathLds == kSamplerPathGlobal, "path split");
 //   kRewalk   - re-walk from the start (never expected; keeps the commit exact regardless)
 constexpr int kWalking = -1, kOverflow = -2, kContinue = -3, kRewalk = -4;
 
+// Membership of the tree being built.  Graphs of up to 131072 vertices keep an n-bit
+// bitmap in LDS (allocation words of 32 vertices).  Larger graphs use the vertex's own
+// record: its nba field holds kFree until the vertex joins the tree (the records are
+// cleared when the tree starts), so a membership test reads the line a walk that ends
+// there needs anyway, and joining is the record write itself (set() does nothing).
+// Records are read for membership with agent-scope loads (past the per-CU L1).
+constexpr int kFree = 0x3FFFFFFF;  // nba of a vertex not in the tree; vertex IDs are below it
+
+// the {nba | flags} word of a record another lane of the wave may have written
+__device__ __forceinline__ int load_nbx(const int *recw, int v) {
+    return __hip_atomic_load(recw + 2 * v + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <bool LDS>
-struct TreeBits {
+struct TreeState;
+
+template <>
+struct TreeState<true> {
     uint32_t *w;
-    __device__ __forceinline__ uint32_t word(int i) const {
-        if (LDS) return w[i];
-        return __hip_atomic_load(w + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __device__ __forceinline__ bool test(int v) const { return (word(v >> 5) >> (v & 31)) & 1u; }
+    static constexpr int kShift = 5;  // allocation word: 32 vertices
+    __device__ __forceinline__ uint32_t word(int i, int /*n*/) const { return w[i]; }
+    __device__ __forceinline__ bool test(int v) const { return (w[v >> 5] >> (v & 31)) & 1u; }
     __device__ __forceinline__ void set(int v) const { atomicOr(w + (v >> 5), 1u << (v & 31)); }
+};
+
+template <>
+struct TreeState<false> {
+    int *recw;                        // int pairs {parent, nba | flags}
+    static constexpr int kShift = 3;  // allocation word: 8 vertices
+    __device__ __forceinline__ int nbx(int v) const { return load_nbx(recw, v); }
+    __device__ __forceinline__ uint32_t word(int i, int n) const {
+        uint32_t m = 0u;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int v = (i << 3) + b;
+            if (v < n && nbx(v) != kFree) m |= 1u << b;
+        }
+        return m;
+    }
+    __device__ __forceinline__ bool test(int v) const { return nbx(v) != kFree; }
+    __device__ __forceinline__ void set(int) const {}
 };
 
 // Marked vertices.  Algorithm 2 adds, for v and each edge (a, b) of P(v), +1 when T
@@ -349,7 +381,7 @@ __device__ __forceinline__ int select_bit64(uint64_t x, int k) {
 // for a whole walk; otherwise the Next pointers of steps 0..k0-1 are already written).  One
 // lane; returns the walk's total step count.
 template <bool LDS, typename CT>
-__device__ long long rewalk_commit(const TreeBits<LDS> &bits, int *recw, const int *__restrict__ rp,
+__device__ long long rewalk_commit(const TreeState<LDS> &bits, int *recw, const int *__restrict__ rp,
                                    const CT *__restrict__ col, const int *__restrict__ bflag, int s0, int x0,
                                    long long k0, uint32_t tlo, uint32_t thi, uint32_t key0, uint32_t key1) {
     int xw = x0;
@@ -376,7 +408,7 @@ __device__ long long rewalk_commit(const TreeBits<LDS> &bits, int *recw, const i
         z = recw[2 * z];
     }
     const int ya = z;
-    const int cva = cv_of(ya, recw[2 * ya + 1]);
+    const int cva = cv_of(ya, load_nbx(recw, ya));
     // nba: the nearest marked vertex strictly closer to ya on the branch, else cv(ya)
     int run = s0;
     z = s0;
@@ -417,7 +449,6 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
 
     const int lane = threadIdx.x;
     int2 *__restrict__ gpath = a.path + (long long)blockIdx.x * kSamplerPathSlot;
-    const TreeBits<LDS> bits{LDS ? lds_bits : a.bits + (long long)blockIdx.x * a.bits_stride};
 
     for (;;) {
     // ---------------------------------------------------------------- next tile
@@ -444,15 +475,22 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     const int robm = rob - 1;
     const uint32_t tlo = (uint32_t)(unsigned long long)t, thi = (uint32_t)((unsigned long long)t >> 32);
     int *recw = reinterpret_cast<int *>(rec);  // recw[2x] = parent (Next while walking)
+    TreeState<LDS> bits;
+    if constexpr (LDS) bits.w = lds_bits;
+    else bits.recw = recw;
+    constexpr int kWShift = TreeState<LDS>::kShift, kW = 1 << kWShift;
+    const int nw = (n + kW - 1) >> kWShift;  // allocation words
     const int *__restrict__ bflag = g.bflag;
     const int u = g.u;
     const int *__restrict__ rp = g.rp;
     const CT *__restrict__ col = reinterpret_cast<const CT *>(g.colv);  // int32, or uint16 when n <= 65536
 
-    wait_global();  // the previous tree's bitmap updates have landed
-    for (int i = lane; i < nwords; i += kWave) {
-        if (LDS) bits.w[i] = 0u;
-        else __hip_atomic_store(bits.w + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    wait_global();  // the previous tree's record writes have landed
+    if constexpr (LDS) {
+        for (int i = lane; i < nwords; i += kWave) bits.w[i] = 0u;
+    } else {
+        for (int i = lane; i < n; i += kWave) rec[i] = make_int2(-1, kFree);
+        wait_global();
     }
     for (int i = lane; i < (2 << kHashBits); i += kWave) htab[i] = kWave;
     wave_sync();
@@ -479,13 +517,13 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
         const int rank = __popcll(idle & lanemask_lt());
         int got = 0, mys = 0;
         while (got < want && cursor < n) {
-            const int wbase = cursor >> 5;
+            const int wbase = cursor >> kWShift;
             const int wi = wbase + lane;
             uint32_t fb = 0u;
-            if (wi < nwords) {
-                fb = ~bits.word(wi);
-                if (lane == 0) fb &= ~0u << (cursor & 31);
-                if (wi == nwords - 1 && (n & 31)) fb &= (1u << (n & 31)) - 1u;
+            if (wi < nw) {
+                fb = ~bits.word(wi, n) & (kW == 32 ? ~0u : (1u << kW) - 1u);
+                if (lane == 0) fb &= ~0u << (cursor & (kW - 1));
+                if (wi == nw - 1 && (n & (kW - 1))) fb &= (1u << (n & (kW - 1))) - 1u;
             }
             const int c = __popc(fb);
             const int incl = wave_scan_dpp(c);
@@ -499,13 +537,13 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 if (__shfl(excl, L + st, kWave) <= j) L += st;
             const uint32_t wL = (uint32_t)__shfl((int)fb, L, kWave);
             const int eL = __shfl(excl, L, kWave);
-            if (mode == 0 && j >= 0 && j < min(total, need)) mys = (wbase + L) * 32 + select_bit(wL, j - eL);
+            if (mode == 0 && j >= 0 && j < min(total, need)) mys = ((wbase + L) << kWShift) + select_bit(wL, j - eL);
             if (total >= need) {
                 got = want;
                 cursor = __shfl(mys, select_bit64(idle, want - 1), kWave) + 1;
             } else {
                 got += total;
-                cursor = (wbase + kWave) * 32;
+                cursor = (wbase + kWave) << kWShift;
             }
         }
         if (got > 0) {
@@ -535,12 +573,17 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             const int y = (int)col[r0 + (int)__umulhi(w, (uint32_t)(r1 - r0))];
             // loads for y: tree bit and B_u flag; then either the chain value (the walk ends
             // here) or the next row bounds (it continues)
-            const bool in = bits.test(y);
-            const int fy = bflag[y];
+            bool in;
             int cvy = 0, ny0 = 0, ny1 = 0;
-            if (in) {
-                cvy = recw[2 * y + 1];
+            const int fy = bflag[y];
+            if constexpr (LDS) {
+                in = bits.test(y);
+                if (in) cvy = recw[2 * y + 1];
             } else {
+                cvy = bits.nbx(y);  // membership and chain value in one load
+                in = cvy != kFree;
+            }
+            if (!in) {
                 ny0 = rp[y];
                 ny1 = rp[y + 1];
             }
@@ -689,7 +732,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 const bool need = commit && istar < K;  // ya joined T after the walk passed it
                 if (__ballot(need)) {
                     wait_global();
-                    if (need) carry = cv_of(ya, recw[2 * ya + 1]);
+                    if (need) carry = cv_of(ya, load_nbx(recw, ya));
                 }
                 if (commit) {
                     int pv = ya, pf = yaf;
@@ -795,7 +838,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                         carry = rob_cv[sl];
                     } else {  // ya joined T after the walk passed it: its record was written since
                         wait_global();
-                        carry = cv_of(ya, recw[2 * ya + 1]);
+                        carry = cv_of(ya, load_nbx(recw, ya));
                     }
                     for (int c = (blen - 1) >> 6; c >= 0; --c) {
                         const int i = c * kWave + lane;

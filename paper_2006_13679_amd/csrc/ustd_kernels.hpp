@@ -36,8 +36,6 @@ struct WilsonArgs {
     int2 *rec;                  // records {parent_T, nba | marked << 31}
     long long rec_stride;
     int2 *path;                 // [blocks][kSamplerPathSlot] recorded steps beyond the LDS part
-    uint32_t *bits;             // [blocks][bits_stride] when the tree bitmap lives in global memory
-    long long bits_stride;
     int *queue;                 // tile counter, zero at launch
     long long *steps;           // [ntiles], nullable
     long long *draws;           // [ntiles], nullable
@@ -80,7 +78,7 @@ constexpr int kRrHist = 64;
 constexpr int kSamplerRobMax = 64;       // reorder-buffer entries of the sampler
 constexpr int kSamplerPathGlobal = 250;  // recorded steps per entry kept in global memory
 constexpr long long kSamplerPathSlot = (long long)kSamplerRobMax * kSamplerPathGlobal;  // int2 per block
-constexpr int kSamplerMaxBlocks = 4096;  // resident sampler blocks (path / bitmap slots)
+constexpr int kSamplerMaxBlocks = 4096;  // resident sampler blocks (path slots)
 constexpr int kMaxSolveGrid = 1024;
 
 // degree-balanced row mapping (see the BFS / SpMV kernels)
