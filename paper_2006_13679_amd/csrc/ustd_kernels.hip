@@ -1356,12 +1356,14 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
     return block_sum(v, sh);
 }
 
-// Conjugate gradients, one iteration = three kernels:
-//   spmv  : q = L p, partial p.q per block
-//   update: alpha = rz_i / p.q; x += alpha p; r -= alpha q; z = r / deg; partial r.z, r.r
-//   pdir  : beta = rz_{i+1} / rz_i; p = z + beta p; convergence (r.r <= tol^2 r0.r0)
-// rz is double-buffered by iteration parity so no block overwrites a value another block
-// of the same kernel still reads.
+// Conjugate gradients, one iteration = five kernels:
+//   spmv  : q = L p, partial p.q per block (a large grid)
+//   alpha : one block sums the partials in index order; alpha = rz_i / p.q (or breakdown)
+//   update: x += alpha p; r -= alpha q; z = r / deg; partial r.z, r.r per block
+//   beta  : one block sums them; convergence (r.r <= tol^2 r0.r0) or beta = rz_{i+1} / rz_i
+//   pdir  : p = z + beta p
+// rz is double-buffered by iteration parity.  Once `done` is set (converged or broken
+// down) every later kernel of the solve returns at once.
 template <typename T, int G>
 __global__ __launch_bounds__(256) void cg_spmv_kernel(CgArgs<T> a, RowMap m) {
     __shared__ double sh[4];
@@ -1378,12 +1380,22 @@ __global__ __launch_bounds__(256) void cg_spmv_kernel(CgArgs<T> a, RowMap m) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void cg_update_kernel(CgArgs<T> a, int it) {
+__global__ __launch_bounds__(256) void cg_alpha_kernel(CgArgs<T> a, int it) {
+    __shared__ double sh[4];
+    CgScalars *S = a.sc;
+    if (S->done) return;
+    const double pq = sum_partials(a.part_pq, a.grid_spmv, 1, sh);
+    if (threadIdx.x == 0) {
+        if (pq > 0.0 && pq == pq) S->alpha = S->rz[it & 1] / pq;
+        else S->done = 1;  // breakdown
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cg_update_kernel(CgArgs<T> a) {
     __shared__ double sh[4];
     if (a.sc->done) return;
-    const double pq = sum_partials(a.part_pq, a.grid_spmv, 1, sh);
-    if (!(pq > 0.0 && pq == pq)) return;  // breakdown: cg_pdir sees the same sum and stops
-    const T al = (T)(a.sc->rz[it & 1] / pq);
+    const T al = (T)a.sc->alpha;
     double rz = 0.0, rr = 0.0;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
         a.x[v] += al * a.p[v];
@@ -1403,30 +1415,29 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgArgs<T> a, int it) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void cg_pdir_kernel(CgArgs<T> a, int it) {
+__global__ __launch_bounds__(256) void cg_beta_kernel(CgArgs<T> a, int it) {
     __shared__ double sh[4];
     CgScalars *S = a.sc;
     if (S->done) return;
-    const double pq = sum_partials(a.part_pq, a.grid_spmv, 1, sh);
-    const bool breakdown = !(pq > 0.0 && pq == pq);
-    const double rzn = breakdown ? 0.0 : sum_partials(a.part_rz, a.grid_vec, 2, sh);
-    const double rr = breakdown ? S->rr : sum_partials(a.part_rz + 1, a.grid_vec, 2, sh);
-    const bool conv = breakdown || !(rr > S->tol2 * S->rr0);
-    if (!conv) {
+    const double rzn = sum_partials(a.part_rz, a.grid_vec, 2, sh);
+    const double rr = sum_partials(a.part_rz + 1, a.grid_vec, 2, sh);
+    if (threadIdx.x == 0) {
         const double rzo = S->rz[it & 1];
-        const T be = (T)(rzo != 0.0 ? rzn / rzo : 0.0);
-        for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x)
-            a.p[v] = a.z[v] + be * a.p[v];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
         S->rz[(it + 1) & 1] = rzn;
-        if (!breakdown) {
-            S->rr = rr;
-            S->iter = it + 1;
-            a.rr_hist[it & (kRrHist - 1)] = rr;
-        }
-        if (conv) S->done = 1;
+        S->rr = rr;
+        S->iter = it + 1;
+        a.rr_hist[it & (kRrHist - 1)] = rr;
+        S->beta = rzo != 0.0 ? rzn / rzo : 0.0;
+        if (!(rr > S->tol2 * S->rr0)) S->done = 1;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cg_pdir_kernel(CgArgs<T> a) {
+    if (a.sc->done) return;
+    const T be = (T)a.sc->beta;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x)
+        a.p[v] = a.z[v] + be * a.p[v];
 }
 
 // start of a CG solve of L d = rhs: d = 0, r = rhs (optionally shifted to mean zero and
@@ -1874,7 +1885,10 @@ hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st) {
     aggregate_kernel<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
-int solve_grid(const RowMap &m, int G) { return std::min(row_grid(m, G), kMaxSolveGrid); }
+int solve_grid(const RowMap &m, int G) {
+    const long long tiles = ((long long)m.n + (256 / G) - 1) / (256 / G);
+    return (int)std::min<long long>(std::max<long long>(tiles, 1), kMaxSolveGrid);
+}
 int vec_grid(int n) { return std::max(1, std::min((n + 255) / 256, kMaxSolveGrid)); }
 
 template <typename Tin, typename T>
@@ -1892,8 +1906,10 @@ template hipError_t launch_cg_small<double, float>(const CgArgs<float> &, const 
 template <typename T>
 hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, int it, hipStream_t st) {
     USTD_DISPATCH_G(G, cg_spmv_kernel<T, GG><<<a.grid_spmv, 256, 0, st>>>(a, m));
-    cg_update_kernel<T><<<a.grid_vec, 256, 0, st>>>(a, it);
-    cg_pdir_kernel<T><<<a.grid_vec, 256, 0, st>>>(a, it);
+    cg_alpha_kernel<T><<<1, 256, 0, st>>>(a, it);
+    cg_update_kernel<T><<<a.grid_vec, 256, 0, st>>>(a);
+    cg_beta_kernel<T><<<1, 256, 0, st>>>(a, it);
+    cg_pdir_kernel<T><<<a.grid_vec, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 template hipError_t launch_cg_iteration<double>(const CgArgs<double> &, const RowMap &, int, int, hipStream_t);

@@ -79,7 +79,7 @@ constexpr int kSamplerRobMax = 64;       // reorder-buffer entries of the sample
 constexpr int kSamplerPathGlobal = 250;  // recorded steps per entry kept in global memory
 constexpr long long kSamplerPathSlot = (long long)kSamplerRobMax * kSamplerPathGlobal;  // int2 per block
 constexpr int kSamplerMaxBlocks = 4096;  // resident sampler blocks (path slots)
-constexpr int kMaxSolveGrid = 1024;
+constexpr int kMaxSolveGrid = 8192;  // blocks of the solve's row and vector kernels
 
 // degree-balanced row mapping (see the BFS / SpMV kernels)
 struct RowMap {
@@ -93,6 +93,7 @@ struct RowMap {
 struct CgScalars {
     double rz[2];    // r.z of the current iteration, double-buffered by iteration parity
     double rr, rr0, tol2;
+    double alpha, beta;
     int iter, done;  // done: converged or broken down; later iterations are no-ops
 };
 
