@@ -9,6 +9,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,7 +47,7 @@ int fail(int code, const char *fmt, ...) {
 
 constexpr long long kAlign = 256;
 constexpr int kLdsBitsMaxWords = 4096;      // tree bitmap in LDS up to 131072 vertices (16 KB)
-constexpr long long kDefaultBudget = 64ll << 30;  // tree records + sampler scratch, of 288 GB HBM
+constexpr long long kDefaultBudget = 96ll << 30;  // tree records + sampler scratch, a third of 288 GB HBM
 constexpr int kMaxTreesPerBatch = 8192;
 constexpr int kEdgeTreesPerChunk = 8;  // trees one edge-counting thread goes through
 
@@ -116,7 +118,7 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     L.scr_stride = align_up(interval_scratch_ints(L.n) * 4) / 4;
     // trees resident at once (records), and sampler blocks resident at once (scratch slots)
     const long long per_tree = L.rec_stride * 8 + 16;
-    const long long per_slot = kSamplerPathSlot * 8;
+    const long long per_slot = kSamplerPathSlot * 4;
     long long K = p->trees_per_batch > 0 ? p->trees_per_batch : std::max(1ll, kDefaultBudget / (per_tree + per_slot));
     K = std::min<long long>(K, kMaxTreesPerBatch);
     if (p->tau_override > 0) K = std::min<long long>(K, p->tau_override);
@@ -144,7 +146,7 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     L.off_steps = take((long long)L.K * 8);
     L.off_draws = take((long long)L.K * 8);
     L.off_rec = take((long long)L.K * L.rec_stride * 8);
-    L.off_path = take((long long)L.slots * kSamplerPathSlot * 8);
+    L.off_path = take((long long)L.slots * kSamplerPathSlot * 4);
     L.off_scr = take(std::max((long long)L.Kiv * L.scr_stride, 3 * n) * 4);
     L.off_part = take((long long)kMaxSolveGrid * 6 * 8);
     L.off_x64 = take(n * 8);
@@ -205,6 +207,30 @@ struct Timer {
     ~Timer() {
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
+    }
+};
+
+// One extra stream per device (default priority, not blocking on the null stream) on which
+// the pivot-column solve runs while the trees are sampled on the caller's stream.  Created
+// on first use and kept until the process ends.
+int side_stream(hipStream_t *out) {
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev]) HIP_TRY(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+    *out = streams[dev];
+    return USTD_OK;
+}
+
+// an event without timing, destroyed with its scope
+struct SyncEvent {
+    hipEvent_t e = nullptr;
+    SyncEvent() { (void)hipEventCreateWithFlags(&e, hipEventDisableTiming); }
+    ~SyncEvent() {
+        if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -391,7 +417,7 @@ int sample_batch(Ctx &c, long long tree_begin, int ntrees, long long *steps, lon
     a.tree_begin = tree_begin;
     a.rec = at<int2>(c.ws, c.L.off_rec);
     a.rec_stride = c.L.rec_stride;
-    a.path = at<int2>(c.ws, c.L.off_path);
+    a.path = at<int>(c.ws, c.L.off_path);
     a.queue = &c.misc->queue;
     a.steps = steps;
     a.draws = draws;
@@ -440,8 +466,10 @@ int edge_count_trees(Ctx &c, int cnt, long long *edge_counts, double *ms) {
 
 // Samples trees tree_begin .. +tree_count-1 in batches of at most K; after each batch,
 // Algorithm 2 adds into `counts` and/or the spanning-edge counts into `edge_counts`.
+// `overlap`, if given, runs on the host once the first batch's sampler is queued, before
+// anything waits for it (work for other streams).
 int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *counts, ustd_report *rep,
-              long long *edge_counts = nullptr) {
+              long long *edge_counts = nullptr, const std::function<void()> &overlap = nullptr) {
     long long steps_total = 0, draws_total = 0;
     int batches = 0;
     std::vector<long long> hs(c.L.K), hd(c.L.K);
@@ -456,6 +484,7 @@ int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *cou
         {
             Timer tm(c.st);
             USTD_TRY(sample_batch(c, tree_begin + b0, cnt, steps, draws));
+            if (overlap && batches == 0) overlap();
             ms_s += tm.stop_ms();
         }
         if (counts) USTD_TRY(aggregate_trees(c, cnt, counts, &ms_a));
@@ -660,7 +689,7 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
     }
     B.max_tiles = std::max(1ll, std::min(bounded ? want_tiles : kMaxBatchTiles, kMaxBatchTiles));
     B.slots = (int)std::min<long long>(kSamplerMaxBlocks, B.max_tiles);
-    const long long slot_bytes = (long long)B.slots * kSamplerPathSlot * 8;
+    const long long slot_bytes = (long long)B.slots * kSamplerPathSlot * 4;
     long long pool = std::max(kDefaultBudget - slot_bytes, min_rec);
     if (bounded) pool = std::min(pool, std::max(want_rec, min_rec));
     B.rec_pool = align_up(pool);
@@ -671,7 +700,7 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
     };
     B.off_queue = take(sizeof(int));
     B.off_rec = take(B.rec_pool);
-    B.off_path = take((long long)B.slots * kSamplerPathSlot * 8);
+    B.off_path = take((long long)B.slots * kSamplerPathSlot * 4);
     B.off_steps = take(B.max_tiles * 8);
     B.off_draws = take(B.max_tiles * 8);
     B.off_tiles = take(B.max_tiles * (long long)sizeof(WilsonTile));
@@ -809,10 +838,36 @@ int ustd_diag_lpinv(const ustd_problem *prob, void *d_ws, size_t ws_bytes, doubl
     r->tau = tau;
     long long *counts = d_counts ? (long long *)d_counts : at<long long>(c.ws, c.L.off_counts);
     HIP_TRY(hipMemsetAsync(counts, 0, (size_t)c.L.n * 8, c.st));
-    USTD_TRY(run_trees(c, 0, tau, counts, r));
+    // The pivot column needs only the graph and the pivot: it is solved on the side stream
+    // while the first batch of trees is sampled (the two touch disjoint workspace).
     double *x = at<double>(c.ws, c.L.off_x64);
-    const int src = solve_column(c, x, r);
-    if (src != USTD_OK && src != USTD_ENOTCONV) return src;
+    hipStream_t side = nullptr;
+    USTD_TRY(side_stream(&side));
+    SyncEvent fork, join;
+    if (!fork.e || !join.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
+    HIP_TRY(hipEventRecord(fork.e, c.st));
+    HIP_TRY(hipStreamWaitEvent(side, fork.e, 0));
+    Ctx cs = c;
+    cs.st = side;
+    int src = USTD_EHIP;
+    bool solved = false;
+    const int trc = run_trees(c, 0, tau, counts, r, nullptr, [&]() {
+        src = solve_column(cs, x, r);
+        solved = true;
+    });
+    if (!solved) {
+        if (trc != USTD_OK) return trc;  // failed before the first sampler launch
+        src = solve_column(cs, x, r);
+    }
+    // the side stream is idle on every return below: solve_column ends with a synchronisation
+    // of it, and an early error return is followed by one here
+    if (src != USTD_OK && src != USTD_ENOTCONV) {
+        (void)hipStreamSynchronize(side);
+        return trc != USTD_OK ? trc : src;
+    }
+    if (trc != USTD_OK) return trc;
+    HIP_TRY(hipEventRecord(join.e, side));
+    HIP_TRY(hipStreamWaitEvent(c.st, join.e, 0));
     {
         Timer tm(c.st);
         HIP_TRY(launch_combine(c.L.n, c.pivot, tau, counts, x, d_diag, c.st));
@@ -884,6 +939,32 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
     int fills = 0;
     long long largest = 0;
     const int resident = wilson_resident_blocks(B.lds_bits, B.col16, B.nwords_max);
+
+    // The members' pivot-column solves run on the side stream while the first pool fill is
+    // sampled (each solve touches only its member's solve vectors).
+    hipStream_t side = nullptr;
+    USTD_TRY(side_stream(&side));
+    SyncEvent fork, join;
+    if (!fork.e || !join.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
+    HIP_TRY(hipEventRecord(fork.e, st));
+    HIP_TRY(hipStreamWaitEvent(side, fork.e, 0));
+    int status = USTD_OK, hard = USTD_OK;
+    bool solved = false;
+    auto solve_all = [&]() {
+        solved = true;
+        for (int i = 0; i < count; ++i) {
+            Ctx ci = cs[i];
+            ci.st = side;
+            const int src = solve_column(ci, at<double>(cs[i].ws, B.g[i].off_x64), &R[i]);
+            if (src == USTD_ENOTCONV) {
+                status = member(i, src);
+            } else if (src != USTD_OK) {
+                hard = member(i, src);
+                (void)hipStreamSynchronize(side);
+                return;
+            }
+        }
+    };
     for (;;) {
         tiles.clear();
         segs.clear();
@@ -911,7 +992,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         a.tiles = d_tiles;
         a.ntiles = nt;
         a.rec = pool;
-        a.path = at<int2>(d_ws, B.off_path);
+        a.path = at<int>(d_ws, B.off_path);
         a.queue = queue;
         a.steps = steps;
         a.draws = draws;
@@ -921,6 +1002,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
             Timer tm(st);
             HIP_TRY(hipMemsetAsync(queue, 0, sizeof(int), st));
             HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, B.nwords_max, st));
+            if (!solved) solve_all();
             ms_s += tm.stop_ms();
         }
         {
@@ -951,17 +1033,17 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         ++fills;
     }
 
-    // per member: pivot-column solve and combination
-    int status = USTD_OK;
+    // per member: combination, once the solves are in
+    if (!solved) solve_all();
+    if (hard != USTD_OK) return hard;
+    HIP_TRY(hipEventRecord(join.e, side));
+    HIP_TRY(hipStreamWaitEvent(st, join.e, 0));
     for (int i = 0; i < count; ++i) {
         R[i].n_batches = fills;
         R[i].trees_per_batch = (int32_t)largest;
         R[i].ms_sample = ms_s;
         R[i].ms_aggregate = ms_a;
         double *x = at<double>(cs[i].ws, B.g[i].off_x64);
-        const int src = solve_column(cs[i], x, &R[i]);
-        if (src != USTD_OK && src != USTD_ENOTCONV) return member(i, src);
-        if (src == USTD_ENOTCONV) status = member(i, src);
         Timer tm(st);
         HIP_TRY(launch_combine(B.g[i].n, cs[i].pivot, tau[i], counts[i], x, d_diags[i], st));
         R[i].ms_combine += tm.stop_ms();

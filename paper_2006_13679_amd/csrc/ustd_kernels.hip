@@ -320,6 +320,12 @@ __device__ __forceinline__ int mark_bits(int x, int fx, int px, int fpx) {
     const unsigned m = ((unsigned)fx >> 31) & (fwd | bwd);
     return (int)((m << 31) | ((m & fwd) << 30));
 }
+// The same two bits in the low bits, for a walk step x -> y: the walk records them with y,
+// since a vertex kept by the loop erasure has as its tree edge the step after its last visit.
+__device__ __forceinline__ int edge_bits(int x, int fx, int y, int fy) {
+    return (int)((unsigned)mark_bits(x, fx, y, fy) >> 30);
+}
+constexpr int kVertexMask = 0x3FFFFFFF;  // a recorded global step is y | edge bits << 30
 
 // The sampler's block is one wavefront.  Its LDS operations execute in issue order, so
 // lanes exchange data through LDS with compiler ordering only; a workgroup barrier would
@@ -342,8 +348,10 @@ __device__ __forceinline__ void wait_global() {
 
 // Batch-commit conflict tables: two tables of minimum-writer lanes under independent
 // hashes; a read conflicts only if both of its slots hold a smaller lane, so collisions
-// rarely cut a batch short and a real conflict is never missed.
-constexpr int kHashBits = 8;
+// rarely cut a batch short and a real conflict is never missed.  240 slots each rather than
+// 256 keep the sampler's LDS at R-MAT scale 16 within 8960 bytes, the size at which a CU
+// holds 18 blocks (16 above it).
+constexpr int kHashSlots = 240;
 
 // inclusive prefix sum over the 64 lanes with DPP row shifts and row broadcasts
 __device__ __forceinline__ int wave_scan_dpp(int x) {
@@ -355,8 +363,11 @@ __device__ __forceinline__ int wave_scan_dpp(int x) {
     x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return x;
 }
-__device__ __forceinline__ int hash_slot(int v) { return (int)(((unsigned)v * 2654435761u) >> (32 - kHashBits)); }
-__device__ __forceinline__ int hash_slot2(int v) { return (int)(((unsigned)v * 2246822519u + 3266489917u) >> (32 - kHashBits)); }
+// multiplicative hashes, scaled to [0, kHashSlots) by their high bits
+__device__ __forceinline__ int hash_slot(int v) { return (int)__umulhi((unsigned)v * 2654435761u, kHashSlots); }
+__device__ __forceinline__ int hash_slot2(int v) {
+    return (int)__umulhi((unsigned)v * 2246822519u + 3266489917u, kHashSlots);
+}
 
 // position of the k-th set bit of x (k < popc(x)), by halving
 __device__ __forceinline__ int select_bit(uint32_t x, int k) {
@@ -437,18 +448,24 @@ __device__ __forceinline__ T sel4(int c, T a0, T a1, T a2, T a3) {
 
 template <bool LDS, typename CT>
 __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
+    // Reorder buffer.  Vertex IDs take the column type (16 bits when n <= 65536), so that
+    // with the tree bitmap a block of R-MAT scale 16 fits 18 to a CU.  A recorded step
+    // keeps the vertex and the step's edge bits (below), not the vertex's B_u flag word.
     extern __shared__ uint32_t lds_bits[];
-    __shared__ int rob_s[kRobMax], rob_k[kRobMax], rob_fs[kRobMax], rob_cv[kRobMax];
-    __shared__ int2 rob_p[kRobMax][kPathLds];
-    __shared__ int htab[2 << kHashBits];
-    int *const hslot = htab;                        // first conflict table
-    int *const hslot2 = htab + (1 << kHashBits);    // second conflict table
-    int *const br = htab;                // long-walk branch buffers share the tables'
-    int *const brf = htab + kPath + 1;   // storage; the slots are cleared again afterwards
-    static_assert(2 * (kPath + 1) <= (2 << kHashBits), "branch buffers fit the conflict tables");
+    __shared__ CT rob_s[kRobMax], rob_cv[kRobMax];
+    __shared__ short rob_k[kRobMax];
+    __shared__ unsigned short rob_pb[kRobMax];  // edge bits of steps 1..kPathLds, 2 bits each
+    __shared__ CT rob_p[kRobMax][kPathLds];
+    __shared__ int htab[2 * kHashSlots];
+    int *const hslot = htab;                     // first conflict table
+    int *const hslot2 = htab + kHashSlots;       // second conflict table
+    int *const br = htab;  // a long walk's branch (vertex | edge bits << 30) shares the tables'
+                           // storage; the slots are cleared again afterwards
+    static_assert(kPath + 1 <= 2 * kHashSlots, "the branch buffer fits the conflict tables");
+    static_assert(kPathLds * 2 <= 16, "edge bits fit rob_pb");
 
     const int lane = threadIdx.x;
-    int2 *__restrict__ gpath = a.path + (long long)blockIdx.x * kSamplerPathSlot;
+    int *__restrict__ gpath = a.path + (long long)blockIdx.x * kSamplerPathSlot;
 
     for (;;) {
     // ---------------------------------------------------------------- next tile
@@ -492,7 +509,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
         for (int i = lane; i < n; i += kWave) rec[i] = make_int2(-1, kFree);
         wait_global();
     }
-    for (int i = lane; i < (2 << kHashBits); i += kWave) htab[i] = kWave;
+    for (int i = lane; i < 2 * kHashSlots; i += kWave) htab[i] = kWave;
     wave_sync();
     if (lane == 0) {
         bits.set(u);
@@ -502,7 +519,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
 
     int head = 0, tail = 0, cursor = 0;  // wave-uniform
     int mode = 0;                        // 0 idle, 1 speculative walk
-    int my_e = 0, x = 0, s = 0, k = 0, r0 = 0, r1 = 0, fs = 0;
+    int my_e = 0, x = 0, s = 0, k = 0, r0 = 0, r1 = 0, fx = 0, pbits = 0;
     uint4 ph = make_uint4(0, 0, 0, 0);
     long long steps = 0, draws = 0;
 
@@ -555,10 +572,11 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 mode = 1;
                 r0 = rp[s];
                 r1 = rp[s + 1];
-                fs = bflag[s];  // stored to the entry with the first step, once loaded
+                fx = bflag[s];
+                pbits = 0;
                 const int sl = my_e & robm;
-                rob_s[sl] = s;
-                rob_k[sl] = kWalking;
+                rob_s[sl] = (CT)s;
+                rob_k[sl] = (short)kWalking;
             }
             tail += got;
         }
@@ -592,13 +610,18 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             ++k;
             ++draws;
             const int sl = my_e & robm;
-            if (k == 1) rob_fs[sl] = fs;
-            if (k <= kPathLds) rob_p[sl][k - 1] = make_int2(y, fy);
-            else gpath[sl * (kPath - kPathLds) + (k - 1 - kPathLds)] = make_int2(y, fy);
-            if (in) { rob_k[sl] = k; rob_cv[sl] = cvy; mode = 0; }
-            else if (k == kPath) { rob_k[sl] = kOverflow; mode = 0; }
+            const int eb = edge_bits(x, fx, y, fy);
+            if (k <= kPathLds) {
+                rob_p[sl][k - 1] = (CT)y;
+                pbits |= eb << (2 * (k - 1));
+                rob_pb[sl] = (unsigned short)pbits;
+            } else {
+                gpath[sl * (kPath - kPathLds) + (k - 1 - kPathLds)] = y | (eb << 30);
+            }
+            if (in) { rob_k[sl] = (short)k; rob_cv[sl] = (CT)cvy; mode = 0; }
+            else if (k == kPath) { rob_k[sl] = (short)kOverflow; mode = 0; }
             else if (bits.test(s)) { rob_k[sl] = 0; mode = 0; }  // s absorbed: never walks
-            else { x = y; r0 = ny0; r1 = ny1; }
+            else { x = y; fx = fy; r0 = ny0; r1 = ny1; }
         }
         wave_sync();
 
@@ -611,7 +634,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 // (all earlier starts are committed).  An overflowed walk whose record misses
                 // the tree resumes after its record: the recorded steps become Next pointers.
                 const int sl = head & robm;
-                const int s0 = rob_s[sl];
+                const int s0 = (int)rob_s[sl];
                 if (!bits.test(s0)) {
                     if (hs == kContinue) wait_global();  // recorded steps stored by another lane
                     if (lane == 0) {
@@ -620,8 +643,8 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                         if (hs == kContinue) {
 #pragma unroll 8
                             for (int j = 1; j <= kPath; ++j) {
-                                const int xj = j <= kPathLds ? rob_p[sl][j - 1].x
-                                                             : gpath[sl * (kPath - kPathLds) + (j - 1 - kPathLds)].x;
+                                const int xj = j <= kPathLds ? (int)rob_p[sl][j - 1]
+                                                             : gpath[sl * (kPath - kPathLds) + (j - 1 - kPathLds)] & kVertexMask;
                                 recw[2 * xs] = xj;
                                 xs = xj;
                             }
@@ -638,7 +661,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 continue;
             }
             const int idx = head + lane;
-            const int sk = idx < tail ? rob_k[idx & robm] : kWalking;
+            const int sk = idx < tail ? (int)rob_k[idx & robm] : kWalking;
             const uint64_t okm = __ballot(sk >= 0 && sk <= kPathLds);
             const int r = (~okm == 0ull) ? kWave : __builtin_ctzll(~okm);
             if (r > 0) {
@@ -652,15 +675,12 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 const bool act = lane < r;
                 const int sl = idx & robm;
                 const int K = act ? sk : 0;
-                int xv[kPathLds + 1], xf[kPathLds + 1];
-                xv[0] = act ? rob_s[sl] : -1;
-                xf[0] = act ? rob_fs[sl] : 0;
+                // xv[j] = x_j; bits j = edge bits of the step x_{j-1} -> x_j
+                int xv[kPathLds + 1];
+                xv[0] = act ? (int)rob_s[sl] : -1;
+                const int pb = act ? (int)rob_pb[sl] : 0;
 #pragma unroll
-                for (int j = 1; j <= kPathLds; ++j) {
-                    const int2 e = (j <= K) ? rob_p[sl][j - 1] : make_int2(-1, 0);
-                    xv[j] = e.x;
-                    xf[j] = e.y;
-                }
+                for (int j = 1; j <= kPathLds; ++j) xv[j] = (j <= K) ? (int)rob_p[sl][j - 1] : -1;
                 const bool live = K > 0 && !bits.test(act ? xv[0] : 0);
                 int istar = kPathLds + 1;
 #pragma unroll
@@ -689,7 +709,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 }
                 const uint64_t badm = __ballot(bad);
                 if (badm & 1ull) {  // never expected: fall back to the exact re-walk
-                    rob_k[head & robm] = kRewalk;
+                    rob_k[head & robm] = (short)kRewalk;
                     wave_sync();
                     continue;
                 }
@@ -721,32 +741,30 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 const uint64_t cm = __ballot(conflict);
                 const int jstar = cm ? __builtin_ctzll(cm) : r;
                 const bool commit = live && !bad && lane < jstar;
-                int ya = -1, yaf = 0;
+                int ya = -1;
 #pragma unroll
                 for (int j = 1; j <= kPathLds; ++j)
-                    if (j == istar) {
-                        ya = xv[j];
-                        yaf = xf[j];
-                    }
-                int carry = commit ? rob_cv[sl] : 0;
+                    if (j == istar) ya = xv[j];
+                int carry = commit ? (int)rob_cv[sl] : 0;
                 const bool need = commit && istar < K;  // ya joined T after the walk passed it
                 if (__ballot(need)) {
                     wait_global();
                     if (need) carry = cv_of(ya, load_nbx(recw, ya));
                 }
                 if (commit) {
-                    int pv = ya, pf = yaf;
+                    // a kept x_j is the last visit of its vertex, so its tree edge is the
+                    // recorded step x_j -> x_{j+1}, whose edge bits are step j+1's
+                    int pv = ya;
 #pragma unroll
                     for (int j = kPathLds; j >= 0; --j) {
                         if ((keep >> j) & 1u) {
-                            const int v = xv[j], fv = xf[j];
-                            const int mb = mark_bits(v, fv, pv, pf);
+                            const int v = xv[j];
+                            const int mb = (int)((unsigned)(pb >> (2 * j)) << 30);  // j + 1 <= kPathLds
                             const int cv = mb ? v : carry;
                             rec[v] = make_int2(pv, carry | mb);
                             bits.set(v);
                             carry = cv;
                             pv = v;
-                            pf = fv;
                         }
                     }
                     steps += istar;
@@ -756,33 +774,37 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 continue;
             }
             // head: recorded walk x_0..x_K, kPathLds < K <= 255 (an overflowed walk: its whole
-            // record, K = 255), committed cooperatively; lane j holds x_{j+64c}, c = 0..3
+            // record, K = 255), committed cooperatively; lane j holds x_{j+64c} and the edge bits
+            // of the step into it, c = 0..3
             const int sl = head & robm;
-            const int s0 = rob_s[sl];
+            const int s0 = (int)rob_s[sl];
             if (!bits.test(s0)) {
                 const bool ended = hs >= 0;  // the walk reached the tree it saw
                 const int K = ended ? hs : kPath;
-                int xv[4] = {-1, -1, -1, -1}, xf[4] = {0, 0, 0, 0};
-                {
-                    int2 e = make_int2(-1, 0);
-                    if (lane == 0) e = make_int2(s0, rob_fs[sl]);
-                    else if (lane <= min(K, kPathLds)) e = rob_p[sl][lane - 1];
-                    xv[0] = e.x;
-                    xf[0] = e.y;
+                int xv[4] = {-1, -1, -1, -1}, xb[4] = {0, 0, 0, 0};
+                if (lane == 0) {
+                    xv[0] = s0;
+                } else if (lane <= min(K, kPathLds)) {
+                    xv[0] = (int)rob_p[sl][lane - 1];
+                    xb[0] = ((int)rob_pb[sl] >> (2 * (lane - 1))) & 3;
                 }
                 if (K > kPathLds) {
                     wait_global();  // steps beyond the LDS part were stored by other lanes
+                    int e[4] = {0, 0, 0, 0};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int j = c * kWave + lane;
+                        if (j > kPathLds && j <= K) e[c] = gpath[sl * (kPath - kPathLds) + (j - 1 - kPathLds)];
+                    }
+                    consume(e[0], e[1], e[2], e[3]);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         const int j = c * kWave + lane;
                         if (j > kPathLds && j <= K) {
-                            const int2 e = gpath[sl * (kPath - kPathLds) + (j - 1 - kPathLds)];
-                            xv[c] = e.x;
-                            xf[c] = e.y;
+                            xv[c] = e[c] & kVertexMask;
+                            xb[c] = (int)((unsigned)e[c] >> 30);
                         }
                     }
-                    consume(xv[0], xv[1], xv[2], xv[3]);
-                    consume(xf[0], xf[1], xf[2], xf[3]);
                 }
                 int istar = -1;
 #pragma unroll
@@ -797,12 +819,12 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 if (istar < 0) {
                     // an overflowed walk that still misses the tree resumes after its record; for
                     // a finished walk this cannot happen, and the re-walk keeps the commit exact
-                    rob_k[sl] = ended ? kRewalk : kContinue;
+                    rob_k[sl] = (short)(ended ? kRewalk : kContinue);
                     wave_sync();
                     continue;
                 }
                 // loop erasure: from b, jump past b's last visit before istar
-                int b = s0, bfl = rob_fs[sl], blen = 0, ya = -1, yaf = 0;
+                int b = s0, blen = 0, ya = -1;
                 for (;;) {
                     int qlast = -1;
 #pragma unroll
@@ -815,27 +837,24 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                     if (qlast < 0) break;  // unreachable for a recorded walk; never spin
                     const int nq = qlast + 1, cq = nq >> 6, lq = nq & 63;
                     const int nx = __shfl(sel4(cq, xv[0], xv[1], xv[2], xv[3]), lq, kWave);
-                    const int nf = __shfl(sel4(cq, xf[0], xf[1], xf[2], xf[3]), lq, kWave);
+                    const int nb = __shfl(sel4(cq, xb[0], xb[1], xb[2], xb[3]), lq, kWave);  // edge b -> nx
                     if (lane == 0) {
-                        br[blen] = b;
-                        brf[blen] = bfl;
+                        br[blen] = b | (nb << 30);
                         bits.set(b);
                     }
                     ++blen;
                     if (nq == istar) {
                         ya = nx;
-                        yaf = nf;
                         break;
                     }
                     b = nx;
-                    bfl = nf;
                 }
                 wave_sync();
                 if (ya >= 0) {
                     // records of the branch b_0 = s .. b_{blen-1}, attached to ya
                     int carry;
                     if (ended && istar == K) {
-                        carry = rob_cv[sl];
+                        carry = (int)rob_cv[sl];
                     } else {  // ya joined T after the walk passed it: its record was written since
                         wait_global();
                         carry = cv_of(ya, load_nbx(recw, ya));
@@ -843,22 +862,22 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                     for (int c = (blen - 1) >> 6; c >= 0; --c) {
                         const int i = c * kWave + lane;
                         const bool mine = i < blen;
-                        const int bi = mine ? br[i] : 0, bfi = mine ? brf[i] : 0;
-                        const int nexti = mine ? (i + 1 < blen ? br[i + 1] : ya) : 0;
-                        const int nextf = mine ? (i + 1 < blen ? brf[i + 1] : yaf) : 0;
-                        const int mb = mine ? mark_bits(bi, bfi, nexti, nextf) : 0;
+                        const int be = mine ? br[i] : 0;
+                        const int bi = be & kVertexMask;
+                        const int nexti = mine ? (i + 1 < blen ? br[i + 1] & kVertexMask : ya) : 0;
+                        const int mb = be & ~kVertexMask;  // the edge bits, in the record's flag position
                         const bool mk = mb != 0;
                         const uint64_t m = __ballot(mk);
                         const uint64_t above = lane < kWave - 1 ? (m & (~0ull << (lane + 1))) : 0ull;
-                        const int nba = above ? br[c * kWave + __builtin_ctzll(above)] : carry;
+                        const int nba = above ? br[c * kWave + __builtin_ctzll(above)] & kVertexMask : carry;
                         if (mine) rec[bi] = make_int2(nexti, nba | mb);
-                        carry = m ? br[c * kWave + __builtin_ctzll(m)] : carry;
+                        carry = m ? br[c * kWave + __builtin_ctzll(m)] & kVertexMask : carry;
                     }
                     if (lane == 0) steps += istar;
                 }
             }
             wave_sync();
-            for (int i = lane; i < 2 * (kPath + 1); i += kWave) htab[i] = kWave;
+            for (int i = lane; i < kPath + 1; i += kWave) htab[i] = kWave;
             ++head;
             wave_sync();
         }

@@ -35,7 +35,7 @@ struct WilsonArgs {
     long long tree_begin;
     int2 *rec;                  // records {parent_T, nba | marked << 31}
     long long rec_stride;
-    int2 *path;                 // [blocks][kSamplerPathSlot] recorded steps beyond the LDS part
+    int *path;                  // [blocks][kSamplerPathSlot] recorded steps beyond the LDS part
     int *queue;                 // tile counter, zero at launch
     long long *steps;           // [ntiles], nullable
     long long *draws;           // [ntiles], nullable
@@ -77,8 +77,8 @@ struct EdgeCountArgs {
 constexpr int kRrHist = 64;
 constexpr int kSamplerRobMax = 64;       // reorder-buffer entries of the sampler
 constexpr int kSamplerPathGlobal = 250;  // recorded steps per entry kept in global memory
-constexpr long long kSamplerPathSlot = (long long)kSamplerRobMax * kSamplerPathGlobal;  // int2 per block
-constexpr int kSamplerMaxBlocks = 4096;  // resident sampler blocks (path slots)
+constexpr long long kSamplerPathSlot = (long long)kSamplerRobMax * kSamplerPathGlobal;  // ints per block
+constexpr int kSamplerMaxBlocks = 8192;  // resident sampler blocks (path slots)
 constexpr int kMaxSolveGrid = 8192;  // blocks of the solve's row and vector kernels
 
 // degree-balanced row mapping (see the BFS / SpMV kernels)
