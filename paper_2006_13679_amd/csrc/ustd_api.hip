@@ -189,6 +189,26 @@ double solver_eta(const ustd_problem *p, int ecc) {
     return kappa * p->eps / (3.0 * std::sqrt(m * n * std::log(n)) * (2.0 * std::max(ecc, 1)));
 }
 
+// start/stop events around queued work, read once the stream has been synchronised
+struct SpanTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    SpanTimer() {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    void start(hipStream_t st) { (void)hipEventRecord(a, st); }
+    void stop(hipStream_t st) { (void)hipEventRecord(b, st); }
+    double ms() const {
+        float m = 0.f;
+        (void)hipEventElapsedTime(&m, a, b);
+        return (double)m;
+    }
+    ~SpanTimer() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+};
+
 struct Timer {
     hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
@@ -466,8 +486,8 @@ int edge_count_trees(Ctx &c, int cnt, long long *edge_counts, double *ms) {
 
 // Samples trees tree_begin .. +tree_count-1 in batches of at most K; after each batch,
 // Algorithm 2 adds into `counts` and/or the spanning-edge counts into `edge_counts`.
-// `overlap`, if given, runs on the host once the first batch's sampler is queued, before
-// anything waits for it (work for other streams).
+// `overlap`, if given, runs on the host once all of the first batch's work is queued,
+// before anything waits for it (work for other streams).
 int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *counts, ustd_report *rep,
               long long *edge_counts = nullptr, const std::function<void()> &overlap = nullptr) {
     long long steps_total = 0, draws_total = 0;
@@ -481,17 +501,21 @@ int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *cou
     const long long per = nb > 0 ? (tree_count + nb - 1) / nb : 0;
     for (long long b0 = 0; b0 < tree_count; b0 += per) {
         const int cnt = (int)std::min<long long>(per, tree_count - b0);
-        {
-            Timer tm(c.st);
-            USTD_TRY(sample_batch(c, tree_begin + b0, cnt, steps, draws));
-            if (overlap && batches == 0) overlap();
-            ms_s += tm.stop_ms();
-        }
-        if (counts) USTD_TRY(aggregate_trees(c, cnt, counts, &ms_a));
-        if (edge_counts) USTD_TRY(edge_count_trees(c, cnt, edge_counts, &ms_a));
+        SpanTimer ts, ta;
+        ts.start(c.st);
+        USTD_TRY(sample_batch(c, tree_begin + b0, cnt, steps, draws));
+        ts.stop(c.st);
+        ta.start(c.st);
+        if (counts) USTD_TRY(aggregate_trees(c, cnt, counts, nullptr));
+        if (edge_counts) USTD_TRY(edge_count_trees(c, cnt, edge_counts, nullptr));
+        ta.stop(c.st);
+        // before the copies: a copy into pageable host memory blocks the host until it is done
+        if (overlap && batches == 0) overlap();
         HIP_TRY(hipMemcpyAsync(hs.data(), steps, cnt * sizeof(long long), hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipMemcpyAsync(hd.data(), draws, cnt * sizeof(long long), hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipStreamSynchronize(c.st));
+        ms_s += ts.ms();
+        ms_a += ta.ms();
         for (int i = 0; i < cnt; ++i) {
             steps_total += hs[i];
             draws_total += hd[i];
@@ -998,15 +1022,13 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         a.draws = draws;
         int blocks = std::min(nt, B.slots);
         if (resident > 0) blocks = std::min(blocks, resident);
+        SpanTimer ts, ta;
+        ts.start(st);
+        HIP_TRY(hipMemsetAsync(queue, 0, sizeof(int), st));
+        HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, B.nwords_max, st));
+        ts.stop(st);
         {
-            Timer tm(st);
-            HIP_TRY(hipMemsetAsync(queue, 0, sizeof(int), st));
-            HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, B.nwords_max, st));
-            if (!solved) solve_all();
-            ms_s += tm.stop_ms();
-        }
-        {
-            Timer tm(st);
+            ta.start(st);
             for (const Seg &sg : segs) {
                 AggregateArgs aa{};
                 aa.n = B.g[sg.graph].n;
@@ -1019,13 +1041,17 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
                 aa.counts = counts[sg.graph];
                 HIP_TRY(launch_aggregate(aa, st));
             }
-            ms_a += tm.stop_ms();
+            ta.stop(st);
         }
+        // before the copies: a copy into pageable host memory blocks the host until it is done
+        if (!solved) solve_all();
         hs.resize(nt);
         hd.resize(nt);
         HIP_TRY(hipMemcpyAsync(hs.data(), steps, sizeof(long long) * (size_t)nt, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(hd.data(), draws, sizeof(long long) * (size_t)nt, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        ms_s += ts.ms();
+        ms_a += ta.ms();
         for (int j = 0; j < nt; ++j) {
             R[tiles[j].graph].walk_steps += hs[j];
             R[tiles[j].graph].walk_draws += hd[j];
