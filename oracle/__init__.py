@@ -65,6 +65,29 @@ def lib():
         L.ustd_oracle_diag_lpinv.argtypes = [i64, P, P, i32, dbl, dbl, dbl, u64, i64, dbl, i64,
                                              P, P, P, P, P, P]
         L.ustd_oracle_diag_lpinv.restype = ctypes.c_int
+        L.ustd_oracle_validate_weights.argtypes = [i64, P, P, P]
+        L.ustd_oracle_validate_weights.restype = ctypes.c_int
+        L.ustd_oracle_bpath_resistance.argtypes = [i64, P, P, P, i32, P, P, P]
+        L.ustd_oracle_bpath_resistance.restype = dbl
+        L.ustd_oracle_tau_weighted.argtypes = [i64, i64, dbl, dbl, dbl, dbl]
+        L.ustd_oracle_tau_weighted.restype = i64
+        L.ustd_oracle_fixed_shift.argtypes = [i64, dbl]
+        L.ustd_oracle_fixed_shift.restype = i32
+        L.ustd_oracle_fixed_weights.argtypes = [i64, i32, P, i32, P]
+        L.ustd_oracle_fixed_weights.restype = None
+        L.ustd_oracle_wilson_weighted.argtypes = [i64, P, P, P, i32, u64, i64, P, P, P]
+        L.ustd_oracle_wilson_weighted.restype = i64
+        L.ustd_oracle_tree_flow_weighted.argtypes = [i64, i32, P, P, P, P]
+        L.ustd_oracle_tree_flow_weighted.restype = ctypes.c_int
+        L.ustd_oracle_trees_weighted.argtypes = [i64, P, P, P, i32, P, P, u64, i64, i64, P, P, P]
+        L.ustd_oracle_trees_weighted.restype = ctypes.c_int
+        L.ustd_oracle_solve_weighted.argtypes = [i64, P, P, P, i32, dbl, i64, P, P]
+        L.ustd_oracle_solve_weighted.restype = i64
+        L.ustd_oracle_combine_weighted.argtypes = [i64, i32, i64, i32, P, P, P]
+        L.ustd_oracle_combine_weighted.restype = None
+        L.ustd_oracle_diag_lpinv_weighted.argtypes = [i64, P, P, P, i32, dbl, dbl, dbl, u64, i64, dbl, i64,
+                                                      P, P, P, P, P, P, P]
+        L.ustd_oracle_diag_lpinv_weighted.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -186,6 +209,130 @@ def diag_lpinv(row_ptr, col, u: int, eps: float, seed: int, delta: float = 0.0, 
                                       solve_tol, solve_maxit, _p(diag), _p(counts), ctypes.byref(t),
                                       ctypes.byref(e), ctypes.byref(s), ctypes.byref(rr))
     return dict(diag=diag, counts=counts, tau=t.value, ecc=e.value, steps=s.value,
+                relres=rr.value, status=rc)
+
+
+# ---------------------------------------------------------------------------------------
+# Weighted graphs (Section "Generalizations"; readings in the C file): conductance-weighted
+# Wilson steps, Algorithm 2 with the Ohm's-law factor 1/w(e) in fixed point (F = 2^k / w of
+# each vertex's B_u edge), tau from the largest B-path resistance, weighted Laplacian solve.
+# ---------------------------------------------------------------------------------------
+def _w(w):
+    return np.ascontiguousarray(w, dtype=np.float64)
+
+
+def validate_weights(row_ptr, col, w) -> int:
+    rp, c = _csr(row_ptr, col)
+    return int(lib().ustd_oracle_validate_weights(len(rp) - 1, _p(rp), _p(c), _p(_w(w))))
+
+
+def bpath_resistance(row_ptr, col, w, u: int):
+    """Returns (wB float64[n], rho float64[n], rho_max): the conductance of each vertex's B_u
+    edge and the resistance of P(v), summed from v towards u."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    _, parB, _ = bfs(rp, c, u)
+    wB = np.zeros(n)
+    rho = np.zeros(n)
+    rmax = float(lib().ustd_oracle_bpath_resistance(n, _p(rp), _p(c), _p(_w(w)), u, _p(parB), _p(wB), _p(rho)))
+    return wB, rho, rmax
+
+
+def tau_weighted(n: int, m: int, rho_max: float, eps: float, delta: float = 0.0, kappa: float = 0.0) -> int:
+    return int(lib().ustd_oracle_tau_weighted(n, m, rho_max, eps, delta, kappa))
+
+
+def fixed_shift(tau_: int, rho_max: float) -> int:
+    return int(lib().ustd_oracle_fixed_shift(tau_, rho_max))
+
+
+def fixed_weights(u: int, wB, k: int) -> np.ndarray:
+    wb = _w(wB)
+    F = np.zeros(len(wb), dtype=np.int64)
+    lib().ustd_oracle_fixed_weights(len(wb), u, _p(wb), k, _p(F))
+    return F
+
+
+def wilson_weighted(row_ptr, col, w, u: int, seed: int, t: int):
+    """One tree drawn with probability proportional to its weight.  Returns (parent, steps)."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    parent = np.zeros(n, dtype=np.int32)
+    nxt = np.zeros(n, dtype=np.int32)
+    intree = np.zeros(n, dtype=np.uint8)
+    steps = int(lib().ustd_oracle_wilson_weighted(n, _p(rp), _p(c), _p(_w(w)), u, seed, t, _p(parent), _p(nxt),
+                                                  _p(intree)))
+    return parent, steps
+
+
+def tree_flow_weighted(u: int, parB, parent, F) -> np.ndarray:
+    """Fixed-point c_T(v) of one given tree (Algorithm 2 with +-F[b] per edge), int64[n]."""
+    pb = np.ascontiguousarray(parB, dtype=np.int32)
+    pt = np.ascontiguousarray(parent, dtype=np.int32)
+    f = np.ascontiguousarray(F, dtype=np.int64)
+    acc = np.zeros(len(pb), dtype=np.int64)
+    rc = lib().ustd_oracle_tree_flow_weighted(len(pb), u, _p(pb), _p(pt), _p(f), _p(acc))
+    if rc != OK:
+        raise RuntimeError("oracle tree_flow_weighted failed: %d" % rc)
+    return acc
+
+
+def trees_weighted(row_ptr, col, w, u: int, seed: int, tree_begin: int, tree_count: int, k: int,
+                   want_parents: bool = True, want_acc: bool = True):
+    """Weighted trees [tree_begin, +tree_count) with fixed-point shift k.
+    Returns (parents or None, steps, acc or None)."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    ww = _w(w)
+    _, parB, _ = bfs(rp, c, u)
+    wB, _, _ = bpath_resistance(rp, c, ww, u)
+    F = fixed_weights(u, wB, k)
+    parents = np.zeros((tree_count, n), dtype=np.int32) if want_parents else None
+    steps = np.zeros(tree_count, dtype=np.int64)
+    acc = np.zeros(n, dtype=np.int64) if want_acc else None
+    rc = lib().ustd_oracle_trees_weighted(n, _p(rp), _p(c), _p(ww), u, _p(parB), _p(F), seed, tree_begin,
+                                          tree_count, _p(parents) if parents is not None else None, _p(steps),
+                                          _p(acc) if acc is not None else None)
+    if rc != OK:
+        raise RuntimeError("oracle trees_weighted failed: %d" % rc)
+    return parents, steps, acc
+
+
+def solve_weighted(row_ptr, col, w, u: int, tol: float = 1e-12, maxit: int = 100000):
+    """Column u of the weighted L^+ (FP64 Jacobi-PCG + projection).  Returns (x, iters, relres)."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    x = np.zeros(n, dtype=np.float64)
+    rr = ctypes.c_double(0.0)
+    it = int(lib().ustd_oracle_solve_weighted(n, _p(rp), _p(c), _p(_w(w)), u, tol, maxit, _p(x), ctypes.byref(rr)))
+    return x, it, rr.value
+
+
+def combine_weighted(u: int, tau_: int, k: int, acc, x) -> np.ndarray:
+    a = np.ascontiguousarray(acc, dtype=np.int64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    diag = np.zeros(len(a), dtype=np.float64)
+    lib().ustd_oracle_combine_weighted(len(a), u, tau_, k, _p(a), _p(xx), _p(diag))
+    return diag
+
+
+def diag_lpinv_weighted(row_ptr, col, w, u: int, eps: float, seed: int, delta: float = 0.0, kappa: float = 0.0,
+                        tau_override: int = 0, solve_tol: float = 0.0, solve_maxit: int = 0):
+    """Algorithm 1 on a weighted graph.  Returns dict(diag, acc, tau, shift, rho_max, steps, relres, status)."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    diag = np.zeros(n, dtype=np.float64)
+    acc = np.zeros(n, dtype=np.int64)
+    t = ctypes.c_int64(0)
+    k = ctypes.c_int32(0)
+    rmax = ctypes.c_double(0.0)
+    s = ctypes.c_int64(0)
+    rr = ctypes.c_double(0.0)
+    rc = lib().ustd_oracle_diag_lpinv_weighted(n, _p(rp), _p(c), _p(_w(w)), u, eps, delta, kappa, seed,
+                                               tau_override, solve_tol, solve_maxit, _p(diag), _p(acc),
+                                               ctypes.byref(t), ctypes.byref(k), ctypes.byref(rmax),
+                                               ctypes.byref(s), ctypes.byref(rr))
+    return dict(diag=diag, acc=acc, tau=t.value, shift=k.value, rho_max=rmax.value, steps=s.value,
                 relres=rr.value, status=rc)
 
 

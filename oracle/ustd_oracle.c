@@ -449,3 +449,352 @@ int ustd_oracle_diag_lpinv(int64_t n, const int64_t *rp, const int32_t *col, int
     free(dist); free(parB); free(counts); free(x);
     return rc;
 }
+
+/* ====================================================================================
+ * Weighted graphs (Section "Generalizations", extension to weighted graphs).
+ *
+ * w[e] > 0 is the conductance of CSR entry e, the same in both directions of an edge.
+ * The paper's text leaves three points open; the readings taken here are:
+ *  1. Wilson's walk moves to a neighbour with probability proportional to the
+ *     conductance, so trees come out with probability proportional to their weight (the
+ *     product of their conductances).  Under that distribution the weighted Kirchhoff
+ *     theorem makes the current on an edge the mean signed traversal count, so every tree
+ *     contributes +-1 per traversed edge and the sum is divided by tau, the number of
+ *     trees.  (Adding each tree's weight as well, as the printed text says, would weight
+ *     the trees twice.)
+ *  2. The potential difference along P(v) is the current times the edge's resistance
+ *     1/w(e) (Ohm's law), a factor the unweighted Eq. N-values-in-path does not show.
+ *  3. The sample size replaces ecc(u), the largest range of a tree's contribution in the
+ *     unweighted bound, by rho_max = max_v of the resistance of P(v).  For unit weights
+ *     rho_max = ecc(u) and every definition below reduces to the unweighted one.
+ * To stay exact and order-independent, a tree's contributions are integers: the edge
+ * (b, parB(b)) of P(v) contributes +-F[b], F[b] = llround(2^k / w(b, parB(b))), with k
+ * the largest shift that keeps every sum below 2^62.
+ * ---------------------------------------------------------------------------------- */
+
+/* 0 if every weight is positive and finite and w(v, x) = w(x, v) for every edge. */
+int ustd_oracle_validate_weights(int64_t n, const int64_t *rp, const int32_t *col, const double *w)
+{
+    for (int64_t v = 0; v < n; ++v) {
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
+            if (!(w[e] > 0.0) || !isfinite(w[e])) return ORC_EGRAPH;
+            int32_t x = col[e];
+            int64_t lo = rp[x], hi = rp[x + 1], f = -1;
+            while (lo < hi) {
+                int64_t mid = lo + (hi - lo) / 2;
+                if (col[mid] == (int32_t)v) { f = mid; break; }
+                if (col[mid] < (int32_t)v) lo = mid + 1; else hi = mid;
+            }
+            if (f < 0 || w[f] != w[e]) return ORC_EGRAPH;
+        }
+    }
+    return ORC_OK;
+}
+
+/* Resistance of P(v): the sum of 1/w over its edges, added from v towards u; wB[v] is
+ * the conductance of v's own B_u edge (wB[u] = 0).  Returns rho_max. */
+double ustd_oracle_bpath_resistance(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
+                                    int32_t u, const int32_t *parB, double *wB, double *rho)
+{
+    for (int64_t v = 0; v < n; ++v) {
+        wB[v] = 0.0;
+        if (v == u) continue;
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e)
+            if (col[e] == parB[v]) { wB[v] = w[e]; break; }
+    }
+    double rmax = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+        double r = 0.0;
+        for (int32_t b = (int32_t)v; b != u; b = parB[b]) r += 1.0 / wB[b];
+        rho[v] = r;
+        if (r > rmax) rmax = r;
+    }
+    return rmax;
+}
+
+/* tau = ceil(rho_max^2 * ceil(log(2m/delta) / (2 (1-kappa)^2 eps^2))) (reading 3). */
+int64_t ustd_oracle_tau_weighted(int64_t n, int64_t m, double rho_max, double eps, double delta, double kappa)
+{
+    if (delta <= 0.0) delta = 1.0 / (double)n;
+    if (kappa <= 0.0) kappa = 0.3;
+    double one_minus = 1.0 - kappa;
+    double q = ceil(log(2.0 * (double)m / delta) / (2.0 * one_minus * one_minus * eps * eps));
+    double r2 = rho_max * rho_max;
+    return (int64_t)ceil(r2 * q);
+}
+
+/* Fixed-point shift k: tau * rho_max * 2^k <= 2^62, so no sum of tau trees' contributions
+ * (each at most 2^k rho(v) plus rounding) leaves int64. */
+int32_t ustd_oracle_fixed_shift(int64_t tau, double rho_max)
+{
+    int e = 0;
+    frexp((double)tau * rho_max, &e);
+    return (int32_t)(62 - e);
+}
+
+/* F[b] = llround(2^k / wB[b]) for b != u; F[u] = 0. */
+void ustd_oracle_fixed_weights(int64_t n, int32_t u, const double *wB, int32_t k, int64_t *F)
+{
+    double S = ldexp(1.0, k);
+    for (int64_t v = 0; v < n; ++v) F[v] = v == u ? 0 : llround(S / wB[v]);
+}
+
+/* Wilson's algorithm with conductance-weighted steps.  The walk at x with word w32 goes to
+ * the first neighbour j (ascending adjacency) whose running conductance sum exceeds
+ * t = (w32 * 2^-32) * W_x, W_x the row total; sums are taken left to right in FP64.  With
+ * all conductances 1, t = w32 deg / 2^32 exactly and j = floor(t): the unweighted step. */
+int64_t ustd_oracle_wilson_weighted(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
+                                    int32_t u, uint64_t seed, int64_t t, int32_t *parent, int32_t *next,
+                                    uint8_t *in_tree)
+{
+    int64_t steps = 0;
+    for (int64_t v = 0; v < n; ++v) { in_tree[v] = 0; parent[v] = -1; next[v] = -1; }
+    in_tree[u] = 1;
+    for (int32_t s = 0; s < n; ++s) {
+        if (in_tree[s]) continue;
+        int32_t x = s;
+        int64_t k = 0;
+        while (!in_tree[x]) {
+            uint32_t word = ustd_oracle_walk_word(seed, t, s, k);
+            double total = 0.0;
+            for (int64_t e = rp[x]; e < rp[x + 1]; ++e) total += w[e];
+            double target = ((double)word * 0x1p-32) * total;
+            double run = 0.0;
+            int64_t pick = rp[x + 1] - 1;
+            for (int64_t e = rp[x]; e < rp[x + 1]; ++e) {
+                run += w[e];
+                if (target < run) { pick = e; break; }
+            }
+            next[x] = col[pick];
+            x = next[x];
+            ++k;
+        }
+        steps += k;
+        x = s;
+        while (!in_tree[x]) {
+            in_tree[x] = 1;
+            parent[x] = next[x];
+            x = next[x];
+        }
+    }
+    return steps;
+}
+
+/* Algorithm 2 with the edge factor: as ustd_oracle_tree_flow, adding +-F[b] for the edge
+ * (parB(b), b) instead of +-1 (reading 2); acc[v] += c_T(v). */
+int ustd_oracle_tree_flow_weighted(int64_t n, int32_t u, const int32_t *parB, const int32_t *parent,
+                                   const int64_t *F, int64_t *acc)
+{
+    int32_t *first_child = malloc(sizeof(int32_t) * n);
+    int32_t *sibling = malloc(sizeof(int32_t) * n);
+    int64_t *alpha = malloc(sizeof(int64_t) * n);
+    int64_t *omega = malloc(sizeof(int64_t) * n);
+    int32_t *stack = malloc(sizeof(int32_t) * n);
+    int32_t *cursor = malloc(sizeof(int32_t) * n);
+    if (!first_child || !sibling || !alpha || !omega || !stack || !cursor) {
+        free(first_child); free(sibling); free(alpha); free(omega); free(stack); free(cursor);
+        return ORC_ENOMEM;
+    }
+    for (int64_t v = 0; v < n; ++v) { first_child[v] = -1; sibling[v] = -1; }
+    for (int64_t v = n - 1; v >= 0; --v) {
+        if (v == u) continue;
+        int32_t p = parent[v];
+        sibling[v] = first_child[p];
+        first_child[p] = (int32_t)v;
+    }
+    int64_t clock = 0, top = 0;
+    stack[top++] = u;
+    alpha[u] = clock++;
+    cursor[u] = first_child[u];
+    while (top > 0) {
+        int32_t v = stack[top - 1];
+        int32_t c = cursor[v];
+        if (c >= 0) {
+            cursor[v] = sibling[c];
+            alpha[c] = clock++;
+            cursor[c] = first_child[c];
+            stack[top++] = c;
+        } else {
+            omega[v] = clock++;
+            --top;
+        }
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        if (v == u) continue;
+        int64_t c = 0;
+        int32_t b = (int32_t)v;
+        while (b != u) {
+            int32_t a = parB[b];
+            if (parent[b] == a) {
+                if (alpha[b] <= alpha[v] && omega[v] <= omega[b]) c += F[b];
+            } else if (parent[a] == b) {
+                if (alpha[a] < alpha[v] && omega[v] < omega[a]) c -= F[b];
+            }
+            b = a;
+        }
+        acc[v] += c;
+    }
+    free(first_child); free(sibling); free(alpha); free(omega); free(stack); free(cursor);
+    return ORC_OK;
+}
+
+/* Weighted trees tree_begin .. +tree_count-1: parents (nullable), steps (nullable) and the
+ * fixed-point flow sums accumulated into acc (nullable; needs F). */
+int ustd_oracle_trees_weighted(int64_t n, const int64_t *rp, const int32_t *col, const double *w, int32_t u,
+                               const int32_t *parB, const int64_t *F, uint64_t seed, int64_t tree_begin,
+                               int64_t tree_count, int32_t *parents, int64_t *steps, int64_t *acc)
+{
+    int32_t *parent = malloc(sizeof(int32_t) * n);
+    int32_t *next = malloc(sizeof(int32_t) * n);
+    uint8_t *in_tree = malloc(n);
+    if (!parent || !next || !in_tree) { free(parent); free(next); free(in_tree); return ORC_ENOMEM; }
+    int rc = ORC_OK;
+    for (int64_t i = 0; i < tree_count && rc == ORC_OK; ++i) {
+        int64_t s = ustd_oracle_wilson_weighted(n, rp, col, w, u, seed, tree_begin + i, parent, next, in_tree);
+        if (steps) steps[i] = s;
+        if (parents) memcpy(parents + i * n, parent, sizeof(int32_t) * n);
+        if (acc) rc = ustd_oracle_tree_flow_weighted(n, u, parB, parent, F, acc);
+    }
+    free(parent); free(next); free(in_tree);
+    return rc;
+}
+
+/* Weighted Laplacian: (L p)_v = wdeg(v) p_v - sum_e w[e] p[col[e]], wdeg(v) the row's
+ * conductance sum (left to right).  Jacobi-PCG as ustd_oracle_solve, preconditioned by
+ * wdeg. */
+static void lap_apply_weighted(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
+                               const double *wdeg, const double *p, double *q)
+{
+    for (int64_t v = 0; v < n; ++v) {
+        double acc = wdeg[v] * p[v];
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e) acc -= w[e] * p[col[e]];
+        q[v] = acc;
+    }
+}
+
+int64_t ustd_oracle_solve_weighted(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
+                                   int32_t u, double tol, int64_t maxit, double *x, double *relres_out)
+{
+    double *r = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n);
+    double *p = malloc(sizeof(double) * n), *q = malloc(sizeof(double) * n);
+    double *wdeg = malloc(sizeof(double) * n);
+    if (!r || !z || !p || !q || !wdeg) { free(r); free(z); free(p); free(q); free(wdeg); return -1; }
+    for (int64_t v = 0; v < n; ++v) {
+        double s = 0.0;
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e) s += w[e];
+        wdeg[v] = s;
+    }
+    double bnorm2 = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+        double b = (v == u ? 1.0 : 0.0) - 1.0 / (double)n;
+        x[v] = 0.0;
+        r[v] = b;
+        bnorm2 += b * b;
+    }
+    double bnorm = sqrt(bnorm2);
+    double rz = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+        z[v] = r[v] / wdeg[v];
+        p[v] = z[v];
+        rz += r[v] * z[v];
+    }
+    int64_t it = 0;
+    int converged = bnorm <= tol * bnorm;
+    while (!converged && it < maxit) {
+        lap_apply_weighted(n, rp, col, w, wdeg, p, q);
+        double pq = 0.0;
+        for (int64_t v = 0; v < n; ++v) pq += p[v] * q[v];
+        double alpha = rz / pq;
+        double rr = 0.0;
+        for (int64_t v = 0; v < n; ++v) {
+            x[v] += alpha * p[v];
+            r[v] -= alpha * q[v];
+            rr += r[v] * r[v];
+        }
+        ++it;
+        if (sqrt(rr) <= tol * bnorm) { converged = 1; break; }
+        double rz_new = 0.0;
+        for (int64_t v = 0; v < n; ++v) {
+            z[v] = r[v] / wdeg[v];
+            rz_new += r[v] * z[v];
+        }
+        double beta = rz_new / rz;
+        rz = rz_new;
+        for (int64_t v = 0; v < n; ++v) p[v] = z[v] + beta * p[v];
+    }
+    double mean = 0.0;
+    for (int64_t v = 0; v < n; ++v) mean += x[v];
+    mean /= (double)n;
+    for (int64_t v = 0; v < n; ++v) x[v] -= mean;
+    lap_apply_weighted(n, rp, col, w, wdeg, x, q);
+    double tr = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+        double b = (v == u ? 1.0 : 0.0) - 1.0 / (double)n;
+        tr += (b - q[v]) * (b - q[v]);
+    }
+    if (relres_out) *relres_out = sqrt(tr) / bnorm;
+    free(r); free(z); free(p); free(q); free(wdeg);
+    return converged ? it : -it - 1;
+}
+
+/* Eq. diag-comp with fixed-point sums: L^+_vv = acc[v] / (tau 2^k) - x[u] + 2 x[v]. */
+void ustd_oracle_combine_weighted(int64_t n, int32_t u, int64_t tau, int32_t k, const int64_t *acc,
+                                  const double *x, double *diag)
+{
+    double den = ldexp((double)tau, k);
+    for (int64_t v = 0; v < n; ++v) {
+        if (v == u) diag[v] = x[u];
+        else diag[v] = (double)acc[v] / den - x[u] + 2.0 * x[v];
+    }
+}
+
+/* ApproxDiagLpinv on a weighted graph, end to end (tau_override > 0 replaces the formula).
+ * Outputs diag, acc (nullable), tau, the fixed-point shift, rho_max, steps and the relative
+ * residual of the solve. */
+int ustd_oracle_diag_lpinv_weighted(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
+                                    int32_t u, double eps, double delta, double kappa, uint64_t seed,
+                                    int64_t tau_override, double solve_tol, int64_t solve_maxit,
+                                    double *diag, int64_t *acc_out, int64_t *tau_out, int32_t *shift_out,
+                                    double *rho_out, int64_t *steps_out, double *relres_out)
+{
+    if (u < 0 || u >= n || !(eps > 0.0)) return ORC_EINVAL;
+    int32_t *dist = malloc(sizeof(int32_t) * n), *parB = malloc(sizeof(int32_t) * n);
+    double *wB = malloc(sizeof(double) * n), *rho = malloc(sizeof(double) * n);
+    int64_t *F = malloc(sizeof(int64_t) * n), *acc = calloc((size_t)n, sizeof(int64_t));
+    double *x = malloc(sizeof(double) * n);
+    if (!dist || !parB || !wB || !rho || !F || !acc || !x) {
+        free(dist); free(parB); free(wB); free(rho); free(F); free(acc); free(x);
+        return ORC_ENOMEM;
+    }
+    int32_t ecc = ustd_oracle_bfs(n, rp, col, u, dist, parB);
+    int64_t m = rp[n] / 2;
+    double rho_max = ustd_oracle_bpath_resistance(n, rp, col, w, u, parB, wB, rho);
+    int64_t tau = tau_override > 0 ? tau_override : ustd_oracle_tau_weighted(n, m, rho_max, eps, delta, kappa);
+    int32_t k = ustd_oracle_fixed_shift(tau, rho_max);
+    ustd_oracle_fixed_weights(n, u, wB, k, F);
+    int64_t total_steps = 0;
+    int64_t *st = malloc(sizeof(int64_t) * (size_t)tau);
+    int rc = st ? ustd_oracle_trees_weighted(n, rp, col, w, u, parB, F, seed, 0, tau, NULL, st, acc) : ORC_ENOMEM;
+    if (st) {
+        for (int64_t i = 0; i < tau && rc == ORC_OK; ++i) total_steps += st[i];
+        free(st);
+    }
+    if (rc == ORC_OK) {
+        double tol = solve_tol;
+        if (!(tol > 0.0)) {
+            double eta = ustd_oracle_eta(n, m, ecc, eps, kappa);
+            tol = eta < 1e-12 ? eta : 1e-12;
+        }
+        int64_t it = ustd_oracle_solve_weighted(n, rp, col, w, u, tol, solve_maxit > 0 ? solve_maxit : 100000,
+                                                x, relres_out);
+        ustd_oracle_combine_weighted(n, u, tau, k, acc, x, diag);
+        if (it < 0) rc = ORC_ENOTCONV;
+    }
+    if (acc_out) memcpy(acc_out, acc, sizeof(int64_t) * n);
+    if (tau_out) *tau_out = tau;
+    if (shift_out) *shift_out = k;
+    if (rho_out) *rho_out = rho_max;
+    if (steps_out) *steps_out = total_steps;
+    free(dist); free(parB); free(wB); free(rho); free(F); free(acc); free(x);
+    return rc;
+}

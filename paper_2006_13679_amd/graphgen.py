@@ -301,6 +301,40 @@ def random_connected(n: int, p: float, seed: int) -> Graph:
 
 
 # ----------------------------------------------------------------------------------------
+# edge weights (conductances)
+# ----------------------------------------------------------------------------------------
+def edge_weights(g: Graph, seed: int, kind: str = "uniform", lo: float = 1.0, hi: float = 4.0) -> np.ndarray:
+    """One positive conductance per undirected edge, stored at both CSR entries (float64[2m]).
+    Edges are drawn in the order of their (a < b) CSR entries with default_rng(seed):
+    "uniform" in [lo, hi); "lognormal" exp(N(0, 1)); "pow2" 2^j for an integer j in
+    [log2(lo), log2(hi)] (exactly representable sums); "ones" all 1."""
+    n = g.n
+    rp = np.asarray(g.row_ptr, dtype=np.int64)
+    col = np.asarray(g.col, dtype=np.int64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    upper = rows < col
+    rng = np.random.default_rng(seed)
+    k = int(upper.sum())
+    if kind == "uniform":
+        wu = rng.uniform(lo, hi, size=k)
+    elif kind == "lognormal":
+        wu = np.exp(rng.standard_normal(k))
+    elif kind == "pow2":
+        wu = np.exp2(rng.integers(int(round(math.log2(lo))), int(round(math.log2(hi))) + 1, size=k)).astype(np.float64)
+    elif kind == "ones":
+        wu = np.ones(k)
+    else:
+        raise ValueError(kind)
+    w = np.zeros(len(col), dtype=np.float64)
+    w[upper] = wu
+    key = rows * n + col                      # ascending over the CSR
+    lower = ~upper
+    mirror = np.searchsorted(key, col[lower] * n + rows[lower])
+    w[lower] = w[mirror]
+    return w
+
+
+# ----------------------------------------------------------------------------------------
 # pivots
 # ----------------------------------------------------------------------------------------
 def max_degree_pivot(g: Graph) -> int:

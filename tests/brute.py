@@ -116,3 +116,41 @@ def check_tree(g, par, root):
             x = int(par[x])
             seen += 1
             assert seen <= n, "cycle"
+
+
+# ---------------------------------------------------------------------------------------
+# weighted graphs: conductance per undirected edge, from the CSR weight array
+# ---------------------------------------------------------------------------------------
+def weight_map(g, w) -> dict:
+    rp, col = g.row_ptr, g.col
+    out = {}
+    for v in range(len(rp) - 1):
+        for e in range(rp[v], rp[v + 1]):
+            b = int(col[e])
+            if v < b:
+                out[(v, b)] = float(w[e])
+    return out
+
+
+def laplacian_weighted(g, w) -> np.ndarray:
+    n = g.n
+    L = np.zeros((n, n))
+    for (a, b), c in weight_map(g, w).items():
+        L[a, b] -= c
+        L[b, a] -= c
+        L[a, a] += c
+        L[b, b] += c
+    return L
+
+
+def pinv_weighted(g, w) -> np.ndarray:
+    return np.linalg.pinv(laplacian_weighted(g, w))
+
+
+def tree_weight(par, wmap) -> float:
+    """Product of the conductances of a parent array's edges."""
+    out = 1.0
+    for v, p in enumerate(par):
+        if p >= 0:
+            out *= wmap[(min(v, int(p)), max(v, int(p)))]
+    return out
