@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 WORKLOADS = {
     "rmat16": dict(kind="rmat", scale=16, ef=16, seed=1),
+    # weighted graphs (Section "Generalizations"): R-MAT 16 with conductances uniform in [1, 4)
+    "rmat16w": dict(kind="rmat", scale=16, ef=16, seed=1, weights=("uniform", 1, 1.0, 4.0)),
     "grid32": dict(kind="grid", side=32, tau=1000),
     "rmat18": dict(kind="rmat", scale=18, ef=16, seed=1),
     "rmat20": dict(kind="rmat", scale=20, ef=16, seed=1),
@@ -79,20 +81,29 @@ def load_traffic(kernel: str, workload: str):
     return t
 
 
-def cpu_baseline(g, u, tau, seed, budget_s: float):
+def cpu_baseline(g, u, tau, seed, budget_s: float, w=None):
     """The oracle as it stands on a bounded sample: as many trees as fit in `budget_s`
-    (sampling + DFS + Algorithm 2), plus one full FP64 solve; scaled to the full tau."""
+    (sampling + DFS + Algorithm 2), plus one full FP64 solve; scaled to the full tau.
+    With conductances w, the oracle's weighted walk, aggregation and solve."""
     import oracle
 
     oracle.build()
     t0 = time.perf_counter()
-    x, it, rr = oracle.solve(g.row_ptr, g.col, u, tol=1e-12)
+    if w is None:
+        x, it, rr = oracle.solve(g.row_ptr, g.col, u, tol=1e-12)
+    else:
+        x, it, rr = oracle.solve_weighted(g.row_ptr, g.col, w, u, tol=1e-12)
+        _, _, rmax = oracle.bpath_resistance(g.row_ptr, g.col, w, u)
+        k = oracle.fixed_shift(tau, rmax)
     t_solve = time.perf_counter() - t0
     done, t_trees, chunk = 0, 0.0, 16
     while t_trees < budget_s and done < tau:
         c = min(chunk, tau - done)
         t0 = time.perf_counter()
-        oracle.trees(g.row_ptr, g.col, u, seed, done, c, want_parents=False)
+        if w is None:
+            oracle.trees(g.row_ptr, g.col, u, seed, done, c, want_parents=False)
+        else:
+            oracle.trees_weighted(g.row_ptr, g.col, w, u, seed, done, c, k, want_parents=False)
         t_trees += time.perf_counter() - t0
         done += c
         chunk = min(chunk * 2, 512)
@@ -318,7 +329,16 @@ def main():
 
     g, u, tau_override, cfg = make_workload(args.workload)
     dev = torch.device("cuda:0")
-    G = api.Graph.from_host(g.row_ptr, g.col, device=dev)
+    wspec = WORKLOADS[args.workload].get("weights")
+    w = None
+    if wspec:
+        from paper_2006_13679_amd import graphgen as gg
+
+        kind, wseed, lo, hi = wspec
+        w = gg.edge_weights(g, wseed, kind, lo, hi)
+        cfg = dict(cfg, workload="%s-weighted-%s%gto%g" % (cfg["workload"], kind, lo, hi),
+                   weights="%s[%g,%g) seed %d" % (kind, lo, hi, wseed))
+    G = api.Graph.from_host(g.row_ptr, g.col, device=dev, weight=w)
     mode = api.SOLVE_MIXED if args.solve == "mixed" else api.SOLVE_FP64
     p = api.problem(G, pivot=u, eps=0.3, seed=1, tau_override=tau_override, solve_mode=mode, solve_tol=1e-12,
                     trees_per_batch=args.trees_per_batch)
@@ -387,7 +407,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(g, u, tau, 1, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(g, u, tau, 1, args.cpu_budget, w)
     print(json.dumps(out), flush=True)
 
 

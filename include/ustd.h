@@ -16,17 +16,18 @@
  *    workspace of at least ustd_workspace_bytes() bytes (256-byte aligned), which it
  *    may overwrite freely.  Calls sharing one workspace must not overlap in time.
  *  - Graph input (Section "Problem Description and Notation"): simple, connected,
- *    undirected, unit weights, CSR with row_ptr int64[n+1] (row_ptr[0] = 0,
- *    row_ptr[n] = nnz = 2m), col int32[nnz], every row strictly ascending, every edge
- *    present in both rows, no self-loops.  With `validate` set the library checks all
- *    of this on the device and returns USTD_EGRAPH if it fails.
+ *    undirected, CSR with row_ptr int64[n+1] (row_ptr[0] = 0, row_ptr[n] = nnz = 2m),
+ *    col int32[nnz], every row strictly ascending, every edge present in both rows, no
+ *    self-loops; unit weights, or conductances d_weight (Section "Generalizations").
+ *    With `validate` set the library checks all of this on the device (weights too) and
+ *    returns USTD_EGRAPH if it fails.
  *  - Return value: USTD_OK or an error code; ustd_last_error() gives a thread-local
  *    message.  No C++ exception crosses this boundary.
- *  - Determinism: for a fixed (graph, pivot, seed, tree range) the sampled trees, the
- *    walk-step counts and the integer flow counts are bit-identical across runs, batch
- *    sizes and devices, and equal those of the sequential definition (ascending Wilson
- *    start order, minimum-ID BFS parents, Philox4x32-10 walk words keyed by
- *    (seed; step/4, walk start, tree)).
+ *  - Determinism: for a fixed (graph, weights, pivot, seed, tree range) the sampled
+ *    trees, the walk-step counts and the integer (or, weighted, fixed-point) flow counts
+ *    are bit-identical across runs, batch sizes and devices, and equal those of the
+ *    sequential definition (ascending Wilson start order, minimum-ID BFS parents,
+ *    Philox4x32-10 walk words keyed by (seed; step/4, walk start, tree)).
  */
 #ifndef USTD_H
 #define USTD_H
@@ -74,6 +75,25 @@ typedef struct ustd_problem {
     int32_t validate;         /* 1 = validate the CSR on the device first */
     int32_t trees_per_batch;  /* trees resident in the workspace at once; <= 0 = automatic */
     int32_t tau_cap;          /* > 0: tau = min(formula, tau_cap) (ignored with tau_override) */
+    /* Conductances (Section "Generalizations", weighted graphs): device double[nnz], w[e] > 0
+     * and finite, equal at both entries of an edge; NULL = unit weights.  With weights:
+     *  - a walk at x with word w32 moves to the first neighbour j (ascending adjacency) with
+     *    t < C_x[j], where C_x[j] is the running sum of the row's conductances taken left to
+     *    right in FP64 and t = (w32 * 2^-32) * C_x[deg-1]; trees are then drawn with
+     *    probability proportional to the product of their conductances, and all-ones weights
+     *    give the unweighted trees exactly;
+     *  - Algorithm 2 counts the edge (parB(b), b) of P(v) as +-F[b] instead of +-1, with
+     *    F[b] = llround(2^k / w(b, parB(b))) (the Ohm's-law factor in int64 fixed point);
+     *    the counts R are then sum_T c_T(v) in units of 2^-k and diag[v] = R[v] / (tau 2^k)
+     *    - x[u] + 2 x[v];
+     *  - rho(v) = sum of 1/w over P(v)'s edges, added from v towards u; rho_max = max_v
+     *    rho(v) replaces ecc(u) in the sample size: tau = ceil(rho_max^2 * ceil(ln(2m/delta)
+     *    / (2 (1-kappa)^2 eps^2))) (then tau_cap / tau_override as above);
+     *  - k = 62 - e, where tau * rho_max = f 2^e with f in [0.5, 1), so sums over up to 2 tau
+     *    trees fit int64 (count calls on tree ranges use the problem's tau to fix k);
+     *  - the pivot-column solve uses the weighted Laplacian (Jacobi on weighted degrees).
+     * ustd_batch_diag_lpinv rejects weighted members (USTD_EINVAL). */
+    const double *d_weight;
 } ustd_problem;
 
 /* Filled by the calls that take it (nullable); times from HIP events on `stream`. */
@@ -89,6 +109,9 @@ typedef struct ustd_report {
     int32_t trees_per_batch;
     double solve_relres;  /* ||b - L x||_2 / ||b||_2 of the returned column, in FP64 */
     double ms_setup, ms_bfs, ms_sample, ms_intervals, ms_aggregate, ms_solve, ms_combine, ms_total;
+    double rho_max;       /* largest B-path resistance (= ecc for unit weights) */
+    int32_t fixed_shift;  /* k of the fixed-point counts of a weighted problem (0 unweighted) */
+    int32_t weighted;     /* 1 if d_weight was given */
 } ustd_report;
 
 /* Minimum workspace size for every call below on this problem (host only, no device work).
@@ -115,8 +138,9 @@ int ustd_sample_trees(const ustd_problem *prob, int64_t tree_begin, int64_t tree
 /* Flow counts of trees tree_begin .. +tree_count-1 (Algorithm 2, summed over the trees):
  * d_counts[v] += sum_T c_T(v), where c_T(v) adds +1 for every edge (a,b) of P(v) that T
  * traverses from a to b on its path from u to v and -1 for every one it traverses from b
- * to a (Kirchhoff's theorem; Eq. N-values-in-path).  d_counts is int64[n], accumulated
- * (the caller zeroes it).  Any split of a tree range gives the same final counts.
+ * to a (Kirchhoff's theorem; Eq. N-values-in-path); for a weighted problem +-F[b] in fixed
+ * point (see d_weight).  d_counts is int64[n], accumulated (the caller zeroes it).  Any
+ * split of a tree range gives the same final counts.
  * rep (nullable) receives walk_steps/draws and phase times.  Synchronises `stream`. */
 int ustd_flow_counts(const ustd_problem *prob, int64_t tree_begin, int64_t tree_count,
                      void *d_ws, size_t ws_bytes, int64_t *d_counts, ustd_report *rep,
@@ -124,7 +148,8 @@ int ustd_flow_counts(const ustd_problem *prob, int64_t tree_begin, int64_t tree_
 
 /* Flow counts of caller-supplied spanning trees (Algorithm 2 only): d_parents is
  * int32[tree_count][n] of parent arrays rooted at the pivot (parent[u] = -1); d_counts
- * (int64[n]) is accumulated.  The trees are not checked.  Synchronises `stream`. */
+ * (int64[n]) is accumulated (fixed point for a weighted problem, k from the problem's
+ * tau).  The trees are not checked.  Synchronises `stream`. */
 int ustd_tree_counts(const ustd_problem *prob, const int32_t *d_parents, int64_t tree_count,
                      void *d_ws, size_t ws_bytes, int64_t *d_counts, void *stream);
 
@@ -139,7 +164,9 @@ int ustd_solve_pivot_column(const ustd_problem *prob, void *d_ws, size_t ws_byte
  * the pivot-column solve, and the combination of Eq. diag-comp,
  *   diag[u] = x[u],  diag[v] = R[v]/tau - x[u] + 2 x[v].
  * d_diag is double[n]; d_counts (int64[n], nullable) receives R (overwritten, not
- * accumulated).  Synchronises `stream`. */
+ * accumulated; fixed point with shift rep->fixed_shift for a weighted problem).  The
+ * pivot-column solve runs on a second stream of the library's own, during sampling.
+ * Synchronises `stream`. */
 int ustd_diag_lpinv(const ustd_problem *prob, void *d_ws, size_t ws_bytes, double *d_diag,
                     int64_t *d_counts, ustd_report *rep, void *stream);
 

@@ -37,6 +37,7 @@ class Problem(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("tau_override", ctypes.c_int64),
         ("solve_tol", ctypes.c_double), ("solve_maxit", ctypes.c_int32),
         ("validate", ctypes.c_int32), ("trees_per_batch", ctypes.c_int32), ("tau_cap", ctypes.c_int32),
+        ("d_weight", ctypes.c_void_p),
     ]
 
 
@@ -49,6 +50,7 @@ class Report(ctypes.Structure):
         ("ms_setup", ctypes.c_double), ("ms_bfs", ctypes.c_double), ("ms_sample", ctypes.c_double),
         ("ms_intervals", ctypes.c_double), ("ms_aggregate", ctypes.c_double), ("ms_solve", ctypes.c_double),
         ("ms_combine", ctypes.c_double), ("ms_total", ctypes.c_double),
+        ("rho_max", ctypes.c_double), ("fixed_shift", ctypes.c_int32), ("weighted", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -111,9 +113,11 @@ def _ptr(t: torch.Tensor | None):
 
 @dataclass
 class Graph:
-    """A CSR graph resident on the device (int64 row pointers, int32 columns)."""
+    """A CSR graph resident on the device (int64 row pointers, int32 columns, optional
+    float64 conductances per CSR entry)."""
     row_ptr: torch.Tensor
     col: torch.Tensor
+    weight: torch.Tensor | None = None
 
     @property
     def n(self) -> int:
@@ -124,10 +128,11 @@ class Graph:
         return self.col.numel()
 
     @staticmethod
-    def from_host(row_ptr, col, device="cuda") -> "Graph":
+    def from_host(row_ptr, col, device="cuda", weight=None) -> "Graph":
         rp = torch.as_tensor(row_ptr, dtype=torch.int64).to(device).contiguous()
         c = torch.as_tensor(col, dtype=torch.int32).to(device).contiguous()
-        return Graph(rp, c)
+        w = None if weight is None else torch.as_tensor(weight, dtype=torch.float64).to(device).contiguous()
+        return Graph(rp, c, w)
 
 
 def problem(g: Graph, pivot: int = -1, eps: float = 0.3, seed: int = 1, delta: float = 0.0, kappa: float = 0.0,
@@ -135,10 +140,14 @@ def problem(g: Graph, pivot: int = -1, eps: float = 0.3, seed: int = 1, delta: f
             validate: bool = False, trees_per_batch: int = 0, tau_cap: int = 0) -> Problem:
     assert g.row_ptr.dtype == torch.int64 and g.col.dtype == torch.int32
     assert g.row_ptr.is_cuda and g.col.is_cuda and g.row_ptr.is_contiguous() and g.col.is_contiguous()
+    w = g.weight
+    if w is not None:
+        assert w.dtype == torch.float64 and w.is_cuda and w.is_contiguous() and w.numel() == g.nnz
     return Problem(n=g.n, nnz=g.nnz, d_row_ptr=g.row_ptr.data_ptr(), d_col=g.col.data_ptr(), pivot=pivot,
                    solve_mode=solve_mode, eps=eps, delta=delta, kappa=kappa, seed=seed & 0xFFFFFFFFFFFFFFFF,
                    tau_override=tau_override, solve_tol=solve_tol, solve_maxit=solve_maxit,
-                   validate=1 if validate else 0, trees_per_batch=trees_per_batch, tau_cap=tau_cap)
+                   validate=1 if validate else 0, trees_per_batch=trees_per_batch, tau_cap=tau_cap,
+                   d_weight=w.data_ptr() if w is not None else None)
 
 
 def workspace_bytes(p: Problem) -> int:
@@ -244,9 +253,10 @@ def diag_lpinv_p(g: Graph, p: Problem, ws: Workspace | None = None, want_counts:
     return diag, counts, out
 
 
-def diag_lpinv(row_ptr, col, pivot: int = -1, eps: float = 0.3, seed: int = 1, **kw):
-    """diag(L^+) of a CSR graph (host or device arrays) by the UST estimator."""
-    g = Graph.from_host(row_ptr, col)
+def diag_lpinv(row_ptr, col, pivot: int = -1, eps: float = 0.3, seed: int = 1, weight=None, **kw):
+    """diag(L^+) of a CSR graph (host or device arrays; optional conductances per CSR entry)
+    by the UST estimator."""
+    g = Graph.from_host(row_ptr, col, weight=weight)
     p = problem(g, pivot=pivot, eps=eps, seed=seed, **kw)
     return diag_lpinv_p(g, p)
 

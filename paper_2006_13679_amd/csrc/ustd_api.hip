@@ -62,6 +62,7 @@ struct Misc {                      // small zero-initialised block at the front 
     int setup_out[2];              // small-graph set-up: ecc, unreached flag
     int pad_[3];
     unsigned long long best_degree;
+    unsigned long long rho_max_bits;  // weighted: the largest B-path resistance, as double bits
     CgScalars sc64, sc32;
     double rr_hist64[kRrHist];
     double rr_hist32[kRrHist];
@@ -71,11 +72,11 @@ struct Misc {                      // small zero-initialised block at the front 
 
 struct Plan {
     int n, nnz, K, Kiv, slots, rob, nwords, G, heavy_thresh;
-    bool lds_bits, col16;
+    bool lds_bits, col16, weighted;
     long long rec_stride, scr_stride;
     long long off_misc, off_rp32, off_col16, off_dist, off_parB, off_bint, off_bflag, off_heavy, off_bcount, off_counts, off_steps,
         off_draws, off_rec, off_path, off_scr, off_part, off_x64, off_r64, off_z64, off_p64, off_q64,
-        off_res64, off_x32, off_r32, off_z32, off_p32, off_q32;
+        off_res64, off_x32, off_r32, off_z32, off_p32, off_q32, off_cw, off_wdeg, off_wB, off_F;
     long long total;
 };
 
@@ -110,6 +111,7 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     L.nwords = (L.n + 31) / 32;
     L.lds_bits = L.nwords <= kLdsBitsMaxWords;
     L.col16 = L.n <= 65536;  // 16-bit column copy for the sampler (half the cache footprint)
+    L.weighted = p->d_weight != nullptr;
     L.rob = std::min(kSamplerRobMax, next_pow2(std::max(L.n, 2)));
     const double avg = (double)L.nnz / (double)L.n;
     L.G = avg <= 6.0 ? 4 : (avg <= 16.0 ? 8 : (avg <= 48.0 ? 16 : 32));
@@ -160,6 +162,12 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     L.off_z32 = take(n * 4);
     L.off_p32 = take(n * 4);
     L.off_q32 = take(n * 4);
+    // weighted graphs: running row sums of the conductances, row totals, B_u edge weights,
+    // fixed-point edge factors
+    L.off_cw = take(L.weighted ? (long long)L.nnz * 8 : 0);
+    L.off_wdeg = take(L.weighted ? n * 8 : 0);
+    L.off_wB = take(L.weighted ? n * 8 : 0);
+    L.off_F = take(L.weighted ? n * 8 : 0);
     L.total = o;
     return L;
 }
@@ -180,6 +188,27 @@ long long sample_size(const ustd_problem *p, int ecc) {
     const double q = std::log(2.0 * m / delta) / (2.0 * om * om * p->eps * p->eps);
     const long long tau = (long long)ecc * (long long)ecc * (long long)std::ceil(q);
     return p->tau_cap > 0 ? std::min<long long>(tau, p->tau_cap) : tau;
+}
+
+// Weighted graphs (Section "Generalizations"): rho_max, the largest resistance of a B_u
+// path, takes the place of ecc(u): tau = ceil(rho_max^2 ceil(ln(2m/delta) / (2 (1-kappa)^2
+// eps^2))), then tau_cap; tau_override replaces the formula.
+long long sample_size_weighted(const ustd_problem *p, double rho_max) {
+    if (p->tau_override > 0) return p->tau_override;
+    const double n = (double)p->n, m = (double)(p->nnz / 2);
+    const double delta = p->delta > 0.0 ? p->delta : 1.0 / n;
+    const double kappa = p->kappa > 0.0 ? p->kappa : 0.3;
+    const double om = 1.0 - kappa;
+    const double q = std::ceil(std::log(2.0 * m / delta) / (2.0 * om * om * p->eps * p->eps));
+    const double r2 = rho_max * rho_max;
+    const long long tau = (long long)std::ceil(r2 * q);
+    return p->tau_cap > 0 ? std::min<long long>(tau, p->tau_cap) : tau;
+}
+// Fixed-point shift of a weighted problem's counts: tau rho_max 2^k <= 2^62.
+int fixed_shift(long long tau, double rho_max) {
+    int e = 0;
+    std::frexp((double)tau * rho_max, &e);
+    return 62 - e;
 }
 
 // eta = kappa eps / (3 sqrt(m n ln n) diam), diam <= 2 ecc (Algorithm 1, solver accuracy)
@@ -263,7 +292,15 @@ struct Ctx {
     int *rp32;
     RowMap rows;
     int pivot = -1, ecc = 0;
+    double rho_max = 0.0;  // weighted: largest B-path resistance
+    long long tau = 0;     // weighted: the problem's tau (fixes the shift)
+    int shift = 0;         // weighted: fixed-point shift k of the counts
 };
+
+// tau of the problem set up in c
+long long problem_tau(const Ctx &c) { return c.L.weighted ? c.tau : sample_size(c.p, c.ecc); }
+// denominator of Eq. diag-comp for the counts: tau, or tau 2^k (fixed point)
+double count_scale(const Ctx &c, long long tau) { return std::ldexp((double)tau, c.L.weighted ? c.shift : 0); }
 
 int check_ws(void *ws, size_t ws_bytes, long long need) {
     if (!ws) return fail(USTD_EINVAL, "workspace is NULL");
@@ -290,6 +327,14 @@ int begin_with(Ctx &c, const ustd_problem *p, const Plan &L, void *ws, void *str
     c.rows.heavy_thresh = c.L.heavy_thresh;
     c.rows.heavy = at<int>(ws, c.L.off_heavy);
     c.rows.nheavy = &c.misc->nheavy;
+    c.rows.w = nullptr;
+    c.rows.wdeg = nullptr;
+    if (c.L.weighted) {
+        c.rows.w = p->d_weight;
+        c.rows.wdeg = at<double>(ws, c.L.off_wdeg);
+        HIP_TRY(launch_row_cumsum(c.L.n, c.rp32, p->d_weight, at<double>(ws, c.L.off_cw), at<double>(ws, c.L.off_wdeg),
+                                  c.st));
+    }
     HIP_TRY(launch_heavy_list(c.L.n, c.rp32, c.L.heavy_thresh, at<int>(ws, c.L.off_bcount), at<int>(ws, c.L.off_heavy),
                               &c.misc->nheavy, c.st));
     return USTD_OK;
@@ -356,6 +401,34 @@ int sweep_pivot(Ctx &c, int *pivot) {
     return USTD_OK;
 }
 
+// Weighted graphs, after B_u: (with validate) the weight checks, then the B_u edge
+// conductances, rho_max (read back), tau, the fixed-point shift and the edge factors F.
+int setup_weighted(Ctx &c) {
+    if (!c.L.weighted) return USTD_OK;
+    const ustd_problem *p = c.p;
+    const int n = c.L.n;
+    if (p->validate) HIP_TRY(launch_check_weights(n, c.rp32, p->d_col, p->d_weight, &c.misc->err_validate, c.st));
+    double *wB = at<double>(c.ws, c.L.off_wB);
+    HIP_TRY(hipMemsetAsync(&c.misc->rho_max_bits, 0, sizeof(unsigned long long), c.st));
+    HIP_TRY(launch_bpath(n, c.pivot, c.rp32, p->d_col, p->d_weight, at<int>(c.ws, c.L.off_parB), wB,
+                         &c.misc->rho_max_bits, c.st));
+    unsigned long long bits = 0;
+    int err = 0;
+    HIP_TRY(hipMemcpyAsync(&bits, &c.misc->rho_max_bits, sizeof(bits), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipMemcpyAsync(&err, &c.misc->err_validate, sizeof(err), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    if (err) return fail(USTD_EGRAPH, "weight validation failed (a conductance is not positive and finite, or "
+                                      "differs between the two entries of its edge)");
+    std::memcpy(&c.rho_max, &bits, sizeof(bits));
+    if (!(c.rho_max > 0.0) || !std::isfinite(c.rho_max))
+        return fail(USTD_EGRAPH, "largest B-path resistance %g is not positive and finite", c.rho_max);
+    c.tau = sample_size_weighted(p, c.rho_max);
+    c.shift = fixed_shift(c.tau, c.rho_max);
+    if (c.shift < 0) return fail(USTD_EINVAL, "tau * rho_max = %g leaves no fixed-point range", (double)c.tau * c.rho_max);
+    HIP_TRY(launch_fixed_weights(n, c.pivot, wB, c.shift, at<long long>(c.ws, c.L.off_F), c.st));
+    return USTD_OK;
+}
+
 // pivot choice, optional validation and the BFS tree B_u; synchronises the stream
 int setup(Ctx &c, ustd_report *rep) {
     const ustd_problem *p = c.p;
@@ -391,9 +464,13 @@ int setup(Ctx &c, ustd_report *rep) {
         HIP_TRY(hipStreamSynchronize(c.st));
         if (out[1]) return fail(USTD_EGRAPH, "graph is not connected");
         c.ecc = out[0];
+        USTD_TRY(setup_weighted(c));
         if (rep) {
             rep->pivot = c.pivot;
             rep->ecc = c.ecc;
+            rep->rho_max = c.L.weighted ? c.rho_max : (double)c.ecc;
+            rep->fixed_shift = c.shift;
+            rep->weighted = c.L.weighted ? 1 : 0;
             rep->ms_bfs += tm.stop_ms();
         }
         return USTD_OK;
@@ -407,9 +484,13 @@ int setup(Ctx &c, ustd_report *rep) {
     // subtree intervals of B_u (fixed for every tree): bint[x] = {pre_B, size_B}
     HIP_TRY(launch_b_intervals(n, c.pivot, c.ecc, dist, parB, at<int>(c.ws, c.L.off_scr), at<int2>(c.ws, c.L.off_bint),
                                at<int>(c.ws, c.L.off_bflag), c.st));
+    USTD_TRY(setup_weighted(c));
     if (rep) {
         rep->pivot = c.pivot;
         rep->ecc = c.ecc;
+        rep->rho_max = c.L.weighted ? c.rho_max : (double)c.ecc;
+        rep->fixed_shift = c.shift;
+        rep->weighted = c.L.weighted ? 1 : 0;
         rep->ms_bfs += tm.stop_ms();
     }
     return USTD_OK;
@@ -424,6 +505,7 @@ WilsonGraph wilson_graph(const Ctx &c) {
     g.rp = c.rp32;
     g.colv = c.L.col16 ? (const void *)at<unsigned short>(c.ws, c.L.off_col16) : (const void *)c.p->d_col;
     g.bflag = at<int>(c.ws, c.L.off_bflag);
+    g.cw = c.L.weighted ? at<double>(c.ws, c.L.off_cw) : nullptr;
     g.key0 = (uint32_t)(c.p->seed & 0xFFFFFFFFull);
     g.key1 = (uint32_t)(c.p->seed >> 32);
     return g;
@@ -442,10 +524,10 @@ int sample_batch(Ctx &c, long long tree_begin, int ntrees, long long *steps, lon
     a.steps = steps;
     a.draws = draws;
     int blocks = std::min(ntrees, c.L.slots);
-    const int resident = wilson_resident_blocks(c.L.lds_bits, c.L.col16, c.L.nwords);
+    const int resident = wilson_resident_blocks(c.L.lds_bits, c.L.col16, c.L.weighted, c.L.nwords);
     if (resident > 0) blocks = std::min(blocks, resident);
     HIP_TRY(hipMemsetAsync(&c.misc->queue, 0, sizeof(int), c.st));
-    HIP_TRY(launch_wilson(a, blocks, c.L.lds_bits, c.L.col16, c.L.nwords, c.st));
+    HIP_TRY(launch_wilson(a, blocks, c.L.lds_bits, c.L.col16, c.L.weighted, c.L.nwords, c.st));
     return USTD_OK;
 }
 
@@ -460,6 +542,7 @@ int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag) {
     aa.rec = at<int2>(c.ws, c.L.off_rec);
     aa.rec_stride = c.L.rec_stride;
     aa.counts = counts;
+    aa.F = c.L.weighted ? at<long long>(c.ws, c.L.off_F) : nullptr;
     Timer tm(c.st);
     HIP_TRY(launch_aggregate(aa, c.st));
     if (ms_ag) *ms_ag += tm.stop_ms();
@@ -553,6 +636,7 @@ CgArgs<T> cg_args(Ctx &c, T *x, T *r, T *z, T *pp, T *q, CgScalars *sc, double *
     a.grid_vec = vec_grid(c.L.n);
     a.sc = sc;
     a.rr_hist = hist;
+    a.wdeg = c.rows.wdeg;
     return a;
 }
 
@@ -692,6 +776,8 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
             const std::string m = g_err;
             return fail(rc, "problem %d: %s", i, m.c_str());
         }
+        if (probs[i].d_weight)
+            return fail(USTD_EINVAL, "problem %d: weighted graphs are not supported by the batch entry point", i);
         const Plan L = make_plan(&probs[i], false);
         B.g.push_back(L);
         B.base.push_back(o);
@@ -858,7 +944,7 @@ int ustd_diag_lpinv(const ustd_problem *prob, void *d_ws, size_t ws_bytes, doubl
     memset(r, 0, sizeof(*r));
     Timer total(c.st);
     USTD_TRY(setup(c, r));
-    const long long tau = sample_size(prob, c.ecc);
+    const long long tau = problem_tau(c);
     r->tau = tau;
     long long *counts = d_counts ? (long long *)d_counts : at<long long>(c.ws, c.L.off_counts);
     HIP_TRY(hipMemsetAsync(counts, 0, (size_t)c.L.n * 8, c.st));
@@ -894,7 +980,7 @@ int ustd_diag_lpinv(const ustd_problem *prob, void *d_ws, size_t ws_bytes, doubl
     HIP_TRY(hipStreamWaitEvent(c.st, join.e, 0));
     {
         Timer tm(c.st);
-        HIP_TRY(launch_combine(c.L.n, c.pivot, tau, counts, x, d_diag, c.st));
+        HIP_TRY(launch_combine(c.L.n, c.pivot, count_scale(c, tau), counts, x, d_diag, c.st));
         r->ms_combine += tm.stop_ms();
     }
     r->ms_total = total.stop_ms();
@@ -962,7 +1048,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
     double ms_s = 0, ms_a = 0;
     int fills = 0;
     long long largest = 0;
-    const int resident = wilson_resident_blocks(B.lds_bits, B.col16, B.nwords_max);
+    const int resident = wilson_resident_blocks(B.lds_bits, B.col16, false, B.nwords_max);
 
     // The members' pivot-column solves run on the side stream while the first pool fill is
     // sampled (each solve touches only its member's solve vectors).
@@ -1025,7 +1111,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         SpanTimer ts, ta;
         ts.start(st);
         HIP_TRY(hipMemsetAsync(queue, 0, sizeof(int), st));
-        HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, B.nwords_max, st));
+        HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, false, B.nwords_max, st));
         ts.stop(st);
         {
             ta.start(st);
@@ -1071,7 +1157,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         R[i].ms_aggregate = ms_a;
         double *x = at<double>(cs[i].ws, B.g[i].off_x64);
         Timer tm(st);
-        HIP_TRY(launch_combine(B.g[i].n, cs[i].pivot, tau[i], counts[i], x, d_diags[i], st));
+        HIP_TRY(launch_combine(B.g[i].n, cs[i].pivot, (double)tau[i], counts[i], x, d_diags[i], st));
         R[i].ms_combine += tm.stop_ms();
     }
     const double ms = total.stop_ms();

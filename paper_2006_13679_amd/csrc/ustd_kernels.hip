@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 namespace ustd {
 
@@ -386,15 +387,37 @@ __device__ __forceinline__ int select_bit64(uint64_t x, int k) {
     return k >= c ? 32 + select_bit((uint32_t)(x >> 32), k - c) : select_bit((uint32_t)x, k);
 }
 
+// Neighbour index (0 .. deg-1) of a walk step with word w from the row [r0, r1).  Unit
+// weights: floor(w deg / 2^32).  Weighted (Section "Generalizations"): the first j with
+// t < C[j], C the row's running conductance sums (cw, taken left to right in FP64) and
+// t = (w 2^-32) C[deg-1]; both products are exact or rounded once, so the choice is the
+// same on every device, and all-ones weights give floor(w deg / 2^32).
+template <bool WT>
+__device__ __forceinline__ int step_index(uint32_t w, int r0, int r1, const double *__restrict__ cw) {
+    if constexpr (!WT) {
+        return (int)__umulhi(w, (uint32_t)(r1 - r0));
+    } else {
+        const double t = ((double)w * 0x1p-32) * cw[r1 - 1];
+        int lo = 0, hi = r1 - r0 - 1;  // the answer lies in [lo, hi]: t < C[deg-1]
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (t < cw[r0 + mid]) hi = mid;
+            else lo = mid + 1;
+        }
+        return lo;
+    }
+}
+
 // The sequential algorithm for one start s0 against the current tree: walk with Next
 // pointers (in the parent field), retrace the loop erasure, and write the branch's records
 // {parent, nba | marked << 31}.  The walk resumes at step k0 from vertex x0 (k0 = 0, x0 = s0
 // for a whole walk; otherwise the Next pointers of steps 0..k0-1 are already written).  One
 // lane; returns the walk's total step count.
-template <bool LDS, typename CT>
+template <bool LDS, typename CT, bool WT>
 __device__ long long rewalk_commit(const TreeState<LDS> &bits, int *recw, const int *__restrict__ rp,
-                                   const CT *__restrict__ col, const int *__restrict__ bflag, int s0, int x0,
-                                   long long k0, uint32_t tlo, uint32_t thi, uint32_t key0, uint32_t key1) {
+                                   const CT *__restrict__ col, const double *__restrict__ cw,
+                                   const int *__restrict__ bflag, int s0, int x0, long long k0, uint32_t tlo,
+                                   uint32_t thi, uint32_t key0, uint32_t key1) {
     int xw = x0;
     int r0 = rp[x0], r1 = rp[x0 + 1];
     long long k = k0;
@@ -403,7 +426,7 @@ __device__ long long rewalk_commit(const TreeState<LDS> &bits, int *recw, const 
         if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
         const int q = (int)(k & 3);
         const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-        const int y = (int)col[r0 + (int)__umulhi(w, (uint32_t)(r1 - r0))];
+        const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw)];
         const int ny0 = rp[y], ny1 = rp[y + 1];
         ++k;
         recw[2 * xw] = y;  // Next pointer; becomes the parent when xw joins T
@@ -446,7 +469,7 @@ __device__ __forceinline__ T sel4(int c, T a0, T a1, T a2, T a3) {
 
 }  // namespace
 
-template <bool LDS, typename CT>
+template <bool LDS, typename CT, bool WT>
 __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     // Reorder buffer.  Vertex IDs take the column type (16 bits when n <= 65536), so that
     // with the tree bitmap a block of R-MAT scale 16 fits 18 to a CU.  A recorded step
@@ -501,6 +524,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     const int u = g.u;
     const int *__restrict__ rp = g.rp;
     const CT *__restrict__ col = reinterpret_cast<const CT *>(g.colv);  // int32, or uint16 when n <= 65536
+    const double *__restrict__ cw = g.cw;
 
     wait_global();  // the previous tree's record writes have landed
     if constexpr (LDS) {
@@ -588,7 +612,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s, tlo, thi), g.key0, g.key1);
             const int q = k & 3;
             const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-            const int y = (int)col[r0 + (int)__umulhi(w, (uint32_t)(r1 - r0))];
+            const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw)];
             // loads for y: tree bit and B_u flag; then either the chain value (the walk ends
             // here) or the next row bounds (it continues)
             bool in;
@@ -651,7 +675,8 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                             k0 = kPath;
                         }
                         const long long kk =
-                            rewalk_commit(bits, recw, rp, col, bflag, s0, xs, k0, tlo, thi, g.key0, g.key1);
+                            rewalk_commit<LDS, CT, WT>(bits, recw, rp, col, cw, bflag, s0, xs, k0, tlo, thi, g.key0,
+                                                       g.key1);
                         steps += kk;
                         draws += kk - k0;
                     }
@@ -1084,6 +1109,9 @@ __global__ __launch_bounds__(kIvThreads) void intervals_kernel(IntervalArgs a) {
 // pre_B(x) <= pre_B(v) < pre_B(x) + size_B(x).  Thread per vertex over a chunk of resident
 // trees; one int64 atomic per vertex and chunk, skipped when the sum is zero.
 // ======================================================================================
+// WT: weighted graph, the edge (parB(b), b) of P(v) counts +-F[b] (Ohm's-law factor in fixed
+// point) instead of +-1.
+template <bool WT>
 __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= a.n || v == a.u) return;
@@ -1096,14 +1124,17 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
     const int2 *__restrict__ rec0 = a.rec + (long long)t0 * a.rec_stride;
     // The chains of the chunk's trees are walked in lockstep, one step of every unfinished
     // chain per round, so their independent loads are in flight together.
+    using Acc = typename std::conditional<WT, long long, int>::type;
+    const long long *__restrict__ F = a.F;
+    const Acc fv = WT ? (Acc)F[v] : (Acc)1;
     int x[kAggChunk];
-    int sum = 0;
+    Acc sum = 0;
 #pragma unroll
     for (int i = 0; i < kAggChunk; ++i) {
         x[i] = u;
         if (i < nt) {
             const int2 rv = rec0[(long long)i * a.rec_stride + v];
-            sum += (rv.x == pbv) ? 1 : 0;
+            sum += (rv.x == pbv) ? fv : (Acc)0;
             x[i] = nba_of(rv.y);
         }
     }
@@ -1126,10 +1157,14 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
                 // a B_u child of x, is on P(v), which needs x on P(v) first
                 if (bx[i].x <= pv && pv < bx[i].x + bx[i].y) {
                     if (rx[i].y & kFwdBit) {
-                        ++sum;
+                        if constexpr (WT) sum += F[x[i]];
+                        else ++sum;
                     } else {
                         const int2 bp = bint[rx[i].x];
-                        if (bp.x <= pv && pv < bp.x + bp.y) --sum;
+                        if (bp.x <= pv && pv < bp.x + bp.y) {
+                            if constexpr (WT) sum -= F[rx[i].x];
+                            else --sum;
+                        }
                     }
                 }
                 x[i] = nba_of(rx[i].y);
@@ -1342,13 +1377,17 @@ template <typename T, int G, int BS = 256, typename Emit>
 __device__ __forceinline__ void lap_apply_rows(const RowMap &m, const T *__restrict__ p, Emit emit) {
     __shared__ T shr[BS / kWave];
     const int nh = *m.nheavy;
+    const double *__restrict__ w = m.w;  // uniform: weighted Laplacian when set
     for (int h = blockIdx.x; h < nh; h += gridDim.x) {
         const int v = m.heavy[h];
         const int lo = m.rp[v], hi = m.rp[v + 1];
         T acc = (T)0;
-        for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) acc += p[m.col[e]];
+        if (w)
+            for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) acc += (T)w[e] * p[m.col[e]];
+        else
+            for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) acc += p[m.col[e]];
         acc = block_sum_t<T>(acc, shr);
-        if (threadIdx.x == 0) emit(v, (T)(hi - lo) * p[v] - acc);
+        if (threadIdx.x == 0) emit(v, (w ? (T)m.wdeg[v] : (T)(hi - lo)) * p[v] - acc);
     }
     constexpr int rows_per_tile = BS / G;
     const int g = threadIdx.x / G, l = threadIdx.x % G;
@@ -1358,12 +1397,22 @@ __device__ __forceinline__ void lap_apply_rows(const RowMap &m, const T *__restr
         const int lo = ok ? m.rp[v] : 0, hi = ok ? m.rp[v + 1] : 0;
         const bool light = ok && (hi - lo <= m.heavy_thresh);
         T acc = (T)0;
-        if (light)
-            for (int e = lo + l; e < hi; e += G) acc += p[m.col[e]];
+        if (light) {
+            if (w)
+                for (int e = lo + l; e < hi; e += G) acc += (T)w[e] * p[m.col[e]];
+            else
+                for (int e = lo + l; e < hi; e += G) acc += p[m.col[e]];
+        }
 #pragma unroll
         for (int dd = G / 2; dd > 0; dd >>= 1) acc += __shfl_xor(acc, dd, G);
-        if (light && l == 0) emit(v, (T)(hi - lo) * p[v] - acc);
+        if (light && l == 0) emit(v, (w ? (T)m.wdeg[v] : (T)(hi - lo)) * p[v] - acc);
     }
+}
+
+// Jacobi diagonal: the degree, or the conductance sum of a weighted Laplacian's row
+template <typename T>
+__device__ __forceinline__ T jacobi_diag(const CgArgs<T> &a, int v) {
+    return a.wdeg ? (T)a.wdeg[v] : (T)(a.rp[v + 1] - a.rp[v]);
 }
 
 // Sum of per-block partials, computed redundantly by every consumer block in index order
@@ -1420,7 +1469,7 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgArgs<T> a) {
         a.x[v] += al * a.p[v];
         const T rv = a.r[v] - al * a.q[v];
         a.r[v] = rv;
-        const T zv = rv / (T)(a.rp[v + 1] - a.rp[v]);
+        const T zv = rv / jacobi_diag(a, v);
         a.z[v] = zv;
         rz += (double)rv * (double)zv;
         rr += (double)rv * (double)rv;
@@ -1474,7 +1523,7 @@ __global__ __launch_bounds__(256) void cg_start_kernel(CgArgs<T> a, const Tin *_
         if (rhs_is_pivot) b = (v == u ? 1.0 : 0.0) - inv_n;
         else b = ((double)rhs[v] - shift) * scale;
         const T rv = (T)b;
-        const T zv = rv / (T)(a.rp[v + 1] - a.rp[v]);
+        const T zv = rv / jacobi_diag(a, v);
         a.x[v] = (T)0;
         a.r[v] = rv;
         a.z[v] = zv;
@@ -1530,7 +1579,7 @@ __global__ __launch_bounds__(kSmallThreads) void cg_small_kernel(CgArgs<T> a, Ro
         if (rhs_is_pivot) b = (v == u ? 1.0 : 0.0) - inv_n;
         else b = ((double)rhs[v] - shift) * scale;
         const T rv = (T)b;
-        const T zv = rv / (T)(a.rp[v + 1] - a.rp[v]);
+        const T zv = rv / jacobi_diag(a, v);
         a.x[v] = (T)0;
         a.r[v] = rv;
         a.z[v] = zv;
@@ -1560,7 +1609,7 @@ __global__ __launch_bounds__(kSmallThreads) void cg_small_kernel(CgArgs<T> a, Ro
             a.x[v] += al * a.p[v];
             const T rv = a.r[v] - al * a.q[v];
             a.r[v] = rv;
-            const T zv = rv / (T)(a.rp[v + 1] - a.rp[v]);
+            const T zv = rv / jacobi_diag(a, v);
             a.z[v] = zv;
             rzn += (double)rv * (double)zv;
             rrn += (double)rv * (double)rv;
@@ -1753,12 +1802,93 @@ __global__ void outer_scalars_kernel(int n, const double *__restrict__ sums, dou
 }
 
 // Final fill (Algorithm 1; Eq. diag-comp): diag[u] = x[u], diag[v] = R[v]/tau - x[u] + 2 x[v]
-__global__ void combine_kernel(int n, int u, long long tau, const long long *__restrict__ counts,
+// ======================================================================================
+// Weighted graphs (Section "Generalizations").  Set-up only: the running conductance sums
+// of every row (the sampler's step table and the Laplacian's diagonal), the weight checks,
+// the B-path resistances and the fixed-point edge factors of Algorithm 2.
+// ======================================================================================
+// One thread per row, left to right, so every device (and the CPU oracle) gets the same
+// FP64 sums; cw[e] = w[row start] + ... + w[e], wdeg[v] = the row total.
+__global__ __launch_bounds__(256) void row_cumsum_kernel(int n, const int *__restrict__ rp, const double *__restrict__ w,
+                                                         double *__restrict__ cw, double *__restrict__ wdeg) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        double run = 0.0;
+        for (int e = rp[v]; e < rp[v + 1]; ++e) {
+            run += w[e];
+            cw[e] = run;
+        }
+        wdeg[v] = run;
+    }
+}
+
+// position of x in the ascending row [lo, hi), or -1
+__device__ __forceinline__ int find_in_row(const int *__restrict__ col, int lo, int hi, int x) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int c = col[mid];
+        if (c == x) return mid;
+        if (c < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return -1;
+}
+
+// err |= 64 if a conductance is not positive and finite or differs from its mirror entry
+__global__ __launch_bounds__(256) void check_weights_kernel(int n, const int *__restrict__ rp, const int *__restrict__ col,
+                                                            const double *__restrict__ w, int *__restrict__ err) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        bool bad = false;
+        for (int e = rp[v]; e < rp[v + 1]; ++e) {
+            const double we = w[e];
+            const int x = col[e];
+            if (!(we > 0.0) || !isfinite(we) || x < 0 || x >= n) { bad = true; break; }
+            const int f = find_in_row(col, rp[x], rp[x + 1], v);
+            if (f < 0 || w[f] != we) { bad = true; break; }
+        }
+        if (bad) atomicOr(err, 64);
+    }
+}
+
+// wB[v] = w(v, parB(v)) (0 at u), then rho(v) = sum of 1 / wB over P(v) from v towards u;
+// the largest rho into *rmax_bits (bits of a non-negative double order like the values)
+__global__ __launch_bounds__(256) void b_edge_weight_kernel(int n, int u, const int *__restrict__ rp,
+                                                            const int *__restrict__ col, const double *__restrict__ w,
+                                                            const int *__restrict__ parB, double *__restrict__ wB) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    double wb = 0.0;
+    if (v != u) {
+        const int f = find_in_row(col, rp[v], rp[v + 1], parB[v]);
+        wb = f >= 0 ? w[f] : 0.0;  // parB(v) is a neighbour of v
+    }
+    wB[v] = wb;
+}
+__global__ __launch_bounds__(256) void bpath_resist_kernel(int n, int u, const int *__restrict__ parB,
+                                                           const double *__restrict__ wB,
+                                                           unsigned long long *__restrict__ rmax_bits) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    double r = 0.0;
+    if (v < n)
+        for (int b = v; b != u; b = parB[b]) r += 1.0 / wB[b];
+    unsigned long long bits = (unsigned long long)__double_as_longlong(r);
+    for (int d = kWave / 2; d > 0; d >>= 1) bits = max(bits, (unsigned long long)__shfl_xor((long long)bits, d, kWave));
+    if (lane_id() == 0 && bits) atomicMax(rmax_bits, bits);
+}
+
+// F[v] = llround(2^shift / wB[v]), F[u] = 0
+__global__ void fixed_weights_kernel(int n, int u, const double *__restrict__ wB, double scale, long long *__restrict__ F) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    F[v] = v == u ? 0ll : llround(scale / wB[v]);
+}
+
+// den = tau, or tau 2^k for the fixed-point counts of a weighted graph
+__global__ void combine_kernel(int n, int u, double den, const long long *__restrict__ counts,
                                const double *__restrict__ x, double *__restrict__ diag) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const double xu = x[u];
-    diag[v] = (v == u) ? xu : (double)counts[v] / (double)tau - xu + 2.0 * x[v];
+    diag[v] = (v == u) ? xu : (double)counts[v] / den - xu + 2.0 * x[v];
 }
 
 __global__ void philox_words_kernel(uint32_t key0, uint32_t key1, long long t, int s, long long k0, long long count,
@@ -1834,28 +1964,42 @@ hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t 
     count_unreached_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, dist, err);
     return hipGetLastError();
 }
-int wilson_resident_blocks(bool lds_bits, bool col16, int nwords) {
+template <bool LDS, typename CT, bool WT>
+int resident_of(size_t dyn, int *per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wilson_kernel<LDS, CT, WT>, 64, dyn) == hipSuccess;
+}
+int wilson_resident_blocks(bool lds_bits, bool col16, bool weighted, int nwords) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     const size_t dyn = lds_bits ? (size_t)nwords * 4 : 0;
-    hipError_t e;
-    if (lds_bits)
-        e = col16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wilson_kernel<true, unsigned short>, 64, dyn)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wilson_kernel<true, int>, 64, dyn);
-    else
-        e = col16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wilson_kernel<false, unsigned short>, 64, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wilson_kernel<false, int>, 64, 0);
-    if (e != hipSuccess) return 0;
+    int ok;
+    if (lds_bits) {
+        if (col16) ok = weighted ? resident_of<true, unsigned short, true>(dyn, &per_cu)
+                                 : resident_of<true, unsigned short, false>(dyn, &per_cu);
+        else ok = weighted ? resident_of<true, int, true>(dyn, &per_cu) : resident_of<true, int, false>(dyn, &per_cu);
+    } else {
+        if (col16) ok = weighted ? resident_of<false, unsigned short, true>(0, &per_cu)
+                                 : resident_of<false, unsigned short, false>(0, &per_cu);
+        else ok = weighted ? resident_of<false, int, true>(0, &per_cu) : resident_of<false, int, false>(0, &per_cu);
+    }
+    if (!ok) return 0;
     return std::max(1, per_cu) * std::max(1, cus);
 }
-hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool col16, int nwords, hipStream_t st) {
+template <bool LDS, typename CT>
+void launch_wilson_t(const WilsonArgs &a, int blocks, bool weighted, size_t dyn, hipStream_t st) {
+    if (weighted) wilson_kernel<LDS, CT, true><<<blocks, 64, dyn, st>>>(a);
+    else wilson_kernel<LDS, CT, false><<<blocks, 64, dyn, st>>>(a);
+}
+hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool col16, bool weighted, int nwords,
+                         hipStream_t st) {
     if (lds_bits) {
-        if (col16) wilson_kernel<true, unsigned short><<<blocks, 64, (size_t)nwords * 4, st>>>(a);
-        else wilson_kernel<true, int><<<blocks, 64, (size_t)nwords * 4, st>>>(a);
+        const size_t dyn = (size_t)nwords * 4;
+        if (col16) launch_wilson_t<true, unsigned short>(a, blocks, weighted, dyn, st);
+        else launch_wilson_t<true, int>(a, blocks, weighted, dyn, st);
     } else {
-        if (col16) wilson_kernel<false, unsigned short><<<blocks, 64, 0, st>>>(a);
-        else wilson_kernel<false, int><<<blocks, 64, 0, st>>>(a);
+        if (col16) launch_wilson_t<false, unsigned short>(a, blocks, weighted, 0, st);
+        else launch_wilson_t<false, int>(a, blocks, weighted, 0, st);
     }
     return hipGetLastError();
 }
@@ -1901,7 +2045,8 @@ hipError_t launch_edge_fold(int n, long long nnz, const int *rp, const int *col,
 }
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st) {
     dim3 grid(blocks_for(a.n, 256), (a.ntrees + kAggChunk - 1) / kAggChunk);
-    aggregate_kernel<<<grid, 256, 0, st>>>(a);
+    if (a.F) aggregate_kernel<true><<<grid, 256, 0, st>>>(a);
+    else aggregate_kernel<false><<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 int solve_grid(const RowMap &m, int G) {
@@ -1967,9 +2112,27 @@ hipError_t launch_outer_scalars(int n, const double *sums, double *ss, hipStream
     outer_scalars_kernel<<<1, 1, 0, st>>>(n, sums, ss);
     return hipGetLastError();
 }
-hipError_t launch_combine(int n, int u, long long tau, const long long *counts, const double *x, double *diag,
+hipError_t launch_combine(int n, int u, double den, const long long *counts, const double *x, double *diag,
                           hipStream_t st) {
-    combine_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, u, tau, counts, x, diag);
+    combine_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, u, den, counts, x, diag);
+    return hipGetLastError();
+}
+hipError_t launch_row_cumsum(int n, const int *rp, const double *w, double *cw, double *wdeg, hipStream_t st) {
+    row_cumsum_kernel<<<std::min(blocks_for(n, 256), 4096), 256, 0, st>>>(n, rp, w, cw, wdeg);
+    return hipGetLastError();
+}
+hipError_t launch_check_weights(int n, const int *rp, const int *col, const double *w, int *err, hipStream_t st) {
+    check_weights_kernel<<<std::min(blocks_for(n, 256), 4096), 256, 0, st>>>(n, rp, col, w, err);
+    return hipGetLastError();
+}
+hipError_t launch_bpath(int n, int u, const int *rp, const int *col, const double *w, const int *parB, double *wB,
+                        unsigned long long *rmax_bits, hipStream_t st) {
+    b_edge_weight_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, u, rp, col, w, parB, wB);
+    bpath_resist_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, u, parB, wB, rmax_bits);
+    return hipGetLastError();
+}
+hipError_t launch_fixed_weights(int n, int u, const double *wB, int shift, long long *F, hipStream_t st) {
+    fixed_weights_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, u, wB, ldexp(1.0, shift), F);
     return hipGetLastError();
 }
 hipError_t launch_philox_words(uint32_t key0, uint32_t key1, long long t, int s, long long k0, long long count,

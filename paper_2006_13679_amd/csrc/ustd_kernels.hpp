@@ -14,6 +14,7 @@ struct WilsonGraph {
     const int *rp;
     const void *colv;       // column indices: int32, or uint16 when the launch says so
     const int *bflag;       // [n] (parB + 1) | (internal in B_u) << 31
+    const double *cw;       // [nnz] running conductance sums of each row (weighted launches)
     uint32_t key0, key1;    // Philox key (seed)
 };
 
@@ -64,6 +65,7 @@ struct AggregateArgs {
     const int2 *rec;
     long long rec_stride;
     long long *counts;
+    const long long *F;     // [n] fixed-point 1/w of each vertex's B_u edge; null = unit weights
 };
 
 struct EdgeCountArgs {
@@ -88,6 +90,8 @@ struct RowMap {
     int heavy_thresh;
     const int *heavy;   // ascending IDs of rows with degree > heavy_thresh
     const int *nheavy;  // device count
+    const double *w;    // [nnz] conductances; null = unit weights
+    const double *wdeg; // [n] conductance sum of each row (with w)
 };
 
 struct CgScalars {
@@ -107,6 +111,7 @@ struct CgArgs {
     int grid_spmv, grid_vec;
     CgScalars *sc;
     double *rr_hist;        // kRrHist
+    const double *wdeg;     // [n] Jacobi diagonal of a weighted Laplacian; null = degrees
 };
 
 inline long long interval_scratch_ints(long long n) { return 10 * n + 3; }
@@ -123,8 +128,16 @@ int solve_grid(const RowMap &m, int G);
 int vec_grid(int n);
 hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t st);
 // resident blocks of one sampler launch on the current device (occupancy x compute units)
-int wilson_resident_blocks(bool lds_bits, bool col16, int nwords);
-hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool col16, int nwords, hipStream_t st);
+int wilson_resident_blocks(bool lds_bits, bool col16, bool weighted, int nwords);
+hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool col16, bool weighted, int nwords,
+                         hipStream_t st);
+// weighted graphs: running row sums and row totals; weight checks; B_u edge conductances,
+// B-path resistances (max into *rmax_bits, as the bits of a non-negative double); F
+hipError_t launch_row_cumsum(int n, const int *rp, const double *w, double *cw, double *wdeg, hipStream_t st);
+hipError_t launch_check_weights(int n, const int *rp, const int *col, const double *w, int *err, hipStream_t st);
+hipError_t launch_bpath(int n, int u, const int *rp, const int *col, const double *w, const int *parB, double *wB,
+                        unsigned long long *rmax_bits, hipStream_t st);
+hipError_t launch_fixed_weights(int n, int u, const double *wB, int shift, long long *F, hipStream_t st);
 hipError_t launch_col_to_u16(long long nnz, const int *col, unsigned short *col16, hipStream_t st);
 hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st);
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st);
@@ -155,7 +168,7 @@ template <typename T>
 hipError_t launch_axpy_project(int n, double *x, const T *d, const double *scale_src, int scale_idx,
                                const double *mean_src, int grid, hipStream_t st);
 hipError_t launch_outer_scalars(int n, const double *sums, double *ss, hipStream_t st);
-hipError_t launch_combine(int n, int u, long long tau, const long long *counts, const double *x, double *diag,
+hipError_t launch_combine(int n, int u, double den, const long long *counts, const double *x, double *diag,
                           hipStream_t st);
 hipError_t launch_philox_words(uint32_t key0, uint32_t key1, long long t, int s, long long k0, long long count,
                                uint32_t *out, hipStream_t st);

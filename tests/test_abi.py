@@ -58,3 +58,40 @@ def test_status_strings():
     assert L.ustd_status_string(0) == b"USTD_OK"
     assert L.ustd_status_string(5) == b"USTD_ENOTCONV"
     assert L.ustd_status_string(99) == b"USTD_UNKNOWN"
+
+
+def test_weighted_workspace_and_batch_rejection():
+    """Weights add the running row sums (nnz doubles) and three n-vectors; the batch entry
+    point rejects a weighted member on the host."""
+    b0 = api.workspace_bytes(_prob())
+    b1 = api.workspace_bytes(_prob(d_weight=0x3000))
+    assert b1 - b0 >= 3968 * 8 + 3 * 1024 * 8
+    probs = (api.Problem * 2)(_prob(), _prob(d_weight=0x3000))
+    size = ctypes.c_size_t(0)
+    rc = api.lib().ustd_batch_workspace_bytes(probs, 2, ctypes.byref(size))
+    assert rc == api.EINVAL
+    assert b"weighted" in api.lib().ustd_last_error()
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors have the C structs' sizes and field offsets (a C program built from
+    include/ustd.h prints them)."""
+    import subprocess
+
+    fields = {"ustd_problem": api.Problem, "ustd_report": api.Report}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "ustd.h"', "int main(void) {"]
+    for cname, cls in fields.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, cls in fields.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)

@@ -97,6 +97,46 @@ def test_rmat16_whole_run(gpu):
     _check_combine(d, counts.cpu().numpy(), xg.cpu().numpy(), u, tau)
 
 
+def test_rmat16_weighted_sampled(gpu):
+    """The weighted benchmark workload (R-MAT 16, conductances uniform in [1, 4), seed 1):
+    tau, rho_max and the fixed-point shift exactly; the first and last trees and the
+    fixed-point counts of two trees bit for bit; the full run's solve residual (weighted
+    Laplacian) and combination."""
+    g = gg.rmat(16, 16, 1)
+    u = gg.max_degree_pivot(g)
+    w = gg.edge_weights(g, 1, "uniform", 1.0, 4.0)
+    G = api.Graph.from_host(g.row_ptr, g.col, weight=w)
+    p = api.problem(G, pivot=u, eps=0.3, seed=1, solve_tol=1e-12)
+    _, _, rmax = oracle.bpath_resistance(g.row_ptr, g.col, w, u)
+    tau = oracle.tau_weighted(g.n, g.m, rmax, 0.3)
+    k = oracle.fixed_shift(tau, rmax)
+    for t in (0, tau - 1):
+        say("weighted tree", t)
+        parents, steps = api.sample_trees(G, p, t, 1)
+        want_par, want_steps = oracle.wilson_weighted(g.row_ptr, g.col, w, u, 1, t)
+        assert int(steps[0]) == want_steps
+        assert (parents[0].cpu().numpy() == want_par).all()
+    say("weighted counts")
+    counts, rep = api.flow_counts(G, p, tau // 2, 2)
+    assert rep["rho_max"] == rmax and rep["fixed_shift"] == k
+    _, st, want = oracle.trees_weighted(g.row_ptr, g.col, w, u, 1, tau // 2, 2, k, want_parents=False)
+    assert (counts.cpu().numpy() == want).all() and rep["walk_steps"] == int(st.sum())
+    say("weighted full run")
+    diag, counts, rep = api.diag_lpinv_p(G, p)
+    assert rep["tau"] == tau and rep["fixed_shift"] == k
+    x, _ = api.solve_pivot_column(G, p)
+    x = x.cpu().numpy()
+    A = sp.csr_matrix((w, g.col, g.row_ptr), shape=(g.n, g.n))
+    L = sp.diags(np.asarray(A.sum(axis=1)).ravel()) - A
+    b = -np.full(g.n, 1.0 / g.n)
+    b[u] += 1.0
+    assert np.linalg.norm(b - L @ x) <= 2e-12 * np.linalg.norm(b)
+    c = counts.cpu().numpy().astype(np.float64)
+    want_d = c / np.ldexp(float(tau), k) - x[u] + 2.0 * x
+    want_d[u] = x[u]
+    np.testing.assert_allclose(diag.cpu().numpy(), want_d, rtol=1e-14, atol=1e-14)
+
+
 def test_rhg_1m_sampled(gpu):
     g = gg.hyperbolic(1_000_000, 20.0, 3.0, seed=1)
     u = gg.max_degree_pivot(g)

@@ -1,0 +1,175 @@
+"""GPU parity on weighted graphs (Section "Generalizations"): the HIP library through its C
+ABI against the CPU oracle on the same seeded graphs and conductances.  Sampled parent
+arrays, walk steps and the fixed-point flow counts must match bit for bit; tau, rho_max
+and the fixed-point shift exactly; the pivot column and diag(L^+) within 1e-10 relative."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2006_13679_amd import api
+from paper_2006_13679_amd import graphgen as gg
+from tests import brute
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def cases():
+    """(name, graph, pivot, weight kind, weight seed); pivot -1 = max degree."""
+    return [
+        ("K4", gg.complete(4), 3, "uniform", 1),
+        ("C5", gg.cycle(5), 0, "lognormal", 2),
+        ("star9-leaf", gg.star(9), 5, "uniform", 3),
+        ("path40-mid", gg.path(40), 20, "lognormal", 4),
+        ("grid3", gg.grid2d(3), 4, "pow2", 5),
+        ("tree50", gg.random_tree(50, 3), 7, "uniform", 6),
+        ("gnp200", gg.random_connected(200, 0.03, 5), -1, "lognormal", 7),
+        ("grid32", gg.grid2d(32), 495, "uniform", 8),
+        ("grid17x9", gg.grid2d(17, 9), 0, "pow2", 9),
+        ("rmat10", gg.rmat(10, 8, 3), -1, "uniform", 10),
+        ("rmat12", gg.rmat(12, 16, 1), -1, "lognormal", 11),
+    ]
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    api.lib()
+    return torch.device("cuda:0")
+
+
+def _setup(idx):
+    name, g, piv, kind, ws = cases()[idx]
+    w = gg.edge_weights(g, ws, kind, 0.5, 4.0)
+    u = piv if piv >= 0 else gg.max_degree_pivot(g)
+    G = api.Graph.from_host(g.row_ptr, g.col, weight=w)
+    return name, g, w, u, G
+
+
+@pytest.mark.parametrize("idx", range(len(cases())))
+def test_weighted_trees_bit_exact(gpu, idx):
+    name, g, w, u, G = _setup(idx)
+    count = 70 if g.n > 500 else 131  # several tiles and a ragged tail
+    say("weighted trees", name, count)
+    p = api.problem(G, pivot=u, seed=17, validate=True)
+    par, steps = api.sample_trees(G, p, 5, count)
+    want_par, want_steps, _ = oracle.trees_weighted(g.row_ptr, g.col, w, u, 17, 5, count, 30, want_acc=False)
+    assert (par.cpu().numpy() == want_par).all()
+    assert (steps.cpu().numpy() == want_steps).all()
+
+
+@pytest.mark.parametrize("idx", range(len(cases())))
+def test_weighted_flow_counts_bit_exact(gpu, idx):
+    name, g, w, u, G = _setup(idx)
+    say("weighted flow counts", name)
+    tau_ = 300 if g.n > 500 else 700
+    p = api.problem(G, pivot=u, seed=3, tau_override=tau_, trees_per_batch=128)
+    counts, rep = api.flow_counts(G, p, 0, tau_)
+    _, _, rmax = oracle.bpath_resistance(g.row_ptr, g.col, w, u)
+    k = oracle.fixed_shift(tau_, rmax)
+    assert rep["weighted"] == 1 and rep["rho_max"] == rmax and rep["fixed_shift"] == k
+    _, st, acc = oracle.trees_weighted(g.row_ptr, g.col, w, u, 3, 0, tau_, k, want_parents=False)
+    assert (counts.cpu().numpy() == acc).all()
+    assert rep["walk_steps"] == int(st.sum())
+
+
+def test_weighted_split_ranges_add_up(gpu):
+    name, g, w, u, G = _setup(9)
+    say("weighted split ranges", name)
+    p = api.problem(G, pivot=u, seed=8, tau_override=400)
+    whole, _ = api.flow_counts(G, p, 0, 400)
+    part = torch.zeros_like(whole)
+    for b0, c in [(0, 1), (1, 150), (151, 249)]:
+        api.flow_counts(G, p, b0, c, counts=part)
+    assert torch.equal(whole, part)
+
+
+def test_unit_weights_give_the_unweighted_trees(gpu):
+    g = gg.rmat(11, 8, 5)
+    u = gg.max_degree_pivot(g)
+    say("unit weights", g.n)
+    w = gg.edge_weights(g, 0, "ones")
+    Gw = api.Graph.from_host(g.row_ptr, g.col, weight=w)
+    G1 = api.Graph.from_host(g.row_ptr, g.col)
+    pw = api.problem(Gw, pivot=u, seed=2, tau_override=200)
+    p1 = api.problem(G1, pivot=u, seed=2, tau_override=200)
+    a, sa = api.sample_trees(Gw, pw, 0, 200)
+    b, sb = api.sample_trees(G1, p1, 0, 200)
+    assert torch.equal(a, b) and torch.equal(sa, sb)
+    cw, rw = api.flow_counts(Gw, pw, 0, 200)
+    c1, r1 = api.flow_counts(G1, p1, 0, 200)
+    assert rw["rho_max"] == r1["ecc"]
+    assert torch.equal(cw, c1 * (1 << rw["fixed_shift"]))
+
+
+@pytest.mark.parametrize("idx", [1, 6, 7, 10])
+def test_weighted_solve_matches_oracle(gpu, idx):
+    name, g, w, u, G = _setup(idx)
+    say("weighted solve", name)
+    for mode in (api.SOLVE_FP64, api.SOLVE_MIXED):
+        p = api.problem(G, pivot=u, solve_mode=mode, solve_tol=1e-12)
+        x, rep = api.solve_pivot_column(G, p)
+        want, _, _ = oracle.solve_weighted(g.row_ptr, g.col, w, u, tol=1e-13)
+        x = x.cpu().numpy()
+        assert rep["solve_relres"] < 1e-11
+        assert np.max(np.abs(x - want)) <= 1e-10 * np.max(np.abs(want))
+        assert abs(x.sum()) < 1e-9
+
+
+@pytest.mark.parametrize("idx", [0, 4, 6, 9])
+def test_weighted_diag_lpinv_matches_oracle(gpu, idx):
+    name, g, w, u, G = _setup(idx)
+    say("weighted diag", name)
+    tau_ = 0 if g.n < 100 else 400
+    p = api.problem(G, pivot=u, eps=0.3, seed=9, tau_override=tau_, solve_tol=1e-12)
+    diag, counts, rep = api.diag_lpinv_p(G, p)
+    want = oracle.diag_lpinv_weighted(g.row_ptr, g.col, w, u, 0.3, 9, tau_override=tau_, solve_tol=1e-13)
+    assert rep["tau"] == want["tau"] and rep["fixed_shift"] == want["shift"] and rep["rho_max"] == want["rho_max"]
+    assert (counts.cpu().numpy() == want["acc"]).all()
+    d = diag.cpu().numpy()
+    assert np.max(np.abs(d - want["diag"])) <= 1e-10 * np.max(np.abs(want["diag"]))
+    if g.n <= 10:  # formula tau: within eps of the weighted pseudoinverse diagonal
+        assert np.max(np.abs(d - np.diag(brute.pinv_weighted(g, w)))) <= 0.3
+
+
+def test_weighted_edge_counts_match_oracle(gpu):
+    name, g, w, u, G = _setup(9)
+    say("weighted edge counts", name)
+    p = api.problem(G, pivot=u, seed=4, tau_override=150)
+    got = api.edge_counts(G, p, 0, 150)[0].cpu().numpy()
+    par, _, _ = oracle.trees_weighted(g.row_ptr, g.col, w, u, 4, 0, 150, 30, want_acc=False)
+    assert (got == oracle.edge_counts(g.row_ptr, g.col, par, u)).all()
+
+
+def test_weighted_validation_rejects_bad_weights(gpu):
+    g = gg.grid2d(6)
+    w = gg.edge_weights(g, 1)
+    for bad_kind in ("asym", "zero", "neg", "nan"):
+        say("bad weights", bad_kind)
+        b = w.copy()
+        if bad_kind == "asym":
+            b[7] *= 2.0
+        elif bad_kind == "zero":
+            b[3] = 0.0
+        elif bad_kind == "neg":
+            b[11] = -1.0
+        else:
+            b[2] = np.nan
+        G = api.Graph.from_host(g.row_ptr, g.col, weight=b)
+        p = api.problem(G, pivot=0, validate=True, tau_override=10)
+        with pytest.raises(api.UstdError) as e:
+            api.sample_trees(G, p, 0, 10)
+        assert e.value.status == api.EGRAPH
+
+
+def test_batch_rejects_weighted_member(gpu):
+    g = gg.grid2d(5)
+    G = api.Graph.from_host(g.row_ptr, g.col, weight=gg.edge_weights(g, 1))
+    G1 = api.Graph.from_host(g.row_ptr, g.col)
+    with pytest.raises(api.UstdError) as e:
+        api.batch_diag_lpinv([G1, G], [api.problem(G1, pivot=0), api.problem(G, pivot=0)])
+    assert e.value.status == api.EINVAL
