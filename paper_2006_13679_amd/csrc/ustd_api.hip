@@ -76,7 +76,7 @@ struct Plan {
     long long rec_stride, scr_stride;
     long long off_misc, off_rp32, off_col16, off_dist, off_parB, off_bint, off_bflag, off_heavy, off_bcount, off_counts, off_steps,
         off_draws, off_rec, off_path, off_scr, off_part, off_x64, off_r64, off_z64, off_p64, off_q64,
-        off_res64, off_x32, off_r32, off_z32, off_p32, off_q32, off_cw, off_wdeg, off_wB, off_F;
+        off_res64, off_x32, off_r32, off_z32, off_p32, off_q32, off_cw, off_guide, off_wdeg, off_wB, off_F;
     long long total;
 };
 
@@ -165,6 +165,7 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     // weighted graphs: running row sums of the conductances, row totals, B_u edge weights,
     // fixed-point edge factors
     L.off_cw = take(L.weighted ? (long long)L.nnz * 8 : 0);
+    L.off_guide = take(L.weighted ? (long long)L.nnz * 4 : 0);
     L.off_wdeg = take(L.weighted ? n * 8 : 0);
     L.off_wB = take(L.weighted ? n * 8 : 0);
     L.off_F = take(L.weighted ? n * 8 : 0);
@@ -329,14 +330,12 @@ int begin_with(Ctx &c, const ustd_problem *p, const Plan &L, void *ws, void *str
     c.rows.nheavy = &c.misc->nheavy;
     c.rows.w = nullptr;
     c.rows.wdeg = nullptr;
-    if (c.L.weighted) {
-        c.rows.w = p->d_weight;
-        c.rows.wdeg = at<double>(ws, c.L.off_wdeg);
-        HIP_TRY(launch_row_cumsum(c.L.n, c.rp32, p->d_weight, at<double>(ws, c.L.off_cw), at<double>(ws, c.L.off_wdeg),
-                                  c.st));
-    }
     HIP_TRY(launch_heavy_list(c.L.n, c.rp32, c.L.heavy_thresh, at<int>(ws, c.L.off_bcount), at<int>(ws, c.L.off_heavy),
                               &c.misc->nheavy, c.st));
+    if (c.L.weighted) {  // the running row sums are queued by setup(), beside the BFS
+        c.rows.w = p->d_weight;
+        c.rows.wdeg = at<double>(ws, c.L.off_wdeg);
+    }
     return USTD_OK;
 }
 
@@ -429,8 +428,41 @@ int setup_weighted(Ctx &c) {
     return USTD_OK;
 }
 
-// pivot choice, optional validation and the BFS tree B_u; synchronises the stream
+int setup_graph(Ctx &c, ustd_report *rep);
+
+// pivot choice, optional validation and the BFS tree B_u; synchronises the stream.  For a
+// weighted graph the running row sums and the step guide (needed from sampling on) are
+// computed on the side stream meanwhile; the caller's stream waits for them on success, and
+// on an error the host waits, so nothing is left writing the workspace.
 int setup(Ctx &c, ustd_report *rep) {
+    if (!c.L.weighted) return setup_graph(c, rep);
+    hipStream_t side = nullptr;
+    USTD_TRY(side_stream(&side));
+    SyncEvent fork, join;
+    if (!fork.e || !join.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
+    HIP_TRY(hipEventRecord(fork.e, c.st));
+    HIP_TRY(hipStreamWaitEvent(side, fork.e, 0));
+    const ustd_problem *p = c.p;
+    int rc = hipSuccess == launch_row_cumsum(c.L.n, c.L.nnz, c.rp32, p->d_weight, c.L.heavy_thresh, c.rows.heavy,
+                                             c.rows.nheavy, at<double>(c.ws, c.L.off_cw),
+                                             at<double>(c.ws, c.L.off_wdeg), at<int>(c.ws, c.L.off_guide), side)
+                 ? USTD_OK
+                 : fail(USTD_EHIP, "row sums launch failed");
+    if (rc == USTD_OK && hipEventRecord(join.e, side) != hipSuccess) rc = fail(USTD_EHIP, "hipEventRecord failed");
+    if (rc != USTD_OK) {
+        (void)hipStreamSynchronize(side);
+        return rc;
+    }
+    rc = setup_graph(c, rep);
+    if (rc != USTD_OK) {
+        (void)hipEventSynchronize(join.e);
+        return rc;
+    }
+    HIP_TRY(hipStreamWaitEvent(c.st, join.e, 0));
+    return USTD_OK;
+}
+
+int setup_graph(Ctx &c, ustd_report *rep) {
     const ustd_problem *p = c.p;
     const int n = c.L.n;
     Timer tm(c.st);
@@ -506,6 +538,7 @@ WilsonGraph wilson_graph(const Ctx &c) {
     g.colv = c.L.col16 ? (const void *)at<unsigned short>(c.ws, c.L.off_col16) : (const void *)c.p->d_col;
     g.bflag = at<int>(c.ws, c.L.off_bflag);
     g.cw = c.L.weighted ? at<double>(c.ws, c.L.off_cw) : nullptr;
+    g.guide = c.L.weighted ? at<int>(c.ws, c.L.off_guide) : nullptr;
     g.key0 = (uint32_t)(c.p->seed & 0xFFFFFFFFull);
     g.key1 = (uint32_t)(c.p->seed >> 32);
     return g;

@@ -392,19 +392,23 @@ __device__ __forceinline__ int select_bit64(uint64_t x, int k) {
 // t < C[j], C the row's running conductance sums (cw, taken left to right in FP64) and
 // t = (w 2^-32) C[deg-1]; both products are exact or rounded once, so the choice is the
 // same on every device, and all-ones weights give floor(w deg / 2^32).
+//
+// The weighted search starts from a guide entry: bucket i = floor(w deg / 2^32) holds the
+// first j with C[j] > t(w_i), w_i the bucket's smallest word.  t is non-decreasing in w, so
+// that j never passes the answer, and a forward scan ends on it; buckets are equally wide
+// in t, so the scan takes one probe on average for any weights (deg boundaries, deg buckets).
 template <bool WT>
-__device__ __forceinline__ int step_index(uint32_t w, int r0, int r1, const double *__restrict__ cw) {
+__device__ __forceinline__ int step_index(uint32_t w, int r0, int r1, const double *__restrict__ cw,
+                                          const int *__restrict__ guide) {
+    const int bucket = (int)__umulhi(w, (uint32_t)(r1 - r0));
     if constexpr (!WT) {
-        return (int)__umulhi(w, (uint32_t)(r1 - r0));
+        return bucket;
     } else {
         const double t = ((double)w * 0x1p-32) * cw[r1 - 1];
-        int lo = 0, hi = r1 - r0 - 1;  // the answer lies in [lo, hi]: t < C[deg-1]
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (t < cw[r0 + mid]) hi = mid;
-            else lo = mid + 1;
-        }
-        return lo;
+        const int last = r1 - r0 - 1;
+        int j = guide[r0 + bucket];
+        while (j < last && !(t < cw[r0 + j])) ++j;  // t < C[deg-1] for any normal row total
+        return j;
     }
 }
 
@@ -416,7 +420,8 @@ __device__ __forceinline__ int step_index(uint32_t w, int r0, int r1, const doub
 template <bool LDS, typename CT, bool WT>
 __device__ long long rewalk_commit(const TreeState<LDS> &bits, int *recw, const int *__restrict__ rp,
                                    const CT *__restrict__ col, const double *__restrict__ cw,
-                                   const int *__restrict__ bflag, int s0, int x0, long long k0, uint32_t tlo,
+                                   const int *__restrict__ guide, const int *__restrict__ bflag, int s0, int x0,
+                                   long long k0, uint32_t tlo,
                                    uint32_t thi, uint32_t key0, uint32_t key1) {
     int xw = x0;
     int r0 = rp[x0], r1 = rp[x0 + 1];
@@ -426,7 +431,7 @@ __device__ long long rewalk_commit(const TreeState<LDS> &bits, int *recw, const 
         if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
         const int q = (int)(k & 3);
         const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-        const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw)];
+        const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw, guide)];
         const int ny0 = rp[y], ny1 = rp[y + 1];
         ++k;
         recw[2 * xw] = y;  // Next pointer; becomes the parent when xw joins T
@@ -525,6 +530,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     const int *__restrict__ rp = g.rp;
     const CT *__restrict__ col = reinterpret_cast<const CT *>(g.colv);  // int32, or uint16 when n <= 65536
     const double *__restrict__ cw = g.cw;
+    const int *__restrict__ guide = g.guide;
 
     wait_global();  // the previous tree's record writes have landed
     if constexpr (LDS) {
@@ -612,7 +618,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s, tlo, thi), g.key0, g.key1);
             const int q = k & 3;
             const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-            const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw)];
+            const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw, guide)];
             // loads for y: tree bit and B_u flag; then either the chain value (the walk ends
             // here) or the next row bounds (it continues)
             bool in;
@@ -675,8 +681,8 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                             k0 = kPath;
                         }
                         const long long kk =
-                            rewalk_commit<LDS, CT, WT>(bits, recw, rp, col, cw, bflag, s0, xs, k0, tlo, thi, g.key0,
-                                                       g.key1);
+                            rewalk_commit<LDS, CT, WT>(bits, recw, rp, col, cw, guide, bflag, s0, xs, k0, tlo, thi,
+                                                       g.key0, g.key1);
                         steps += kk;
                         draws += kk - k0;
                     }
@@ -1807,17 +1813,89 @@ __global__ void outer_scalars_kernel(int n, const double *__restrict__ sums, dou
 // of every row (the sampler's step table and the Laplacian's diagonal), the weight checks,
 // the B-path resistances and the fixed-point edge factors of Algorithm 2.
 // ======================================================================================
-// One thread per row, left to right, so every device (and the CPU oracle) gets the same
-// FP64 sums; cw[e] = w[row start] + ... + w[e], wdeg[v] = the row total.
+// Running sums taken left to right, so every device (and the CPU oracle) gets the same FP64
+// sums: cw[e] = w[row start] + ... + w[e], wdeg[v] = the row total.  One thread per light
+// row; rows above `heavy_thresh` entries are left to row_cumsum_heavy_kernel.
 __global__ __launch_bounds__(256) void row_cumsum_kernel(int n, const int *__restrict__ rp, const double *__restrict__ w,
-                                                         double *__restrict__ cw, double *__restrict__ wdeg) {
+                                                         int heavy_thresh, double *__restrict__ cw,
+                                                         double *__restrict__ wdeg) {
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         double run = 0.0;
-        for (int e = rp[v]; e < rp[v + 1]; ++e) {
+        int e = rp[v];
+        const int end = rp[v + 1];
+        if (end - e > heavy_thresh) continue;
+        for (; e + 8 <= end; e += 8) {  // eight loads in flight, the additions still in order
+            double wv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) wv[k] = w[e + k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                run += wv[k];
+                cw[e + k] = run;
+            }
+        }
+        for (; e < end; ++e) {
             run += w[e];
             cw[e] = run;
         }
         wdeg[v] = run;
+    }
+}
+
+// A heavy row per wavefront: each 64-entry chunk is loaded at once (the next one while the
+// current is summed), and the running sum passes through the lanes in order, one addition
+// per entry as in the sequential loop; lane k keeps the sum up to its own entry.
+__global__ __launch_bounds__(64) void row_cumsum_heavy_kernel(const int *__restrict__ rp, const double *__restrict__ w,
+                                                              const int *__restrict__ heavy, const int *__restrict__ nheavy,
+                                                              double *__restrict__ cw, double *__restrict__ wdeg) {
+    const int nh = *nheavy;
+    const int lane = threadIdx.x;
+    for (int h = blockIdx.x; h < nh; h += gridDim.x) {
+        const int v = heavy[h];
+        const int r0 = rp[v], end = rp[v + 1];
+        double run = 0.0;
+        double wn = r0 + lane < end ? w[r0 + lane] : 0.0;
+        for (int base = r0; base < end; base += kWave) {
+            const double wc = wn;
+            wn = base + kWave + lane < end ? w[base + kWave + lane] : 0.0;
+            const int cnt = min(kWave, end - base);
+            const long long bits = __double_as_longlong(wc);
+            const int lo = (int)(bits & 0xFFFFFFFFll), hi = (int)(bits >> 32);
+            double mine = 0.0;
+            for (int k = 0; k < cnt; ++k) {
+                const long long bk = ((long long)(unsigned)__builtin_amdgcn_readlane(hi, k) << 32) |
+                                     (long long)(unsigned)__builtin_amdgcn_readlane(lo, k);
+                run += __longlong_as_double(bk);
+                if (lane == k) mine = run;
+            }
+            if (lane < cnt) cw[base + lane] = mine;
+        }
+        if (lane == 0) wdeg[v] = run;
+    }
+}
+
+// Guide of the weighted step search, one thread per CSR entry e = (row v, bucket i):
+// guide[e] = the first j (at most deg-1) with C[j] > t(w_i), w_i = ceil(i 2^32 / deg) the
+// smallest word of bucket i.  The row is found by a binary search over the row pointers.
+__global__ __launch_bounds__(256) void step_guide_kernel(int n, int nnz, const int *__restrict__ rp,
+                                                         const double *__restrict__ cw, int *__restrict__ guide) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x) {
+        int lo = 0, hi = n - 1;  // the last v with rp[v] <= e
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rp[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        const int r0 = rp[lo], deg = rp[lo + 1] - r0, i = e - r0;
+        const unsigned long long wi = (((unsigned long long)i << 32) + (unsigned long long)(deg - 1)) / (unsigned)deg;
+        const double ti = ((double)wi * 0x1p-32) * cw[r0 + deg - 1];
+        int a = 0, b = deg - 1;  // the first j with ti < C[j], or deg-1
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (ti < cw[r0 + mid]) b = mid;
+            else a = mid + 1;
+        }
+        guide[e] = a;
     }
 }
 
@@ -2117,8 +2195,11 @@ hipError_t launch_combine(int n, int u, double den, const long long *counts, con
     combine_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, u, den, counts, x, diag);
     return hipGetLastError();
 }
-hipError_t launch_row_cumsum(int n, const int *rp, const double *w, double *cw, double *wdeg, hipStream_t st) {
-    row_cumsum_kernel<<<std::min(blocks_for(n, 256), 4096), 256, 0, st>>>(n, rp, w, cw, wdeg);
+hipError_t launch_row_cumsum(int n, int nnz, const int *rp, const double *w, int heavy_thresh, const int *heavy,
+                             const int *nheavy, double *cw, double *wdeg, int *guide, hipStream_t st) {
+    row_cumsum_kernel<<<std::min(blocks_for(n, 256), 4096), 256, 0, st>>>(n, rp, w, heavy_thresh, cw, wdeg);
+    row_cumsum_heavy_kernel<<<1024, kWave, 0, st>>>(rp, w, heavy, nheavy, cw, wdeg);
+    step_guide_kernel<<<std::min(blocks_for(nnz, 256), 8192), 256, 0, st>>>(n, nnz, rp, cw, guide);
     return hipGetLastError();
 }
 hipError_t launch_check_weights(int n, const int *rp, const int *col, const double *w, int *err, hipStream_t st) {

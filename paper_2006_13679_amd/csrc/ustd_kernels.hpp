@@ -15,6 +15,7 @@ struct WilsonGraph {
     const void *colv;       // column indices: int32, or uint16 when the launch says so
     const int *bflag;       // [n] (parB + 1) | (internal in B_u) << 31
     const double *cw;       // [nnz] running conductance sums of each row (weighted launches)
+    const int *guide;       // [nnz] start of the weighted step search per (row, bucket)
     uint32_t key0, key1;    // Philox key (seed)
 };
 
@@ -133,7 +134,8 @@ hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool co
                          hipStream_t st);
 // weighted graphs: running row sums and row totals; weight checks; B_u edge conductances,
 // B-path resistances (max into *rmax_bits, as the bits of a non-negative double); F
-hipError_t launch_row_cumsum(int n, const int *rp, const double *w, double *cw, double *wdeg, hipStream_t st);
+hipError_t launch_row_cumsum(int n, int nnz, const int *rp, const double *w, int heavy_thresh, const int *heavy,
+                             const int *nheavy, double *cw, double *wdeg, int *guide, hipStream_t st);
 hipError_t launch_check_weights(int n, const int *rp, const int *col, const double *w, int *err, hipStream_t st);
 hipError_t launch_bpath(int n, int u, const int *rp, const int *col, const double *w, const int *parB, double *wB,
                         unsigned long long *rmax_bits, hipStream_t st);
