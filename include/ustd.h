@@ -130,7 +130,8 @@ int ustd_bfs(const ustd_problem *prob, void *d_ws, size_t ws_bytes, int32_t *d_d
  * pivot (Appendix "Wilson's UST Algorithm").  d_parents: int32[tree_count][n], row i is
  * the parent array of tree tree_begin+i (parent[u] = -1).  d_steps: int64[tree_count]
  * walk steps of each tree under the sequential definition (nullable).  tree_count <=
- * trees per batch of the workspace.  Synchronises `stream` (pivot selection). */
+ * trees per batch of the workspace; with tree_count = 0 nothing is written (d_parents may
+ * then be NULL).  Synchronises `stream` (pivot selection). */
 int ustd_sample_trees(const ustd_problem *prob, int64_t tree_begin, int64_t tree_count,
                       void *d_ws, size_t ws_bytes, int32_t *d_parents, int64_t *d_steps,
                       void *stream);
@@ -149,7 +150,8 @@ int ustd_flow_counts(const ustd_problem *prob, int64_t tree_begin, int64_t tree_
 /* Flow counts of caller-supplied spanning trees (Algorithm 2 only): d_parents is
  * int32[tree_count][n] of parent arrays rooted at the pivot (parent[u] = -1); d_counts
  * (int64[n]) is accumulated (fixed point for a weighted problem, k from the problem's
- * tau).  The trees are not checked.  Synchronises `stream`. */
+ * tau).  d_parents may be NULL when tree_count = 0.  A parent array that is not a spanning
+ * tree rooted at the pivot returns USTD_EINVAL.  Synchronises `stream`. */
 int ustd_tree_counts(const ustd_problem *prob, const int32_t *d_parents, int64_t tree_count,
                      void *d_ws, size_t ws_bytes, int64_t *d_counts, void *stream);
 

@@ -895,7 +895,7 @@ int ustd_sample_trees(const ustd_problem *prob, int64_t tree_begin, int64_t tree
     USTD_TRY(begin(c, prob, d_ws, ws_bytes, stream));
     if (tree_begin < 0 || tree_count < 0) return fail(USTD_EINVAL, "negative tree range");
     if (tree_count > c.L.K) return fail(USTD_EINVAL, "tree_count %lld exceeds trees per batch %d", (long long)tree_count, c.L.K);
-    if (!d_parents) return fail(USTD_EINVAL, "d_parents is NULL");
+    if (!d_parents && tree_count > 0) return fail(USTD_EINVAL, "d_parents is NULL");
     USTD_TRY(setup(c, nullptr));
     if (tree_count == 0) return USTD_OK;
     long long *steps = d_steps ? (long long *)d_steps : at<long long>(c.ws, c.L.off_steps);
@@ -928,8 +928,8 @@ int ustd_tree_counts(const ustd_problem *prob, const int32_t *d_parents, int64_t
     g_err.clear();
     Ctx c;
     USTD_TRY(begin(c, prob, d_ws, ws_bytes, stream));
-    if (!d_parents || !d_counts) return fail(USTD_EINVAL, "NULL parents / counts");
     if (tree_count < 0) return fail(USTD_EINVAL, "negative tree count");
+    if ((!d_parents && tree_count > 0) || !d_counts) return fail(USTD_EINVAL, "NULL parents / counts");
     USTD_TRY(setup(c, nullptr));
     for (long long b0 = 0; b0 < tree_count; b0 += c.L.Kiv) {
         const int cnt = (int)std::min<long long>(c.L.Kiv, tree_count - b0);

@@ -1,0 +1,101 @@
+"""GPU edge cases against the oracle: empty tree ranges on every entry point, the exact size
+boundaries of the sampler's layouts (16-bit columns and reorder-buffer IDs up to n = 65536,
+the LDS tree bitmap up to n = 131072), tree indices and seeds with high bits set, one tree
+per batch, and a batch of one member."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2006_13679_amd import api
+from paper_2006_13679_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    api.lib()
+    return torch.device("cuda:0")
+
+
+def test_empty_tree_ranges(gpu):
+    g = gg.grid2d(6)
+    G = api.Graph.from_host(g.row_ptr, g.col)
+    p = api.problem(G, pivot=7, seed=2, tau_override=5)
+    say("empty ranges")
+    par, steps = api.sample_trees(G, p, 3, 0)
+    assert par.shape == (0, g.n) and steps.numel() == 0
+    counts = torch.full((g.n,), 7, dtype=torch.int64, device="cuda")
+    out, rep = api.flow_counts(G, p, 3, 0, counts=counts)
+    assert (out.cpu().numpy() == 7).all() and rep["walk_steps"] == 0
+    # no trees: only the fold of the input moves each (a > b) entry onto its (b, a) entry
+    ec = torch.full((len(g.col),), 3, dtype=torch.int64, device="cuda")
+    out, _ = api.edge_counts(G, p, 0, 0, counts=ec)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    want = np.where(rows < g.col, 6, 0)
+    assert (out.cpu().numpy() == want).all()
+    tc = api.tree_counts(G, p, torch.empty((0, g.n), dtype=torch.int32), counts=torch.zeros(g.n, dtype=torch.int64,
+                                                                                               device="cuda"))
+    assert (tc.cpu().numpy() == 0).all()
+
+
+@pytest.mark.parametrize("n,pivot", [(65536, 5), (65537, 5), (131072, 70000), (131073, 70000)])
+def test_layout_boundaries_stars(gpu, n, pivot):
+    """Stars with a leaf pivot: every tree is the star, reached through long walks (centre ->
+    random leaves -> centre ...) at the largest vertex IDs of each layout."""
+    g = gg.star(n)
+    G = api.Graph.from_host(g.row_ptr, g.col)
+    p = api.problem(G, pivot=pivot, seed=3, tau_override=4)
+    say("star", n, pivot)
+    par, steps = api.sample_trees(G, p, 0, 4)
+    _, want_steps, want_counts = oracle.trees(g.row_ptr, g.col, pivot, 3, 0, 4, want_parents=False)
+    par = par.cpu().numpy()
+    assert par[0, pivot] == -1 and par[0, 0] == pivot and (np.delete(par[0], [0, pivot]) == 0).all()
+    assert (steps.cpu().numpy() == want_steps).all()
+    counts, _ = api.flow_counts(G, p, 0, 4)
+    assert (counts.cpu().numpy() == want_counts).all()
+
+
+def test_high_tree_index_and_seed(gpu):
+    g = gg.rmat(9, 8, 4)
+    u = gg.max_degree_pivot(g)
+    G = api.Graph.from_host(g.row_ptr, g.col)
+    seed = 0xFFFFFFFF00000001
+    t0 = (1 << 40) + 12345
+    p = api.problem(G, pivot=u, seed=seed, tau_override=100)
+    say("high tree index")
+    par, steps = api.sample_trees(G, p, t0, 9)
+    want_par, want_steps, _ = oracle.trees(g.row_ptr, g.col, u, seed, t0, 9, want_counts=False)
+    assert (par.cpu().numpy() == want_par).all() and (steps.cpu().numpy() == want_steps).all()
+
+
+def test_one_tree_per_batch(gpu):
+    g = gg.rmat(10, 8, 6)
+    u = gg.max_degree_pivot(g)
+    G = api.Graph.from_host(g.row_ptr, g.col)
+    say("one tree per batch")
+    p1 = api.problem(G, pivot=u, seed=5, tau_override=37, trees_per_batch=1)
+    pa = api.problem(G, pivot=u, seed=5, tau_override=37)
+    d1, c1, r1 = api.diag_lpinv_p(G, p1)
+    da, ca, ra = api.diag_lpinv_p(G, pa)
+    assert r1["n_batches"] == 37 and r1["trees_per_batch"] == 1
+    assert torch.equal(c1, ca) and torch.equal(d1, da)
+    _, _, want = oracle.trees(g.row_ptr, g.col, u, 5, 0, 37, want_parents=False)
+    assert (c1.cpu().numpy() == want).all()
+
+
+def test_batch_of_one_member(gpu):
+    g = gg.grid2d(12)
+    G = api.Graph.from_host(g.row_ptr, g.col)
+    say("batch of one")
+    p = api.problem(G, pivot=gg.grid_center_pivot(12), seed=4, tau_override=300)
+    (db,), (cb,), (rb,) = api.batch_diag_lpinv([G], [p])
+    ds, cs, rs = api.diag_lpinv_p(G, p)
+    assert torch.equal(cb, cs) and torch.equal(db, ds)
+    assert rb["tau"] == rs["tau"] == 300 and rb["walk_steps"] == rs["walk_steps"]
