@@ -108,6 +108,8 @@ typedef struct ustd_report {
     int32_t n_batches;    /* tree batches */
     int32_t trees_per_batch;
     double solve_relres;  /* ||b - L x||_2 / ||b||_2 of the returned column, in FP64 */
+    /* phase times; ms_sample and ms_aggregate sum the launches of every tree batch, which on
+     * graphs above 131072 vertices run on two streams at once (ms_total is wall time) */
     double ms_setup, ms_bfs, ms_sample, ms_intervals, ms_aggregate, ms_solve, ms_combine, ms_total;
     double rho_max;       /* largest B-path resistance (= ecc for unit weights) */
     int32_t fixed_shift;  /* k of the fixed-point counts of a weighted problem (0 unweighted) */

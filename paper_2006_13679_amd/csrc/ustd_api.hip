@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -49,6 +50,7 @@ constexpr long long kAlign = 256;
 constexpr int kLdsBitsMaxWords = 4096;      // tree bitmap in LDS up to 131072 vertices (16 KB)
 constexpr long long kDefaultBudget = 96ll << 30;  // tree records + sampler scratch, a third of 288 GB HBM
 constexpr int kMaxTreesPerBatch = 8192;
+constexpr long long kPoolMinTrees = 4096;  // a pool that fills the GPU's sampler slots
 constexpr int kEdgeTreesPerChunk = 8;  // trees one edge-counting thread goes through
 
 inline long long align_up(long long v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -58,11 +60,12 @@ struct Misc {                      // small zero-initialised block at the front 
     int bfs_found;
     int err_interval;
     int nheavy;
-    int queue;                     // sampler tile counter
+    int queue[2];                  // sampler tile counters, one per tree pool
     int setup_out[2];              // small-graph set-up: ecc, unreached flag
     int pad_[3];
     unsigned long long best_degree;
     unsigned long long rho_max_bits;  // weighted: the largest B-path resistance, as double bits
+    unsigned long long walk_totals[2];  // walk steps and draws of a run of batches
     CgScalars sc64, sc32;
     double rr_hist64[kRrHist];
     double rr_hist32[kRrHist];
@@ -71,7 +74,7 @@ struct Misc {                      // small zero-initialised block at the front 
 };
 
 struct Plan {
-    int n, nnz, K, Kiv, slots, rob, nwords, G, heavy_thresh;
+    int n, nnz, K, Kiv, slots, pools, rob, nwords, G, heavy_thresh;
     bool lds_bits, col16, weighted;
     long long rec_stride, scr_stride;
     long long off_misc, off_rp32, off_col16, off_dist, off_parB, off_bint, off_bflag, off_heavy, off_bcount, off_counts, off_steps,
@@ -118,10 +121,19 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     L.heavy_thresh = 32 * L.G;
     L.rec_stride = align_up((long long)L.n * 8) / 8;  // int2 records
     L.scr_stride = align_up(interval_scratch_ints(L.n) * 4) / 4;
-    // trees resident at once (records), and sampler blocks resident at once (scratch slots)
+    // trees resident at once (records), and sampler blocks resident at once (scratch slots).
+    // Graphs past the LDS bitmap run several batches.  When the budget holds two pools that
+    // can each fill the GPU (kPoolMinTrees trees), they are sampled on two streams, so one
+    // batch's tail and its Algorithm 2 overlap the next batch; smaller pools would leave
+    // every batch short of the resident sampler slots, so the budget stays one pool.
     const long long per_tree = L.rec_stride * 8 + 16;
     const long long per_slot = kSamplerPathSlot * 4;
-    long long K = p->trees_per_batch > 0 ? p->trees_per_batch : std::max(1ll, kDefaultBudget / (per_tree + per_slot));
+    L.pools = (with_trees && !L.lds_bits && p->trees_per_batch <= 0 &&
+               kDefaultBudget / (per_tree + per_slot) >= 2 * kPoolMinTrees)
+                  ? 2
+                  : 1;
+    long long K = p->trees_per_batch > 0 ? p->trees_per_batch
+                                         : std::max(1ll, kDefaultBudget / L.pools / (per_tree + per_slot));
     K = std::min<long long>(K, kMaxTreesPerBatch);
     if (p->tau_override > 0) K = std::min<long long>(K, p->tau_override);
     if (p->tau_cap > 0) K = std::min<long long>(K, p->tau_cap);
@@ -145,10 +157,10 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     L.off_heavy = take(n * 4);
     L.off_bcount = take((n / 256 + 2) * 4);
     L.off_counts = take(n * 8);
-    L.off_steps = take((long long)L.K * 8);
-    L.off_draws = take((long long)L.K * 8);
-    L.off_rec = take((long long)L.K * L.rec_stride * 8);
-    L.off_path = take((long long)L.slots * kSamplerPathSlot * 4);
+    L.off_steps = take((long long)L.pools * L.K * 8);
+    L.off_draws = take((long long)L.pools * L.K * 8);
+    L.off_rec = take((long long)L.pools * L.K * L.rec_stride * 8);
+    L.off_path = take((long long)L.pools * L.slots * kSamplerPathSlot * 4);
     L.off_scr = take(std::max((long long)L.Kiv * L.scr_stride, 3 * n) * 4);
     L.off_part = take((long long)kMaxSolveGrid * 6 * 8);
     L.off_x64 = take(n * 8);
@@ -260,18 +272,22 @@ struct Timer {
     }
 };
 
-// One extra stream per device (default priority, not blocking on the null stream) on which
-// the pivot-column solve runs while the trees are sampled on the caller's stream.  Created
-// on first use and kept until the process ends.
-int side_stream(hipStream_t *out) {
+// Extra streams per device (default priority, not blocking on the null stream): stream 0
+// runs the pivot-column solve (and a weighted graph's row sums) while the trees are sampled
+// on the caller's stream; stream 1 runs the second tree pool of a large graph.  Created on
+// first use and kept until the process ends.
+constexpr int kSideStreams = 2;
+int side_stream(hipStream_t *out, int which = 0) {
     static std::mutex mu;
     static std::vector<hipStream_t> streams;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(mu);
-    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
-    if (!streams[dev]) HIP_TRY(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
-    *out = streams[dev];
+    const size_t need = (size_t)(dev + 1) * kSideStreams;
+    if (streams.size() < need) streams.resize(need, nullptr);
+    hipStream_t &s = streams[(size_t)dev * kSideStreams + which];
+    if (!s) HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    *out = s;
     return USTD_OK;
 }
 
@@ -544,46 +560,56 @@ WilsonGraph wilson_graph(const Ctx &c) {
     return g;
 }
 
-// trees tree_begin .. +ntrees-1 into the record slots 0 .. ntrees-1 (ntrees <= K)
-int sample_batch(Ctx &c, long long tree_begin, int ntrees, long long *steps, long long *draws) {
+// records, sampler slots, step and draw counts of tree pool `pool`
+int2 *pool_rec(const Ctx &c, int pool) { return at<int2>(c.ws, c.L.off_rec) + (long long)pool * c.L.K * c.L.rec_stride; }
+long long *pool_steps(const Ctx &c, int pool) { return at<long long>(c.ws, c.L.off_steps) + (long long)pool * c.L.K; }
+long long *pool_draws(const Ctx &c, int pool) { return at<long long>(c.ws, c.L.off_draws) + (long long)pool * c.L.K; }
+
+// trees tree_begin .. +ntrees-1 into the record slots 0 .. ntrees-1 of a pool (ntrees <= K),
+// on stream st
+int sample_batch(Ctx &c, long long tree_begin, int ntrees, long long *steps, long long *draws, int pool = 0,
+                 hipStream_t st = nullptr) {
+    if (!st) st = c.st;
     WilsonArgs a{};
     a.g = wilson_graph(c);
     a.ntiles = ntrees;
     a.tree_begin = tree_begin;
-    a.rec = at<int2>(c.ws, c.L.off_rec);
+    a.rec = pool_rec(c, pool);
     a.rec_stride = c.L.rec_stride;
-    a.path = at<int>(c.ws, c.L.off_path);
-    a.queue = &c.misc->queue;
+    a.path = at<int>(c.ws, c.L.off_path) + (long long)pool * c.L.slots * kSamplerPathSlot;
+    a.queue = &c.misc->queue[pool];
     a.steps = steps;
     a.draws = draws;
     int blocks = std::min(ntrees, c.L.slots);
     const int resident = wilson_resident_blocks(c.L.lds_bits, c.L.col16, c.L.weighted, c.L.nwords);
     if (resident > 0) blocks = std::min(blocks, resident);
-    HIP_TRY(hipMemsetAsync(&c.misc->queue, 0, sizeof(int), c.st));
-    HIP_TRY(launch_wilson(a, blocks, c.L.lds_bits, c.L.col16, c.L.weighted, c.L.nwords, c.st));
+    HIP_TRY(hipMemsetAsync(&c.misc->queue[pool], 0, sizeof(int), st));
+    HIP_TRY(launch_wilson(a, blocks, c.L.lds_bits, c.L.col16, c.L.weighted, c.L.nwords, st));
     return USTD_OK;
 }
 
-// Algorithm 2 over `cnt` resident trees (records in the workspace)
-int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag) {
+// Algorithm 2 over `cnt` resident trees (records of a pool), on stream st
+int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag, int pool = 0, hipStream_t st = nullptr) {
+    if (!st) st = c.st;
     AggregateArgs aa{};
     aa.n = c.L.n;
     aa.u = c.pivot;
     aa.ntrees = cnt;
     aa.parB = at<int>(c.ws, c.L.off_parB);
     aa.bint = at<int2>(c.ws, c.L.off_bint);
-    aa.rec = at<int2>(c.ws, c.L.off_rec);
+    aa.rec = pool_rec(c, pool);
     aa.rec_stride = c.L.rec_stride;
     aa.counts = counts;
     aa.F = c.L.weighted ? at<long long>(c.ws, c.L.off_F) : nullptr;
-    Timer tm(c.st);
-    HIP_TRY(launch_aggregate(aa, c.st));
+    Timer tm(st);
+    HIP_TRY(launch_aggregate(aa, st));
     if (ms_ag) *ms_ag += tm.stop_ms();
     return USTD_OK;
 }
 
-// Spanning-edge counts over `cnt` resident trees (records in the workspace)
-int edge_count_trees(Ctx &c, int cnt, long long *edge_counts, double *ms) {
+// Spanning-edge counts over `cnt` resident trees (records of a pool), on stream st
+int edge_count_trees(Ctx &c, int cnt, long long *edge_counts, double *ms, int pool = 0, hipStream_t st = nullptr) {
+    if (!st) st = c.st;
     EdgeCountArgs ea{};
     ea.n = c.L.n;
     ea.u = c.pivot;
@@ -591,56 +617,87 @@ int edge_count_trees(Ctx &c, int cnt, long long *edge_counts, double *ms) {
     ea.trees_per_chunk = kEdgeTreesPerChunk;
     ea.rp = c.rp32;
     ea.col = c.p->d_col;
-    ea.rec = at<int2>(c.ws, c.L.off_rec);
+    ea.rec = pool_rec(c, pool);
     ea.rec_stride = c.L.rec_stride;
     ea.counts = edge_counts;
-    Timer tm(c.st);
-    HIP_TRY(launch_edge_counts(ea, c.st));
+    Timer tm(st);
+    HIP_TRY(launch_edge_counts(ea, st));
     if (ms) *ms += tm.stop_ms();
     return USTD_OK;
 }
 
 // Samples trees tree_begin .. +tree_count-1 in batches of at most K; after each batch,
-// Algorithm 2 adds into `counts` and/or the spanning-edge counts into `edge_counts`.
-// `overlap`, if given, runs on the host once all of the first batch's work is queued,
-// before anything waits for it (work for other streams).
+// Algorithm 2 adds into `counts` and/or the spanning-edge counts into `edge_counts`.  With
+// two tree pools, batches alternate between the caller's stream and side stream 1, so a
+// batch's tail and its Algorithm 2 overlap the next batch (integer counts make the order
+// irrelevant).  Walk totals are summed on the device and read once.  `overlap`, if given,
+// runs on the host once all batches are queued, before anything waits for them (work for
+// other streams).
 int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *counts, ustd_report *rep,
               long long *edge_counts = nullptr, const std::function<void()> &overlap = nullptr) {
-    long long steps_total = 0, draws_total = 0;
-    int batches = 0;
-    std::vector<long long> hs(c.L.K), hd(c.L.K);
-    long long *steps = at<long long>(c.ws, c.L.off_steps);
-    long long *draws = at<long long>(c.ws, c.L.off_draws);
-    double ms_s = 0, ms_a = 0;
     // equal batches: ceil(count / K) of them, none larger than K
     const long long nb = (tree_count + c.L.K - 1) / c.L.K;
     const long long per = nb > 0 ? (tree_count + nb - 1) / nb : 0;
-    for (long long b0 = 0; b0 < tree_count; b0 += per) {
+    const int npools = (c.L.pools == 2 && nb > 1) ? 2 : 1;
+    hipStream_t st[2] = {c.st, c.st};
+    unsigned long long *totals = c.misc->walk_totals;
+    HIP_TRY(hipMemsetAsync(totals, 0, 2 * sizeof(unsigned long long), c.st));
+    SyncEvent fork, join;
+    if (npools == 2) {
+        USTD_TRY(side_stream(&st[1], 1));
+        if (!fork.e || !join.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
+        HIP_TRY(hipEventRecord(fork.e, c.st));
+        HIP_TRY(hipStreamWaitEvent(st[1], fork.e, 0));
+    }
+    std::vector<std::unique_ptr<SpanTimer>> ts, ta;
+    int batches = 0;
+    int rc = USTD_OK;
+    for (long long b0 = 0; b0 < tree_count && rc == USTD_OK; b0 += per) {
         const int cnt = (int)std::min<long long>(per, tree_count - b0);
-        SpanTimer ts, ta;
-        ts.start(c.st);
-        USTD_TRY(sample_batch(c, tree_begin + b0, cnt, steps, draws));
-        ts.stop(c.st);
-        ta.start(c.st);
-        if (counts) USTD_TRY(aggregate_trees(c, cnt, counts, nullptr));
-        if (edge_counts) USTD_TRY(edge_count_trees(c, cnt, edge_counts, nullptr));
-        ta.stop(c.st);
-        // before the copies: a copy into pageable host memory blocks the host until it is done
-        if (overlap && batches == 0) overlap();
-        HIP_TRY(hipMemcpyAsync(hs.data(), steps, cnt * sizeof(long long), hipMemcpyDeviceToHost, c.st));
-        HIP_TRY(hipMemcpyAsync(hd.data(), draws, cnt * sizeof(long long), hipMemcpyDeviceToHost, c.st));
-        HIP_TRY(hipStreamSynchronize(c.st));
-        ms_s += ts.ms();
-        ms_a += ta.ms();
-        for (int i = 0; i < cnt; ++i) {
-            steps_total += hs[i];
-            draws_total += hd[i];
+        const int pool = batches % npools;
+        hipStream_t s = st[pool];
+        ts.emplace_back(new SpanTimer());
+        ta.emplace_back(new SpanTimer());
+        ts.back()->start(s);
+        rc = sample_batch(c, tree_begin + b0, cnt, pool_steps(c, pool), pool_draws(c, pool), pool, s);
+        if (rc != USTD_OK) break;
+        ts.back()->stop(s);
+        if (launch_sum_walks(cnt, pool_steps(c, pool), pool_draws(c, pool), totals, s) != hipSuccess) {
+            rc = fail(USTD_EHIP, "walk totals launch failed");
+            break;
         }
+        ta.back()->start(s);
+        if (counts) rc = aggregate_trees(c, cnt, counts, nullptr, pool, s);
+        if (rc == USTD_OK && edge_counts) rc = edge_count_trees(c, cnt, edge_counts, nullptr, pool, s);
+        ta.back()->stop(s);
         ++batches;
     }
+    // every batch is queued; the host is free for the other streams' work meanwhile
+    if (rc == USTD_OK && overlap) overlap();
+    if (npools == 2) {
+        // the caller's stream takes up after both pools' work; on an error the host waits
+        if (rc == USTD_OK && hipEventRecord(join.e, st[1]) == hipSuccess &&
+            hipStreamWaitEvent(c.st, join.e, 0) == hipSuccess) {
+        } else {
+            (void)hipStreamSynchronize(st[1]);
+            if (rc == USTD_OK) rc = fail(USTD_EHIP, "joining the tree pools failed");
+        }
+    }
+    if (rc != USTD_OK) {
+        (void)hipStreamSynchronize(c.st);
+        return rc;
+    }
+    unsigned long long tot[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(tot, totals, sizeof(tot), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    double ms_s = 0, ms_a = 0;
+    for (size_t i = 0; i < ts.size(); ++i) {
+        ms_s += ts[i]->ms();
+        ms_a += ta[i]->ms();
+    }
     if (rep) {
-        rep->walk_steps += steps_total;
-        rep->walk_draws += draws_total;
+        rep->walk_steps += (long long)tot[0];
+        rep->walk_draws += (long long)tot[1];
         rep->n_batches += batches;
         rep->trees_per_batch = c.L.K;
         rep->ms_sample += ms_s;

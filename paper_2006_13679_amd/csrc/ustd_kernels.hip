@@ -1960,6 +1960,25 @@ __global__ void fixed_weights_kernel(int n, int u, const double *__restrict__ wB
     F[v] = v == u ? 0ll : llround(scale / wB[v]);
 }
 
+// walk steps and draws of `cnt` trees added to totals[0], totals[1] (one block)
+__global__ __launch_bounds__(256) void sum_walks_kernel(int cnt, const long long *__restrict__ steps,
+                                                        const long long *__restrict__ draws,
+                                                        unsigned long long *__restrict__ totals) {
+    long long a = 0, b = 0;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        a += steps[i];
+        b += draws[i];
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        a += __shfl_xor(a, d, kWave);
+        b += __shfl_xor(b, d, kWave);
+    }
+    if (lane_id() == 0) {
+        atomicAdd(&totals[0], (unsigned long long)a);
+        atomicAdd(&totals[1], (unsigned long long)b);
+    }
+}
+
 // den = tau, or tau 2^k for the fixed-point counts of a weighted graph
 __global__ void combine_kernel(int n, int u, double den, const long long *__restrict__ counts,
                                const double *__restrict__ x, double *__restrict__ diag) {
@@ -2193,6 +2212,11 @@ hipError_t launch_outer_scalars(int n, const double *sums, double *ss, hipStream
 hipError_t launch_combine(int n, int u, double den, const long long *counts, const double *x, double *diag,
                           hipStream_t st) {
     combine_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, u, den, counts, x, diag);
+    return hipGetLastError();
+}
+hipError_t launch_sum_walks(int cnt, const long long *steps, const long long *draws, unsigned long long *totals,
+                            hipStream_t st) {
+    sum_walks_kernel<<<1, 256, 0, st>>>(cnt, steps, draws, totals);
     return hipGetLastError();
 }
 hipError_t launch_row_cumsum(int n, int nnz, const int *rp, const double *w, int heavy_thresh, const int *heavy,

@@ -134,6 +134,8 @@ hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool co
                          hipStream_t st);
 // weighted graphs: running row sums and row totals; weight checks; B_u edge conductances,
 // B-path resistances (max into *rmax_bits, as the bits of a non-negative double); F
+hipError_t launch_sum_walks(int cnt, const long long *steps, const long long *draws, unsigned long long *totals,
+                            hipStream_t st);
 hipError_t launch_row_cumsum(int n, int nnz, const int *rp, const double *w, int heavy_thresh, const int *heavy,
                              const int *nheavy, double *cw, double *wdeg, int *guide, hipStream_t st);
 hipError_t launch_check_weights(int n, const int *rp, const int *col, const double *w, int *err, hipStream_t st);

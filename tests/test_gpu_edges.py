@@ -99,3 +99,34 @@ def test_batch_of_one_member(gpu):
     ds, cs, rs = api.diag_lpinv_p(G, p)
     assert torch.equal(cb, cs) and torch.equal(db, ds)
     assert rb["tau"] == rs["tau"] == 300 and rb["walk_steps"] == rs["walk_steps"]
+
+
+def test_two_tree_pools_match_one(gpu):
+    """A graph past the LDS bitmap runs its batches on two pools and two streams; the counts,
+    walk totals and diagonal are those of a single-pool run with the same batch split and of
+    a run split by tree ranges (integer counts: any order of batches gives the same sums)."""
+    g = gg.rmat(18, 8, 2)
+    assert g.n > 131072
+    u = gg.max_degree_pivot(g)
+    G = api.Graph.from_host(g.row_ptr, g.col)
+    tau_ = 9000
+    say("two pools", g.n, tau_)
+    p2 = api.problem(G, pivot=u, seed=6, tau_override=tau_)
+    ws = api.Workspace("cuda")
+    assert api.workspace_bytes(p2) > 0
+    d2, c2, r2 = api.diag_lpinv_p(G, p2, ws=ws)
+    assert r2["n_batches"] >= 2
+    p1 = api.problem(G, pivot=u, seed=6, tau_override=tau_, trees_per_batch=-(-tau_ // r2["n_batches"]))
+    d1, c1, r1 = api.diag_lpinv_p(G, p1, ws=ws)
+    assert r1["n_batches"] == r2["n_batches"]
+    assert torch.equal(c1, c2) and torch.equal(d1, d2)
+    assert r1["walk_steps"] == r2["walk_steps"] and r1["walk_draws"] == r2["walk_draws"]
+    part = torch.zeros_like(c2)
+    steps = 0
+    for b0, c in [(0, 4000), (4000, 5000)]:
+        _, rp = api.flow_counts(G, p2, b0, c, counts=part)
+        steps += rp["walk_steps"]
+    assert torch.equal(part, c2) and steps == r2["walk_steps"]
+    _, st, want = oracle.trees(g.row_ptr, g.col, u, 6, 8990, 10, want_parents=False)
+    got, rp = api.flow_counts(G, p2, 8990, 10)
+    assert (got.cpu().numpy() == want).all() and rp["walk_steps"] == int(st.sum())
