@@ -889,7 +889,7 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
     }
     B.max_tiles = std::max(1ll, std::min(bounded ? want_tiles : kMaxBatchTiles, kMaxBatchTiles));
     B.slots = (int)std::min<long long>(kSamplerMaxBlocks, B.max_tiles);
-    const long long slot_bytes = (long long)B.slots * kSamplerPathSlot * 4;
+    const long long slot_bytes = 2 * (long long)B.slots * kSamplerPathSlot * 4;
     long long pool = std::max(kDefaultBudget - slot_bytes, min_rec);
     if (bounded) pool = std::min(pool, std::max(want_rec, min_rec));
     B.rec_pool = align_up(pool);
@@ -898,9 +898,9 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
         o += align_up(bytes);
         return at;
     };
-    B.off_queue = take(sizeof(int));
+    B.off_queue = take(2 * sizeof(int));
     B.off_rec = take(B.rec_pool);
-    B.off_path = take((long long)B.slots * kSamplerPathSlot * 4);
+    B.off_path = take(2 * (long long)B.slots * kSamplerPathSlot * 4);  // two launches per fill
     B.off_steps = take(B.max_tiles * 8);
     B.off_draws = take(B.max_tiles * 8);
     B.off_tiles = take(B.max_tiles * (long long)sizeof(WilsonTile));
@@ -1124,26 +1124,35 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
     int *queue = at<int>(d_ws, B.off_queue);
     HIP_TRY(hipMemcpyAsync(d_graphs, gt.data(), sizeof(WilsonGraph) * (size_t)count, hipMemcpyHostToDevice, st));
 
-    // tiles: members by decreasing size (longest trees start first), each member's trees in order
+    // Each pool fill runs as two persistent launches on two streams.  Launch A takes the
+    // members whose Algorithm 2 costs most (the largest eccentricity: the longest B-paths),
+    // until it holds about half of the fill's sampling work (tau n); launch B the rest.  A's
+    // blocks fill the GPU first and B's take over as A drains, so A's Algorithm 2 runs
+    // beside B's sampling.  Within a launch, tiles go by decreasing graph size (the longest
+    // trees start first), each member's trees in order.
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B.g[a].n > B.g[b].n; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return cs[a].ecc != cs[b].ecc ? cs[a].ecc > cs[b].ecc : B.g[a].n > B.g[b].n;
+    });
     struct Seg {
         int graph;
         long long ntrees, rec_off;
     };
     std::vector<WilsonTile> tiles;
-    std::vector<Seg> segs;
+    std::vector<Seg> segs[2];
     std::vector<long long> hs, hd;
     double ms_s = 0, ms_a = 0;
     int fills = 0;
     long long largest = 0;
     const int resident = wilson_resident_blocks(B.lds_bits, B.col16, false, B.nwords_max);
 
-    // The members' pivot-column solves run on the side stream while the first pool fill is
-    // sampled (each solve touches only its member's solve vectors).
-    hipStream_t side = nullptr;
-    USTD_TRY(side_stream(&side));
+    // The members' pivot-column solves run on side stream 0 while the first pool fill is
+    // sampled (each solve touches only its member's solve vectors); launch B runs on side
+    // stream 1.
+    hipStream_t side = nullptr, sideB = nullptr;
+    USTD_TRY(side_stream(&side, 0));
+    USTD_TRY(side_stream(&sideB, 1));
     SyncEvent fork, join;
     if (!fork.e || !join.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
     HIP_TRY(hipEventRecord(fork.e, st));
@@ -1166,46 +1175,82 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         }
     };
     for (;;) {
-        tiles.clear();
-        segs.clear();
-        long long used = 0;  // bytes of the record pool
+        // members taking part in this fill, in `order`, with their tree counts
+        std::vector<std::pair<int, long long>> part;
+        long long used = 0, ntiles = 0;  // bytes of the record pool, tiles
         for (int gi : order) {
             const long long left = tau[gi] - next[gi];
             if (left <= 0) continue;
             const long long rb = B.g[gi].rec_stride * 8;
-            const long long fit = std::min((B.rec_pool - used) / rb, B.max_tiles - (long long)tiles.size());
+            const long long fit = std::min((B.rec_pool - used) / rb, B.max_tiles - ntiles);
             const long long lim = probs[gi].trees_per_batch > 0 ? probs[gi].trees_per_batch : left;
             const long long take = std::min(std::min(left, fit), lim);
             if (take <= 0) break;
-            segs.push_back(Seg{gi, take, used / 8});
-            for (long long j = 0; j < take; ++j)
-                tiles.push_back(WilsonTile{next[gi] + j, used / 8 + j * B.g[gi].rec_stride, gi, 0});
+            part.emplace_back(gi, take);
             used += take * rb;
-            next[gi] += take;
+            ntiles += take;
         }
-        if (tiles.empty()) break;
+        if (part.empty()) break;
+        // split: launch A up to half of the sampling work, the rest to B (A is never empty)
+        double work = 0.0, half = 0.0;
+        for (auto &pr : part) work += (double)pr.second * (double)B.g[pr.first].n;
+        size_t split = 0;
+        while (split < part.size() && (split == 0 || half < 0.5 * work)) {
+            half += (double)part[split].second * (double)B.g[part[split].first].n;
+            ++split;
+        }
+        tiles.clear();
+        segs[0].clear();
+        segs[1].clear();
+        long long rec_used = 0;
+        int ntA = 0;
+        for (int grp = 0; grp < 2; ++grp) {
+            std::vector<std::pair<int, long long>> mem(part.begin() + (grp ? split : 0),
+                                                       grp ? part.end() : part.begin() + split);
+            std::stable_sort(mem.begin(), mem.end(), [&](const std::pair<int, long long> &x,
+                                                         const std::pair<int, long long> &y) {
+                return B.g[x.first].n > B.g[y.first].n;
+            });
+            for (auto &pr : mem) {
+                const int gi = pr.first;
+                const long long take = pr.second;
+                segs[grp].push_back(Seg{gi, take, rec_used / 8});
+                for (long long j = 0; j < take; ++j)
+                    tiles.push_back(WilsonTile{next[gi] + j, rec_used / 8 + j * B.g[gi].rec_stride, gi, 0});
+                rec_used += take * B.g[gi].rec_stride * 8;
+                next[gi] += take;
+            }
+            if (grp == 0) ntA = (int)tiles.size();
+        }
         const int nt = (int)tiles.size();
         largest = std::max<long long>(largest, nt);
         HIP_TRY(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(WilsonTile) * tiles.size(), hipMemcpyHostToDevice, st));
-        WilsonArgs a{};
-        a.graphs = d_graphs;
-        a.tiles = d_tiles;
-        a.ntiles = nt;
-        a.rec = pool;
-        a.path = at<int>(d_ws, B.off_path);
-        a.queue = queue;
-        a.steps = steps;
-        a.draws = draws;
-        int blocks = std::min(nt, B.slots);
-        if (resident > 0) blocks = std::min(blocks, resident);
-        SpanTimer ts, ta;
-        ts.start(st);
-        HIP_TRY(hipMemsetAsync(queue, 0, sizeof(int), st));
-        HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, false, B.nwords_max, st));
-        ts.stop(st);
-        {
-            ta.start(st);
-            for (const Seg &sg : segs) {
+        HIP_TRY(hipMemsetAsync(queue, 0, 2 * sizeof(int), st));
+        SyncEvent ready, doneB;
+        if (!ready.e || !doneB.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
+        HIP_TRY(hipEventRecord(ready.e, st));
+        HIP_TRY(hipStreamWaitEvent(sideB, ready.e, 0));
+        SpanTimer ts[2], ta[2];
+        for (int grp = 0; grp < 2; ++grp) {
+            const int t0 = grp ? ntA : 0, cnt = grp ? nt - ntA : ntA;
+            if (cnt == 0) continue;
+            hipStream_t s = grp ? sideB : st;
+            WilsonArgs a{};
+            a.graphs = d_graphs;
+            a.tiles = d_tiles + t0;
+            a.ntiles = cnt;
+            a.rec = pool;
+            a.path = at<int>(d_ws, B.off_path) + (long long)grp * B.slots * kSamplerPathSlot;
+            a.queue = queue + grp;
+            a.steps = steps + t0;
+            a.draws = draws + t0;
+            int blocks = std::min(cnt, B.slots);
+            if (resident > 0) blocks = std::min(blocks, resident);
+            ts[grp].start(s);
+            HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, false, B.nwords_max, s));
+            ts[grp].stop(s);
+            ta[grp].start(s);
+            for (const Seg &sg : segs[grp]) {
                 AggregateArgs aa{};
                 aa.n = B.g[sg.graph].n;
                 aa.u = cs[sg.graph].pivot;
@@ -1215,10 +1260,12 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
                 aa.rec = pool + sg.rec_off;
                 aa.rec_stride = B.g[sg.graph].rec_stride;
                 aa.counts = counts[sg.graph];
-                HIP_TRY(launch_aggregate(aa, st));
+                HIP_TRY(launch_aggregate(aa, s));
             }
-            ta.stop(st);
+            ta[grp].stop(s);
         }
+        HIP_TRY(hipEventRecord(doneB.e, sideB));
+        HIP_TRY(hipStreamWaitEvent(st, doneB.e, 0));
         // before the copies: a copy into pageable host memory blocks the host until it is done
         if (!solved) solve_all();
         hs.resize(nt);
@@ -1226,8 +1273,11 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         HIP_TRY(hipMemcpyAsync(hs.data(), steps, sizeof(long long) * (size_t)nt, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(hd.data(), draws, sizeof(long long) * (size_t)nt, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        ms_s += ts.ms();
-        ms_a += ta.ms();
+        for (int grp = 0; grp < 2; ++grp) {
+            if ((grp ? nt - ntA : ntA) == 0) continue;
+            ms_s += ts[grp].ms();
+            ms_a += ta[grp].ms();
+        }
         for (int j = 0; j < nt; ++j) {
             R[tiles[j].graph].walk_steps += hs[j];
             R[tiles[j].graph].walk_draws += hd[j];
