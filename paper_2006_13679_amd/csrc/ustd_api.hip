@@ -51,6 +51,7 @@ constexpr int kLdsBitsMaxWords = 4096;      // tree bitmap in LDS up to 131072 v
 constexpr long long kDefaultBudget = 96ll << 30;  // tree records + sampler scratch, a third of 288 GB HBM
 constexpr int kMaxTreesPerBatch = 8192;
 constexpr long long kPoolMinTrees = 4096;  // a pool that fills the GPU's sampler slots
+constexpr int kBatchGroupFills = 2;        // sampler group of a batch fill, in GPU-fills of trees
 constexpr int kEdgeTreesPerChunk = 8;  // trees one edge-counting thread goes through
 
 inline long long align_up(long long v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -274,9 +275,10 @@ struct Timer {
 
 // Extra streams per device (default priority, not blocking on the null stream): stream 0
 // runs the pivot-column solve (and a weighted graph's row sums) while the trees are sampled
-// on the caller's stream; stream 1 runs the second tree pool of a large graph.  Created on
-// first use and kept until the process ends.
-constexpr int kSideStreams = 2;
+// on the caller's stream; stream 1 runs the second tree pool of a large graph (and every
+// other sampler group of a batch); stream 2 runs a batch's Algorithm 2.  Created on first
+// use and kept until the process ends.
+constexpr int kSideStreams = 3;
 int side_stream(hipStream_t *out, int which = 0) {
     static std::mutex mu;
     static std::vector<hipStream_t> streams;
@@ -1124,12 +1126,12 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
     int *queue = at<int>(d_ws, B.off_queue);
     HIP_TRY(hipMemcpyAsync(d_graphs, gt.data(), sizeof(WilsonGraph) * (size_t)count, hipMemcpyHostToDevice, st));
 
-    // Each pool fill runs as two persistent launches on two streams.  Launch A takes the
-    // members whose Algorithm 2 costs most (the largest eccentricity: the longest B-paths),
-    // until it holds about half of the fill's sampling work (tau n); launch B the rest.  A's
-    // blocks fill the GPU first and B's take over as A drains, so A's Algorithm 2 runs
-    // beside B's sampling.  Within a launch, tiles go by decreasing graph size (the longest
-    // trees start first), each member's trees in order.
+    // A pool fill is sampled in groups of about kBatchGroupFills GPU-fills of trees, members in
+    // order of decreasing eccentricity (the longest B-paths, so the costliest Algorithm 2,
+    // first).  Groups alternate between the caller's stream and side stream 1, so one group's
+    // tail overlaps the next; each group's Algorithm 2 runs on side stream 2 once that group
+    // is sampled, beside the later groups' sampling.  Within a group, tiles go by decreasing
+    // graph size (the longest trees start first), each member's trees in order.
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -1140,19 +1142,19 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         long long ntrees, rec_off;
     };
     std::vector<WilsonTile> tiles;
-    std::vector<Seg> segs[2];
     std::vector<long long> hs, hd;
     double ms_s = 0, ms_a = 0;
     int fills = 0;
     long long largest = 0;
     const int resident = wilson_resident_blocks(B.lds_bits, B.col16, false, B.nwords_max);
+    const long long group_trees = (long long)kBatchGroupFills * std::max(resident, 1);
 
     // The members' pivot-column solves run on side stream 0 while the first pool fill is
-    // sampled (each solve touches only its member's solve vectors); launch B runs on side
-    // stream 1.
-    hipStream_t side = nullptr, sideB = nullptr;
+    // sampled (each solve touches only its member's solve vectors).
+    hipStream_t side = nullptr, samp1 = nullptr, aggq = nullptr;
     USTD_TRY(side_stream(&side, 0));
-    USTD_TRY(side_stream(&sideB, 1));
+    USTD_TRY(side_stream(&samp1, 1));
+    USTD_TRY(side_stream(&aggq, 2));
     SyncEvent fork, join;
     if (!fork.e || !join.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
     HIP_TRY(hipEventRecord(fork.e, st));
@@ -1191,66 +1193,72 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
             ntiles += take;
         }
         if (part.empty()) break;
-        // split: launch A up to half of the sampling work, the rest to B (A is never empty)
-        double work = 0.0, half = 0.0;
-        for (auto &pr : part) work += (double)pr.second * (double)B.g[pr.first].n;
-        size_t split = 0;
-        while (split < part.size() && (split == 0 || half < 0.5 * work)) {
-            half += (double)part[split].second * (double)B.g[part[split].first].n;
-            ++split;
-        }
+        // groups of whole members, each reaching group_trees trees (the last one may not)
+        std::vector<std::vector<Seg>> groups;
+        std::vector<int> gstart;  // first tile of each group
         tiles.clear();
-        segs[0].clear();
-        segs[1].clear();
         long long rec_used = 0;
-        int ntA = 0;
-        for (int grp = 0; grp < 2; ++grp) {
-            std::vector<std::pair<int, long long>> mem(part.begin() + (grp ? split : 0),
-                                                       grp ? part.end() : part.begin() + split);
+        for (size_t k = 0; k < part.size();) {
+            size_t e = k;
+            long long cnt = 0;
+            while (e < part.size() && (e == k || cnt < group_trees)) cnt += part[e++].second;
+            std::vector<std::pair<int, long long>> mem(part.begin() + k, part.begin() + e);
             std::stable_sort(mem.begin(), mem.end(), [&](const std::pair<int, long long> &x,
                                                          const std::pair<int, long long> &y) {
                 return B.g[x.first].n > B.g[y.first].n;
             });
+            gstart.push_back((int)tiles.size());
+            groups.emplace_back();
             for (auto &pr : mem) {
                 const int gi = pr.first;
                 const long long take = pr.second;
-                segs[grp].push_back(Seg{gi, take, rec_used / 8});
+                groups.back().push_back(Seg{gi, take, rec_used / 8});
                 for (long long j = 0; j < take; ++j)
                     tiles.push_back(WilsonTile{next[gi] + j, rec_used / 8 + j * B.g[gi].rec_stride, gi, 0});
                 rec_used += take * B.g[gi].rec_stride * 8;
                 next[gi] += take;
             }
-            if (grp == 0) ntA = (int)tiles.size();
+            k = e;
         }
+        gstart.push_back((int)tiles.size());
         const int nt = (int)tiles.size();
         largest = std::max<long long>(largest, nt);
         HIP_TRY(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(WilsonTile) * tiles.size(), hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemsetAsync(queue, 0, 2 * sizeof(int), st));
-        SyncEvent ready, doneB;
-        if (!ready.e || !doneB.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
+        SyncEvent ready;
+        if (!ready.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
         HIP_TRY(hipEventRecord(ready.e, st));
-        HIP_TRY(hipStreamWaitEvent(sideB, ready.e, 0));
-        SpanTimer ts[2], ta[2];
-        for (int grp = 0; grp < 2; ++grp) {
-            const int t0 = grp ? ntA : 0, cnt = grp ? nt - ntA : ntA;
-            if (cnt == 0) continue;
-            hipStream_t s = grp ? sideB : st;
+        HIP_TRY(hipStreamWaitEvent(samp1, ready.e, 0));
+        HIP_TRY(hipStreamWaitEvent(aggq, ready.e, 0));
+        const size_t ng = groups.size();
+        std::vector<std::unique_ptr<SpanTimer>> ts, ta;
+        std::vector<std::unique_ptr<SyncEvent>> sampled;
+        for (size_t gidx = 0; gidx < ng; ++gidx) {
+            const int pool2 = (int)(gidx & 1);
+            hipStream_t s = pool2 ? samp1 : st;
+            const int t0 = gstart[gidx], cnt = gstart[gidx + 1] - gstart[gidx];
             WilsonArgs a{};
             a.graphs = d_graphs;
             a.tiles = d_tiles + t0;
             a.ntiles = cnt;
             a.rec = pool;
-            a.path = at<int>(d_ws, B.off_path) + (long long)grp * B.slots * kSamplerPathSlot;
-            a.queue = queue + grp;
+            a.path = at<int>(d_ws, B.off_path) + (long long)pool2 * B.slots * kSamplerPathSlot;
+            a.queue = queue + pool2;
             a.steps = steps + t0;
             a.draws = draws + t0;
             int blocks = std::min(cnt, B.slots);
             if (resident > 0) blocks = std::min(blocks, resident);
-            ts[grp].start(s);
+            ts.emplace_back(new SpanTimer());
+            ta.emplace_back(new SpanTimer());
+            sampled.emplace_back(new SyncEvent());
+            if (!sampled.back()->e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
+            ts.back()->start(s);
+            HIP_TRY(hipMemsetAsync(queue + pool2, 0, sizeof(int), s));
             HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, false, B.nwords_max, s));
-            ts[grp].stop(s);
-            ta[grp].start(s);
-            for (const Seg &sg : segs[grp]) {
+            ts.back()->stop(s);
+            HIP_TRY(hipEventRecord(sampled.back()->e, s));
+            HIP_TRY(hipStreamWaitEvent(aggq, sampled.back()->e, 0));
+            ta.back()->start(aggq);
+            for (const Seg &sg : groups[gidx]) {
                 AggregateArgs aa{};
                 aa.n = B.g[sg.graph].n;
                 aa.u = cs[sg.graph].pivot;
@@ -1260,12 +1268,16 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
                 aa.rec = pool + sg.rec_off;
                 aa.rec_stride = B.g[sg.graph].rec_stride;
                 aa.counts = counts[sg.graph];
-                HIP_TRY(launch_aggregate(aa, s));
+                HIP_TRY(launch_aggregate(aa, aggq));
             }
-            ta[grp].stop(s);
+            ta.back()->stop(aggq);
         }
-        HIP_TRY(hipEventRecord(doneB.e, sideB));
-        HIP_TRY(hipStreamWaitEvent(st, doneB.e, 0));
+        SyncEvent s1done, aggdone;
+        if (!s1done.e || !aggdone.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
+        HIP_TRY(hipEventRecord(s1done.e, samp1));
+        HIP_TRY(hipEventRecord(aggdone.e, aggq));
+        HIP_TRY(hipStreamWaitEvent(st, s1done.e, 0));
+        HIP_TRY(hipStreamWaitEvent(st, aggdone.e, 0));
         // before the copies: a copy into pageable host memory blocks the host until it is done
         if (!solved) solve_all();
         hs.resize(nt);
@@ -1273,10 +1285,9 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         HIP_TRY(hipMemcpyAsync(hs.data(), steps, sizeof(long long) * (size_t)nt, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(hd.data(), draws, sizeof(long long) * (size_t)nt, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        for (int grp = 0; grp < 2; ++grp) {
-            if ((grp ? nt - ntA : ntA) == 0) continue;
-            ms_s += ts[grp].ms();
-            ms_a += ta[grp].ms();
+        for (size_t gidx = 0; gidx < ng; ++gidx) {
+            ms_s += ts[gidx]->ms();
+            ms_a += ta[gidx]->ms();
         }
         for (int j = 0; j < nt; ++j) {
             R[tiles[j].graph].walk_steps += hs[j];
