@@ -1003,7 +1003,7 @@ int ustd_tree_counts(const ustd_problem *prob, const int32_t *d_parents, int64_t
         ia.rec_stride = c.L.rec_stride;
         ia.bflag = at<int>(c.ws, c.L.off_bflag);
         ia.err = &c.misc->err_interval;
-        HIP_TRY(launch_intervals(ia, cnt, c.st));
+        HIP_TRY(launch_tree_records(ia, cnt, c.st));
         USTD_TRY(aggregate_trees(c, cnt, (long long *)d_counts, nullptr));
         int err = 0;
         HIP_TRY(hipMemcpyAsync(&err, &c.misc->err_interval, sizeof(int), hipMemcpyDeviceToHost, c.st));

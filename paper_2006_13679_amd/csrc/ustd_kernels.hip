@@ -313,12 +313,12 @@ __device__ __forceinline__ bool bf_internal(int f) { return (unsigned)f >> 31; }
 // cv(x) follows from the record.
 constexpr int kMarkBit = (int)0x80000000u;
 constexpr int kFwdBit = 0x40000000;
-__device__ __forceinline__ int cv_of(int x, int nbx) { return nbx < 0 ? x : nbx; }
+__device__ __forceinline__ int cv_of(int x, int nbx) { return (nbx & kMarkBit) ? x : nbx; }
 __device__ __forceinline__ int nba_of(int nbx) { return nbx & 0x3FFFFFFF; }
 // the flag bits of vertex x (B_u flag word fx) whose tree parent is px (flag word fpx)
 __device__ __forceinline__ int mark_bits(int x, int fx, int px, int fpx) {
     const unsigned fwd = px == bf_parent(fx), bwd = bf_parent(fpx) == x;
-    const unsigned m = ((unsigned)fx >> 31) & (fwd | bwd);
+    const unsigned m = (unsigned)bf_internal(fx) & (fwd | bwd);
     return (int)((m << 31) | ((m & fwd) << 30));
 }
 // The same two bits in the low bits, for a walk step x -> y: the walk records them with y,
@@ -924,17 +924,16 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
 }
 
 // ======================================================================================
-// Tree intervals.  Algorithm 2 asks whether v lies below an edge of T, which the paper
-// answers with DFS discovery/finish times.  Any subtree-interval labelling answers it the
-// same way: v is in the subtree of b  <=>  pre[b] <= pre[v] < pre[b] + size[b].  One block
-// per tree builds a child CSR (counting sort by parent), expands a BFS order of T level
-// by level (children of one vertex are contiguous), sums subtree sizes bottom-up with
-// per-level prefix sums, and assigns pre-order numbers top-down as parent's number + 1 +
-// sizes of the earlier siblings.  Output: {parent, pre, size, 0} per vertex.
+// Records of caller-supplied trees.  The sampler writes each vertex's record {parent,
+// nba | flags} as it commits; for trees given as parent arrays the same records are built
+// here.  One block per tree checks the parents, builds a child CSR (counting sort by
+// parent), expands a BFS order of T level by level (children of one vertex contiguous),
+// and writes the records top-down along that order, so a vertex's parent is done first.
+// A parent array that is not a spanning tree rooted at u sets err |= 64.
 // ======================================================================================
 constexpr int kIvThreads = 256;
 
-__global__ __launch_bounds__(kIvThreads) void intervals_kernel(IntervalArgs a) {
+__global__ __launch_bounds__(kIvThreads) void tree_records_kernel(IntervalArgs a) {
     __shared__ int sh[kIvThreads / kWave + 1];
     __shared__ int bigq[kIvThreads];
     __shared__ int nbig;
@@ -948,11 +947,7 @@ __global__ __launch_bounds__(kIvThreads) void intervals_kernel(IntervalArgs a) {
     int *__restrict__ ord = child + n;      // n
     int *__restrict__ fc = ord + n;         // n   first-child position of each position
     int *__restrict__ ppos = fc + n;        // n   parent position of each position
-    int *__restrict__ sz = ppos + n;        // n
-    int *__restrict__ ps = sz + n;          // n   per-level inclusive prefix sums of sz
-    int *__restrict__ pre = ps + n;         // n
-    int *__restrict__ lv = pre + n;         // n + 2 level starts
-    int4 *__restrict__ pk = a.pk + (long long)blockIdx.x * a.pk_stride;
+    int *__restrict__ lv = ppos + n;        // n + 2 level starts
 
     for (int v = tid; v < n; v += kIvThreads) cnt[v] = 0;
     __syncthreads();
@@ -1045,64 +1040,18 @@ __global__ __launch_bounds__(kIvThreads) void intervals_kernel(IntervalArgs a) {
     if (tid == 0 && ls != n) atomicOr(a.err, 64);  // not a spanning tree rooted at u
     if (ls != n) return;
 
-    if (a.rec) {
-        // {parent, nba | marked << 31} top-down along the BFS order of T
-        int2 *rec = a.rec + (long long)blockIdx.x * a.rec_stride;
-        if (tid == 0) rec[u] = make_int2(-1, u);
-        __syncthreads();
-        for (int L = 1; L < nlev; ++L) {
-            for (int j = lv[L] + tid; j < lv[L + 1]; j += kIvThreads) {
-                const int xv = ord[j];
-                const int pv = par[xv];
-                const int nba = cv_of(pv, rec[pv].y);
-                rec[xv] = make_int2(pv, nba | mark_bits(xv, a.bflag[xv], pv, a.bflag[pv]));
-            }
-            __syncthreads();
-        }
-        return;
-    }
-
-    // subtree sizes, deepest level first; ps holds the inclusive prefix of the level below
-    for (int L = nlev - 1; L >= 0; --L) {
-        const int lb = lv[L], le2 = lv[L + 1];
-        for (int i = lb + tid; i < le2; i += kIvThreads) {
-            const int xv = ord[i];
-            const int c = cst[xv + 1] - cst[xv];
-            int sv = 1;
-            if (c > 0) {
-                const int f = fc[i];
-                sv += ps[f + c - 1] - (f > le2 ? ps[f - 1] : 0);
-            }
-            sz[i] = sv;
-        }
-        __syncthreads();
-        carry = 0;
-        for (int base = lb; base < le2; base += kIvThreads) {
-            const int i = base + tid;
-            const int sv = i < le2 ? sz[i] : 0;
-            int tot;
-            const int incl = block_incl_scan(sv, &tot, sh);
-            if (i < le2) ps[i] = carry + incl;
-            carry += tot;
-        }
-        __syncthreads();
-    }
-    // pre-order numbers, top level first
-    if (tid == 0) pre[0] = 0;
+    // {parent, nba | marked << 31} top-down along the BFS order of T
+    int2 *rec = a.rec + (long long)blockIdx.x * a.rec_stride;
+    if (tid == 0) rec[u] = make_int2(-1, u);
     __syncthreads();
     for (int L = 1; L < nlev; ++L) {
-        const int lb = lv[L], le2 = lv[L + 1];
-        for (int j = lb + tid; j < le2; j += kIvThreads) {
-            const int i = ppos[j];
-            const int f = fc[i];
-            const int before = j > f ? ps[j - 1] - (f > lb ? ps[f - 1] : 0) : 0;
-            pre[j] = pre[i] + 1 + before;
+        for (int j = lv[L] + tid; j < lv[L + 1]; j += kIvThreads) {
+            const int xv = ord[j];
+            const int pv = par[xv];
+            const int nba = cv_of(pv, rec[pv].y);
+            rec[xv] = make_int2(pv, nba | mark_bits(xv, a.bflag[xv], pv, a.bflag[pv]));
         }
         __syncthreads();
-    }
-    for (int j = tid; j < n; j += kIvThreads) {
-        const int xv = ord[j];
-        pk[xv] = make_int4(par[xv], pre[j], sz[j], 0);
     }
 }
 
@@ -2100,8 +2049,8 @@ hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool co
     }
     return hipGetLastError();
 }
-hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st) {
-    intervals_kernel<<<ntrees, kIvThreads, 0, st>>>(a);
+hipError_t launch_tree_records(const IntervalArgs &a, int ntrees, hipStream_t st) {
+    tree_records_kernel<<<ntrees, kIvThreads, 0, st>>>(a);
     return hipGetLastError();
 }
 hipError_t launch_extract_parents(int n, int ntrees, const int2 *rec, long long rec_stride, int *out, hipStream_t st) {

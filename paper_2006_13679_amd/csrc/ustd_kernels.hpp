@@ -47,13 +47,11 @@ struct IntervalArgs {
     int n, u;
     const int *par;         // [ntrees][par_stride]
     long long par_stride;
-    int *scratch;           // [ntrees][scratch_stride], scratch_stride >= 10n + 3
+    int *scratch;           // [ntrees][scratch_stride], scratch_stride >= 7n + 3
     long long scratch_stride;
-    int4 *pk;               // [ntrees][pk_stride] {parent, pre, size, 0} (when rec is null)
-    long long pk_stride;
-    int2 *rec;              // nullable: [ntrees][rec_stride] {parent, nba | marked << 31} instead of pk
+    int2 *rec;              // [ntrees][rec_stride] {parent, nba | flags} records out
     long long rec_stride;
-    const int *bflag;       // needed with rec
+    const int *bflag;       // [n] B_u flag words
     int *err;
 };
 
@@ -115,7 +113,7 @@ struct CgArgs {
     const double *wdeg;     // [n] Jacobi diagonal of a weighted Laplacian; null = degrees
 };
 
-inline long long interval_scratch_ints(long long n) { return 10 * n + 3; }
+inline long long interval_scratch_ints(long long n) { return 7 * n + 3; }
 
 hipError_t launch_rp_to_i32(int n, const long long *rp64, int *rp32, hipStream_t st);
 hipError_t launch_validate(int n, long long nnz, const long long *rp64, const int *col, int *err, hipStream_t st);
@@ -143,7 +141,7 @@ hipError_t launch_bpath(int n, int u, const int *rp, const int *col, const doubl
                         unsigned long long *rmax_bits, hipStream_t st);
 hipError_t launch_fixed_weights(int n, int u, const double *wB, int shift, long long *F, hipStream_t st);
 hipError_t launch_col_to_u16(long long nnz, const int *col, unsigned short *col16, hipStream_t st);
-hipError_t launch_intervals(const IntervalArgs &a, int ntrees, hipStream_t st);
+hipError_t launch_tree_records(const IntervalArgs &a, int ntrees, hipStream_t st);
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st);
 hipError_t launch_extract_parents(int n, int ntrees, const int2 *rec, long long rec_stride, int *out, hipStream_t st);
 hipError_t launch_centralities(long long n, const double *diag, double *farness, double *closeness, double *nrwb,
