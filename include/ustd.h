@@ -92,7 +92,7 @@ typedef struct ustd_problem {
      *  - k = 62 - e, where tau * rho_max = f 2^e with f in [0.5, 1), so sums over up to 2 tau
      *    trees fit int64 (count calls on tree ranges use the problem's tau to fix k);
      *  - the pivot-column solve uses the weighted Laplacian (Jacobi on weighted degrees).
-     * ustd_batch_diag_lpinv rejects weighted members (USTD_EINVAL). */
+     * ustd_batch_diag_lpinv takes weighted and unweighted members together. */
     const double *d_weight;
 } ustd_problem;
 

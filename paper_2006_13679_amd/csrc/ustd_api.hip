@@ -868,8 +868,6 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
             const std::string m = g_err;
             return fail(rc, "problem %d: %s", i, m.c_str());
         }
-        if (probs[i].d_weight)
-            return fail(USTD_EINVAL, "problem %d: weighted graphs are not supported by the batch entry point", i);
         const Plan L = make_plan(&probs[i], false);
         B.g.push_back(L);
         B.base.push_back(o);
@@ -1112,7 +1110,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         void *wsi = static_cast<char *>(d_ws) + B.base[i];
         USTD_TRY(member(i, begin_with(cs[i], &probs[i], B.g[i], wsi, stream)));
         USTD_TRY(member(i, setup(cs[i], &R[i])));
-        tau[i] = sample_size(&probs[i], cs[i].ecc);
+        tau[i] = problem_tau(cs[i]);
         R[i].tau = tau[i];
         counts[i] = (d_counts && d_counts[i]) ? (long long *)d_counts[i] : at<long long>(wsi, B.g[i].off_counts);
         HIP_TRY(hipMemsetAsync(counts[i], 0, (size_t)B.g[i].n * 8, st));
@@ -1126,8 +1124,9 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
     int *queue = at<int>(d_ws, B.off_queue);
     HIP_TRY(hipMemcpyAsync(d_graphs, gt.data(), sizeof(WilsonGraph) * (size_t)count, hipMemcpyHostToDevice, st));
 
-    // A pool fill is sampled in groups of about kBatchGroupFills GPU-fills of trees, members in
-    // order of decreasing eccentricity (the longest B-paths, so the costliest Algorithm 2,
+    // A pool fill is sampled in groups of about kBatchGroupFills GPU-fills of trees, unweighted
+    // members before weighted ones (a group holds one kind: one sampler variant per launch),
+    // each kind in order of decreasing eccentricity (the longest B-paths, so the costliest Algorithm 2,
     // first).  Groups alternate between the caller's stream and side stream 1, so one group's
     // tail overlaps the next; each group's Algorithm 2 runs on side stream 2 once that group
     // is sampled, beside the later groups' sampling.  Within a group, tiles go by decreasing
@@ -1135,6 +1134,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (B.g[a].weighted != B.g[b].weighted) return !B.g[a].weighted;  // one kind per group
         return cs[a].ecc != cs[b].ecc ? cs[a].ecc > cs[b].ecc : B.g[a].n > B.g[b].n;
     });
     struct Seg {
@@ -1147,6 +1147,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
     int fills = 0;
     long long largest = 0;
     const int resident = wilson_resident_blocks(B.lds_bits, B.col16, false, B.nwords_max);
+    const int resident_w = wilson_resident_blocks(B.lds_bits, B.col16, true, B.nwords_max);
     const long long group_trees = (long long)kBatchGroupFills * std::max(resident, 1);
 
     // The members' pivot-column solves run on side stream 0 while the first pool fill is
@@ -1198,10 +1199,14 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         std::vector<int> gstart;  // first tile of each group
         tiles.clear();
         long long rec_used = 0;
+        std::vector<char> gweighted;  // each group is all weighted or all unweighted (one kernel)
         for (size_t k = 0; k < part.size();) {
             size_t e = k;
             long long cnt = 0;
-            while (e < part.size() && (e == k || cnt < group_trees)) cnt += part[e++].second;
+            const bool wk = B.g[part[k].first].weighted;
+            while (e < part.size() && (e == k || cnt < group_trees) && B.g[part[e].first].weighted == wk)
+                cnt += part[e++].second;
+            gweighted.push_back(wk ? 1 : 0);
             std::vector<std::pair<int, long long>> mem(part.begin() + k, part.begin() + e);
             std::stable_sort(mem.begin(), mem.end(), [&](const std::pair<int, long long> &x,
                                                          const std::pair<int, long long> &y) {
@@ -1245,15 +1250,17 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
             a.queue = queue + pool2;
             a.steps = steps + t0;
             a.draws = draws + t0;
+            const bool wt = gweighted[gidx] != 0;
+            const int res = wt ? resident_w : resident;
             int blocks = std::min(cnt, B.slots);
-            if (resident > 0) blocks = std::min(blocks, resident);
+            if (res > 0) blocks = std::min(blocks, res);
             ts.emplace_back(new SpanTimer());
             ta.emplace_back(new SpanTimer());
             sampled.emplace_back(new SyncEvent());
             if (!sampled.back()->e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
             ts.back()->start(s);
             HIP_TRY(hipMemsetAsync(queue + pool2, 0, sizeof(int), s));
-            HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, false, B.nwords_max, s));
+            HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, wt, B.nwords_max, s));
             ts.back()->stop(s);
             HIP_TRY(hipEventRecord(sampled.back()->e, s));
             HIP_TRY(hipStreamWaitEvent(aggq, sampled.back()->e, 0));
@@ -1268,6 +1275,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
                 aa.rec = pool + sg.rec_off;
                 aa.rec_stride = B.g[sg.graph].rec_stride;
                 aa.counts = counts[sg.graph];
+                aa.F = B.g[sg.graph].weighted ? at<long long>(cs[sg.graph].ws, B.g[sg.graph].off_F) : nullptr;
                 HIP_TRY(launch_aggregate(aa, aggq));
             }
             ta.back()->stop(aggq);
@@ -1308,7 +1316,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
         R[i].ms_aggregate = ms_a;
         double *x = at<double>(cs[i].ws, B.g[i].off_x64);
         Timer tm(st);
-        HIP_TRY(launch_combine(B.g[i].n, cs[i].pivot, (double)tau[i], counts[i], x, d_diags[i], st));
+        HIP_TRY(launch_combine(B.g[i].n, cs[i].pivot, count_scale(cs[i], tau[i]), counts[i], x, d_diags[i], st));
         R[i].ms_combine += tm.stop_ms();
     }
     const double ms = total.stop_ms();

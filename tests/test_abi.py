@@ -60,17 +60,22 @@ def test_status_strings():
     assert L.ustd_status_string(99) == b"USTD_UNKNOWN"
 
 
-def test_weighted_workspace_and_batch_rejection():
-    """Weights add the running row sums (nnz doubles) and three n-vectors; the batch entry
-    point rejects a weighted member on the host."""
+def test_weighted_workspace_single_and_batch():
+    """Weights add the running row sums (nnz doubles) and three n-vectors, to a single problem's
+    workspace and to that member's share of a batch workspace."""
     b0 = api.workspace_bytes(_prob())
     b1 = api.workspace_bytes(_prob(d_weight=0x3000))
     assert b1 - b0 >= 3968 * 8 + 3 * 1024 * 8
-    probs = (api.Problem * 2)(_prob(), _prob(d_weight=0x3000))
-    size = ctypes.c_size_t(0)
-    rc = api.lib().ustd_batch_workspace_bytes(probs, 2, ctypes.byref(size))
-    assert rc == api.EINVAL
-    assert b"weighted" in api.lib().ustd_last_error()
+
+    def batch_bytes(*ps):
+        arr = (api.Problem * len(ps))(*ps)
+        size = ctypes.c_size_t(0)
+        assert api.lib().ustd_batch_workspace_bytes(arr, len(ps), ctypes.byref(size)) == api.OK
+        return size.value
+
+    plain = batch_bytes(_prob(), _prob(seed=2))
+    mixed = batch_bytes(_prob(), _prob(seed=2, d_weight=0x3000))
+    assert mixed - plain >= 3968 * 8 + 3 * 1024 * 8
 
 
 def test_struct_layouts_match_header(tmp_path):

@@ -166,10 +166,32 @@ def test_weighted_validation_rejects_bad_weights(gpu):
         assert e.value.status == api.EGRAPH
 
 
-def test_batch_rejects_weighted_member(gpu):
-    g = gg.grid2d(5)
-    G = api.Graph.from_host(g.row_ptr, g.col, weight=gg.edge_weights(g, 1))
-    G1 = api.Graph.from_host(g.row_ptr, g.col)
-    with pytest.raises(api.UstdError) as e:
-        api.batch_diag_lpinv([G1, G], [api.problem(G1, pivot=0), api.problem(G, pivot=0)])
-    assert e.value.status == api.EINVAL
+def test_batch_mixes_weighted_and_unweighted_members(gpu):
+    """A batch of weighted and unweighted members (one sampler variant per launch group): each
+    member's counts, report and diagonal equal those of the single-problem call, and the
+    weighted members' counts equal the oracle's fixed-point sums."""
+    members = []
+    for idx, tau_ in [(9, 300), (6, 250), (7, 200)]:
+        name, g, w, u, Gw = _setup(idx)
+        members.append((g, w, u, Gw, api.problem(Gw, pivot=u, seed=idx, tau_override=tau_)))
+    for k, (g, tau_) in enumerate([(gg.rmat(10, 8, 7), 280), (gg.grid2d(20), 310)]):
+        G = api.Graph.from_host(g.row_ptr, g.col)
+        u = gg.max_degree_pivot(g)
+        members.append((g, None, u, G, api.problem(G, pivot=u, seed=40 + k, tau_override=tau_)))
+    # interleave the kinds so the grouping has to separate them
+    members = [members[i] for i in (3, 0, 4, 1, 2)]
+    say("mixed batch", [(m[0].n, m[1] is not None) for m in members])
+    diags, counts, reps = api.batch_diag_lpinv([m[3] for m in members], [m[4] for m in members])
+    for (g, w, u, G, p), db, cb, rb in zip(members, diags, counts, reps):
+        ds, cs_, rs = api.diag_lpinv_p(G, p)
+        assert torch.equal(cb, cs_) and torch.equal(db, ds)
+        for key in ("tau", "walk_steps", "walk_draws", "pivot", "ecc", "rho_max", "fixed_shift", "weighted"):
+            assert rb[key] == rs[key], key
+        if w is not None:
+            assert rb["weighted"] == 1
+            _, st, acc = oracle.trees_weighted(g.row_ptr, g.col, w, u, p.seed, 0, rb["tau"], rb["fixed_shift"],
+                                               want_parents=False)
+            assert (cb.cpu().numpy() == acc).all() and rb["walk_steps"] == int(st.sum())
+        else:
+            _, st, want = oracle.trees(g.row_ptr, g.col, u, p.seed, 0, rb["tau"], want_parents=False)
+            assert (cb.cpu().numpy() == want).all()
