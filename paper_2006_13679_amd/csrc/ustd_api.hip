@@ -77,8 +77,9 @@ struct Misc {                      // small zero-initialised block at the front 
 struct Plan {
     int n, nnz, K, Kiv, slots, pools, rob, nwords, G, heavy_thresh;
     bool lds_bits, col16, weighted;
+    bool edges;  // edge entries for the sampler (tree state in global memory)
     long long rec_stride, scr_stride;
-    long long off_misc, off_rp32, off_col16, off_dist, off_parB, off_bint, off_bflag, off_heavy, off_bcount, off_counts, off_steps,
+    long long off_misc, off_rp32, off_col16, off_dist, off_parB, off_bint, off_bflag, off_vrow, off_edge, off_heavy, off_bcount, off_counts, off_steps,
         off_draws, off_rec, off_path, off_scr, off_part, off_x64, off_r64, off_z64, off_p64, off_q64,
         off_res64, off_x32, off_r32, off_z32, off_p32, off_q32, off_cw, off_guide, off_wdeg, off_wB, off_F;
     long long total;
@@ -108,13 +109,14 @@ int check_problem(const ustd_problem *p) {
 
 // Workspace layout of one problem.  Without trees (a batch member's own region) the tree
 // records and sampler slots are left out: a batch keeps them in a shared pool.
-Plan make_plan(const ustd_problem *p, bool with_trees = true) {
+Plan make_plan(const ustd_problem *p, bool with_trees = true, bool force_edges = false) {
     Plan L{};
     L.n = (int)p->n;
     L.nnz = (int)p->nnz;
     L.nwords = (L.n + 31) / 32;
     L.lds_bits = L.nwords <= kLdsBitsMaxWords;
     L.col16 = L.n <= 65536;  // 16-bit column copy for the sampler (half the cache footprint)
+    L.edges = !L.lds_bits || force_edges;
     L.weighted = p->d_weight != nullptr;
     L.rob = std::min(kSamplerRobMax, next_pow2(std::max(L.n, 2)));
     const double avg = (double)L.nnz / (double)L.n;
@@ -155,6 +157,8 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true) {
     L.off_parB = take(n * 4);
     L.off_bint = take(n * 8);
     L.off_bflag = take(n * 4);
+    L.off_vrow = take(n * 16);
+    L.off_edge = take(L.edges ? (long long)L.nnz * 16 : 0);
     L.off_heavy = take(n * 4);
     L.off_bcount = take((n / 256 + 2) * 4);
     L.off_counts = take(n * 8);
@@ -514,6 +518,9 @@ int setup_graph(Ctx &c, ustd_report *rep) {
         HIP_TRY(hipStreamSynchronize(c.st));
         if (out[1]) return fail(USTD_EGRAPH, "graph is not connected");
         c.ecc = out[0];
+        HIP_TRY(launch_vertex_rows(n, c.rp32, at<int>(c.ws, c.L.off_bflag), at<int4>(c.ws, c.L.off_vrow), c.st));
+        if (c.L.edges)
+            HIP_TRY(launch_edge_rows(c.L.nnz, c.p->d_col, at<int4>(c.ws, c.L.off_vrow), at<int4>(c.ws, c.L.off_edge), c.st));
         USTD_TRY(setup_weighted(c));
         if (rep) {
             rep->pivot = c.pivot;
@@ -534,6 +541,9 @@ int setup_graph(Ctx &c, ustd_report *rep) {
     // subtree intervals of B_u (fixed for every tree): bint[x] = {pre_B, size_B}
     HIP_TRY(launch_b_intervals(n, c.pivot, c.ecc, dist, parB, at<int>(c.ws, c.L.off_scr), at<int2>(c.ws, c.L.off_bint),
                                at<int>(c.ws, c.L.off_bflag), c.st));
+    HIP_TRY(launch_vertex_rows(n, c.rp32, at<int>(c.ws, c.L.off_bflag), at<int4>(c.ws, c.L.off_vrow), c.st));
+    if (c.L.edges)
+        HIP_TRY(launch_edge_rows(c.L.nnz, c.p->d_col, at<int4>(c.ws, c.L.off_vrow), at<int4>(c.ws, c.L.off_edge), c.st));
     USTD_TRY(setup_weighted(c));
     if (rep) {
         rep->pivot = c.pivot;
@@ -555,6 +565,8 @@ WilsonGraph wilson_graph(const Ctx &c) {
     g.rp = c.rp32;
     g.colv = c.L.col16 ? (const void *)at<unsigned short>(c.ws, c.L.off_col16) : (const void *)c.p->d_col;
     g.bflag = at<int>(c.ws, c.L.off_bflag);
+    g.vrow = at<int4>(c.ws, c.L.off_vrow);
+    g.edge = c.L.edges ? at<int4>(c.ws, c.L.off_edge) : nullptr;
     g.cw = c.L.weighted ? at<double>(c.ws, c.L.off_cw) : nullptr;
     g.guide = c.L.weighted ? at<int>(c.ws, c.L.off_guide) : nullptr;
     g.key0 = (uint32_t)(c.p->seed & 0xFFFFFFFFull);
@@ -868,11 +880,14 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
             const std::string m = g_err;
             return fail(rc, "problem %d: %s", i, m.c_str());
         }
-        const Plan L = make_plan(&probs[i], false);
+        B.lds_bits = B.lds_bits && make_plan(&probs[i], false).lds_bits;
+    }
+    // one sampler variant serves every member: without the LDS bitmap all need edge entries
+    for (int i = 0; i < count; ++i) {
+        const Plan L = make_plan(&probs[i], false, !B.lds_bits);
         B.g.push_back(L);
         B.base.push_back(o);
         o += align_up(L.total);
-        B.lds_bits = B.lds_bits && L.lds_bits;
         B.col16 = B.col16 && L.col16;
         B.nwords_max = std::max(B.nwords_max, L.nwords);
         const long long rb = L.rec_stride * 8;

@@ -417,28 +417,56 @@ __device__ __forceinline__ int step_index(uint32_t w, int r0, int r1, const doub
 // {parent, nba | marked << 31}.  The walk resumes at step k0 from vertex x0 (k0 = 0, x0 = s0
 // for a whole walk; otherwise the Next pointers of steps 0..k0-1 are already written).  One
 // lane; returns the walk's total step count.
+//
+// Graphs past the LDS bitmap read the edge entries {y, row of y, B_u flag of y}: the entry
+// of step k gives everything step k + 1 needs, so step k + 1's entry is loaded together with
+// the tree test of y (before its answer is known) and each step waits for one load, not two
+// in a row.  Small graphs keep the compact column and row arrays, which stay in the L1.
 template <bool LDS, typename CT, bool WT>
 __device__ long long rewalk_commit(const TreeState<LDS> &bits, int *recw, const int *__restrict__ rp,
-                                   const CT *__restrict__ col, const double *__restrict__ cw,
+                                   const CT *__restrict__ col, const int4 *__restrict__ edge,
+                                   const int4 *__restrict__ vrow, const double *__restrict__ cw,
                                    const int *__restrict__ guide, const int *__restrict__ bflag, int s0, int x0,
                                    long long k0, uint32_t tlo,
                                    uint32_t thi, uint32_t key0, uint32_t key1) {
     int xw = x0;
-    int r0 = rp[x0], r1 = rp[x0 + 1];
     long long k = k0;
     uint4 ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
+    if constexpr (LDS) {
+        int r0 = rp[x0], r1 = rp[x0 + 1];
+        for (;;) {
+            if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
+            const int q = (int)(k & 3);
+            const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
+            const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw, guide)];
+            const int ny0 = rp[y], ny1 = rp[y + 1];
+            ++k;
+            recw[2 * xw] = y;  // Next pointer; becomes the parent when xw joins T
+            if (bits.test(y)) break;
+            xw = y;
+            r0 = ny0;
+            r1 = ny1;
+        }
+    } else {
+    int4 e;  // entry of step k: the step from xw
+    {
+        const int4 v0 = vrow[x0];
+        const int q = (int)(k & 3);
+        const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
+        e = edge[v0.x + step_index<WT>(w, v0.x, v0.y, cw, guide)];
+    }
     for (;;) {
+        const int y = e.x;
+        ++k;
         if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
         const int q = (int)(k & 3);
         const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-        const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw, guide)];
-        const int ny0 = rp[y], ny1 = rp[y + 1];
-        ++k;
+        const int4 en = edge[e.y + step_index<WT>(w, e.y, e.z, cw, guide)];  // step k from y
         recw[2 * xw] = y;  // Next pointer; becomes the parent when xw joins T
         if (bits.test(y)) break;
         xw = y;
-        r0 = ny0;
-        r1 = ny1;
+        e = en;
+    }
     }
     // retrace the loop erasure from s0 to the tree vertex ya it reaches
     int z = s0;
@@ -526,6 +554,8 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     constexpr int kWShift = TreeState<LDS>::kShift, kW = 1 << kWShift;
     const int nw = (n + kW - 1) >> kWShift;  // allocation words
     const int *__restrict__ bflag = g.bflag;
+    const int4 *__restrict__ vrow = g.vrow;
+    const int4 *__restrict__ edge = g.edge;  // set when the tree state is in global memory
     const int u = g.u;
     const int *__restrict__ rp = g.rp;
     const CT *__restrict__ col = reinterpret_cast<const CT *>(g.colv);  // int32, or uint16 when n <= 65536
@@ -600,9 +630,10 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 x = s;
                 k = 0;
                 mode = 1;
-                r0 = rp[s];
-                r1 = rp[s + 1];
-                fx = bflag[s];
+                const int4 vs = vrow[s];
+                r0 = vs.x;
+                r1 = vs.y;
+                fx = vs.z;
                 pbits = 0;
                 const int sl = my_e & robm;
                 rob_s[sl] = (CT)s;
@@ -618,12 +649,23 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s, tlo, thi), g.key0, g.key1);
             const int q = k & 3;
             const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-            const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw, guide)];
-            // loads for y: tree bit and B_u flag; then either the chain value (the walk ends
-            // here) or the next row bounds (it continues)
+            // y, its row bounds and its B_u flag: with the tree bitmap in LDS (small graphs,
+            // whose compact column and vertex arrays stay in cache) a column load and then a
+            // vertex load; otherwise one edge-entry load
+            const int e = r0 + step_index<WT>(w, r0, r1, cw, guide);
+            int y;
+            int4 vy;
+            if constexpr (LDS) {
+                y = (int)col[e];
+                vy = vrow[y];
+            } else {
+                const int4 ey = edge[e];
+                y = ey.x;
+                vy = make_int4(ey.y, ey.z, ey.w, 0);
+            }
+            // y's tree membership, with the chain value when the walk ends here
             bool in;
-            int cvy = 0, ny0 = 0, ny1 = 0;
-            const int fy = bflag[y];
+            int cvy = 0;
             if constexpr (LDS) {
                 in = bits.test(y);
                 if (in) cvy = recw[2 * y + 1];
@@ -631,10 +673,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 cvy = bits.nbx(y);  // membership and chain value in one load
                 in = cvy != kFree;
             }
-            if (!in) {
-                ny0 = rp[y];
-                ny1 = rp[y + 1];
-            }
+            const int fy = vy.z, ny0 = vy.x, ny1 = vy.y;
             consume(fy, cvy, ny0, ny1);  // no load may stay in flight into the commit phase
             if (in) cvy = cv_of(y, cvy);
             ++k;
@@ -681,7 +720,8 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                             k0 = kPath;
                         }
                         const long long kk =
-                            rewalk_commit<LDS, CT, WT>(bits, recw, rp, col, cw, guide, bflag, s0, xs, k0, tlo, thi,
+                            rewalk_commit<LDS, CT, WT>(bits, recw, rp, col, edge, vrow, cw, guide, bflag, s0, xs, k0,
+                                                       tlo, thi,
                                                        g.key0, g.key1);
                         steps += kk;
                         draws += kk - k0;
@@ -2173,6 +2213,27 @@ hipError_t launch_row_cumsum(int n, int nnz, const int *rp, const double *w, int
     row_cumsum_kernel<<<std::min(blocks_for(n, 256), 4096), 256, 0, st>>>(n, rp, w, heavy_thresh, cw, wdeg);
     row_cumsum_heavy_kernel<<<1024, kWave, 0, st>>>(rp, w, heavy, nheavy, cw, wdeg);
     step_guide_kernel<<<std::min(blocks_for(nnz, 256), 8192), 256, 0, st>>>(n, nnz, rp, cw, guide);
+    return hipGetLastError();
+}
+__global__ void vertex_rows_kernel(int n, const int *__restrict__ rp, const int *__restrict__ bflag,
+                                   int4 *__restrict__ vrow) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) vrow[v] = make_int4(rp[v], rp[v + 1], bflag[v], 0);
+}
+hipError_t launch_vertex_rows(int n, const int *rp, const int *bflag, int4 *vrow, hipStream_t st) {
+    vertex_rows_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, rp, bflag, vrow);
+    return hipGetLastError();
+}
+__global__ void edge_rows_kernel(long long nnz, const int *__restrict__ col, const int4 *__restrict__ vrow,
+                                 int4 *__restrict__ edge) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nnz; i += (long long)gridDim.x * blockDim.x) {
+        const int y = col[i];
+        const int4 r = vrow[y];
+        edge[i] = make_int4(y, r.x, r.y, r.z);
+    }
+}
+hipError_t launch_edge_rows(long long nnz, const int *col, const int4 *vrow, int4 *edge, hipStream_t st) {
+    edge_rows_kernel<<<(int)std::min<long long>(blocks_for(nnz, 256), 16384), 256, 0, st>>>(nnz, col, vrow, edge);
     return hipGetLastError();
 }
 hipError_t launch_check_weights(int n, const int *rp, const int *col, const double *w, int *err, hipStream_t st) {

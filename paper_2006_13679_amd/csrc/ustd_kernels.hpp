@@ -14,6 +14,8 @@ struct WilsonGraph {
     const int *rp;
     const void *colv;       // column indices: int32, or uint16 when the launch says so
     const int *bflag;       // [n] (parB + 1) | (internal in B_u) << 31
+    const int4 *vrow;       // [n] {rp[v], rp[v+1], bflag[v], 0}: a walk step's loads for v in one
+    const int4 *edge;       // [nnz] entry (x, y): {y, rp[y], rp[y+1], bflag[y]}, for the one-lane walk
     const double *cw;       // [nnz] running conductance sums of each row (weighted launches)
     const int *guide;       // [nnz] start of the weighted step search per (row, bucket)
     uint32_t key0, key1;    // Philox key (seed)
@@ -137,6 +139,8 @@ hipError_t launch_sum_walks(int cnt, const long long *steps, const long long *dr
 hipError_t launch_row_cumsum(int n, int nnz, const int *rp, const double *w, int heavy_thresh, const int *heavy,
                              const int *nheavy, double *cw, double *wdeg, int *guide, hipStream_t st);
 hipError_t launch_check_weights(int n, const int *rp, const int *col, const double *w, int *err, hipStream_t st);
+hipError_t launch_vertex_rows(int n, const int *rp, const int *bflag, int4 *vrow, hipStream_t st);
+hipError_t launch_edge_rows(long long nnz, const int *col, const int4 *vrow, int4 *edge, hipStream_t st);
 hipError_t launch_bpath(int n, int u, const int *rp, const int *col, const double *w, const int *parB, double *wB,
                         unsigned long long *rmax_bits, hipStream_t st);
 hipError_t launch_fixed_weights(int n, int u, const double *wB, int shift, long long *F, hipStream_t st);
