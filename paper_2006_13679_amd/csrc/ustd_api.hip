@@ -157,7 +157,7 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true, bool force_edges =
     L.off_parB = take(n * 4);
     L.off_bint = take(n * 8);
     L.off_bflag = take(n * 4);
-    L.off_vrow = take(n * 16);
+    L.off_vrow = take(L.edges ? n * 16 : 0);
     L.off_edge = take(L.edges ? (long long)L.nnz * 16 : 0);
     L.off_heavy = take(n * 4);
     L.off_bcount = take((n / 256 + 2) * 4);
@@ -518,9 +518,10 @@ int setup_graph(Ctx &c, ustd_report *rep) {
         HIP_TRY(hipStreamSynchronize(c.st));
         if (out[1]) return fail(USTD_EGRAPH, "graph is not connected");
         c.ecc = out[0];
-        HIP_TRY(launch_vertex_rows(n, c.rp32, at<int>(c.ws, c.L.off_bflag), at<int4>(c.ws, c.L.off_vrow), c.st));
-        if (c.L.edges)
+        if (c.L.edges) {
+            HIP_TRY(launch_vertex_rows(n, c.rp32, at<int>(c.ws, c.L.off_bflag), at<int4>(c.ws, c.L.off_vrow), c.st));
             HIP_TRY(launch_edge_rows(c.L.nnz, c.p->d_col, at<int4>(c.ws, c.L.off_vrow), at<int4>(c.ws, c.L.off_edge), c.st));
+        }
         USTD_TRY(setup_weighted(c));
         if (rep) {
             rep->pivot = c.pivot;
@@ -541,9 +542,10 @@ int setup_graph(Ctx &c, ustd_report *rep) {
     // subtree intervals of B_u (fixed for every tree): bint[x] = {pre_B, size_B}
     HIP_TRY(launch_b_intervals(n, c.pivot, c.ecc, dist, parB, at<int>(c.ws, c.L.off_scr), at<int2>(c.ws, c.L.off_bint),
                                at<int>(c.ws, c.L.off_bflag), c.st));
-    HIP_TRY(launch_vertex_rows(n, c.rp32, at<int>(c.ws, c.L.off_bflag), at<int4>(c.ws, c.L.off_vrow), c.st));
-    if (c.L.edges)
+    if (c.L.edges) {  // the sampler's vertex and edge entries
+        HIP_TRY(launch_vertex_rows(n, c.rp32, at<int>(c.ws, c.L.off_bflag), at<int4>(c.ws, c.L.off_vrow), c.st));
         HIP_TRY(launch_edge_rows(c.L.nnz, c.p->d_col, at<int4>(c.ws, c.L.off_vrow), at<int4>(c.ws, c.L.off_edge), c.st));
+    }
     USTD_TRY(setup_weighted(c));
     if (rep) {
         rep->pivot = c.pivot;
@@ -565,7 +567,7 @@ WilsonGraph wilson_graph(const Ctx &c) {
     g.rp = c.rp32;
     g.colv = c.L.col16 ? (const void *)at<unsigned short>(c.ws, c.L.off_col16) : (const void *)c.p->d_col;
     g.bflag = at<int>(c.ws, c.L.off_bflag);
-    g.vrow = at<int4>(c.ws, c.L.off_vrow);
+    g.vrow = c.L.edges ? at<int4>(c.ws, c.L.off_vrow) : nullptr;
     g.edge = c.L.edges ? at<int4>(c.ws, c.L.off_edge) : nullptr;
     g.cw = c.L.weighted ? at<double>(c.ws, c.L.off_cw) : nullptr;
     g.guide = c.L.weighted ? at<int>(c.ws, c.L.off_guide) : nullptr;
@@ -867,7 +869,7 @@ struct BatchPlan {
     int nwords_max = 0, slots = 0;
     long long rec_pool = 0, max_tiles = 0;
     long long off_queue = 0, off_rec = 0, off_path = 0, off_steps = 0, off_draws = 0, off_tiles = 0,
-              off_graphs = 0, total = 0;
+              off_graphs = 0, off_jobs = 0, total = 0;
 };
 
 int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
@@ -920,6 +922,7 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
     B.off_draws = take(B.max_tiles * 8);
     B.off_tiles = take(B.max_tiles * (long long)sizeof(WilsonTile));
     B.off_graphs = take((long long)count * (long long)sizeof(WilsonGraph));
+    B.off_jobs = take((long long)count * (long long)sizeof(CgSmallJob));
     B.total = o;
     return USTD_OK;
 }
@@ -928,6 +931,77 @@ int member(int i, int rc) {
     if (rc == USTD_OK) return rc;
     const std::string m = g_err;
     return fail(rc, "problem %d: %s", i, m.c_str());
+}
+
+// FP64 pivot-column solves of the batch members listed in `idx` (each of at most
+// kSmallSolveMaxN vertices) on `st`: the same one-workgroup CG, projection, final residual
+// and convergence rule as solve_column, with the CG of all of them in one launch per row
+// group size.  Each member's ms_solve is the time of the whole batched solve.  A member
+// that does not converge sets *status to USTD_ENOTCONV (its message names it).
+int solve_small_batch(std::vector<Ctx> &cs, const std::vector<int> &idx, const BatchPlan &B, void *d_ws,
+                      hipStream_t st, ustd_report *R, int *status) {
+    std::vector<CgSmallJob> jobs;
+    std::vector<int> order;
+    std::vector<double> tols(idx.size());
+    for (int G : {4, 8, 16, 32})
+        for (size_t k = 0; k < idx.size(); ++k) {
+            Ctx &c = cs[idx[k]];
+            if (c.L.G != G) continue;
+            const ustd_problem *p = c.p;
+            double tol = p->solve_tol;
+            if (!(tol > 0.0)) tol = std::min(solver_eta(p, c.ecc), 1e-12);
+            tols[k] = tol;
+            CgSmallJob j{};
+            j.a = cg_args<double>(c, at<double>(c.ws, B.g[idx[k]].off_x64), at<double>(c.ws, c.L.off_r64),
+                                  at<double>(c.ws, c.L.off_z64), at<double>(c.ws, c.L.off_p64),
+                                  at<double>(c.ws, c.L.off_q64), &c.misc->sc64, c.misc->rr_hist64);
+            j.m = c.rows;
+            j.u = c.pivot;
+            j.maxit = p->solve_maxit > 0 ? p->solve_maxit : 20000;
+            j.tol2 = tol * tol;
+            jobs.push_back(j);
+            order.push_back((int)k);
+        }
+    if (jobs.size() != idx.size()) return fail(USTD_EINVAL, "unexpected row-group size in a batched solve");
+    CgSmallJob *d_jobs = at<CgSmallJob>(d_ws, B.off_jobs);
+    Timer tm(st);
+    HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(CgSmallJob) * jobs.size(), hipMemcpyHostToDevice, st));
+    for (size_t s = 0; s < jobs.size();) {
+        size_t e = s;
+        const int G = cs[idx[order[s]]].L.G;
+        while (e < jobs.size() && cs[idx[order[e]]].L.G == G) ++e;
+        HIP_TRY(launch_cg_small_batch(d_jobs + s, (int)(e - s), G, st));
+        s = e;
+    }
+    for (int i : idx) {
+        Ctx &c = cs[i];
+        double *x64 = at<double>(c.ws, B.g[i].off_x64);
+        double *part = at<double>(c.ws, c.L.off_part) + 3 * kMaxSolveGrid;
+        double *sums = c.misc->sums;
+        HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, sums, st));
+        HIP_TRY(launch_axpy_project<double>(c.L.n, x64, nullptr, nullptr, 0, sums + 2, vec_grid(c.L.n), st));
+        HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, sums, st));
+    }
+    const double ms = tm.stop_ms();  // synchronises st
+    for (size_t k = 0; k < idx.size(); ++k) {
+        const int i = idx[k];
+        Ctx &c = cs[i];
+        CgScalars sc{};
+        double hs[4];
+        HIP_TRY(hipMemcpy(&sc, &c.misc->sc64, sizeof(sc), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hs, c.misc->sums, sizeof(hs), hipMemcpyDeviceToHost));
+        const double bnorm = std::sqrt((double)(c.L.n - 1) / (double)c.L.n);
+        const double relres = std::sqrt(std::max(hs[1], 0.0)) / bnorm;
+        const bool conv = (sc.done && sc.rr <= sc.tol2 * sc.rr0) || relres <= tols[k];
+        R[i].solve_iters += sc.iter;
+        R[i].solve_outer += 1;
+        R[i].solve_relres = relres;
+        R[i].ms_solve += ms;
+        if (!conv && relres > std::max(tols[k], 1e-9))
+            *status = member(i, fail(USTD_ENOTCONV, "solve stopped at relative residual %.3e (target %.3e)", relres,
+                                     tols[k]));
+    }
+    return USTD_OK;
 }
 
 }  // namespace
@@ -1179,7 +1253,22 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
     bool solved = false;
     auto solve_all = [&]() {
         solved = true;
+        // FP64 members of up to kSmallSolveMaxN vertices: one launch per row-group size with a
+        // workgroup per member, so their one-workgroup solves run side by side; then each
+        // member's projection and final residual, one synchronisation and the readbacks
+        std::vector<int> small;
+        for (int i = 0; i < count; ++i)
+            if (B.g[i].n <= kSmallSolveMaxN && probs[i].solve_mode == USTD_SOLVE_FP64) small.push_back(i);
+        if (!small.empty()) {
+            const int rc = solve_small_batch(cs, small, B, d_ws, side, R, &status);
+            if (rc != USTD_OK) {
+                hard = rc;
+                (void)hipStreamSynchronize(side);
+                return;
+            }
+        }
         for (int i = 0; i < count; ++i) {
+            if (std::find(small.begin(), small.end(), i) != small.end()) continue;
             Ctx ci = cs[i];
             ci.st = side;
             const int src = solve_column(ci, at<double>(cs[i].ws, B.g[i].off_x64), &R[i]);

@@ -630,10 +630,9 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 x = s;
                 k = 0;
                 mode = 1;
-                const int4 vs = vrow[s];
-                r0 = vs.x;
-                r1 = vs.y;
-                fx = vs.z;
+                r0 = rp[s];
+                r1 = rp[s + 1];
+                fx = bflag[s];
                 pbits = 0;
                 const int sl = my_e & robm;
                 rob_s[sl] = (CT)s;
@@ -649,31 +648,36 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s, tlo, thi), g.key0, g.key1);
             const int q = k & 3;
             const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-            // y, its row bounds and its B_u flag: with the tree bitmap in LDS (small graphs,
-            // whose compact column and vertex arrays stay in cache) a column load and then a
-            // vertex load; otherwise one edge-entry load
+            // y, its B_u flag and its row bounds.  With the tree bitmap in LDS (small graphs,
+            // whose compact column and row arrays stay in cache): a column load, then the
+            // flag, and the row bounds only if the walk goes on.  Otherwise one edge-entry load.
             const int e = r0 + step_index<WT>(w, r0, r1, cw, guide);
-            int y;
-            int4 vy;
+            int y, fy, ny0 = 0, ny1 = 0;
             if constexpr (LDS) {
                 y = (int)col[e];
-                vy = vrow[y];
+                fy = bflag[y];
             } else {
                 const int4 ey = edge[e];
                 y = ey.x;
-                vy = make_int4(ey.y, ey.z, ey.w, 0);
+                fy = ey.w;
+                ny0 = ey.y;
+                ny1 = ey.z;
             }
             // y's tree membership, with the chain value when the walk ends here
             bool in;
             int cvy = 0;
             if constexpr (LDS) {
                 in = bits.test(y);
-                if (in) cvy = recw[2 * y + 1];
+                if (in) {
+                    cvy = recw[2 * y + 1];
+                } else {
+                    ny0 = rp[y];
+                    ny1 = rp[y + 1];
+                }
             } else {
                 cvy = bits.nbx(y);  // membership and chain value in one load
                 in = cvy != kFree;
             }
-            const int fy = vy.z, ny0 = vy.x, ny1 = vy.y;
             consume(fy, cvy, ny0, ny1);  // no load may stay in flight into the commit phase
             if (in) cvy = cv_of(y, cvy);
             ++k;
@@ -1368,12 +1372,15 @@ __device__ __forceinline__ T block_sum_t(T v, T *sh) {
 
 // y = L p over all rows, degree-balanced; calls emit(v, (L p)_v) once per row from one
 // thread.  Fixed grid and fixed per-row reduction trees: deterministic.  BS = block size.
+// Block blk of nblk takes every nblk-th heavy row and row tile (a whole grid: blockIdx.x of
+// gridDim.x; a workgroup that solves a graph alone: 0 of 1).
 template <typename T, int G, int BS = 256, typename Emit>
-__device__ __forceinline__ void lap_apply_rows(const RowMap &m, const T *__restrict__ p, Emit emit) {
+__device__ __forceinline__ void lap_apply_rows(const RowMap &m, const T *__restrict__ p, Emit emit, int blk,
+                                               int nblk) {
     __shared__ T shr[BS / kWave];
     const int nh = *m.nheavy;
     const double *__restrict__ w = m.w;  // uniform: weighted Laplacian when set
-    for (int h = blockIdx.x; h < nh; h += gridDim.x) {
+    for (int h = blk; h < nh; h += nblk) {
         const int v = m.heavy[h];
         const int lo = m.rp[v], hi = m.rp[v + 1];
         T acc = (T)0;
@@ -1386,7 +1393,7 @@ __device__ __forceinline__ void lap_apply_rows(const RowMap &m, const T *__restr
     }
     constexpr int rows_per_tile = BS / G;
     const int g = threadIdx.x / G, l = threadIdx.x % G;
-    for (int tile = blockIdx.x; tile * rows_per_tile < m.n; tile += gridDim.x) {
+    for (int tile = blk; tile * rows_per_tile < m.n; tile += nblk) {
         const int v = tile * rows_per_tile + g;
         const bool ok = v < m.n;
         const int lo = ok ? m.rp[v] : 0, hi = ok ? m.rp[v + 1] : 0;
@@ -1434,10 +1441,13 @@ __global__ __launch_bounds__(256) void cg_spmv_kernel(CgArgs<T> a, RowMap m) {
     double acc = 0.0;
     T *__restrict__ q = a.q;
     const T *__restrict__ p = a.p;
-    lap_apply_rows<T, G>(m, p, [&](int v, T qv) {
-        q[v] = qv;
-        acc += (double)p[v] * (double)qv;
-    });
+    lap_apply_rows<T, G>(
+        m, p,
+        [&](int v, T qv) {
+            q[v] = qv;
+            acc += (double)p[v] * (double)qv;
+        },
+        blockIdx.x, gridDim.x);
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) a.part_pq[blockIdx.x] = acc;
 }
@@ -1559,11 +1569,9 @@ __global__ __launch_bounds__(256) void cg_start_finish_kernel(CgArgs<T> a, doubl
 constexpr int kSmallThreads = 1024;
 
 template <typename Tin, typename T, int G>
-__global__ __launch_bounds__(kSmallThreads) void cg_small_kernel(CgArgs<T> a, RowMap m, const Tin *__restrict__ rhs,
-                                                                 int rhs_is_pivot, int u,
-                                                                 const double *__restrict__ shift_scale, double tol2,
-                                                                 int maxit) {
-    __shared__ double sh[kSmallThreads / kWave];
+__device__ __forceinline__ void cg_small_body(const CgArgs<T> &a, const RowMap &m, const Tin *__restrict__ rhs,
+                                              int rhs_is_pivot, int u, const double *__restrict__ shift_scale,
+                                              double tol2, int maxit, double *sh) {
     const int n = a.n, tid = threadIdx.x;
     const double shift = shift_scale ? shift_scale[0] : 0.0;
     const double scale = shift_scale ? shift_scale[1] : 1.0;
@@ -1589,10 +1597,13 @@ __global__ __launch_bounds__(kSmallThreads) void cg_small_kernel(CgArgs<T> a, Ro
     bool done = !(rr > 0.0);
     while (!done && it < maxit) {
         double pq = 0.0;
-        lap_apply_rows<T, G, kSmallThreads>(m, a.p, [&](int v, T qv) {
-            a.q[v] = qv;
-            pq += (double)a.p[v] * (double)qv;
-        });
+        lap_apply_rows<T, G, kSmallThreads>(
+            m, a.p,
+            [&](int v, T qv) {
+                a.q[v] = qv;
+                pq += (double)a.p[v] * (double)qv;
+            },
+            0, 1);
         pq = block_sum_t<double>(pq, sh);
         if (!(pq > 0.0 && pq == pq)) {  // breakdown
             done = true;
@@ -1632,6 +1643,23 @@ __global__ __launch_bounds__(kSmallThreads) void cg_small_kernel(CgArgs<T> a, Ro
         S->iter = it;
         S->done = done ? 1 : 0;
     }
+}
+
+template <typename Tin, typename T, int G>
+__global__ __launch_bounds__(kSmallThreads) void cg_small_kernel(CgArgs<T> a, RowMap m, const Tin *__restrict__ rhs,
+                                                                 int rhs_is_pivot, int u,
+                                                                 const double *__restrict__ shift_scale, double tol2,
+                                                                 int maxit) {
+    __shared__ double sh[kSmallThreads / kWave];
+    cg_small_body<Tin, T, G>(a, m, rhs, rhs_is_pivot, u, shift_scale, tol2, maxit, sh);
+}
+
+// Independent small solves side by side: workgroup i runs job i (one graph's pivot column).
+template <int G>
+__global__ __launch_bounds__(kSmallThreads) void cg_small_batch_kernel(const CgSmallJob *__restrict__ jobs) {
+    __shared__ double sh[kSmallThreads / kWave];
+    const CgSmallJob &j = jobs[blockIdx.x];
+    cg_small_body<double, double, G>(j.a, j.m, nullptr, 1, j.u, nullptr, j.tol2, j.maxit, sh);
 }
 
 // ======================================================================================
@@ -1742,13 +1770,16 @@ __global__ __launch_bounds__(256) void residual64_kernel(RowMap m, int u, const 
     __shared__ double sh[4];
     const double inv_n = 1.0 / (double)m.n;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    lap_apply_rows<double, G>(m, x, [&](int v, double lx) {
-        const double rv = ((v == u ? 1.0 : 0.0) - inv_n) - lx;
-        if (res) res[v] = rv;
-        s0 += rv;
-        s1 += rv * rv;
-        s2 += x[v];
-    });
+    lap_apply_rows<double, G>(
+        m, x,
+        [&](int v, double lx) {
+            const double rv = ((v == u ? 1.0 : 0.0) - inv_n) - lx;
+            if (res) res[v] = rv;
+            s0 += rv;
+            s1 += rv * rv;
+            s2 += x[v];
+        },
+        blockIdx.x, gridDim.x);
     s0 = block_sum(s0, sh);
     s1 = block_sum(s1, sh);
     s2 = block_sum(s2, sh);
@@ -2152,6 +2183,12 @@ template hipError_t launch_cg_small<double, double>(const CgArgs<double> &, cons
                                                     int, const double *, double, int, hipStream_t);
 template hipError_t launch_cg_small<double, float>(const CgArgs<float> &, const RowMap &, int, const double *, int,
                                                    int, const double *, double, int, hipStream_t);
+
+hipError_t launch_cg_small_batch(const CgSmallJob *jobs, int count, int G, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    USTD_DISPATCH_G(G, (cg_small_batch_kernel<GG><<<count, kSmallThreads, 0, st>>>(jobs)));
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, int it, hipStream_t st) {

@@ -14,8 +14,9 @@ struct WilsonGraph {
     const int *rp;
     const void *colv;       // column indices: int32, or uint16 when the launch says so
     const int *bflag;       // [n] (parB + 1) | (internal in B_u) << 31
-    const int4 *vrow;       // [n] {rp[v], rp[v+1], bflag[v], 0}: a walk step's loads for v in one
-    const int4 *edge;       // [nnz] entry (x, y): {y, rp[y], rp[y+1], bflag[y]}, for the one-lane walk
+    // graphs whose tree state is in global memory (past the LDS bitmap):
+    const int4 *vrow;       // [n] {rp[v], rp[v+1], bflag[v], 0}
+    const int4 *edge;       // [nnz] entry (x, y): {y, rp[y], rp[y+1], bflag[y]}: a walk step's loads
     const double *cw;       // [nnz] running conductance sums of each row (weighted launches)
     const int *guide;       // [nnz] start of the weighted step search per (row, bucket)
     uint32_t key0, key1;    // Philox key (seed)
@@ -115,6 +116,15 @@ struct CgArgs {
     const double *wdeg;     // [n] Jacobi diagonal of a weighted Laplacian; null = degrees
 };
 
+// One FP64 pivot-column solve of a batched one-workgroup launch (graphs up to
+// kSmallSolveMaxN vertices): right-hand side e_u - 1/n.
+struct CgSmallJob {
+    CgArgs<double> a;
+    RowMap m;
+    int u, maxit;
+    double tol2;
+};
+
 inline long long interval_scratch_ints(long long n) { return 7 * n + 3; }
 
 hipError_t launch_rp_to_i32(int n, const long long *rp64, int *rp32, hipStream_t st);
@@ -168,6 +178,7 @@ hipError_t launch_cg_small(const CgArgs<T> &a, const RowMap &m, int G, const Tin
 template <typename Tin, typename T>
 hipError_t launch_cg_start(const CgArgs<T> &a, const Tin *rhs, int rhs_is_pivot, int u, const double *shift_scale,
                            double tol2, hipStream_t st);
+hipError_t launch_cg_small_batch(const CgSmallJob *jobs, int count, int G, hipStream_t st);
 hipError_t launch_residual64(const RowMap &m, int G, int u, const double *x, double *res, double *part, double *out,
                              hipStream_t st);
 template <typename T>

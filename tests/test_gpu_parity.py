@@ -293,6 +293,40 @@ def test_batch_large_member(gpu):
     _check_batch_against_single(members, oracle_idx=(0, 1, 2))
 
 
+def test_batch_fp64_small_solves(gpu):
+    """FP64 members of up to 16384 vertices share batched one-workgroup solve launches (one per
+    row-group size).  Each member's diagonal, counts, solve iterations and residual equal those
+    of the single-problem call, beside a mixed-precision member and one past the size limit;
+    a member stopped by its iteration limit is reported (USTD_ENOTCONV, naming it) while the
+    others are still written."""
+    members = [
+        (gg.grid2d(20), 210, 3, dict(tau_cap=60)),
+        (gg.rmat(10, 8, 1), -1, 4, dict(tau_cap=60)),
+        (gg.rmat(11, 24, 2), -1, 5, dict(tau_cap=40)),
+        (gg.path(50), 0, 6, dict(tau_cap=30)),
+        (gg.grid2d(130), 8450, 7, dict(tau_cap=8)),
+        (gg.grid2d(16), 0, 8, dict(tau_cap=30, solve_mode=api.SOLVE_MIXED)),
+    ]
+    assert members[4][0].n > 16384
+    graphs = [dev_graph(m[0]) for m in members]
+    probs = [api.problem(G, pivot=m[1], seed=m[2], solve_tol=1e-12, **m[3]) for G, m in zip(graphs, members)]
+    say("batch fp64 small solves")
+    diags, counts, reps = api.batch_diag_lpinv(graphs, probs)
+    for i, (G, p) in enumerate(zip(graphs, probs)):
+        d1, c1, r1 = api.diag_lpinv_p(G, p, ws=api.Workspace(G.row_ptr.device))
+        assert torch.equal(counts[i], c1) and torch.equal(diags[i], d1), i
+        assert reps[i]["solve_iters"] == r1["solve_iters"] and reps[i]["solve_relres"] == r1["solve_relres"], i
+        assert reps[i]["solve_relres"] <= 1e-12
+    probs[1] = api.problem(graphs[1], pivot=-1, seed=4, solve_tol=1e-12, solve_maxit=2, tau_cap=60)
+    with pytest.raises(api.UstdError) as e:
+        api.batch_diag_lpinv(graphs, probs)
+    assert e.value.status == api.ENOTCONV and "problem 1" in str(e.value)
+    d2, c2, r2 = api.batch_diag_lpinv(graphs, probs, allow_notconv=True)
+    assert r2[1]["solve_iters"] == 2 and r2[1]["solve_relres"] > 1e-9
+    for i in (0, 2, 3, 4, 5):
+        assert torch.equal(d2[i], diags[i]) and torch.equal(c2[i], counts[i]), i
+
+
 def test_batch_member_error(gpu):
     graphs, probs = _batch_case([(gg.grid2d(5), 0, 1, {}), (gg.cycle(7), 0, 2, {})])
     probs[1].eps = 0.0
