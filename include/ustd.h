@@ -182,7 +182,9 @@ int ustd_batch_workspace_bytes(const ustd_problem *probs, int32_t count, size_t 
  * pointers, d_diags[i] double[n_i].  d_counts: nullable host array of nullable device
  * pointers (int64[n_i], overwritten with R of problem i).  reps: nullable, `count`
  * entries; ms_sample, ms_aggregate and ms_total there are those of the whole batch
- * (members share launches), the other fields are per member.  Each member's trees,
+ * (members share launches), the other fields are per member.  FP64 members of up to 16384
+ * vertices solve side by side in one launch (a workgroup each); each reports an equal share of
+ * that launch's time as ms_solve.  Each member's trees,
  * counts and diagonal are bit-identical to those of ustd_diag_lpinv on that problem alone.
  * The members' trees share one pool of records in the workspace and are sampled by
  * persistent launches that take (member, tree) tiles, larger graphs first.

@@ -936,7 +936,7 @@ int member(int i, int rc) {
 // FP64 pivot-column solves of the batch members listed in `idx` (each of at most
 // kSmallSolveMaxN vertices) on `st`: the same one-workgroup CG, projection, final residual
 // and convergence rule as solve_column, with the CG of all of them in one launch per row
-// group size.  Each member's ms_solve is the time of the whole batched solve.  A member
+// group size.  Each member's ms_solve is an equal share of the batched solve's time.  A member
 // that does not converge sets *status to USTD_ENOTCONV (its message names it).
 int solve_small_batch(std::vector<Ctx> &cs, const std::vector<int> &idx, const BatchPlan &B, void *d_ws,
                       hipStream_t st, ustd_report *R, int *status) {
@@ -996,7 +996,7 @@ int solve_small_batch(std::vector<Ctx> &cs, const std::vector<int> &idx, const B
         R[i].solve_iters += sc.iter;
         R[i].solve_outer += 1;
         R[i].solve_relres = relres;
-        R[i].ms_solve += ms;
+        R[i].ms_solve += ms / (double)idx.size();
         if (!conv && relres > std::max(tols[k], 1e-9))
             *status = member(i, fail(USTD_ENOTCONV, "solve stopped at relative residual %.3e (target %.3e)", relres,
                                      tols[k]));
