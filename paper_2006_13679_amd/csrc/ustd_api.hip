@@ -48,6 +48,7 @@ int fail(int code, const char *fmt, ...) {
 
 constexpr long long kAlign = 256;
 constexpr int kLdsBitsMaxWords = 4096;      // tree bitmap in LDS up to 131072 vertices (16 KB)
+constexpr long long kGraphLdsMaxBytes = 40960;  // graph copy in the sampler's LDS (small graphs)
 constexpr long long kDefaultBudget = 96ll << 30;  // tree records + sampler scratch, a third of 288 GB HBM
 constexpr int kMaxTreesPerBatch = 8192;
 constexpr long long kPoolMinTrees = 4096;  // a pool that fills the GPU's sampler slots
@@ -599,8 +600,14 @@ int sample_batch(Ctx &c, long long tree_begin, int ntrees, long long *steps, lon
     int blocks = std::min(ntrees, c.L.slots);
     const int resident = wilson_resident_blocks(c.L.lds_bits, c.L.col16, c.L.weighted, c.L.nwords);
     if (resident > 0) blocks = std::min(blocks, resident);
+    // a small unweighted graph also goes into LDS when that leaves as many trees running at once
+    long long gl = 0;
+    if (c.L.lds_bits && c.L.col16 && !c.L.weighted) {
+        const long long gb = wilson_graph_lds_bytes(c.L.n, c.L.nnz);
+        if (gb <= kGraphLdsMaxBytes && wilson_resident_blocks_graph_lds(c.L.nwords, gb) >= blocks) gl = gb;
+    }
     HIP_TRY(hipMemsetAsync(&c.misc->queue[pool], 0, sizeof(int), st));
-    HIP_TRY(launch_wilson(a, blocks, c.L.lds_bits, c.L.col16, c.L.weighted, c.L.nwords, st));
+    HIP_TRY(launch_wilson(a, blocks, c.L.lds_bits, c.L.col16, c.L.weighted, c.L.nwords, st, gl));
     return USTD_OK;
 }
 

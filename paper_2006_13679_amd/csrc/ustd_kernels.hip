@@ -502,7 +502,7 @@ __device__ __forceinline__ T sel4(int c, T a0, T a1, T a2, T a3) {
 
 }  // namespace
 
-template <bool LDS, typename CT, bool WT>
+template <bool LDS, typename CT, bool WT, bool GL = false>
 __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     // Reorder buffer.  Vertex IDs take the column type (16 bits when n <= 65536), so that
     // with the tree bitmap a block of R-MAT scale 16 fits 18 to a CU.  A recorded step
@@ -522,6 +522,28 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
 
     const int lane = threadIdx.x;
     int *__restrict__ gpath = a.path + (long long)blockIdx.x * kSamplerPathSlot;
+
+    // GL (small graphs, single-graph launches): the row pointers, B_u flags and 16-bit columns
+    // are copied into LDS after the tree bitmap, once per block, so that walk steps (above all
+    // the one-lane re-walk of long walks) read LDS instead of the L1/L2.
+    const int *lrp = nullptr, *lbf = nullptr;
+    const CT *lcol = nullptr;
+    if constexpr (GL) {
+        static_assert(LDS && !WT && sizeof(CT) == 2, "graph in LDS: small unweighted graphs");
+        const int n0 = a.g.n;
+        int *srp = reinterpret_cast<int *>(lds_bits + a.g.nwords);
+        int *sbf = srp + n0 + 1;
+        CT *scol = reinterpret_cast<CT *>(sbf + n0);
+        const int nnz0 = a.g.rp[n0];
+        const CT *gcol = reinterpret_cast<const CT *>(a.g.colv);
+        for (int i = lane; i <= n0; i += kWave) srp[i] = a.g.rp[i];
+        for (int i = lane; i < n0; i += kWave) sbf[i] = a.g.bflag[i];
+        for (int i = lane; i < nnz0; i += kWave) scol[i] = gcol[i];
+        wave_sync();
+        lrp = srp;
+        lbf = sbf;
+        lcol = scol;
+    }
 
     for (;;) {
     // ---------------------------------------------------------------- next tile
@@ -553,12 +575,12 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     else bits.recw = recw;
     constexpr int kWShift = TreeState<LDS>::kShift, kW = 1 << kWShift;
     const int nw = (n + kW - 1) >> kWShift;  // allocation words
-    const int *__restrict__ bflag = g.bflag;
+    const int *__restrict__ bflag = GL ? lbf : g.bflag;
     const int4 *__restrict__ vrow = g.vrow;
     const int4 *__restrict__ edge = g.edge;  // set when the tree state is in global memory
     const int u = g.u;
-    const int *__restrict__ rp = g.rp;
-    const CT *__restrict__ col = reinterpret_cast<const CT *>(g.colv);  // int32, or uint16 when n <= 65536
+    const int *__restrict__ rp = GL ? lrp : g.rp;
+    const CT *__restrict__ col = GL ? lcol : reinterpret_cast<const CT *>(g.colv);  // int32, or uint16 when n <= 65536
     const double *__restrict__ cw = g.cw;
     const int *__restrict__ guide = g.guide;
 
@@ -2103,13 +2125,39 @@ int wilson_resident_blocks(bool lds_bits, bool col16, bool weighted, int nwords)
     if (!ok) return 0;
     return std::max(1, per_cu) * std::max(1, cus);
 }
+long long wilson_graph_lds_bytes(int n, long long nnz) {
+    return ((long long)(n + 1) * 4 + (long long)n * 4 + nnz * 2 + 3) / 4 * 4;
+}
+int wilson_resident_blocks_graph_lds(int nwords, long long graph_bytes) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(wilson_kernel<true, unsigned short, false, true>)) !=
+        hipSuccess)
+        return 0;
+    const long long dyn = (long long)nwords * 4 + graph_bytes;
+    const long long bytes = ((long long)fa.sharedSizeBytes + dyn + 255) / 256 * 256;
+    if (bytes > 65536) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wilson_kernel<true, unsigned short, false, true>, 64,
+                                                     (size_t)dyn) != hipSuccess)
+        return 0;
+    const int by_lds = 2 * (int)(81920 / bytes);  // two 80 KB halves, whole blocks in each
+    return std::max(0, std::min(per_cu, by_lds)) * std::max(1, cus);
+}
 template <bool LDS, typename CT>
 void launch_wilson_t(const WilsonArgs &a, int blocks, bool weighted, size_t dyn, hipStream_t st) {
     if (weighted) wilson_kernel<LDS, CT, true><<<blocks, 64, dyn, st>>>(a);
     else wilson_kernel<LDS, CT, false><<<blocks, 64, dyn, st>>>(a);
 }
 hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool col16, bool weighted, int nwords,
-                         hipStream_t st) {
+                         hipStream_t st, long long graph_lds_bytes) {
+    if (graph_lds_bytes > 0) {
+        if (!lds_bits || !col16 || weighted || a.tiles) return hipErrorInvalidValue;
+        wilson_kernel<true, unsigned short, false, true>
+            <<<blocks, 64, (size_t)nwords * 4 + (size_t)graph_lds_bytes, st>>>(a);
+        return hipGetLastError();
+    }
     if (lds_bits) {
         const size_t dyn = (size_t)nwords * 4;
         if (col16) launch_wilson_t<true, unsigned short>(a, blocks, weighted, dyn, st);

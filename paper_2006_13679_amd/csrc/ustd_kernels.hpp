@@ -140,8 +140,14 @@ int vec_grid(int n);
 hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t st);
 // resident blocks of one sampler launch on the current device (occupancy x compute units)
 int wilson_resident_blocks(bool lds_bits, bool col16, bool weighted, int nwords);
+// Small unweighted graphs (16-bit columns, LDS tree bitmap) may keep the graph in LDS as well:
+// its bytes there (row pointers, B_u flags, columns), and the resident blocks of such a
+// launch by the LDS residency measured on gfx950 (two 80 KB halves, 256-byte units).
+long long wilson_graph_lds_bytes(int n, long long nnz);
+int wilson_resident_blocks_graph_lds(int nwords, long long graph_bytes);
+// graph_lds_bytes > 0 (single-graph launches only): the graph-in-LDS variant
 hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool col16, bool weighted, int nwords,
-                         hipStream_t st);
+                         hipStream_t st, long long graph_lds_bytes = 0);
 // weighted graphs: running row sums and row totals; weight checks; B_u edge conductances,
 // B-path resistances (max into *rmax_bits, as the bits of a non-negative double); F
 hipError_t launch_sum_walks(int cnt, const long long *steps, const long long *draws, unsigned long long *totals,
