@@ -412,63 +412,15 @@ __device__ __forceinline__ int step_index(uint32_t w, int r0, int r1, const doub
     }
 }
 
-// The sequential algorithm for one start s0 against the current tree: walk with Next
-// pointers (in the parent field), retrace the loop erasure, and write the branch's records
-// {parent, nba | marked << 31}.  The walk resumes at step k0 from vertex x0 (k0 = 0, x0 = s0
-// for a whole walk; otherwise the Next pointers of steps 0..k0-1 are already written).  One
-// lane; returns the walk's total step count.
-//
-// Graphs past the LDS bitmap read the edge entries {y, row of y, B_u flag of y}: the entry
-// of step k gives everything step k + 1 needs, so step k + 1's entry is loaded together with
-// the tree test of y (before its answer is known) and each step waits for one load, not two
-// in a row.  Small graphs keep the compact column and row arrays, which stay in the L1.
-template <bool LDS, typename CT, bool WT>
-__device__ long long rewalk_commit(const TreeState<LDS> &bits, int *recw, const int *__restrict__ rp,
-                                   const CT *__restrict__ col, const int4 *__restrict__ edge,
-                                   const int4 *__restrict__ vrow, const double *__restrict__ cw,
-                                   const int *__restrict__ guide, const int *__restrict__ bflag, int s0, int x0,
-                                   long long k0, uint32_t tlo,
-                                   uint32_t thi, uint32_t key0, uint32_t key1) {
-    int xw = x0;
-    long long k = k0;
-    uint4 ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
-    if constexpr (LDS) {
-        int r0 = rp[x0], r1 = rp[x0 + 1];
-        for (;;) {
-            if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
-            const int q = (int)(k & 3);
-            const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-            const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw, guide)];
-            const int ny0 = rp[y], ny1 = rp[y + 1];
-            ++k;
-            recw[2 * xw] = y;  // Next pointer; becomes the parent when xw joins T
-            if (bits.test(y)) break;
-            xw = y;
-            r0 = ny0;
-            r1 = ny1;
-        }
-    } else {
-    int4 e;  // entry of step k: the step from xw
-    {
-        const int4 v0 = vrow[x0];
-        const int q = (int)(k & 3);
-        const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-        e = edge[v0.x + step_index<WT>(w, v0.x, v0.y, cw, guide)];
-    }
-    for (;;) {
-        const int y = e.x;
-        ++k;
-        if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
-        const int q = (int)(k & 3);
-        const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
-        const int4 en = edge[e.y + step_index<WT>(w, e.y, e.z, cw, guide)];  // step k from y
-        recw[2 * xw] = y;  // Next pointer; becomes the parent when xw joins T
-        if (bits.test(y)) break;
-        xw = y;
-        e = en;
-    }
-    }
-    // retrace the loop erasure from s0 to the tree vertex ya it reaches
+// The sequential algorithm for one start s0 against the current tree, in two parts: a walk
+// that writes Next pointers (in the parent field) until it reaches the tree, then the retrace
+// of the loop erasure that writes the branch's records {parent, nba | marked << 31}.  The walk
+// resumes at step k0 from vertex x0 (k0 = 0, x0 = s0 for a whole walk; otherwise the Next
+// pointers of steps 0..k0-1 are already written).
+
+// Retrace from s0 to the tree vertex the walk reached.  One lane.
+template <bool LDS>
+__device__ void retrace_commit(const TreeState<LDS> &bits, int *recw, const int *__restrict__ bflag, int s0) {
     int z = s0;
     while (!bits.test(z)) {
         bits.set(z);
@@ -492,7 +444,114 @@ __device__ long long rewalk_commit(const TreeState<LDS> &bits, int *recw, const 
         const int nz = recw[2 * z];
         recw[2 * z + 1] |= mark_bits(z, bflag[z], nz, bflag[nz]);
     }
+}
+
+// The walk on graphs held in LDS (the graph-in-LDS sampler).  Every lane calls it; lane 0 walks.  The
+// wave computes the walk's Philox words 256 at a time (lane i the block of steps 4(b0+i) ..
+// 4(b0+i)+3) into wbuf (LDS), so the walking lane reads a word per step instead of running a
+// ten-round Philox block on one lane every fourth step.  Returns the walk's total step count
+// on every lane.
+template <typename CT, bool WT>
+__device__ long long walk_next_wave(const TreeState<true> &bits, int *recw, const int *__restrict__ rp,
+                                    const CT *__restrict__ col, const double *__restrict__ cw,
+                                    const int *__restrict__ guide, int s0, int x0, long long k0, uint32_t tlo,
+                                    uint32_t thi, uint32_t key0, uint32_t key1, uint32_t *wbuf) {
+    const int lane = threadIdx.x;
+    long long k = k0;  // wave-uniform between word blocks
+    int xw = x0, r0 = 0, r1 = 0;
+    if (lane == 0) {
+        r0 = rp[x0];
+        r1 = rp[x0 + 1];
+    }
+    for (;;) {
+        const long long b0 = k >> 2;
+        const uint4 ph = philox4x32_10(make_uint4((uint32_t)(b0 + lane), (uint32_t)s0, tlo, thi), key0, key1);
+        wbuf[4 * lane] = ph.x;
+        wbuf[4 * lane + 1] = ph.y;
+        wbuf[4 * lane + 2] = ph.z;
+        wbuf[4 * lane + 3] = ph.w;
+        wave_sync();
+        int fin = 0;
+        if (lane == 0) {
+            const long long kend = (b0 + kWave) * 4;
+            while (k < kend) {
+                const uint32_t w = wbuf[(int)(k - b0 * 4)];
+                const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw, guide)];
+                const int ny0 = rp[y], ny1 = rp[y + 1];
+                ++k;
+                recw[2 * xw] = y;  // Next pointer; becomes the parent when xw joins T
+                if (bits.test(y)) {
+                    fin = 1;
+                    break;
+                }
+                xw = y;
+                r0 = ny0;
+                r1 = ny1;
+            }
+        }
+        wave_sync();  // the words are read before they are overwritten
+        fin = __shfl(fin, 0, kWave);
+        const int klo = __shfl((int)(unsigned long long)k, 0, kWave);
+        const int khi = __shfl((int)((unsigned long long)k >> 32), 0, kWave);
+        k = (long long)(((unsigned long long)(unsigned)khi << 32) | (unsigned)klo);
+        if (fin) return k;
+    }
+}
+
+// The walk and retrace by one lane.  Graphs past the LDS bitmap read the edge entries {y,
+// row of y, B_u flag of y}: the entry of step k gives everything step k + 1 needs, so step
+// k + 1's entry is loaded together with the tree test of y (before its answer is known) and
+// each step waits for one load, not two in a row.  Graphs within it read the compact column
+// and row arrays, which stay in the L1.  Returns the walk's total step count.
+template <bool LDS, typename CT, bool WT>
+__device__ long long rewalk_commit(const TreeState<LDS> &bits, int *recw, const int *__restrict__ rp,
+                                   const CT *__restrict__ col, const int4 *__restrict__ edge,
+                                   const int4 *__restrict__ vrow, const double *__restrict__ cw,
+                                   const int *__restrict__ guide, const int *__restrict__ bflag, int s0, int x0,
+                                   long long k0, uint32_t tlo, uint32_t thi, uint32_t key0, uint32_t key1) {
+    int xw = x0;
+    long long k = k0;
+    uint4 ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
+    if constexpr (LDS) {
+        int r0 = rp[x0], r1 = rp[x0 + 1];
+        for (;;) {
+            if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
+            const int q = (int)(k & 3);
+            const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
+            const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw, guide)];
+            const int ny0 = rp[y], ny1 = rp[y + 1];
+            ++k;
+            recw[2 * xw] = y;  // Next pointer; becomes the parent when xw joins T
+            if (bits.test(y)) break;
+            xw = y;
+            r0 = ny0;
+            r1 = ny1;
+        }
+        retrace_commit<true>(bits, recw, bflag, s0);
+        return k;
+    } else {
+    int4 e;  // entry of step k: the step from xw
+    {
+        const int4 v0 = vrow[x0];
+        const int q = (int)(k & 3);
+        const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
+        e = edge[v0.x + step_index<WT>(w, v0.x, v0.y, cw, guide)];
+    }
+    for (;;) {
+        const int y = e.x;
+        ++k;
+        if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
+        const int q = (int)(k & 3);
+        const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
+        const int4 en = edge[e.y + step_index<WT>(w, e.y, e.z, cw, guide)];  // step k from y
+        recw[2 * xw] = y;  // Next pointer; becomes the parent when xw joins T
+        if (bits.test(y)) break;
+        xw = y;
+        e = en;
+    }
+    retrace_commit<false>(bits, recw, bflag, s0);
     return k;
+    }
 }
 
 template <typename T>
@@ -518,6 +577,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     int *const br = htab;  // a long walk's branch (vertex | edge bits << 30) shares the tables'
                            // storage; the slots are cleared again afterwards
     static_assert(kPath + 1 <= 2 * kHashSlots, "the branch buffer fits the conflict tables");
+    static_assert(4 * kWave <= 2 * kHashSlots, "a re-walk's Philox words fit the conflict tables");
     static_assert(kPathLds * 2 <= 16, "edge bits fit rob_pb");
 
     const int lane = threadIdx.x;
@@ -732,23 +792,32 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 const int s0 = (int)rob_s[sl];
                 if (!bits.test(s0)) {
                     if (hs == kContinue) wait_global();  // recorded steps stored by another lane
-                    if (lane == 0) {
-                        int xs = s0;
-                        long long k0 = 0;
-                        if (hs == kContinue) {
+                    int xs = s0;
+                    const long long k0 = hs == kContinue ? kPath : 0;
+                    if (lane == 0 && hs == kContinue) {
 #pragma unroll 8
-                            for (int j = 1; j <= kPath; ++j) {
-                                const int xj = j <= kPathLds ? (int)rob_p[sl][j - 1]
-                                                             : gpath[sl * (kPath - kPathLds) + (j - 1 - kPathLds)] & kVertexMask;
-                                recw[2 * xs] = xj;
-                                xs = xj;
-                            }
-                            k0 = kPath;
+                        for (int j = 1; j <= kPath; ++j) {
+                            const int xj = j <= kPathLds ? (int)rob_p[sl][j - 1]
+                                                         : gpath[sl * (kPath - kPathLds) + (j - 1 - kPathLds)] & kVertexMask;
+                            recw[2 * xs] = xj;
+                            xs = xj;
                         }
-                        const long long kk =
-                            rewalk_commit<LDS, CT, WT>(bits, recw, rp, col, edge, vrow, cw, guide, bflag, s0, xs, k0,
-                                                       tlo, thi,
-                                                       g.key0, g.key1);
+                    }
+                    long long kk = 0;
+                    if constexpr (GL) {
+                        // the conflict tables (all free now) hold the walk's Philox words meanwhile
+                        xs = __shfl(xs, 0, kWave);
+                        kk = walk_next_wave<CT, WT>(bits, recw, rp, col, cw, guide, s0, xs, k0, tlo, thi, g.key0,
+                                                    g.key1, reinterpret_cast<uint32_t *>(htab));
+                        for (int i = lane; i < 4 * kWave; i += kWave) htab[i] = kWave;
+                        wave_sync();
+                        if (lane == 0) retrace_commit<true>(bits, recw, bflag, s0);
+                    } else {
+                        if (lane == 0)
+                            kk = rewalk_commit<LDS, CT, WT>(bits, recw, rp, col, edge, vrow, cw, guide, bflag, s0, xs,
+                                                            k0, tlo, thi, g.key0, g.key1);
+                    }
+                    if (lane == 0) {
                         steps += kk;
                         draws += kk - k0;
                     }
