@@ -130,3 +130,23 @@ def test_two_tree_pools_match_one(gpu):
     _, st, want = oracle.trees(g.row_ptr, g.col, u, 6, 8990, 10, want_parents=False)
     got, rp = api.flow_counts(G, p2, 8990, 10)
     assert (got.cpu().numpy() == want).all() and rp["walk_steps"] == int(st.sum())
+
+
+@pytest.mark.parametrize("name,make", [("grid50", lambda: gg.grid2d(50)), ("grid51", lambda: gg.grid2d(51)),
+                                       ("rmat11", lambda: gg.rmat(11, 4, 1))])
+def test_graph_in_lds_boundary(gpu, name, make):
+    """Small unweighted graphs whose row pointers, flag words and 16-bit columns fit 40 KB are
+    sampled from LDS (grid 50x50: 39,604 B; R-MAT 11 with edge factor 4: 38,164 B), with the
+    long re-walks' Philox words computed by the whole wave; grid 51x51 (41,212 B) just misses.
+    Parents, steps and counts match the oracle on both sides."""
+    g = make()
+    u = gg.max_degree_pivot(g) if name.startswith("rmat") else gg.grid_center_pivot(int(name[4:]))
+    G = api.Graph.from_host(g.row_ptr, g.col)
+    p = api.problem(G, pivot=u, seed=8, tau_override=70)
+    say("graph in LDS", name, g.n)
+    par, steps = api.sample_trees(G, p, 3, 70)
+    want_par, want_steps, _ = oracle.trees(g.row_ptr, g.col, u, 8, 3, 70, want_counts=False)
+    assert (par.cpu().numpy() == want_par).all() and (steps.cpu().numpy() == want_steps).all()
+    counts, rep = api.flow_counts(G, p, 0, 70)
+    _, st, want = oracle.trees(g.row_ptr, g.col, u, 8, 0, 70, want_parents=False)
+    assert (counts.cpu().numpy() == want).all() and rep["walk_steps"] == int(st.sum())
