@@ -364,10 +364,27 @@ __device__ __forceinline__ int wave_scan_dpp(int x) {
     x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return x;
 }
-// multiplicative hashes, scaled to [0, kHashSlots) by their high bits
-__device__ __forceinline__ int hash_slot(int v) { return (int)__umulhi((unsigned)v * 2654435761u, kHashSlots); }
+// Multiplicative hashes scaled to [0, kHashSlots).  Any hash keeps the commit exact: a
+// collision only ends a batch early.  With the tree bitmap in LDS (vertex IDs below 2^17) they
+// take bits 16..23 of a 24 x 24-bit product (odd multipliers near 2^24 times the golden ratio
+// and another irrational, so consecutive IDs spread over the table), then x 240 / 256: two
+// full-rate v_mul_u32_u24 instead of a quarter-rate 32-bit multiply and high multiply, as that
+// sampler is bound by instruction issue.  The large-graph sampler keeps the 32-bit hashes (the
+// other form costs it a register and one wave per SIMD).
+template <bool LDS>
+__device__ __forceinline__ int hash_slot(int v) {
+    if constexpr (LDS)
+        return (int)(__umul24((__umul24((unsigned)v, 0x9E3779u) >> 16) & 0xFFu, (unsigned)kHashSlots) >> 8);
+    else
+        return (int)__umulhi((unsigned)v * 2654435761u, kHashSlots);
+}
+template <bool LDS>
 __device__ __forceinline__ int hash_slot2(int v) {
-    return (int)__umulhi((unsigned)v * 2246822519u + 3266489917u, kHashSlots);
+    if constexpr (LDS)
+        return (int)(__umul24(((__umul24((unsigned)v, 0xC2B2AFu) + 0x5BD1E9u) >> 16) & 0xFFu, (unsigned)kHashSlots) >>
+                     8);
+    else
+        return (int)__umulhi((unsigned)v * 2246822519u + 3266489917u, kHashSlots);
 }
 
 // position of the k-th set bit of x (k < popc(x)), by halving
@@ -883,8 +900,8 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
 #pragma unroll
                     for (int j = 0; j <= kPathLds; ++j)
                         if ((keep >> j) & 1u) {
-                            atomicMin(&hslot[hash_slot(xv[j])], lane);
-                            atomicMin(&hslot2[hash_slot2(xv[j])], lane);
+                            atomicMin(&hslot[hash_slot<LDS>(xv[j])], lane);
+                            atomicMin(&hslot2[hash_slot2<LDS>(xv[j])], lane);
                         }
                 }
                 wave_sync();
@@ -892,7 +909,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 if (live && !bad) {
 #pragma unroll
                     for (int j = 0; j <= kPathLds; ++j)
-                        if (j < istar && hslot[hash_slot(xv[j])] < lane && hslot2[hash_slot2(xv[j])] < lane)
+                        if (j < istar && hslot[hash_slot<LDS>(xv[j])] < lane && hslot2[hash_slot2<LDS>(xv[j])] < lane)
                             conflict = true;
                 }
                 wave_sync();
@@ -900,8 +917,8 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
 #pragma unroll
                     for (int j = 0; j <= kPathLds; ++j)
                         if ((keep >> j) & 1u) {
-                            hslot[hash_slot(xv[j])] = kWave;
-                            hslot2[hash_slot2(xv[j])] = kWave;
+                            hslot[hash_slot<LDS>(xv[j])] = kWave;
+                            hslot2[hash_slot2<LDS>(xv[j])] = kWave;
                         }
                 }
                 const uint64_t cm = __ballot(conflict);
