@@ -312,7 +312,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (trees would shard by range "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (trees would shard by range "
               "across GPUs with one all-reduce of the integer counts; see the design notes)", file=sys.stderr)
         sys.exit(2)
     if WORKLOADS[args.workload]["kind"] == "batch":
