@@ -313,7 +313,7 @@ def main():
 
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (trees would shard by range "
-              "across GPUs with one all-reduce of the integer counts; see the design notes)", file=sys.stderr)
+              "across GPUs with one all-reduce of the integer counts)", file=sys.stderr)
         sys.exit(2)
     if WORKLOADS[args.workload]["kind"] == "batch":
         run_batch(args)
