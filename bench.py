@@ -64,9 +64,10 @@ def make_workload(name: str):
 
 
 def algorithmic_bytes(n: int, tau: int, steps: int, farness: int) -> dict:
-    """Bytes the method must move (per the design notes): 20 B per walk step plus 12 B per
-    vertex and tree for the commit (sampler); 18 B per (vertex, B-path edge) pair plus 12 B
-    per vertex and tree for Algorithm 2 (aggregation)."""
+    """Bytes the method must move: 20 B per walk step (the landing vertex's column entry, row
+    bounds, flag word and tree test) plus 12 B per vertex and tree for the commit (sampler);
+    18 B per (vertex, B-path edge) pair plus 12 B per vertex and tree for Algorithm 2
+    (aggregation)."""
     return dict(sample=20 * steps + 12 * n * tau, aggregate=(18 * farness + 12 * n) * tau)
 
 
