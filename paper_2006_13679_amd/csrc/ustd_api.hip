@@ -405,6 +405,15 @@ int sweep_pivot(Ctx &c, int *pivot) {
     int *dist = at<int>(c.ws, c.L.off_dist);
     int *parB = at<int>(c.ws, c.L.off_parB);
     int *bound = at<int>(c.ws, c.L.off_scr);
+    if (n <= kSmallSolveMaxN) {  // all sweeps in one workgroup, one readback
+        HIP_TRY(launch_sweep_small(c.rows, c.L.G, kPivotSweeps, dist, bound, c.misc->setup_out, c.st));
+        int piv = -1;
+        HIP_TRY(hipMemcpyAsync(&piv, c.misc->setup_out, sizeof(int), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        if (piv < 0 || piv >= n) return fail(USTD_EHIP, "sweep pivot out of range");
+        *pivot = piv;
+        return USTD_OK;
+    }
     unsigned long long key = 0;
     HIP_TRY(hipMemsetAsync(&c.misc->best_degree, 0, sizeof(key), c.st));
     HIP_TRY(launch_argmax_degree(n, c.rp32, &c.misc->best_degree, c.st));

@@ -1343,6 +1343,99 @@ __global__ void bsub_pack_kernel(int n, const int *__restrict__ parB, const int 
     bflag[v] = (int)((unsigned)(pb + 1) | (z > 1 ? 0x80000000u : 0u));
 }
 
+// The pivot by BFS sweeps for a small graph, in one workgroup and with no host round trip:
+// the same first source (largest degree, then smallest ID), the same level-synchronous BFS, the
+// same bounds (the distances of the first sweep, then their running maximum) and next source
+// (the farthest vertex, then smallest ID) as sweep_update_kernel, and the same choice (smallest
+// bound, then smallest ID) as argmin_bound_kernel.  *pivot receives the choice.
+constexpr int kSweepThreads = 1024;
+
+__device__ __forceinline__ unsigned long long block_max_key(unsigned long long key, unsigned long long *sh) {
+#pragma unroll
+    for (int dd = 32; dd > 0; dd >>= 1) {
+        const unsigned long long o = __shfl_xor(key, dd, 64);
+        key = o > key ? o : key;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = key;
+    __syncthreads();
+    unsigned long long r = 0;
+    for (int i = 0; i < kSweepThreads / kWave; ++i) r = sh[i] > r ? sh[i] : r;
+    __syncthreads();  // every thread has read sh before it is written again
+    return r;
+}
+
+template <int G>
+__global__ __launch_bounds__(kSweepThreads) void sweep_small_kernel(RowMap m, int sweeps, int *__restrict__ dist,
+                                                                    int *__restrict__ bound, int *__restrict__ pivot) {
+    __shared__ unsigned long long shk[kSweepThreads / kWave];
+    __shared__ int found;
+    const int n = m.n, tid = threadIdx.x;
+    const int nh = *m.nheavy;
+    unsigned long long key = 0;
+    for (int v = tid; v < n; v += kSweepThreads) {
+        const unsigned long long k = ((unsigned long long)(unsigned)(m.rp[v + 1] - m.rp[v]) << 32) |
+                                     (unsigned long long)(0xFFFFFFFFu - (unsigned)v);
+        key = k > key ? k : key;
+    }
+    int src = (int)(0xFFFFFFFFu - (unsigned)(block_max_key(key, shk) & 0xFFFFFFFFull));
+    for (int it = 0; it < sweeps; ++it) {
+        for (int v = tid; v < n; v += kSweepThreads) dist[v] = (v == src) ? 0 : INT_MAX;
+        for (int d = 0;; ++d) {
+            if (tid == 0) found = 0;
+            __syncthreads();
+            int any = 0;
+            for (int h = 0; h < nh; ++h) {
+                const int v = m.heavy[h];
+                if (dist[v] != d) continue;  // uniform in the block
+                for (int e = m.rp[v] + tid; e < m.rp[v + 1]; e += kSweepThreads) {
+                    const int y = m.col[e];
+                    if (dist[y] > d + 1) {
+                        dist[y] = d + 1;
+                        any = 1;
+                    }
+                }
+            }
+            constexpr int rows_per_tile = kSweepThreads / G;
+            const int g = tid / G, l = tid % G;
+            for (int base = 0; base < n; base += rows_per_tile) {
+                const int v = base + g;
+                if (v >= n || dist[v] != d) continue;
+                const int lo = m.rp[v], hi = m.rp[v + 1];
+                if (hi - lo > m.heavy_thresh) continue;
+                for (int e = lo + l; e < hi; e += G) {
+                    const int y = m.col[e];
+                    if (dist[y] > d + 1) {
+                        dist[y] = d + 1;
+                        any = 1;
+                    }
+                }
+            }
+            if (any) found = 1;
+            __syncthreads();
+            const int f = found;
+            __syncthreads();  // every thread has read `found` before it is reset
+            if (!f) break;
+        }
+        key = 0;
+        for (int v = tid; v < n; v += kSweepThreads) {
+            const int d = dist[v];
+            bound[v] = it == 0 ? d : max(bound[v], d);
+            const unsigned long long k = ((unsigned long long)(unsigned)d << 32) |
+                                         (unsigned long long)(0xFFFFFFFFu - (unsigned)v);
+            key = k > key ? k : key;
+        }
+        src = (int)(0xFFFFFFFFu - (unsigned)(block_max_key(key, shk) & 0xFFFFFFFFull));
+    }
+    key = 0;
+    for (int v = tid; v < n; v += kSweepThreads) {
+        const unsigned long long k = ((unsigned long long)(0x7FFFFFFFu - (unsigned)bound[v]) << 32) |
+                                     (unsigned long long)(0xFFFFFFFFu - (unsigned)v);
+        key = k > key ? k : key;
+    }
+    key = block_max_key(key, shk);
+    if (tid == 0) *pivot = (int)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+}
+
 // Set-up of a small graph in one workgroup: the BFS levels (the same minimum-ID parent
 // rule as bfs_level_kernel), the connectivity check, and the subtree intervals and flag
 // words of B_u (as the bsub_* kernels).  out[0] = ecc(u), out[1] = 1 if a vertex is
@@ -2270,6 +2363,10 @@ hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int 
     for (int d = ecc; d >= 1; --d) bsub_size_kernel<<<nb, 256, 0, st>>>(n, d, dist, parB, sz);
     for (int d = 1; d <= ecc; ++d) bsub_pre_kernel<<<nb, 256, 0, st>>>(n, d, dist, parB, sz, cur, pre);
     bsub_pack_kernel<<<nb, 256, 0, st>>>(n, parB, pre, sz, bint, bflag);
+    return hipGetLastError();
+}
+hipError_t launch_sweep_small(const RowMap &m, int G, int sweeps, int *dist, int *bound, int *pivot, hipStream_t st) {
+    USTD_DISPATCH_G(G, (sweep_small_kernel<GG><<<1, kSweepThreads, 0, st>>>(m, sweeps, dist, bound, pivot)));
     return hipGetLastError();
 }
 hipError_t launch_setup_small(const RowMap &m, int G, int u, int *dist, int *parB, int *scratch, int2 *bint,

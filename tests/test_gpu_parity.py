@@ -408,6 +408,19 @@ def test_sweep_pivot_matches_oracle(gpu, idx):
     assert ecc == oracle.bfs(g.row_ptr, g.col, want)[2]
 
 
+@pytest.mark.parametrize("name,make", [("grid100", lambda: gg.grid2d(100)), ("rmat14", lambda: gg.rmat(14, 8, 2))])
+def test_sweep_pivot_one_workgroup_sizes(gpu, name, make):
+    """Graphs of up to 16384 vertices run all ten sweeps in one workgroup: a 100x100 grid (198
+    BFS levels per sweep) and an R-MAT graph with heavy hub rows choose the oracle's pivot."""
+    g = make()
+    assert g.n <= 16384
+    G = dev_graph(g)
+    say("sweep pivot", name, g.n)
+    _, _, ecc, pivot = api.bfs(G, api.problem(G, pivot=-2))
+    want, _ = oracle.sweep_pivot(g.row_ptr, g.col)
+    assert pivot == want and ecc == oracle.bfs(g.row_ptr, g.col, want)[2]
+
+
 def test_sweep_pivot_rmat16(gpu):
     g = gg.rmat(16, 16, 1)
     G = dev_graph(g)
