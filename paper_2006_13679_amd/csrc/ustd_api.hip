@@ -59,7 +59,7 @@ inline long long align_up(long long v) { return (v + kAlign - 1) / kAlign * kAli
 
 struct Misc {                      // small zero-initialised block at the front of the workspace
     int err_validate;
-    int bfs_found;
+    int bfs_found[4];              // found flags of a group of queued BFS levels (kBfsGroup)
     int err_interval;
     int nheavy;
     int queue[2];                  // sampler tile counters, one per tree pool
@@ -370,19 +370,27 @@ int begin(Ctx &c, const ustd_problem *p, void *ws, size_t ws_bytes, void *stream
 }
 
 // level-synchronous BFS from src into dist / parB, one readback per level; *ecc = levels - 1
+// Levels are queued kBfsGroup at a time with one readback per group: a level after one that
+// reached nothing returns at once (the group's first level runs: the previous group's last
+// level reached something, or the loop would have ended).
+constexpr int kBfsGroup = 4;
 int bfs_levels(Ctx &c, int src, int *dist, int *parB, int *ecc) {
+    static_assert(sizeof(c.misc->bfs_found) == kBfsGroup * sizeof(int), "one flag per queued level");
     HIP_TRY(launch_bfs_init(c.L.n, src, dist, parB, c.st));
-    int d = 0;
-    for (;; ++d) {
-        HIP_TRY(hipMemsetAsync(&c.misc->bfs_found, 0, sizeof(int), c.st));
-        HIP_TRY(launch_bfs_level(c.rows, c.L.G, d, dist, parB, &c.misc->bfs_found, c.st));
-        int found = 0;
-        HIP_TRY(hipMemcpyAsync(&found, &c.misc->bfs_found, sizeof(int), hipMemcpyDeviceToHost, c.st));
+    int *fl = c.misc->bfs_found;
+    for (int d0 = 0;; d0 += kBfsGroup) {
+        HIP_TRY(hipMemsetAsync(fl, 0, sizeof(int) * kBfsGroup, c.st));
+        for (int j = 0; j < kBfsGroup; ++j)
+            HIP_TRY(launch_bfs_level(c.rows, c.L.G, d0 + j, dist, parB, fl + j, j ? fl + j - 1 : nullptr, c.st));
+        int found[kBfsGroup] = {};
+        HIP_TRY(hipMemcpyAsync(found, fl, sizeof(found), hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipStreamSynchronize(c.st));
-        if (!found) break;
+        for (int j = 0; j < kBfsGroup; ++j)
+            if (!found[j]) {
+                *ecc = d0 + j;
+                return USTD_OK;
+            }
     }
-    *ecc = d;
-    return USTD_OK;
 }
 
 unsigned packed_id(unsigned long long key) { return 0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull); }

@@ -125,9 +125,13 @@ __global__ void bfs_init_kernel(int n, int u, int *__restrict__ dist, int *__res
 // One BFS level: every vertex at distance d offers itself as parent to its unvisited
 // neighbours; atomicMin keeps the smallest-ID one among all of them, which is the
 // minimum-ID neighbour one level closer to u.  `found` is set if any vertex is reached.
+// Levels are queued several at a time: a level whose predecessor reached nothing (*prev == 0)
+// has no vertex at distance d and returns at once.
 template <int G>
 __global__ __launch_bounds__(256) void bfs_level_kernel(RowMap m, int d, int *__restrict__ dist,
-                                                        int *__restrict__ parB, int *__restrict__ found) {
+                                                        int *__restrict__ parB, int *__restrict__ found,
+                                                        const int *__restrict__ prev) {
+    if (prev && *prev == 0) return;  // uniform over the grid
     int any = 0;
     const int nh = *m.nheavy;
     for (int h = blockIdx.x; h < nh; h += gridDim.x) {
@@ -2266,9 +2270,10 @@ static inline int row_grid(const RowMap &m, int G) {
     return (int)std::min<long long>(std::max<long long>(tiles, 1), 4096);
 }
 
-hipError_t launch_bfs_level(const RowMap &m, int G, int d, int *dist, int *parB, int *found, hipStream_t st) {
+hipError_t launch_bfs_level(const RowMap &m, int G, int d, int *dist, int *parB, int *found, const int *prev,
+                            hipStream_t st) {
     const int grid = row_grid(m, G);
-    USTD_DISPATCH_G(G, bfs_level_kernel<GG><<<grid, 256, 0, st>>>(m, d, dist, parB, found));
+    USTD_DISPATCH_G(G, bfs_level_kernel<GG><<<grid, 256, 0, st>>>(m, d, dist, parB, found, prev));
     return hipGetLastError();
 }
 hipError_t launch_heavy_list(int n, const int *rp, int thresh, int *bcount, int *heavy, int *nheavy, hipStream_t st) {

@@ -135,7 +135,9 @@ hipError_t launch_sweep_update(int n, const int *dist, int *bound, int first, un
 hipError_t launch_argmin_bound(int n, const int *bound, unsigned long long *best, hipStream_t st);
 // the whole sweep-pivot choice in one workgroup (n <= kSmallSolveMaxN); *pivot = the pivot
 hipError_t launch_sweep_small(const RowMap &m, int G, int sweeps, int *dist, int *bound, int *pivot, hipStream_t st);
-hipError_t launch_bfs_level(const RowMap &m, int G, int d, int *dist, int *parB, int *found, hipStream_t st);
+// one BFS level; with prev (the previous level's found flag) set, it returns at once if that is 0
+hipError_t launch_bfs_level(const RowMap &m, int G, int d, int *dist, int *parB, int *found, const int *prev,
+                            hipStream_t st);
 hipError_t launch_heavy_list(int n, const int *rp, int thresh, int *bcount, int *heavy, int *nheavy, hipStream_t st);
 int solve_grid(const RowMap &m, int G);
 int vec_grid(int n);
