@@ -641,6 +641,7 @@ int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag, int pool 
     aa.rec_stride = c.L.rec_stride;
     aa.counts = counts;
     aa.F = c.L.weighted ? at<long long>(c.ws, c.L.off_F) : nullptr;
+    aa.chunk = c.L.lds_bits ? kAggChunk : kAggChunkLarge;
     Timer tm(st);
     HIP_TRY(launch_aggregate(aa, st));
     if (ms_ag) *ms_ag += tm.stop_ms();
@@ -1404,6 +1405,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
                 aa.rec_stride = B.g[sg.graph].rec_stride;
                 aa.counts = counts[sg.graph];
                 aa.F = B.g[sg.graph].weighted ? at<long long>(cs[sg.graph].ws, B.g[sg.graph].off_F) : nullptr;
+                aa.chunk = B.g[sg.graph].lds_bits ? kAggChunk : kAggChunkLarge;
                 HIP_TRY(launch_aggregate(aa, aggq));
             }
             ta.back()->stop(aggq);

@@ -1222,12 +1222,12 @@ __global__ __launch_bounds__(kIvThreads) void tree_records_kernel(IntervalArgs a
 // ======================================================================================
 // WT: weighted graph, the edge (parB(b), b) of P(v) counts +-F[b] (Ohm's-law factor in fixed
 // point) instead of +-1.
-template <bool WT>
+template <bool WT, int CH>
 __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= a.n || v == a.u) return;
-    const int t0 = blockIdx.y * kAggChunk;
-    const int nt = min(a.ntrees - t0, kAggChunk);
+    const int t0 = blockIdx.y * CH;
+    const int nt = min(a.ntrees - t0, CH);
     const int u = a.u;
     const int2 *__restrict__ bint = a.bint;
     const int pbv = a.parB[v];
@@ -1238,10 +1238,10 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
     using Acc = typename std::conditional<WT, long long, int>::type;
     const long long *__restrict__ F = a.F;
     const Acc fv = WT ? (Acc)F[v] : (Acc)1;
-    int x[kAggChunk];
+    int x[CH];
     Acc sum = 0;
 #pragma unroll
-    for (int i = 0; i < kAggChunk; ++i) {
+    for (int i = 0; i < CH; ++i) {
         x[i] = u;
         if (i < nt) {
             const int2 rv = rec0[(long long)i * a.rec_stride + v];
@@ -1250,10 +1250,10 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
         }
     }
     for (;;) {
-        int2 rx[kAggChunk], bx[kAggChunk];
+        int2 rx[CH], bx[CH];
         bool act = false;
 #pragma unroll
-        for (int i = 0; i < kAggChunk; ++i) {
+        for (int i = 0; i < CH; ++i) {
             if (x[i] != u) {
                 act = true;
                 rx[i] = rec0[(long long)i * a.rec_stride + x[i]];
@@ -1262,7 +1262,7 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
         }
         if (!act) break;
 #pragma unroll
-        for (int i = 0; i < kAggChunk; ++i) {
+        for (int i = 0; i < CH; ++i) {
             if (x[i] != u) {
                 // a forward x counts +1 if x is on P(v); a backward x counts -1 if parent_T(x),
                 // a B_u child of x, is on P(v), which needs x on P(v) first
@@ -2397,9 +2397,15 @@ hipError_t launch_edge_fold(int n, long long nnz, const int *rp, const int *col,
     return hipGetLastError();
 }
 hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st) {
-    dim3 grid(blocks_for(a.n, 256), (a.ntrees + kAggChunk - 1) / kAggChunk);
-    if (a.F) aggregate_kernel<true><<<grid, 256, 0, st>>>(a);
-    else aggregate_kernel<false><<<grid, 256, 0, st>>>(a);
+    const int ch = a.chunk == kAggChunkLarge ? kAggChunkLarge : kAggChunk;
+    dim3 grid(blocks_for(a.n, 256), (a.ntrees + ch - 1) / ch);
+    if (ch == kAggChunkLarge) {
+        if (a.F) aggregate_kernel<true, kAggChunkLarge><<<grid, 256, 0, st>>>(a);
+        else aggregate_kernel<false, kAggChunkLarge><<<grid, 256, 0, st>>>(a);
+    } else {
+        if (a.F) aggregate_kernel<true, kAggChunk><<<grid, 256, 0, st>>>(a);
+        else aggregate_kernel<false, kAggChunk><<<grid, 256, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 int solve_grid(const RowMap &m, int G) {

@@ -58,7 +58,10 @@ struct IntervalArgs {
     int *err;
 };
 
-constexpr int kAggChunk = 8;  // trees one aggregation thread walks together
+// trees one aggregation thread walks together: 8, or 4 for graphs past the LDS bitmap, whose
+// records are not cache-resident (fewer registers, more threads to cover the chain loads)
+constexpr int kAggChunk = 8;
+constexpr int kAggChunkLarge = 4;
 
 struct AggregateArgs {
     int n, u, ntrees;
@@ -68,6 +71,7 @@ struct AggregateArgs {
     long long rec_stride;
     long long *counts;
     const long long *F;     // [n] fixed-point 1/w of each vertex's B_u edge; null = unit weights
+    int chunk;              // trees per thread: kAggChunk or kAggChunkLarge (0 = kAggChunk)
 };
 
 struct EdgeCountArgs {
