@@ -628,6 +628,13 @@ int sample_batch(Ctx &c, long long tree_begin, int ntrees, long long *steps, lon
     return USTD_OK;
 }
 
+// Trees per Algorithm 2 thread: deep B_u (long marked-ancestor chains: grids, hyperbolic
+// graphs) walks 4 trees per thread, which leaves registers for more threads to cover the chain
+// loads; shallow small-world B_u walks 8 (measured: RHG 1M and the 64-graph batch gain 15-18%
+// of Algorithm 2 time with 4, R-MAT 16 loses 6%).
+constexpr int kAggDeepEcc = 8;
+int agg_chunk(int ecc) { return ecc >= kAggDeepEcc ? kAggChunkLarge : kAggChunk; }
+
 // Algorithm 2 over `cnt` resident trees (records of a pool), on stream st
 int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag, int pool = 0, hipStream_t st = nullptr) {
     if (!st) st = c.st;
@@ -641,7 +648,7 @@ int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag, int pool 
     aa.rec_stride = c.L.rec_stride;
     aa.counts = counts;
     aa.F = c.L.weighted ? at<long long>(c.ws, c.L.off_F) : nullptr;
-    aa.chunk = c.L.lds_bits ? kAggChunk : kAggChunkLarge;
+    aa.chunk = agg_chunk(c.ecc);
     Timer tm(st);
     HIP_TRY(launch_aggregate(aa, st));
     if (ms_ag) *ms_ag += tm.stop_ms();
@@ -1405,7 +1412,7 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
                 aa.rec_stride = B.g[sg.graph].rec_stride;
                 aa.counts = counts[sg.graph];
                 aa.F = B.g[sg.graph].weighted ? at<long long>(cs[sg.graph].ws, B.g[sg.graph].off_F) : nullptr;
-                aa.chunk = B.g[sg.graph].lds_bits ? kAggChunk : kAggChunkLarge;
+                aa.chunk = agg_chunk(cs[sg.graph].ecc);
                 HIP_TRY(launch_aggregate(aa, aggq));
             }
             ta.back()->stop(aggq);

@@ -58,8 +58,8 @@ struct IntervalArgs {
     int *err;
 };
 
-// trees one aggregation thread walks together: 8, or 4 for graphs past the LDS bitmap, whose
-// records are not cache-resident (fewer registers, more threads to cover the chain loads)
+// trees one aggregation thread walks together: 8, or 4 where the marked-ancestor chains are
+// long (fewer registers, more threads to cover the chain loads)
 constexpr int kAggChunk = 8;
 constexpr int kAggChunkLarge = 4;
 
