@@ -59,7 +59,7 @@ inline long long align_up(long long v) { return (v + kAlign - 1) / kAlign * kAli
 
 struct Misc {                      // small zero-initialised block at the front of the workspace
     int err_validate;
-    int bfs_found[4];              // found flags of a group of queued BFS levels (kBfsGroup)
+    int bfs_found[64];             // found flags of a group of queued BFS levels (kBfsGroupMax)
     int err_interval;
     int nheavy;
     int queue[2];                  // sampler tile counters, one per tree pool
@@ -370,26 +370,30 @@ int begin(Ctx &c, const ustd_problem *p, void *ws, size_t ws_bytes, void *stream
 }
 
 // level-synchronous BFS from src into dist / parB, one readback per level; *ecc = levels - 1
-// Levels are queued kBfsGroup at a time with one readback per group: a level after one that
-// reached nothing returns at once (the group's first level runs: the previous group's last
-// level reached something, or the loop would have ended).
-constexpr int kBfsGroup = 4;
+// Levels are queued in groups with one readback per group, of 4, 4, then doubling to 64 (few
+// round trips on deep graphs; small-world graphs, eccentricity below 8, queue two groups of 4
+// and no idle launch beyond the second): a level after one
+// that reached nothing returns at once (the group's first level runs: the previous group's
+// last level reached something, or the loop would have ended).
+constexpr int kBfsGroupFirst = 4, kBfsGroupMax = 64;
 int bfs_levels(Ctx &c, int src, int *dist, int *parB, int *ecc) {
-    static_assert(sizeof(c.misc->bfs_found) == kBfsGroup * sizeof(int), "one flag per queued level");
+    static_assert(sizeof(c.misc->bfs_found) == kBfsGroupMax * sizeof(int), "one flag per queued level");
     HIP_TRY(launch_bfs_init(c.L.n, src, dist, parB, c.st));
     int *fl = c.misc->bfs_found;
-    for (int d0 = 0;; d0 += kBfsGroup) {
-        HIP_TRY(hipMemsetAsync(fl, 0, sizeof(int) * kBfsGroup, c.st));
-        for (int j = 0; j < kBfsGroup; ++j)
+    for (int d0 = 0, group = kBfsGroupFirst;;) {
+        HIP_TRY(hipMemsetAsync(fl, 0, sizeof(int) * group, c.st));
+        for (int j = 0; j < group; ++j)
             HIP_TRY(launch_bfs_level(c.rows, c.L.G, d0 + j, dist, parB, fl + j, j ? fl + j - 1 : nullptr, c.st));
-        int found[kBfsGroup] = {};
-        HIP_TRY(hipMemcpyAsync(found, fl, sizeof(found), hipMemcpyDeviceToHost, c.st));
+        int found[kBfsGroupMax] = {};
+        HIP_TRY(hipMemcpyAsync(found, fl, sizeof(int) * group, hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipStreamSynchronize(c.st));
-        for (int j = 0; j < kBfsGroup; ++j)
+        for (int j = 0; j < group; ++j)
             if (!found[j]) {
                 *ecc = d0 + j;
                 return USTD_OK;
             }
+        d0 += group;
+        group = d0 < 2 * kBfsGroupFirst ? kBfsGroupFirst : std::min(2 * group, kBfsGroupMax);
     }
 }
 
