@@ -48,6 +48,8 @@ def lib():
         L.ustd_oracle_validate.restype = ctypes.c_int
         L.ustd_oracle_bfs.argtypes = [i64, P, P, i32, P, P]
         L.ustd_oracle_bfs.restype = i32
+        L.ustd_oracle_max_degree_pivot.argtypes = [i64, P]
+        L.ustd_oracle_max_degree_pivot.restype = i32
         L.ustd_oracle_tau.argtypes = [i64, i64, i32, dbl, dbl, dbl]
         L.ustd_oracle_tau.restype = i64
         L.ustd_oracle_eta.argtypes = [i64, i64, i32, dbl, dbl]
@@ -127,6 +129,12 @@ def bfs(row_ptr, col, u: int):
     parB = np.zeros(n, dtype=np.int32)
     ecc = int(lib().ustd_oracle_bfs(n, _p(rp), _p(c), u, _p(dist), _p(parB)))
     return dist, parB, ecc
+
+
+def max_degree_pivot(row_ptr) -> int:
+    """Vertex of largest degree, smallest ID among equal degrees (the pivot rule of pivot = -1)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    return int(lib().ustd_oracle_max_degree_pivot(len(rp) - 1, _p(rp)))
 
 
 def tau(n: int, m: int, ecc: int, eps: float, delta: float = 0.0, kappa: float = 0.0) -> int:

@@ -162,6 +162,19 @@ int32_t ustd_oracle_bfs(int64_t n, const int64_t *rp, const int32_t *col, int32_
 }
 
 /* ------------------------------------------------------------------------------------
+ * Pivot by degree.  The paper picks a pivot of low eccentricity (engineering appendix,
+ * "Pivot Selection"); the degree rule taken for graphs whose workload names no pivot is the
+ * vertex of largest degree, and among several of equal degree the one with the smallest ID.
+ * ---------------------------------------------------------------------------------- */
+int32_t ustd_oracle_max_degree_pivot(int64_t n, const int64_t *rp)
+{
+    int32_t best = 0;
+    for (int64_t v = 1; v < n; ++v)
+        if (rp[v + 1] - rp[v] > rp[best + 1] - rp[best]) best = (int32_t)v;
+    return best;
+}
+
+/* ------------------------------------------------------------------------------------
  * Sample size (Algorithm 1, initialisation; Appendix proof of the main theorem):
  * tau = ecc(u)^2 * ceil( log(2m/delta) / (2 (1-kappa)^2 eps^2) ), natural log.
  * Solver accuracy eta = kappa eps / (3 sqrt(m n log n) diam(G)), diam(G) <= 2 ecc(u).

@@ -147,6 +147,18 @@ def test_bfs_against_scipy(seed):
 # -------------------------------------------------------------------------------------
 # tau / eta
 # -------------------------------------------------------------------------------------
+def test_max_degree_pivot_rule():
+    """pivot = -1: the vertex of largest degree, the smallest ID among equal degrees."""
+    assert oracle.max_degree_pivot(gg.star(9).row_ptr) == 0
+    assert oracle.max_degree_pivot(gg.path(5).row_ptr) == 1          # 1, 2, 3 all have degree 2
+    assert oracle.max_degree_pivot(gg.complete(6).row_ptr) == 0
+    assert oracle.max_degree_pivot(gg.grid2d(4).row_ptr) == 5        # interior vertices 5, 6, 9, 10
+    assert oracle.max_degree_pivot(gg.complete_bipartite(2, 3).row_ptr) == 0  # the side of 2 has degree 3
+    # a hand-built graph whose largest degree first appears at the last vertex
+    g = gg.from_edges(6, [(0, 1), (1, 2), (2, 3), (3, 4), (5, 0), (5, 1), (5, 2), (5, 3)])
+    assert oracle.max_degree_pivot(g.row_ptr) == 5
+
+
 def test_tau_worked_examples():
     with open(os.path.join(GOLD, "tau_worked_examples.txt")) as f:
         for line in f:
@@ -156,11 +168,39 @@ def test_tau_worked_examples():
             assert oracle.tau(int(n), int(m), int(ecc), float(eps)) == int(want)
 
 
-def test_eta_monotone_and_scaling():
-    e1 = oracle.eta(1000, 5000, 4, 0.3)
-    assert 0 < e1 < 1e-3
-    assert oracle.eta(1000, 5000, 4, 0.6) == pytest.approx(2 * e1)
-    assert oracle.eta(1000, 5000, 8, 0.3) == pytest.approx(e1 / 2)
+def test_eta_worked_examples():
+    """eta against hand-worked values (tests/golden/eta_worked_examples.txt): a base-2 log, a
+    missing factor 3 or a diameter bound of ecc instead of 2 ecc each move every row."""
+    rows = 0
+    with open(os.path.join(GOLD, "eta_worked_examples.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            n, m, ecc, eps, kappa, want = line.split()
+            got = oracle.eta(int(n), int(m), int(ecc), float(eps), float(kappa))
+            assert got == pytest.approx(float(want), rel=1e-14), (n, m, ecc)
+            rows += 1
+    assert rows == 6
+    # kappa <= 0 selects 0.3
+    assert oracle.eta(1024, 1984, 32, 0.3, 0.0) == oracle.eta(1024, 1984, 32, 0.3, 0.3)
+
+
+@pytest.mark.parametrize("name", ["K4", "C5", "grid3", "K23", "pendant_cycle"])
+def test_eta_bounds_the_solve_error(name):
+    """What eta is for (Appendix proof of the running-time theorem): a solution with relative
+    L-norm error eta errs by at most kappa eps / 3 in every entry.  The largest |e_i| over
+    e perpendicular to 1 with ||e||_L = c is c sqrt(L+_ii), so the worst case over all such
+    errors is eta ||x||_L sqrt(max_i L+_ii), checked for every pivot."""
+    g = TINY[name]()
+    P = brute.pinv(g)
+    for u in range(g.n):
+        _, _, ecc = oracle.bfs(g.row_ptr, g.col, u)
+        for eps, kappa in ((0.3, 0.3), (0.9, 0.5), (0.05, 0.1)):
+            eta = oracle.eta(g.n, g.m, ecc, eps, kappa)
+            x = P[:, u]
+            xl = math.sqrt(x @ brute.laplacian(g) @ x)
+            worst = eta * xl * math.sqrt(np.diag(P).max())
+            assert worst <= kappa * eps / 3
 
 
 # -------------------------------------------------------------------------------------
