@@ -45,12 +45,24 @@ enum {
     USTD_EGRAPH = 2,   /* graph fails validation (asymmetric, self-loop, unsorted, disconnected) */
     USTD_ENOMEM = 3,   /* workspace smaller than ustd_workspace_bytes() */
     USTD_EHIP = 4,     /* a HIP runtime call failed */
-    USTD_ENOTCONV = 5  /* the pivot-column solve hit its iteration cap; outputs are still written */
+    USTD_ENOTCONV = 5  /* the pivot-column solve ended above its residual target; outputs are still written */
 };
 
 enum {
     USTD_SOLVE_FP64 = 0,  /* FP64 Jacobi-preconditioned CG */
-    USTD_SOLVE_MIXED = 1  /* FP32 Jacobi-PCG inner solves, FP64 residual/refinement/projection */
+    USTD_SOLVE_MIXED = 1  /* FP32 Jacobi-PCG iterations, FP64 solution and reliable updates (true residuals) */
+};
+
+/* Where the pivot-column solve's iterations run.  Both engines run the same algorithm (Jacobi
+ * PCG with reliable updates) and differ only in the order of their FP64 partial sums, so a
+ * solve is bit-reproducible for a fixed engine. */
+enum {
+    USTD_ENGINE_AUTO = 0,      /* single calls: WORKGROUP up to 16384 vertices, else MULTI;
+                                  ustd_batch_diag_lpinv: WORKGROUP for every member */
+    USTD_ENGINE_WORKGROUP = 1, /* the whole solve in one workgroup, no host round trip (batches run
+                                  all members' solves side by side in one launch) */
+    USTD_ENGINE_MULTI = 2      /* eight kernels per iteration over the whole GPU, enqueued ahead of a
+                                  device-side done flag */
 };
 
 /* One problem instance: the inputs of ApproxDiagLpinv(G, u, eps, delta) (Algorithm 1)
@@ -94,6 +106,8 @@ typedef struct ustd_problem {
      *  - the pivot-column solve uses the weighted Laplacian (Jacobi on weighted degrees).
      * ustd_batch_diag_lpinv takes weighted and unweighted members together. */
     const double *d_weight;
+    int32_t solve_engine;     /* USTD_ENGINE_AUTO, USTD_ENGINE_WORKGROUP or USTD_ENGINE_MULTI (below) */
+    int32_t reserved_;        /* must be 0 */
 } ustd_problem;
 
 /* Filled by the calls that take it (nullable); times from HIP events on `stream`. */
@@ -114,6 +128,12 @@ typedef struct ustd_report {
     double rho_max;       /* largest B-path resistance (= ecc for unit weights) */
     int32_t fixed_shift;  /* k of the fixed-point counts of a weighted problem (0 unweighted) */
     int32_t weighted;     /* 1 if d_weight was given */
+    /* eta = kappa eps / (3 sqrt(m n ln n) diam(G)) of Algorithm 1 (solver accuracy), with
+     * diam(G) <= 2 ecc(u); natural log */
+    double eta;
+    double solve_tol;        /* relative residual target of the solve: prob->solve_tol, or min(eta, 1e-12) */
+    int32_t solve_converged; /* 1 if solve_relres <= solve_tol (else the call returned USTD_ENOTCONV) */
+    int32_t pad_;
 } ustd_report;
 
 /* Minimum workspace size for every call below on this problem (host only, no device work).
@@ -138,7 +158,8 @@ int ustd_sample_trees(const ustd_problem *prob, int64_t tree_begin, int64_t tree
                       void *d_ws, size_t ws_bytes, int32_t *d_parents, int64_t *d_steps,
                       void *stream);
 
-/* Flow counts of trees tree_begin .. +tree_count-1 (Algorithm 2, summed over the trees):
+/* Flow counts of trees tree_begin .. +tree_count-1 (Algorithm 2, summed over the trees; a
+ * weighted problem takes at most 2 tau trees per call, else USTD_EINVAL):
  * d_counts[v] += sum_T c_T(v), where c_T(v) adds +1 for every edge (a,b) of P(v) that T
  * traverses from a to b on its path from u to v and -1 for every one it traverses from b
  * to a (Kirchhoff's theorem; Eq. N-values-in-path); for a weighted problem +-F[b] in fixed
@@ -153,14 +174,20 @@ int ustd_flow_counts(const ustd_problem *prob, int64_t tree_begin, int64_t tree_
  * int32[tree_count][n] of parent arrays rooted at the pivot (parent[u] = -1); d_counts
  * (int64[n]) is accumulated (fixed point for a weighted problem, k from the problem's
  * tau).  d_parents may be NULL when tree_count = 0.  A parent array that is not a spanning
- * tree rooted at the pivot returns USTD_EINVAL.  Synchronises `stream`. */
+ * tree rooted at the pivot (a parent out of range, a cycle, a vertex that does not reach the
+ * pivot) returns USTD_EINVAL and leaves d_counts unchanged: every array is checked before
+ * Algorithm 2 reads it, and the counts are added to d_counts only at the end.  A weighted
+ * problem takes at most 2 tau trees per call (the fixed-point range), else USTD_EINVAL.
+ * Synchronises `stream`. */
 int ustd_tree_counts(const ustd_problem *prob, const int32_t *d_parents, int64_t tree_count,
                      void *d_ws, size_t ws_bytes, int64_t *d_counts, void *stream);
 
 /* Column u of L^+ (Section "Overview", step 1): solves L x = e_u - (1/n) 1 with x
- * orthogonal to 1 to relative residual solve_tol, by FP64 Jacobi-PCG or by FP32 PCG with
- * FP64 iterative refinement (solve_mode).  d_x is double[n].  Returns USTD_ENOTCONV (with
- * d_x written) if the cap is reached.  Synchronises `stream`. */
+ * orthogonal to 1 to relative residual solve_tol (default min(eta, 1e-12), Algorithm 1's
+ * solver accuracy), by FP64 Jacobi-PCG or by FP32 PCG with FP64 residuals and refinement
+ * (solve_mode).  d_x is double[n].  Returns USTD_ENOTCONV (with d_x written and
+ * rep->solve_converged = 0) whenever the final relative residual ||b - L x|| / ||b|| of the
+ * projected solution exceeds the target.  Synchronises `stream`. */
 int ustd_solve_pivot_column(const ustd_problem *prob, void *d_ws, size_t ws_bytes, double *d_x,
                             ustd_report *rep, void *stream);
 

@@ -68,11 +68,8 @@ struct Misc {                      // small zero-initialised block at the front 
     unsigned long long best_degree;
     unsigned long long rho_max_bits;  // weighted: the largest B-path resistance, as double bits
     unsigned long long walk_totals[2];  // walk steps and draws of a run of batches
-    CgScalars sc64, sc32;
-    double rr_hist64[kRrHist];
-    double rr_hist32[kRrHist];
+    SolveScalars sc;
     double sums[4];
-    double shift_scale[4];
 };
 
 struct Plan {
@@ -103,6 +100,9 @@ int check_problem(const ustd_problem *p) {
     if (p->kappa > 0.0 && !(p->kappa < 1.0)) return fail(USTD_EINVAL, "kappa must lie in (0,1)");
     if (p->solve_mode != USTD_SOLVE_FP64 && p->solve_mode != USTD_SOLVE_MIXED)
         return fail(USTD_EINVAL, "unknown solve_mode %d", p->solve_mode);
+    if (p->solve_engine < USTD_ENGINE_AUTO || p->solve_engine > USTD_ENGINE_MULTI)
+        return fail(USTD_EINVAL, "unknown solve_engine %d", p->solve_engine);
+    if (p->reserved_ != 0) return fail(USTD_EINVAL, "reserved field must be 0");
     if (p->trees_per_batch > kMaxTreesPerBatch)
         return fail(USTD_EINVAL, "trees_per_batch %d exceeds %d", p->trees_per_batch, kMaxTreesPerBatch);
     return USTD_OK;
@@ -326,6 +326,15 @@ long long problem_tau(const Ctx &c) { return c.L.weighted ? c.tau : sample_size(
 // denominator of Eq. diag-comp for the counts: tau, or tau 2^k (fixed point)
 double count_scale(const Ctx &c, long long tau) { return std::ldexp((double)tau, c.L.weighted ? c.shift : 0); }
 
+// Weighted problems sum fixed-point contributions scaled so that the sums of up to 2 tau trees
+// fit int64 (the shift comes from the problem's tau): a single call on more trees is refused.
+int check_fixed_point_range(const Ctx &c, long long tree_count) {
+    if (c.L.weighted && tree_count > 2 * c.tau)
+        return fail(USTD_EINVAL, "a weighted count call covers at most 2 tau = %lld trees (got %lld)", 2 * c.tau,
+                    tree_count);
+    return USTD_OK;
+}
+
 int check_ws(void *ws, size_t ws_bytes, long long need) {
     if (!ws) return fail(USTD_EINVAL, "workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return fail(USTD_EINVAL, "workspace must be 256-byte aligned");
@@ -472,6 +481,22 @@ int setup_weighted(Ctx &c) {
     return USTD_OK;
 }
 
+// relative residual target of the pivot-column solve: the caller's, else min(eta, 1e-12)
+double solve_target(const ustd_problem *p, int ecc) {
+    return p->solve_tol > 0.0 ? p->solve_tol : std::min(solver_eta(p, ecc), 1e-12);
+}
+
+// what set-up fixed: pivot, ecc, rho_max, the fixed-point shift, eta and the solve target
+void setup_report(const Ctx &c, ustd_report *rep) {
+    rep->pivot = c.pivot;
+    rep->ecc = c.ecc;
+    rep->rho_max = c.L.weighted ? c.rho_max : (double)c.ecc;
+    rep->fixed_shift = c.shift;
+    rep->weighted = c.L.weighted ? 1 : 0;
+    rep->eta = solver_eta(c.p, c.ecc);
+    rep->solve_tol = solve_target(c.p, c.ecc);
+}
+
 int setup_graph(Ctx &c, ustd_report *rep);
 
 // pivot choice, optional validation and the BFS tree B_u; synchronises the stream.  For a
@@ -546,11 +571,7 @@ int setup_graph(Ctx &c, ustd_report *rep) {
         }
         USTD_TRY(setup_weighted(c));
         if (rep) {
-            rep->pivot = c.pivot;
-            rep->ecc = c.ecc;
-            rep->rho_max = c.L.weighted ? c.rho_max : (double)c.ecc;
-            rep->fixed_shift = c.shift;
-            rep->weighted = c.L.weighted ? 1 : 0;
+            setup_report(c, rep);
             rep->ms_bfs += tm.stop_ms();
         }
         return USTD_OK;
@@ -570,11 +591,7 @@ int setup_graph(Ctx &c, ustd_report *rep) {
     }
     USTD_TRY(setup_weighted(c));
     if (rep) {
-        rep->pivot = c.pivot;
-        rep->ecc = c.ecc;
-        rep->rho_max = c.L.weighted ? c.rho_max : (double)c.ecc;
-        rep->fixed_shift = c.shift;
-        rep->weighted = c.L.weighted ? 1 : 0;
+        setup_report(c, rep);
         rep->ms_bfs += tm.stop_ms();
     }
     return USTD_OK;
@@ -761,132 +778,141 @@ int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *cou
 // ---------------------------------------------------------------------------------------
 // pivot-column solve
 // ---------------------------------------------------------------------------------------
+// Reliable-update threshold of the pivot-column solve: an update when |r_s| has fallen by delta
+// since the largest residual after the last one.  FP32 iterations drift from the true residual
+// after a few orders of magnitude, FP64 ones only near the rounding floor.
+constexpr double kDeltaMixed = 1e-1, kDeltaFp64 = 1e-6;
+
 template <typename T>
-CgArgs<T> cg_args(Ctx &c, T *x, T *r, T *z, T *pp, T *q, CgScalars *sc, double *hist) {
-    CgArgs<T> a{};
-    a.n = c.L.n;
-    a.rp = c.rp32;
-    a.col = c.p->d_col;
+SolveArgs<T> solve_args(const Ctx &c, void *ws, const Plan &L, double *x) {
+    SolveArgs<T> a{};
+    a.n = L.n;
+    a.u = c.pivot;
     a.x = x;
-    a.r = r;
-    a.z = z;
-    a.p = pp;
-    a.q = q;
-    a.part_pq = at<double>(c.ws, c.L.off_part);
-    a.part_rz = a.part_pq + kMaxSolveGrid;
-    a.grid_spmv = solve_grid(c.rows, c.L.G);
-    a.grid_vec = vec_grid(c.L.n);
-    a.sc = sc;
-    a.rr_hist = hist;
+    if constexpr (sizeof(T) == 8) {
+        a.xs = (T *)at<double>(ws, L.off_res64);
+        a.rs = (T *)at<double>(ws, L.off_r64);
+        a.z = (T *)at<double>(ws, L.off_z64);
+        a.p = (T *)at<double>(ws, L.off_p64);
+        a.q = (T *)at<double>(ws, L.off_q64);
+    } else {
+        a.xs = (T *)at<float>(ws, L.off_x32);
+        a.rs = (T *)at<float>(ws, L.off_r32);
+        a.z = (T *)at<float>(ws, L.off_z32);
+        a.p = (T *)at<float>(ws, L.off_p32);
+        a.q = (T *)at<float>(ws, L.off_q32);
+    }
+    a.part = at<double>(ws, L.off_part);
+    a.grid_spmv = solve_grid(c.rows, L.G);
+    a.grid_vec = vec_grid(L.n);
+    a.sc = &c.misc->sc;
+    a.rp = c.rp32;
     a.wdeg = c.rows.wdeg;
     return a;
 }
 
-// Runs CG iterations until the device flags convergence (rr <= tol2 * rr0) or breakdown,
-// or `maxit` iterations; launches in chunks and polls the device scalars between chunks.
-template <typename T>
-int cg_iterate(Ctx &c, const CgArgs<T> &a, int maxit, int *iters_out, bool *conv) {
-    CgScalars sc{};
-    *conv = false;
-    int launched = 0;
-    const int chunk = 16;
-    for (;;) {
-        HIP_TRY(hipMemcpyAsync(&sc, a.sc, sizeof(sc), hipMemcpyDeviceToHost, c.st));
-        HIP_TRY(hipStreamSynchronize(c.st));
-        if (sc.done || launched >= maxit) break;
-        const int todo = std::min(chunk, maxit - launched);
-        for (int i = 0; i < todo; ++i) HIP_TRY(launch_cg_iteration<T>(a, c.rows, c.L.G, launched + i, c.st));
-        launched += todo;
+double solve_delta2(const ustd_problem *p) {
+    const double d = p->solve_mode == USTD_SOLVE_MIXED ? kDeltaMixed : kDeltaFp64;
+    return d * d;
+}
+
+// A small pinned host buffer per thread and device for the solve's scalars, so that reading
+// them back does not stall the stream (allocated on first use, kept until the process ends).
+SolveScalars *pinned_scalars(int slots) {
+    thread_local std::vector<SolveScalars *> bufs;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if ((int)bufs.size() <= dev) bufs.resize(dev + 1, nullptr);
+    if (!bufs[dev]) {
+        void *h = nullptr;
+        if (hipHostMalloc(&h, sizeof(SolveScalars) * 4, hipHostMallocDefault) != hipSuccess) return nullptr;
+        bufs[dev] = static_cast<SolveScalars *>(h);
     }
-    *conv = sc.done && sc.rr <= sc.tol2 * sc.rr0;
-    *iters_out = sc.iter;
+    return slots <= 4 ? bufs[dev] : nullptr;
+}
+
+// the engine of a solve: `batch` for a member of ustd_batch_diag_lpinv
+bool one_workgroup(const ustd_problem *p, int n, bool batch) {
+    if (p->solve_engine == USTD_ENGINE_WORKGROUP) return true;
+    if (p->solve_engine == USTD_ENGINE_MULTI) return false;
+    return batch || n <= kSmallSolveMaxN;
+}
+
+// PCG with reliable updates on the vectors of type T, in one workgroup or by iteration kernels.
+// The iteration kernels are enqueued in chunks of 8, 16, ... 256 iterations, each followed by an
+// asynchronous copy of the scalars into pinned memory; the host stays one chunk ahead and stops
+// enqueueing once a copied `done` is set, so the device never waits for the host.  Leaves x
+// (not yet projected) and the final scalars in *out.
+template <typename T>
+int solve_iterate(Ctx &c, double *x, double tol2, int maxit, SolveScalars *out) {
+    const SolveArgs<T> a = solve_args<T>(c, c.ws, c.L, x);
+    const double delta2 = solve_delta2(c.p);
+    if (one_workgroup(c.p, c.L.n, false)) {
+        HIP_TRY(launch_solve_small<T>(a, c.rows, c.L.G, tol2, delta2, maxit, c.st));
+    } else {
+        SolveScalars *hs = pinned_scalars(2);
+        if (!hs) return fail(USTD_EHIP, "pinned host buffer for the solve scalars");
+        SyncEvent ev[2];
+        if (!ev[0].e || !ev[1].e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
+        HIP_TRY(launch_solve_start<T>(a, tol2, delta2, maxit, c.st));
+        int launched = 0, chunk = 8, k = 0;
+        for (;;) {
+            const int todo = std::min(chunk, maxit - launched);
+            for (int i = 0; i < todo; ++i) HIP_TRY(launch_solve_iteration<T>(a, c.rows, c.L.G, c.st));
+            launched += todo;
+            chunk = std::min(2 * chunk, 256);
+            HIP_TRY(hipMemcpyAsync(&hs[k & 1], a.sc, sizeof(SolveScalars), hipMemcpyDeviceToHost, c.st));
+            HIP_TRY(hipEventRecord(ev[k & 1].e, c.st));
+            if (launched >= maxit) break;
+            if (k > 0) {  // the chunk before the one just queued
+                HIP_TRY(hipEventSynchronize(ev[(k - 1) & 1].e));
+                if (hs[(k - 1) & 1].done) break;
+            }
+            ++k;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(out, a.sc, sizeof(*out), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
     return USTD_OK;
 }
 
-// One CG solve of L d = rhs (or the pivot right-hand side): in one workgroup for small
-// graphs, else by iteration kernels polled in chunks.
-template <typename T>
-int cg_solve(Ctx &c, const CgArgs<T> &a, const double *rhs, int rhs_is_pivot, const double *shift_scale, double tol2,
-             int maxit, int *iters, bool *conv) {
-    if (c.L.n <= kSmallSolveMaxN) {
-        HIP_TRY(launch_cg_small<double, T>(a, c.rows, c.L.G, rhs, rhs_is_pivot, c.pivot, shift_scale, tol2, maxit,
-                                           c.st));
-        CgScalars sc{};
-        HIP_TRY(hipMemcpyAsync(&sc, a.sc, sizeof(sc), hipMemcpyDeviceToHost, c.st));
-        HIP_TRY(hipStreamSynchronize(c.st));
-        *iters = sc.iter;
-        *conv = sc.done && sc.rr <= sc.tol2 * sc.rr0;
-        return USTD_OK;
-    }
-    HIP_TRY(launch_cg_start<double, T>(a, rhs, rhs_is_pivot, c.pivot, shift_scale, tol2, c.st));
-    return cg_iterate<T>(c, a, maxit, iters, conv);
-}
-
-int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
-    const ustd_problem *p = c.p;
-    const int n = c.L.n;
-    const int grid = vec_grid(n);
-    const double bnorm = std::sqrt((double)(n - 1) / (double)n);
-    double tol = p->solve_tol;
-    if (!(tol > 0.0)) tol = std::min(solver_eta(p, c.ecc), 1e-12);
-    const int maxit = p->solve_maxit > 0 ? p->solve_maxit : 20000;
-    double *x64 = x_out;
+// x <- x - mean(x), then the true relative residual ||b - L x|| / ||b|| of the projected x
+int project_and_residual(Ctx &c, double *x, double *relres) {
     double *part = at<double>(c.ws, c.L.off_part) + 3 * kMaxSolveGrid;  // residual partials
     double *sums = c.misc->sums;
-    int total_it = 0, outer = 0;
-    bool conv = false;
-    Timer tm(c.st);
-    if (p->solve_mode == USTD_SOLVE_FP64) {
-        CgArgs<double> a = cg_args<double>(c, x64, at<double>(c.ws, c.L.off_r64), at<double>(c.ws, c.L.off_z64),
-                                           at<double>(c.ws, c.L.off_p64), at<double>(c.ws, c.L.off_q64),
-                                           &c.misc->sc64, c.misc->rr_hist64);
-        USTD_TRY(cg_solve<double>(c, a, nullptr, 1, nullptr, tol * tol, maxit, &total_it, &conv));
-        outer = 1;
-        HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, sums, c.st));
-        HIP_TRY(launch_axpy_project<double>(n, x64, nullptr, nullptr, 0, sums + 2, grid, c.st));
-    } else {
-        double *res = at<double>(c.ws, c.L.off_res64);
-        float *x32 = at<float>(c.ws, c.L.off_x32);
-        CgArgs<float> a = cg_args<float>(c, x32, at<float>(c.ws, c.L.off_r32), at<float>(c.ws, c.L.off_z32),
-                                         at<float>(c.ws, c.L.off_p32), at<float>(c.ws, c.L.off_q32),
-                                         &c.misc->sc32, c.misc->rr_hist32);
-        HIP_TRY(hipMemsetAsync(x64, 0, (size_t)n * 8, c.st));
-        const double inner_tol = 1e-5;
-        double prev = INFINITY;
-        for (outer = 0; outer < 40; ++outer) {
-            HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, res, part, sums, c.st));
-            HIP_TRY(launch_axpy_project<double>(n, x64, nullptr, nullptr, 0, sums + 2, grid, c.st));
-            HIP_TRY(launch_outer_scalars(n, sums, c.misc->shift_scale, c.st));
-            double hs[4];
-            HIP_TRY(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, c.st));
-            HIP_TRY(hipStreamSynchronize(c.st));
-            const double rnorm = std::sqrt(std::max(hs[1], 0.0));
-            if (rnorm <= tol * bnorm) { conv = true; break; }
-            if (outer > 0 && rnorm > 0.5 * prev) break;  // refinement stagnates at FP64 rounding
-            prev = rnorm;
-            if (total_it >= maxit) break;
-            int it = 0;
-            bool ic = false;
-            USTD_TRY(cg_solve<float>(c, a, res, 0, c.misc->shift_scale, inner_tol * inner_tol, maxit - total_it, &it,
-                                     &ic));
-            total_it += it;
-            HIP_TRY(launch_axpy_project<float>(n, x64, x32, c.misc->shift_scale, 2, nullptr, grid, c.st));
-        }
-    }
-    // final residual of the projected solution
-    HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, sums, c.st));
+    HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x, nullptr, part, sums, c.st));
+    HIP_TRY(launch_project(c.L.n, x, sums + 2, vec_grid(c.L.n), c.st));
+    HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x, nullptr, part, sums, c.st));
     double hs[4];
     HIP_TRY(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
-    const double relres = std::sqrt(std::max(hs[1], 0.0)) / bnorm;
-    if (relres <= tol) conv = true;
+    const double bnorm = std::sqrt((double)(c.L.n - 1) / (double)c.L.n);
+    *relres = std::sqrt(std::max(hs[1], 0.0)) / bnorm;
+    return USTD_OK;
+}
+
+// Column u of L^+ into x_out: FP64 PCG, or FP32 PCG with FP64 reliable updates (mixed).
+// Success is judged on the true FP64 residual of the projected solution alone.
+int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
+    const ustd_problem *p = c.p;
+    const double tol = solve_target(p, c.ecc);
+    const int maxit = p->solve_maxit > 0 ? p->solve_maxit : 20000;
+    Timer tm(c.st);
+    SolveScalars sc{};
+    if (p->solve_mode == USTD_SOLVE_FP64) USTD_TRY(solve_iterate<double>(c, x_out, tol * tol, maxit, &sc));
+    else USTD_TRY(solve_iterate<float>(c, x_out, tol * tol, maxit, &sc));
+    double relres = 0.0;
+    USTD_TRY(project_and_residual(c, x_out, &relres));
+    const bool conv = relres <= tol;
     if (rep) {
-        rep->solve_iters += total_it;
-        rep->solve_outer += outer;
+        rep->solve_iters += sc.iter;
+        rep->solve_outer += sc.updates;
         rep->solve_relres = relres;
+        rep->solve_tol = tol;
+        rep->solve_converged = conv ? 1 : 0;
         rep->ms_solve += tm.stop_ms();
     }
-    if (!conv && relres > std::max(tol, 1e-9)) return fail(USTD_ENOTCONV, "solve stopped at relative residual %.3e (target %.3e)", relres, tol);
+    if (!conv) return fail(USTD_ENOTCONV, "solve stopped at relative residual %.3e (target %.3e)", relres, tol);
     return USTD_OK;
 }
 
@@ -905,7 +931,7 @@ struct BatchPlan {
     int nwords_max = 0, slots = 0;
     long long rec_pool = 0, max_tiles = 0;
     long long off_queue = 0, off_rec = 0, off_path = 0, off_steps = 0, off_draws = 0, off_tiles = 0,
-              off_graphs = 0, off_jobs = 0, total = 0;
+              off_graphs = 0, off_jobs = 0, off_jobs32 = 0, total = 0;
 };
 
 int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
@@ -958,7 +984,8 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
     B.off_draws = take(B.max_tiles * 8);
     B.off_tiles = take(B.max_tiles * (long long)sizeof(WilsonTile));
     B.off_graphs = take((long long)count * (long long)sizeof(WilsonGraph));
-    B.off_jobs = take((long long)count * (long long)sizeof(CgSmallJob));
+    B.off_jobs = take((long long)count * (long long)sizeof(SolveJob<double>));
+    B.off_jobs32 = take((long long)count * (long long)sizeof(SolveJob<float>));
     B.total = o;
     return USTD_OK;
 }
@@ -969,45 +996,54 @@ int member(int i, int rc) {
     return fail(rc, "problem %d: %s", i, m.c_str());
 }
 
-// FP64 pivot-column solves of the batch members listed in `idx` (each of at most
-// kSmallSolveMaxN vertices) on `st`: the same one-workgroup CG, projection, final residual
-// and convergence rule as solve_column, with the CG of all of them in one launch per row
-// group size.  Each member's ms_solve is an equal share of the batched solve's time.  A member
-// that does not converge sets *status to USTD_ENOTCONV (its message names it).
+// One-workgroup pivot-column solves of the batch members listed in `idx` on `st`: one launch
+// per precision and row-group size with a workgroup per member (the same kernel body, stopping
+// rule, projection and final residual as a single call with the one-workgroup engine, so the
+// results are bit-identical to it).  Each member's ms_solve is an equal share of the batched
+// solve's time.  A member that does not converge sets *status to USTD_ENOTCONV (its message
+// names it).
 int solve_small_batch(std::vector<Ctx> &cs, const std::vector<int> &idx, const BatchPlan &B, void *d_ws,
                       hipStream_t st, ustd_report *R, int *status) {
-    std::vector<CgSmallJob> jobs;
-    std::vector<int> order;
-    std::vector<double> tols(idx.size());
-    for (int G : {4, 8, 16, 32})
-        for (size_t k = 0; k < idx.size(); ++k) {
-            Ctx &c = cs[idx[k]];
-            if (c.L.G != G) continue;
-            const ustd_problem *p = c.p;
-            double tol = p->solve_tol;
-            if (!(tol > 0.0)) tol = std::min(solver_eta(p, c.ecc), 1e-12);
-            tols[k] = tol;
-            CgSmallJob j{};
-            j.a = cg_args<double>(c, at<double>(c.ws, B.g[idx[k]].off_x64), at<double>(c.ws, c.L.off_r64),
-                                  at<double>(c.ws, c.L.off_z64), at<double>(c.ws, c.L.off_p64),
-                                  at<double>(c.ws, c.L.off_q64), &c.misc->sc64, c.misc->rr_hist64);
-            j.m = c.rows;
-            j.u = c.pivot;
-            j.maxit = p->solve_maxit > 0 ? p->solve_maxit : 20000;
-            j.tol2 = tol * tol;
-            jobs.push_back(j);
-            order.push_back((int)k);
+    std::vector<SolveJob<double>> j64;
+    std::vector<SolveJob<float>> j32;
+    std::vector<std::pair<int, int>> runs64, runs32;  // (row-group size, jobs) in launch order
+    std::vector<double> tols(cs.size(), 0.0);
+    for (int mixed = 0; mixed < 2; ++mixed)
+        for (int G : {4, 8, 16, 32}) {
+            int cnt = 0;
+            for (int i : idx) {
+                Ctx &c = cs[i];
+                const bool mx = c.p->solve_mode == USTD_SOLVE_MIXED;
+                if (c.L.G != G || (int)mx != mixed) continue;
+                const double tol = solve_target(c.p, c.ecc);
+                tols[i] = tol;
+                const int maxit = c.p->solve_maxit > 0 ? c.p->solve_maxit : 20000;
+                double *x = at<double>(c.ws, B.g[i].off_x64);
+                if (mx) j32.push_back(SolveJob<float>{solve_args<float>(c, c.ws, c.L, x), c.rows, tol * tol,
+                                                      solve_delta2(c.p), maxit});
+                else j64.push_back(SolveJob<double>{solve_args<double>(c, c.ws, c.L, x), c.rows, tol * tol,
+                                                    solve_delta2(c.p), maxit});
+                ++cnt;
+            }
+            if (cnt) (mixed ? runs32 : runs64).emplace_back(G, cnt);
         }
-    if (jobs.size() != idx.size()) return fail(USTD_EINVAL, "unexpected row-group size in a batched solve");
-    CgSmallJob *d_jobs = at<CgSmallJob>(d_ws, B.off_jobs);
+    if (j64.size() + j32.size() != idx.size()) return fail(USTD_EINVAL, "unexpected row-group size in a batched solve");
+    SolveJob<double> *d64 = at<SolveJob<double>>(d_ws, B.off_jobs);
+    SolveJob<float> *d32 = at<SolveJob<float>>(d_ws, B.off_jobs32);
     Timer tm(st);
-    HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(CgSmallJob) * jobs.size(), hipMemcpyHostToDevice, st));
-    for (size_t s = 0; s < jobs.size();) {
-        size_t e = s;
-        const int G = cs[idx[order[s]]].L.G;
-        while (e < jobs.size() && cs[idx[order[e]]].L.G == G) ++e;
-        HIP_TRY(launch_cg_small_batch(d_jobs + s, (int)(e - s), G, st));
-        s = e;
+    if (!j64.empty())
+        HIP_TRY(hipMemcpyAsync(d64, j64.data(), sizeof(SolveJob<double>) * j64.size(), hipMemcpyHostToDevice, st));
+    if (!j32.empty())
+        HIP_TRY(hipMemcpyAsync(d32, j32.data(), sizeof(SolveJob<float>) * j32.size(), hipMemcpyHostToDevice, st));
+    int off = 0;
+    for (auto &r : runs64) {
+        HIP_TRY(launch_solve_small_batch<double>(d64 + off, r.second, r.first, st));
+        off += r.second;
+    }
+    off = 0;
+    for (auto &r : runs32) {
+        HIP_TRY(launch_solve_small_batch<float>(d32 + off, r.second, r.first, st));
+        off += r.second;
     }
     for (int i : idx) {
         Ctx &c = cs[i];
@@ -1015,27 +1051,28 @@ int solve_small_batch(std::vector<Ctx> &cs, const std::vector<int> &idx, const B
         double *part = at<double>(c.ws, c.L.off_part) + 3 * kMaxSolveGrid;
         double *sums = c.misc->sums;
         HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, sums, st));
-        HIP_TRY(launch_axpy_project<double>(c.L.n, x64, nullptr, nullptr, 0, sums + 2, vec_grid(c.L.n), st));
+        HIP_TRY(launch_project(c.L.n, x64, sums + 2, vec_grid(c.L.n), st));
         HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, sums, st));
     }
     const double ms = tm.stop_ms();  // synchronises st
-    for (size_t k = 0; k < idx.size(); ++k) {
-        const int i = idx[k];
+    for (int i : idx) {
         Ctx &c = cs[i];
-        CgScalars sc{};
+        SolveScalars sc{};
         double hs[4];
-        HIP_TRY(hipMemcpy(&sc, &c.misc->sc64, sizeof(sc), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&sc, &c.misc->sc, sizeof(sc), hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(hs, c.misc->sums, sizeof(hs), hipMemcpyDeviceToHost));
         const double bnorm = std::sqrt((double)(c.L.n - 1) / (double)c.L.n);
         const double relres = std::sqrt(std::max(hs[1], 0.0)) / bnorm;
-        const bool conv = (sc.done && sc.rr <= sc.tol2 * sc.rr0) || relres <= tols[k];
+        const bool conv = relres <= tols[i];
         R[i].solve_iters += sc.iter;
-        R[i].solve_outer += 1;
+        R[i].solve_outer += sc.updates;
         R[i].solve_relres = relres;
+        R[i].solve_tol = tols[i];
+        R[i].solve_converged = conv ? 1 : 0;
         R[i].ms_solve += ms / (double)idx.size();
-        if (!conv && relres > std::max(tols[k], 1e-9))
+        if (!conv)
             *status = member(i, fail(USTD_ENOTCONV, "solve stopped at relative residual %.3e (target %.3e)", relres,
-                                     tols[k]));
+                                     tols[i]));
     }
     return USTD_OK;
 }
@@ -1097,6 +1134,7 @@ int ustd_flow_counts(const ustd_problem *prob, int64_t tree_begin, int64_t tree_
     if (rep) memset(rep, 0, sizeof(*rep));
     Timer total(c.st);
     USTD_TRY(setup(c, rep));
+    USTD_TRY(check_fixed_point_range(c, tree_count));
     USTD_TRY(run_trees(c, tree_begin, tree_count, (long long *)d_counts, rep));
     if (rep) {
         rep->tau = tree_count;
@@ -1113,6 +1151,12 @@ int ustd_tree_counts(const ustd_problem *prob, const int32_t *d_parents, int64_t
     if (tree_count < 0) return fail(USTD_EINVAL, "negative tree count");
     if ((!d_parents && tree_count > 0) || !d_counts) return fail(USTD_EINVAL, "NULL parents / counts");
     USTD_TRY(setup(c, nullptr));
+    USTD_TRY(check_fixed_point_range(c, tree_count));
+    // Every batch's parent arrays are checked (tree_records_kernel) before Algorithm 2 reads the
+    // records built from them, and the counts go to the workspace first: a parent array that is
+    // not a spanning tree rooted at the pivot returns USTD_EINVAL with d_counts unchanged.
+    long long *acc = at<long long>(c.ws, c.L.off_counts);
+    HIP_TRY(launch_fill_i64(c.L.n, acc, 0, c.st));
     for (long long b0 = 0; b0 < tree_count; b0 += c.L.Kiv) {
         const int cnt = (int)std::min<long long>(c.L.Kiv, tree_count - b0);
         IntervalArgs ia{};
@@ -1127,12 +1171,14 @@ int ustd_tree_counts(const ustd_problem *prob, const int32_t *d_parents, int64_t
         ia.bflag = at<int>(c.ws, c.L.off_bflag);
         ia.err = &c.misc->err_interval;
         HIP_TRY(launch_tree_records(ia, cnt, c.st));
-        USTD_TRY(aggregate_trees(c, cnt, (long long *)d_counts, nullptr));
         int err = 0;
         HIP_TRY(hipMemcpyAsync(&err, &c.misc->err_interval, sizeof(int), hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipStreamSynchronize(c.st));
-        if (err) return fail(USTD_EINVAL, "a parent array is not a spanning tree rooted at the pivot");
+        if (err) return fail(USTD_EINVAL, "parent array of tree %lld..%lld is not a spanning tree rooted at the pivot",
+                             b0, b0 + cnt - 1);
+        USTD_TRY(aggregate_trees(c, cnt, acc, nullptr));
     }
+    HIP_TRY(launch_add_i64(c.L.n, acc, (long long *)d_counts, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
     return USTD_OK;
 }
@@ -1289,12 +1335,12 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
     bool solved = false;
     auto solve_all = [&]() {
         solved = true;
-        // FP64 members of up to kSmallSolveMaxN vertices: one launch per row-group size with a
-        // workgroup per member, so their one-workgroup solves run side by side; then each
-        // member's projection and final residual, one synchronisation and the readbacks
+        // members on the one-workgroup engine (all of them by default): one launch per precision
+        // and row-group size with a workgroup per member, so their solves run side by side; then
+        // each member's projection and final residual, one synchronisation and the readbacks
         std::vector<int> small;
         for (int i = 0; i < count; ++i)
-            if (B.g[i].n <= kSmallSolveMaxN && probs[i].solve_mode == USTD_SOLVE_FP64) small.push_back(i);
+            if (one_workgroup(&probs[i], B.g[i].n, true)) small.push_back(i);
         if (!small.empty()) {
             const int rc = solve_small_batch(cs, small, B, d_ws, side, R, &status);
             if (rc != USTD_OK) {

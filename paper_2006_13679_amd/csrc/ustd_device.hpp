@@ -82,4 +82,18 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return s;
 }
 
+// Block-wide sum of one value per thread in a fixed order (deterministic for a fixed blockDim);
+// `sh` holds at least blockDim.x / 64 values.  Contains two barriers.
+template <typename T>
+__device__ __forceinline__ T block_sum_t(T v, T *sh) {
+    const int l = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    v = wave_sum(v);
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    T s = (T)0;
+    for (int i = 0; i < nw; ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
 }  // namespace ustd

@@ -1558,316 +1558,6 @@ __global__ void extract_parents_kernel(int n, int ntrees, const int2 *__restrict
 }
 
 // ======================================================================================
-// Pivot-column solve: L x = e_u - (1/n) 1, x orthogonal to 1 (Section "Overview", step 1),
-// with conjugate gradients and the diagonal (Jacobi) preconditioner the paper uses.
-// Reductions are deterministic: fixed grid, per-block partials, and the last block to
-// finish sums the partials in index order.
-// ======================================================================================
-template <typename T>
-__device__ __forceinline__ T block_sum_t(T v, T *sh) {
-    const int l = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    v = wave_sum(v);
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    T s = (T)0;
-    for (int i = 0; i < nw; ++i) s += sh[i];
-    __syncthreads();
-    return s;
-}
-
-// y = L p over all rows, degree-balanced; calls emit(v, (L p)_v) once per row from one
-// thread.  Fixed grid and fixed per-row reduction trees: deterministic.  BS = block size.
-// Block blk of nblk takes every nblk-th heavy row and row tile (a whole grid: blockIdx.x of
-// gridDim.x; a workgroup that solves a graph alone: 0 of 1).
-template <typename T, int G, int BS = 256, typename Emit>
-__device__ __forceinline__ void lap_apply_rows(const RowMap &m, const T *__restrict__ p, Emit emit, int blk,
-                                               int nblk) {
-    __shared__ T shr[BS / kWave];
-    const int nh = *m.nheavy;
-    const double *__restrict__ w = m.w;  // uniform: weighted Laplacian when set
-    for (int h = blk; h < nh; h += nblk) {
-        const int v = m.heavy[h];
-        const int lo = m.rp[v], hi = m.rp[v + 1];
-        T acc = (T)0;
-        if (w)
-            for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) acc += (T)w[e] * p[m.col[e]];
-        else
-            for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) acc += p[m.col[e]];
-        acc = block_sum_t<T>(acc, shr);
-        if (threadIdx.x == 0) emit(v, (w ? (T)m.wdeg[v] : (T)(hi - lo)) * p[v] - acc);
-    }
-    constexpr int rows_per_tile = BS / G;
-    const int g = threadIdx.x / G, l = threadIdx.x % G;
-    for (int tile = blk; tile * rows_per_tile < m.n; tile += nblk) {
-        const int v = tile * rows_per_tile + g;
-        const bool ok = v < m.n;
-        const int lo = ok ? m.rp[v] : 0, hi = ok ? m.rp[v + 1] : 0;
-        const bool light = ok && (hi - lo <= m.heavy_thresh);
-        T acc = (T)0;
-        if (light) {
-            if (w)
-                for (int e = lo + l; e < hi; e += G) acc += (T)w[e] * p[m.col[e]];
-            else
-                for (int e = lo + l; e < hi; e += G) acc += p[m.col[e]];
-        }
-#pragma unroll
-        for (int dd = G / 2; dd > 0; dd >>= 1) acc += __shfl_xor(acc, dd, G);
-        if (light && l == 0) emit(v, (w ? (T)m.wdeg[v] : (T)(hi - lo)) * p[v] - acc);
-    }
-}
-
-// Jacobi diagonal: the degree, or the conductance sum of a weighted Laplacian's row
-template <typename T>
-__device__ __forceinline__ T jacobi_diag(const CgArgs<T> &a, int v) {
-    return a.wdeg ? (T)a.wdeg[v] : (T)(a.rp[v + 1] - a.rp[v]);
-}
-
-// Sum of per-block partials, computed redundantly by every consumer block in index order
-// (deterministic; no atomics).  The partials were written by an earlier kernel.
-__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nparts, int stride,
-                                               double *sh) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += part[(long long)i * stride];
-    return block_sum(v, sh);
-}
-
-// Conjugate gradients, one iteration = five kernels:
-//   spmv  : q = L p, partial p.q per block (a large grid)
-//   alpha : one block sums the partials in index order; alpha = rz_i / p.q (or breakdown)
-//   update: x += alpha p; r -= alpha q; z = r / deg; partial r.z, r.r per block
-//   beta  : one block sums them; convergence (r.r <= tol^2 r0.r0) or beta = rz_{i+1} / rz_i
-//   pdir  : p = z + beta p
-// rz is double-buffered by iteration parity.  Once `done` is set (converged or broken
-// down) every later kernel of the solve returns at once.
-template <typename T, int G>
-__global__ __launch_bounds__(256) void cg_spmv_kernel(CgArgs<T> a, RowMap m) {
-    __shared__ double sh[4];
-    if (a.sc->done) return;  // uniform: written by an earlier kernel
-    double acc = 0.0;
-    T *__restrict__ q = a.q;
-    const T *__restrict__ p = a.p;
-    lap_apply_rows<T, G>(
-        m, p,
-        [&](int v, T qv) {
-            q[v] = qv;
-            acc += (double)p[v] * (double)qv;
-        },
-        blockIdx.x, gridDim.x);
-    acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) a.part_pq[blockIdx.x] = acc;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void cg_alpha_kernel(CgArgs<T> a, int it) {
-    __shared__ double sh[4];
-    CgScalars *S = a.sc;
-    if (S->done) return;
-    const double pq = sum_partials(a.part_pq, a.grid_spmv, 1, sh);
-    if (threadIdx.x == 0) {
-        if (pq > 0.0 && pq == pq) S->alpha = S->rz[it & 1] / pq;
-        else S->done = 1;  // breakdown
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void cg_update_kernel(CgArgs<T> a) {
-    __shared__ double sh[4];
-    if (a.sc->done) return;
-    const T al = (T)a.sc->alpha;
-    double rz = 0.0, rr = 0.0;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
-        a.x[v] += al * a.p[v];
-        const T rv = a.r[v] - al * a.q[v];
-        a.r[v] = rv;
-        const T zv = rv / jacobi_diag(a, v);
-        a.z[v] = zv;
-        rz += (double)rv * (double)zv;
-        rr += (double)rv * (double)rv;
-    }
-    rz = block_sum(rz, sh);
-    rr = block_sum(rr, sh);
-    if (threadIdx.x == 0) {
-        a.part_rz[2 * blockIdx.x] = rz;
-        a.part_rz[2 * blockIdx.x + 1] = rr;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void cg_beta_kernel(CgArgs<T> a, int it) {
-    __shared__ double sh[4];
-    CgScalars *S = a.sc;
-    if (S->done) return;
-    const double rzn = sum_partials(a.part_rz, a.grid_vec, 2, sh);
-    const double rr = sum_partials(a.part_rz + 1, a.grid_vec, 2, sh);
-    if (threadIdx.x == 0) {
-        const double rzo = S->rz[it & 1];
-        S->rz[(it + 1) & 1] = rzn;
-        S->rr = rr;
-        S->iter = it + 1;
-        a.rr_hist[it & (kRrHist - 1)] = rr;
-        S->beta = rzo != 0.0 ? rzn / rzo : 0.0;
-        if (!(rr > S->tol2 * S->rr0)) S->done = 1;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void cg_pdir_kernel(CgArgs<T> a) {
-    if (a.sc->done) return;
-    const T be = (T)a.sc->beta;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x)
-        a.p[v] = a.z[v] + be * a.p[v];
-}
-
-// start of a CG solve of L d = rhs: d = 0, r = rhs (optionally shifted to mean zero and
-// scaled), z = r/deg, p = z; partial r.z, r.r per block (cg_start_finish sums them)
-template <typename Tin, typename T>
-__global__ __launch_bounds__(256) void cg_start_kernel(CgArgs<T> a, const Tin *__restrict__ rhs, int rhs_is_pivot,
-                                                      int u, const double *__restrict__ shift_scale) {
-    __shared__ double sh[4];
-    double rz = 0.0, rr = 0.0;
-    const double shift = shift_scale ? shift_scale[0] : 0.0;
-    const double scale = shift_scale ? shift_scale[1] : 1.0;
-    const double inv_n = 1.0 / (double)a.n;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
-        double b;
-        if (rhs_is_pivot) b = (v == u ? 1.0 : 0.0) - inv_n;
-        else b = ((double)rhs[v] - shift) * scale;
-        const T rv = (T)b;
-        const T zv = rv / jacobi_diag(a, v);
-        a.x[v] = (T)0;
-        a.r[v] = rv;
-        a.z[v] = zv;
-        a.p[v] = zv;
-        rz += (double)rv * (double)zv;
-        rr += (double)rv * (double)rv;
-    }
-    rz = block_sum(rz, sh);
-    rr = block_sum(rr, sh);
-    if (threadIdx.x == 0) {
-        a.part_rz[2 * blockIdx.x] = rz;
-        a.part_rz[2 * blockIdx.x + 1] = rr;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void cg_start_finish_kernel(CgArgs<T> a, double tol2) {
-    __shared__ double sh[4];
-    const double rz = sum_partials(a.part_rz, a.grid_vec, 2, sh);
-    const double rr = sum_partials(a.part_rz + 1, a.grid_vec, 2, sh);
-    if (threadIdx.x == 0) {
-        CgScalars *S = a.sc;
-        S->rz[0] = rz;
-        S->rz[1] = 0.0;
-        S->rr = rr;
-        S->rr0 = rr;
-        S->tol2 = tol2;
-        S->iter = 0;
-        S->done = (rr > 0.0) ? 0 : 1;
-        a.rr_hist[kRrHist - 1] = rr;
-    }
-}
-
-// Whole CG solve in one workgroup, for small graphs: the same start, iteration, Jacobi
-// preconditioner and stopping rule as the kernels above (dot products in FP64, vectors in
-// T), with no kernel boundary or host poll between iterations.  Ends with the scalars
-// the multi-kernel path leaves (iter, rr, rr0, tol2, done).
-constexpr int kSmallThreads = 1024;
-
-template <typename Tin, typename T, int G>
-__device__ __forceinline__ void cg_small_body(const CgArgs<T> &a, const RowMap &m, const Tin *__restrict__ rhs,
-                                              int rhs_is_pivot, int u, const double *__restrict__ shift_scale,
-                                              double tol2, int maxit, double *sh) {
-    const int n = a.n, tid = threadIdx.x;
-    const double shift = shift_scale ? shift_scale[0] : 0.0;
-    const double scale = shift_scale ? shift_scale[1] : 1.0;
-    const double inv_n = 1.0 / (double)n;
-    double rz = 0.0, rr = 0.0;
-    for (int v = tid; v < n; v += kSmallThreads) {
-        double b;
-        if (rhs_is_pivot) b = (v == u ? 1.0 : 0.0) - inv_n;
-        else b = ((double)rhs[v] - shift) * scale;
-        const T rv = (T)b;
-        const T zv = rv / jacobi_diag(a, v);
-        a.x[v] = (T)0;
-        a.r[v] = rv;
-        a.z[v] = zv;
-        a.p[v] = zv;
-        rz += (double)rv * (double)zv;
-        rr += (double)rv * (double)rv;
-    }
-    rz = block_sum_t<double>(rz, sh);
-    rr = block_sum_t<double>(rr, sh);  // the barriers also publish p before the first product
-    const double rr0 = rr;
-    int it = 0;
-    bool done = !(rr > 0.0);
-    while (!done && it < maxit) {
-        double pq = 0.0;
-        lap_apply_rows<T, G, kSmallThreads>(
-            m, a.p,
-            [&](int v, T qv) {
-                a.q[v] = qv;
-                pq += (double)a.p[v] * (double)qv;
-            },
-            0, 1);
-        pq = block_sum_t<double>(pq, sh);
-        if (!(pq > 0.0 && pq == pq)) {  // breakdown
-            done = true;
-            break;
-        }
-        const T al = (T)(rz / pq);
-        double rzn = 0.0, rrn = 0.0;
-        for (int v = tid; v < n; v += kSmallThreads) {
-            a.x[v] += al * a.p[v];
-            const T rv = a.r[v] - al * a.q[v];
-            a.r[v] = rv;
-            const T zv = rv / jacobi_diag(a, v);
-            a.z[v] = zv;
-            rzn += (double)rv * (double)zv;
-            rrn += (double)rv * (double)rv;
-        }
-        rzn = block_sum_t<double>(rzn, sh);
-        rrn = block_sum_t<double>(rrn, sh);
-        ++it;
-        rr = rrn;
-        if (!(rrn > tol2 * rr0)) {
-            done = true;
-            break;
-        }
-        const T be = (T)(rz != 0.0 ? rzn / rz : 0.0);
-        rz = rzn;
-        for (int v = tid; v < n; v += kSmallThreads) a.p[v] = a.z[v] + be * a.p[v];
-        __syncthreads();  // p complete before the next product gathers it
-    }
-    if (tid == 0) {
-        CgScalars *S = a.sc;
-        S->rz[0] = rz;
-        S->rz[1] = 0.0;
-        S->rr = rr;
-        S->rr0 = rr0;
-        S->tol2 = tol2;
-        S->iter = it;
-        S->done = done ? 1 : 0;
-    }
-}
-
-template <typename Tin, typename T, int G>
-__global__ __launch_bounds__(kSmallThreads) void cg_small_kernel(CgArgs<T> a, RowMap m, const Tin *__restrict__ rhs,
-                                                                 int rhs_is_pivot, int u,
-                                                                 const double *__restrict__ shift_scale, double tol2,
-                                                                 int maxit) {
-    __shared__ double sh[kSmallThreads / kWave];
-    cg_small_body<Tin, T, G>(a, m, rhs, rhs_is_pivot, u, shift_scale, tol2, maxit, sh);
-}
-
-// Independent small solves side by side: workgroup i runs job i (one graph's pivot column).
-template <int G>
-__global__ __launch_bounds__(kSmallThreads) void cg_small_batch_kernel(const CgSmallJob *__restrict__ jobs) {
-    __shared__ double sh[kSmallThreads / kWave];
-    const CgSmallJob &j = jobs[blockIdx.x];
-    cg_small_body<double, double, G>(j.a, j.m, nullptr, 1, j.u, nullptr, j.tol2, j.maxit, sh);
-}
-
-// ======================================================================================
 // Measures that depend only on diag(L^+) (section on electrical closeness, Eq. elec-farness;
 // Lemma on normalized random-walk betweenness; Kirchhoff index appendix):
 //   tr = sum_v diag[v], farness[v] = n diag[v] + tr, closeness[v] = (n-1) / farness[v],
@@ -1965,71 +1655,6 @@ __global__ __launch_bounds__(256) void edge_fold_kernel(int n, long long nnz, co
     if (l == end || col[l] != a) return;  // asymmetric input: left where it is
     atomicAdd((unsigned long long *)&counts[l], (unsigned long long)c);
     counts[e] = 0;
-}
-
-// FP64 residual of the current x64: res = b - L x with b = e_u - 1/n; per-block partials of
-// [sum res, |res|^2, sum x]; reduce3_kernel sums them into out[0..3)
-template <int G>
-__global__ __launch_bounds__(256) void residual64_kernel(RowMap m, int u, const double *__restrict__ x,
-                                                         double *__restrict__ res, double *__restrict__ part) {
-    __shared__ double sh[4];
-    const double inv_n = 1.0 / (double)m.n;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    lap_apply_rows<double, G>(
-        m, x,
-        [&](int v, double lx) {
-            const double rv = ((v == u ? 1.0 : 0.0) - inv_n) - lx;
-            if (res) res[v] = rv;
-            s0 += rv;
-            s1 += rv * rv;
-            s2 += x[v];
-        },
-        blockIdx.x, gridDim.x);
-    s0 = block_sum(s0, sh);
-    s1 = block_sum(s1, sh);
-    s2 = block_sum(s2, sh);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x * 3] = s0;
-        part[blockIdx.x * 3 + 1] = s1;
-        part[blockIdx.x * 3 + 2] = s2;
-    }
-}
-
-__global__ __launch_bounds__(256) void reduce3_kernel(const double *__restrict__ part, int nparts,
-                                                      double *__restrict__ out) {
-    __shared__ double sh[4];
-    const double a0 = sum_partials(part, nparts, 3, sh);
-    const double a1 = sum_partials(part + 1, nparts, 3, sh);
-    const double a2 = sum_partials(part + 2, nparts, 3, sh);
-    if (threadIdx.x == 0) {
-        out[0] = a0;
-        out[1] = a1;
-        out[2] = a2;
-    }
-}
-
-// x64 += scale * d (FP32 or FP64 correction) and optionally subtract mean_src[0] / n
-template <typename T>
-__global__ __launch_bounds__(256) void axpy_project_kernel(int n, double *__restrict__ x, const T *__restrict__ d,
-                                                           const double *__restrict__ scale_src, int scale_idx,
-                                                           const double *__restrict__ mean_src) {
-    const double sc = scale_src ? scale_src[scale_idx] : 1.0;
-    const double mean = mean_src ? mean_src[0] / (double)n : 0.0;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        double xv = x[v];
-        if (d) xv += sc * (double)d[v];
-        x[v] = xv - mean;
-    }
-}
-
-// [shift, scale] for the next inner solve: shift = mean(res), scale = 1 / ||res - shift||
-__global__ void outer_scalars_kernel(int n, const double *__restrict__ sums, double *__restrict__ ss) {
-    const double mean = sums[0] / (double)n;
-    const double nrm2 = sums[1] - (double)n * mean * mean;
-    const double nrm = nrm2 > 0.0 ? sqrt(nrm2) : 0.0;
-    ss[0] = mean;
-    ss[1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    ss[2] = nrm;
 }
 
 // Final fill (Algorithm 1; Eq. diag-comp): diag[u] = x[u], diag[v] = R[v]/tau - x[u] + 2 x[v]
@@ -2257,14 +1882,6 @@ hipError_t launch_bfs_init(int n, int u, int *dist, int *parB, hipStream_t st) {
     bfs_init_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, u, dist, parB);
     return hipGetLastError();
 }
-#define USTD_DISPATCH_G(G, ...)                            \
-    switch (G) {                                           \
-        case 4: { constexpr int GG = 4; __VA_ARGS__; break; }   \
-        case 8: { constexpr int GG = 8; __VA_ARGS__; break; }   \
-        case 16: { constexpr int GG = 16; __VA_ARGS__; break; } \
-        default: { constexpr int GG = 32; __VA_ARGS__; break; } \
-    }
-
 static inline int row_grid(const RowMap &m, int G) {
     const long long tiles = ((long long)m.n + (256 / G) - 1) / (256 / G);
     return (int)std::min<long long>(std::max<long long>(tiles, 1), 4096);
@@ -2408,73 +2025,20 @@ hipError_t launch_aggregate(const AggregateArgs &a, hipStream_t st) {
     }
     return hipGetLastError();
 }
-int solve_grid(const RowMap &m, int G) {
-    const long long tiles = ((long long)m.n + (256 / G) - 1) / (256 / G);
-    return (int)std::min<long long>(std::max<long long>(tiles, 1), kMaxSolveGrid);
+__global__ void fill_i64_kernel(long long n, long long *__restrict__ a, long long v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
 }
-int vec_grid(int n) { return std::max(1, std::min((n + 255) / 256, kMaxSolveGrid)); }
-
-template <typename Tin, typename T>
-hipError_t launch_cg_small(const CgArgs<T> &a, const RowMap &m, int G, const Tin *rhs, int rhs_is_pivot, int u,
-                           const double *shift_scale, double tol2, int maxit, hipStream_t st) {
-    USTD_DISPATCH_G(G, (cg_small_kernel<Tin, T, GG><<<1, kSmallThreads, 0, st>>>(a, m, rhs, rhs_is_pivot, u, shift_scale,
-                                                                               tol2, maxit)));
+__global__ void add_i64_kernel(long long n, const long long *__restrict__ a, long long *__restrict__ b) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] += a[i];
+}
+hipError_t launch_fill_i64(long long n, long long *a, long long v, hipStream_t st) {
+    if (n > 0) fill_i64_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, a, v);
     return hipGetLastError();
 }
-template hipError_t launch_cg_small<double, double>(const CgArgs<double> &, const RowMap &, int, const double *, int,
-                                                    int, const double *, double, int, hipStream_t);
-template hipError_t launch_cg_small<double, float>(const CgArgs<float> &, const RowMap &, int, const double *, int,
-                                                   int, const double *, double, int, hipStream_t);
-
-hipError_t launch_cg_small_batch(const CgSmallJob *jobs, int count, int G, hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    USTD_DISPATCH_G(G, (cg_small_batch_kernel<GG><<<count, kSmallThreads, 0, st>>>(jobs)));
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, int it, hipStream_t st) {
-    USTD_DISPATCH_G(G, cg_spmv_kernel<T, GG><<<a.grid_spmv, 256, 0, st>>>(a, m));
-    cg_alpha_kernel<T><<<1, 256, 0, st>>>(a, it);
-    cg_update_kernel<T><<<a.grid_vec, 256, 0, st>>>(a);
-    cg_beta_kernel<T><<<1, 256, 0, st>>>(a, it);
-    cg_pdir_kernel<T><<<a.grid_vec, 256, 0, st>>>(a);
-    return hipGetLastError();
-}
-template hipError_t launch_cg_iteration<double>(const CgArgs<double> &, const RowMap &, int, int, hipStream_t);
-template hipError_t launch_cg_iteration<float>(const CgArgs<float> &, const RowMap &, int, int, hipStream_t);
-
-template <typename Tin, typename T>
-hipError_t launch_cg_start(const CgArgs<T> &a, const Tin *rhs, int rhs_is_pivot, int u, const double *shift_scale,
-                           double tol2, hipStream_t st) {
-    cg_start_kernel<Tin, T><<<a.grid_vec, 256, 0, st>>>(a, rhs, rhs_is_pivot, u, shift_scale);
-    cg_start_finish_kernel<T><<<1, 256, 0, st>>>(a, tol2);
-    return hipGetLastError();
-}
-template hipError_t launch_cg_start<double, double>(const CgArgs<double> &, const double *, int, int, const double *,
-                                                    double, hipStream_t);
-template hipError_t launch_cg_start<double, float>(const CgArgs<float> &, const double *, int, int, const double *,
-                                                   double, hipStream_t);
-
-hipError_t launch_residual64(const RowMap &m, int G, int u, const double *x, double *res, double *part, double *out,
-                             hipStream_t st) {
-    const int grid = solve_grid(m, G);
-    USTD_DISPATCH_G(G, residual64_kernel<GG><<<grid, 256, 0, st>>>(m, u, x, res, part));
-    reduce3_kernel<<<1, 256, 0, st>>>(part, grid, out);
-    return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_axpy_project(int n, double *x, const T *d, const double *scale_src, int scale_idx,
-                               const double *mean_src, int grid, hipStream_t st) {
-    axpy_project_kernel<T><<<grid, 256, 0, st>>>(n, x, d, scale_src, scale_idx, mean_src);
-    return hipGetLastError();
-}
-template hipError_t launch_axpy_project<double>(int, double *, const double *, const double *, int, const double *,
-                                                int, hipStream_t);
-template hipError_t launch_axpy_project<float>(int, double *, const float *, const double *, int, const double *,
-                                               int, hipStream_t);
-hipError_t launch_outer_scalars(int n, const double *sums, double *ss, hipStream_t st) {
-    outer_scalars_kernel<<<1, 1, 0, st>>>(n, sums, ss);
+hipError_t launch_add_i64(long long n, const long long *a, long long *b, hipStream_t st) {
+    if (n > 0) add_i64_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, a, b);
     return hipGetLastError();
 }
 hipError_t launch_combine(int n, int u, double den, const long long *counts, const double *x, double *diag,

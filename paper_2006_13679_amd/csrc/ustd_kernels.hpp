@@ -8,6 +8,16 @@
 
 namespace ustd {
 
+// instantiate a launch for the row-group size G (lanes per light row) of a graph
+#define USTD_DISPATCH_G(G, ...)                            \
+    switch (G) {                                           \
+        case 4: { constexpr int GG = 4; __VA_ARGS__; break; }   \
+        case 8: { constexpr int GG = 8; __VA_ARGS__; break; }   \
+        case 16: { constexpr int GG = 16; __VA_ARGS__; break; } \
+        default: { constexpr int GG = 32; __VA_ARGS__; break; } \
+    }
+
+
 // One graph as the sampler sees it (read-only while sampling).
 struct WilsonGraph {
     int n, u, nwords, rob;
@@ -82,7 +92,6 @@ struct EdgeCountArgs {
     long long *counts;          // [nnz], accumulated
 };
 
-constexpr int kRrHist = 64;
 constexpr int kSamplerRobMax = 64;       // reorder-buffer entries of the sampler
 constexpr int kSamplerPathGlobal = 250;  // recorded steps per entry kept in global memory
 constexpr long long kSamplerPathSlot = (long long)kSamplerRobMax * kSamplerPathGlobal;  // ints per block
@@ -100,33 +109,49 @@ struct RowMap {
     const double *wdeg; // [n] conductance sum of each row (with w)
 };
 
-struct CgScalars {
-    double rz[2];    // r.z of the current iteration, double-buffered by iteration parity
-    double rr, rr0, tol2;
+// Scalars of one pivot-column solve on the device: preconditioned CG with reliable updates.
+// The solution x is kept in FP64; the iteration runs on vectors of type T (FP64, or FP32 in
+// the mixed mode) holding the correction xs since the last reliable update and the iterated
+// residual rs.  A reliable update folds xs into x and replaces rs by the true FP64 residual
+// b - L x; it is taken when |rs|^2 drops below delta2 times the largest |r|^2 since the
+// last one, when |rs|^2 reaches the target, or at the iteration cap.  The solve ends at an
+// update whose true residual meets the target (or at the cap, or on stagnation).
+struct SolveScalars {
+    double rz;       // z.r of the iterated residual
     double alpha, beta;
-    int iter, done;  // done: converged or broken down; later iterations are no-ops
+    double rr;       // |rs|^2
+    double rr_max;   // largest |r|^2 since the last reliable update
+    double rr_true;  // |b - L x|^2 at the last reliable update
+    double bb;       // |b|^2
+    double tol2;     // target |b - L x|^2 <= tol2 bb
+    double delta2;
+    int iter, maxit;
+    int done;        // later kernels of the solve are no-ops
+    int upd;         // a reliable update is due in this iteration
+    int updates;     // reliable updates taken
+    int stalls;      // consecutive updates whose true residual fell by less than 2x
+    int broke;       // p.q was not positive (breakdown): the next update ends the solve
 };
 
 template <typename T>
-struct CgArgs {
-    int n;
-    const int *rp, *col;
-    T *x, *r, *z, *p, *q;
-    double *part_pq;        // [grid_spmv] partial p.q
-    double *part_rz;        // [2 * grid_vec] partial r.z, r.r
+struct SolveArgs {
+    int n, u;
+    double *x;                // FP64 solution (the pivot column)
+    T *xs, *rs, *z, *p, *q;   // correction, iterated residual, preconditioned residual, direction, L p
+    double *part;             // per-block partials, 6 * kMaxSolveGrid
     int grid_spmv, grid_vec;
-    CgScalars *sc;
-    double *rr_hist;        // kRrHist
-    const double *wdeg;     // [n] Jacobi diagonal of a weighted Laplacian; null = degrees
+    SolveScalars *sc;
+    const int *rp;            // row pointers (degrees as the Jacobi diagonal)
+    const double *wdeg;       // Jacobi diagonal of a weighted Laplacian; null = degrees
 };
 
-// One FP64 pivot-column solve of a batched one-workgroup launch (graphs up to
-// kSmallSolveMaxN vertices): right-hand side e_u - 1/n.
-struct CgSmallJob {
-    CgArgs<double> a;
+// One pivot-column solve of a batched one-workgroup launch: right-hand side e_u - 1/n.
+template <typename T>
+struct SolveJob {
+    SolveArgs<T> a;
     RowMap m;
-    int u, maxit;
-    double tol2;
+    double tol2, delta2;
+    int maxit;
 };
 
 inline long long interval_scratch_ints(long long n) { return 7 * n + 3; }
@@ -182,23 +207,27 @@ hipError_t launch_setup_small(const RowMap &m, int G, int u, int *dist, int *par
                               int *bflag, int *out, hipStream_t st);
 hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int *parB, int *scratch, int2 *bint,
                               int *bflag, hipStream_t st);
-template <typename T>
-hipError_t launch_cg_iteration(const CgArgs<T> &a, const RowMap &m, int G, int it, hipStream_t st);
-// whole CG solve in one workgroup (small graphs); leaves the same scalars as the iteration kernels
+// Pivot-column solve (SolveScalars): start (x = 0, r = b) and iterations of the multi-kernel
+// engine; the whole solve in one workgroup (one-workgroup engine); many one-workgroup solves in
+// one launch (one workgroup each).
 constexpr int kSmallSolveMaxN = 16384;
-template <typename Tin, typename T>
-hipError_t launch_cg_small(const CgArgs<T> &a, const RowMap &m, int G, const Tin *rhs, int rhs_is_pivot, int u,
-                           const double *shift_scale, double tol2, int maxit, hipStream_t st);
-template <typename Tin, typename T>
-hipError_t launch_cg_start(const CgArgs<T> &a, const Tin *rhs, int rhs_is_pivot, int u, const double *shift_scale,
-                           double tol2, hipStream_t st);
-hipError_t launch_cg_small_batch(const CgSmallJob *jobs, int count, int G, hipStream_t st);
+template <typename T>
+hipError_t launch_solve_start(const SolveArgs<T> &a, double tol2, double delta2, int maxit, hipStream_t st);
+template <typename T>
+hipError_t launch_solve_iteration(const SolveArgs<T> &a, const RowMap &m, int G, hipStream_t st);
+template <typename T>
+hipError_t launch_solve_small(const SolveArgs<T> &a, const RowMap &m, int G, double tol2, double delta2, int maxit,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_solve_small_batch(const SolveJob<T> *jobs, int count, int G, hipStream_t st);
+// res = b - L x (nullable), sums of [res, res^2, x] into out[0..3)
 hipError_t launch_residual64(const RowMap &m, int G, int u, const double *x, double *res, double *part, double *out,
                              hipStream_t st);
-template <typename T>
-hipError_t launch_axpy_project(int n, double *x, const T *d, const double *scale_src, int scale_idx,
-                               const double *mean_src, int grid, hipStream_t st);
-hipError_t launch_outer_scalars(int n, const double *sums, double *ss, hipStream_t st);
+// x -= mean_src[0] / n
+hipError_t launch_project(int n, double *x, const double *mean_src, int grid, hipStream_t st);
+// a[0..n) = v; b[0..n) += a[0..n) (int64)
+hipError_t launch_fill_i64(long long n, long long *a, long long v, hipStream_t st);
+hipError_t launch_add_i64(long long n, const long long *a, long long *b, hipStream_t st);
 hipError_t launch_combine(int n, int u, double den, const long long *counts, const double *x, double *diag,
                           hipStream_t st);
 hipError_t launch_philox_words(uint32_t key0, uint32_t key1, long long t, int s, long long k0, long long count,

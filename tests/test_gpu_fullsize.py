@@ -177,7 +177,8 @@ def test_batch64_members(gpu):
         assert (counts[i].cpu().numpy() == want).all() and reps[i]["walk_steps"] == int(st.sum())
     for i in (grid_big, rmat_big, rmat_small):
         say("batch member vs single call", i, members[i]["graph"].name)
-        d1, c1, r1 = api.diag_lpinv_p(graphs[i], probs[i], ws=api.Workspace(graphs[i].row_ptr.device))
+        d1, c1, r1 = api.diag_lpinv_p(graphs[i], api.with_engine(probs[i], api.ENGINE_WORKGROUP),
+                                      ws=api.Workspace(graphs[i].row_ptr.device))
         assert torch.equal(c1, counts[i]) and torch.equal(d1, diags[i]) and r1["tau"] == reps[i]["tau"]
     g, m = members[grid_big]["graph"], members[grid_big]
     say("batch big grid tree")

@@ -66,7 +66,7 @@ def test_bfs_matches_oracle(gpu, idx):
     G = dev_graph(g)
     p = api.problem(G, pivot=piv, validate=True)
     dist, parB, ecc, pivot = api.bfs(G, p)
-    want_piv = piv if piv >= 0 else gg.max_degree_pivot(g)
+    want_piv = piv if piv >= 0 else oracle.max_degree_pivot(g.row_ptr)
     assert pivot == want_piv
     d0, pb0, e0 = oracle.bfs(g.row_ptr, g.col, want_piv)
     assert ecc == e0
@@ -247,11 +247,13 @@ def _batch_case(members):
 
 
 def _check_batch_against_single(members, oracle_idx=()):
+    """Batch members solve on the one-workgroup engine: the single calls they are compared
+    with use it too."""
     graphs, probs = _batch_case(members)
     diags, counts, reps = api.batch_diag_lpinv(graphs, probs)
     for i, (G, p) in enumerate(zip(graphs, probs)):
         say("batch member", i, members[i][0].name)
-        d1, c1, r1 = api.diag_lpinv_p(G, p, ws=api.Workspace(G.row_ptr.device))
+        d1, c1, r1 = api.diag_lpinv_p(G, api.with_engine(p, api.ENGINE_WORKGROUP), ws=api.Workspace(G.row_ptr.device))
         assert reps[i]["tau"] == r1["tau"] and reps[i]["pivot"] == r1["pivot"] and reps[i]["ecc"] == r1["ecc"]
         assert reps[i]["walk_steps"] == r1["walk_steps"]
         assert torch.equal(counts[i], c1)
@@ -294,11 +296,11 @@ def test_batch_large_member(gpu):
 
 
 def test_batch_fp64_small_solves(gpu):
-    """FP64 members of up to 16384 vertices share batched one-workgroup solve launches (one per
-    row-group size).  Each member's diagonal, counts, solve iterations and residual equal those
-    of the single-problem call, beside a mixed-precision member and one past the size limit;
-    a member stopped by its iteration limit is reported (USTD_ENOTCONV, naming it) while the
-    others are still written."""
+    """Members share batched one-workgroup solve launches (one per precision and row-group
+    size), also a member past 16384 vertices and a mixed-precision one.  Each member's diagonal,
+    counts, solve iterations and residual equal those of the single-problem call on the same
+    engine; a member stopped by its iteration limit is reported (USTD_ENOTCONV, naming it)
+    while the others are still written."""
     members = [
         (gg.grid2d(20), 210, 3, dict(tau_cap=60)),
         (gg.rmat(10, 8, 1), -1, 4, dict(tau_cap=60)),
@@ -313,7 +315,7 @@ def test_batch_fp64_small_solves(gpu):
     say("batch fp64 small solves")
     diags, counts, reps = api.batch_diag_lpinv(graphs, probs)
     for i, (G, p) in enumerate(zip(graphs, probs)):
-        d1, c1, r1 = api.diag_lpinv_p(G, p, ws=api.Workspace(G.row_ptr.device))
+        d1, c1, r1 = api.diag_lpinv_p(G, api.with_engine(p, api.ENGINE_WORKGROUP), ws=api.Workspace(G.row_ptr.device))
         assert torch.equal(counts[i], c1) and torch.equal(diags[i], d1), i
         assert reps[i]["solve_iters"] == r1["solve_iters"] and reps[i]["solve_relres"] == r1["solve_relres"], i
         assert reps[i]["solve_relres"] <= 1e-12
@@ -427,3 +429,80 @@ def test_sweep_pivot_rmat16(gpu):
     say("sweep pivot rmat16")
     _, _, ecc, pivot = api.bfs(G, api.problem(G, pivot=-2))
     assert pivot == oracle.sweep_pivot(g.row_ptr, g.col)[0]
+
+
+# ---------------------------------------------------------------------------------------
+def test_report_eta_and_solve_target(gpu):
+    """The report's eta is the oracle's (Algorithm 1, solver accuracy; pinned by hand-worked
+    values on the CPU), and the default solve target is min(eta, 1e-12)."""
+    for g, u in [(gg.grid2d(32), 495), (gg.rmat(12, 16, 1), -1), (gg.complete(6), 0), (gg.path(40), 3)]:
+        G = dev_graph(g)
+        for eps, kappa in ((0.3, 0.0), (0.9, 0.5)):
+            say("eta", g.name, eps, kappa)
+            p = api.problem(G, pivot=u, eps=eps, kappa=kappa, tau_override=8)
+            _, _, rep = api.diag_lpinv_p(G, p)
+            want = oracle.eta(g.n, g.m, rep["ecc"], eps, kappa)
+            assert rep["eta"] == pytest.approx(want, rel=1e-15)
+            assert rep["solve_tol"] == min(want, 1e-12)
+            assert rep["solve_converged"] == 1 and rep["solve_relres"] <= rep["solve_tol"]
+        p = api.problem(G, pivot=u, solve_tol=1e-9, tau_override=8)
+        _, rep = api.solve_pivot_column(G, p)
+        assert rep["solve_tol"] == 1e-9 and rep["solve_relres"] <= 1e-9
+
+
+@pytest.mark.parametrize("engine", ["workgroup", "multi"])
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_solve_engines_match_oracle(gpu, engine, mode):
+    """Both engines and both precisions reach the FP64 target on the true residual and agree
+    with the oracle's FP64 column to 1e-9 relative, on graphs on either side of 16384 vertices
+    (a 140x140 grid, whose solve takes hundreds of iterations and several reliable updates)."""
+    eng = api.ENGINE_WORKGROUP if engine == "workgroup" else api.ENGINE_MULTI
+    md = api.SOLVE_MIXED if mode == "mixed" else api.SOLVE_FP64
+    for g, u in [(gg.grid2d(140), gg.grid_center_pivot(140)), (gg.rmat(14, 12, 3), 0), (gg.grid2d(20), 0)]:
+        say("engine", engine, mode, g.name)
+        G = dev_graph(g)
+        p = api.problem(G, pivot=u, solve_mode=md, solve_tol=1e-12, solve_engine=eng)
+        x, rep = api.solve_pivot_column(G, p)
+        ref, _, _ = oracle.solve(g.row_ptr, g.col, u, tol=1e-13)
+        err = np.abs(x.cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err <= 1e-9, (g.name, err, rep)
+        assert rep["solve_converged"] == 1 and rep["solve_relres"] <= 1e-12
+        assert rep["solve_outer"] >= 1  # at least the final reliable update
+        if md == api.SOLVE_MIXED:
+            # FP32 iterations drift after a few orders of magnitude: several true-residual updates
+            assert rep["solve_outer"] >= 3
+
+
+def test_tree_counts_rejects_non_trees(gpu):
+    """A parent array that is not a spanning tree rooted at the pivot (a cycle away from the
+    pivot, a parent out of range, a self-parent) returns USTD_EINVAL, and the caller's counts
+    stay as they were, also when valid trees come before the bad one."""
+    g = gg.grid2d(6)
+    u = 14
+    G = dev_graph(g)
+    good, _ = api.sample_trees(G, api.problem(G, pivot=u, trees_per_batch=4), 0, 3)
+    p = api.problem(G, pivot=u, trees_per_batch=1)  # one tree per batch of records
+    good = good.cpu().numpy()
+    cyc = good[0].copy()
+    a, b = 0, 1  # 0 -> 1 -> 0, with both off the pivot's component
+    cyc[a], cyc[b] = b, a
+    oor = good[1].copy()
+    oor[5] = g.n + 3
+    selfp = good[2].copy()
+    selfp[7] = 7
+    for name, bad in (("cycle", cyc), ("out of range", oor), ("self parent", selfp)):
+        for pos in (0, 2):  # first, then after two valid trees have been counted
+            arr = np.stack([good[0], good[1], good[2]])
+            arr[pos] = bad
+            counts = torch.full((g.n,), 7, dtype=torch.int64, device="cuda")
+            say("tree_counts reject", name, pos)
+            with pytest.raises(api.UstdError) as e:
+                api.tree_counts(G, p, torch.from_numpy(arr), counts=counts)
+            assert e.value.status == api.EINVAL
+            assert (counts.cpu().numpy() == 7).all()
+    # and the valid trees still count (accumulated onto the caller's values)
+    counts = torch.full((g.n,), 7, dtype=torch.int64, device="cuda")
+    api.tree_counts(G, p, torch.from_numpy(good), counts=counts)
+    _, parB, _ = oracle.bfs(g.row_ptr, g.col, u)
+    want = 7 + sum(oracle.tree_flow(u, parB, t) for t in good)
+    assert (counts.cpu().numpy() == want).all()

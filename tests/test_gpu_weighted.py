@@ -195,3 +195,21 @@ def test_batch_mixes_weighted_and_unweighted_members(gpu):
         else:
             _, st, want = oracle.trees(g.row_ptr, g.col, u, p.seed, 0, rb["tau"], want_parents=False)
             assert (cb.cpu().numpy() == want).all()
+
+
+def test_weighted_count_calls_limited_to_two_tau(gpu):
+    """The fixed-point shift keeps sums of up to 2 tau trees inside int64: a weighted count call
+    on more trees is refused (USTD_EINVAL) before any counting, with the counts untouched."""
+    name, g, w, u, G = _setup(9)
+    p = api.problem(G, pivot=u, seed=8, tau_override=20)
+    counts = torch.full((g.n,), 3, dtype=torch.int64, device="cuda")
+    say("weighted 2 tau limit", name)
+    api.flow_counts(G, p, 0, 40, counts=counts)  # exactly 2 tau: accepted
+    before = counts.clone()
+    with pytest.raises(api.UstdError) as e:
+        api.flow_counts(G, p, 0, 41, counts=counts)
+    assert e.value.status == api.EINVAL and torch.equal(counts, before)
+    par, _ = api.sample_trees(G, api.problem(G, pivot=u, seed=8, trees_per_batch=41), 0, 41)
+    with pytest.raises(api.UstdError) as e:
+        api.tree_counts(G, p, par, counts=counts)
+    assert e.value.status == api.EINVAL and torch.equal(counts, before)
