@@ -2,14 +2,15 @@
 """Benchmark of the UST estimator of diag(L^+) on one MI355X.
 
 One step = one full ApproxDiagLpinv run (BFS tree and sample size, all tau trees sampled
-with Wilson's algorithm, tree intervals, Algorithm 2 aggregation, the pivot-column solve
-and the combination) on a graph already resident in HBM.  Default workload: R-MAT scale 16
-(edge factor 16, Graph500 a/b/c/d), largest component, unit weights, max-degree pivot,
-eps = 0.3 (tau = 4576), Philox seed 1.
+with Wilson's algorithm, Algorithm 2 aggregation, the pivot-column solve and the
+combination) on a graph already resident in HBM.  Default workload: R-MAT scale 22 (edge
+factor 16, Graph500 a/b/c/d), largest component, unit weights, max-degree pivot, eps = 0.3
+(tau = 9475), Philox seed 1.
 
 Prints one JSON line: trees/s end to end (`value`), walk steps/s of the sampler, the
 end-to-end time, a roofline entry for the dominant kernel and the CPU oracle's rate on a
-bounded sample of the same workload.
+bounded sample of the same workload (one host thread, and all host threads over disjoint
+tree ranges).
 """
 from __future__ import annotations
 
@@ -82,38 +83,76 @@ def load_traffic(kernel: str, workload: str):
     return t
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Host threads for the parallel oracle leg: the CPUs this process may run on, at most
+    OMP_NUM_THREADS when the environment sets it (the GPU machine's CPU share)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
 def cpu_baseline(g, u, tau, seed, budget_s: float, w=None):
-    """The oracle as it stands on a bounded sample: as many trees as fit in `budget_s`
-    (sampling + DFS + Algorithm 2), plus one full FP64 solve; scaled to the full tau.
-    With conductances w, the oracle's weighted walk, aggregation and solve."""
+    """The oracle as it stands on a bounded sample of the workload, scaled to the full tau,
+    plus one full FP64 solve: first single-threaded (as many trees as fit in `budget_s`), then
+    with every host thread taking a contiguous range of further trees (about `budget_s` of work
+    per thread; trees are independent and counts integers, so this is the same computation).
+    With conductances w, the oracle's weighted walk, aggregation and solve (single-threaded)."""
     import oracle
 
     oracle.build()
     t0 = time.perf_counter()
     if w is None:
         x, it, rr = oracle.solve(g.row_ptr, g.col, u, tol=1e-12)
+        _, parB, _ = oracle.bfs(g.row_ptr, g.col, u)
     else:
         x, it, rr = oracle.solve_weighted(g.row_ptr, g.col, w, u, tol=1e-12)
         _, _, rmax = oracle.bpath_resistance(g.row_ptr, g.col, w, u)
         k = oracle.fixed_shift(tau, rmax)
     t_solve = time.perf_counter() - t0
-    done, t_trees, chunk = 0, 0.0, 16
+    done, t_trees, chunk = 0, 0.0, 1
     while t_trees < budget_s and done < tau:
         c = min(chunk, tau - done)
         t0 = time.perf_counter()
         if w is None:
-            oracle.trees(g.row_ptr, g.col, u, seed, done, c, want_parents=False)
+            oracle.trees(g.row_ptr, g.col, u, seed, done, c, want_parents=False, parB=parB)
         else:
             oracle.trees_weighted(g.row_ptr, g.col, w, u, seed, done, c, k, want_parents=False)
         t_trees += time.perf_counter() - t0
         done += c
         chunk = min(chunk * 2, 512)
     per_tree = t_trees / done
-    full = per_tree * tau + t_solve
-    return {"value": tau / full, "unit": "trees/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of %d trees (%.1f s) + one FP64 Jacobi-PCG solve (%.2f s), single-threaded C; "
-                      "value = tau / (per-tree time * tau + solve time)" % (done, tau, t_trees, t_solve),
-            "ms_per_tree": per_tree * 1e3}
+    one = tau / (per_tree * tau + t_solve)
+    out = {"value": one, "unit": "trees/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": "%d of %d trees (%.1f s) + one FP64 Jacobi-PCG solve (%.2f s), single-threaded C; "
+                     "value = tau / (per-tree time * tau + solve time)" % (done, tau, t_trees, t_solve),
+           "ms_per_tree": per_tree * 1e3}
+    th = host_threads()
+    if w is not None or th < 2:
+        return out
+    per_thread = max(1, min(int(budget_s / per_tree), (tau - 1) // th + 1))
+    cnt = min(per_thread * th, tau)
+    t0 = time.perf_counter()
+    oracle.trees_threads(g.row_ptr, g.col, u, seed, 0, cnt, th, parB=parB)
+    t_par = time.perf_counter() - t0
+    allc = tau / (t_par / cnt * tau + t_solve)
+    return {"value": allc, "unit": "trees/s", "cores": th, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": "%d of %d trees over %d host threads, contiguous tree ranges (%.1f s wall) + one FP64 "
+                      "Jacobi-PCG solve (%.2f s, one thread); value = tau / (wall per tree * tau + solve time)"
+                      % (cnt, tau, th, t_par, t_solve),
+            "ms_per_tree": t_par / cnt * 1e3, "single_thread": out}
 
 
 def run_batch(args):
@@ -288,7 +327,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--solve", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--trees-per-batch", type=int, default=0)
     ap.add_argument("--pivot", default="workload", choices=["workload", "sweep"],
@@ -386,12 +425,36 @@ def main():
     phases = {"sample": ms_sample, "aggregate": ms_ag}
     dom = max(phases, key=phases.get)
     kname = {"sample": "wilson", "aggregate": "aggregate"}[dom]
+    # one launch of either kernel per batch of trees: per-launch bytes over the mean launch time
+    launches = max(1, reps[0]["n_batches"])
     achieved = ab[dom] / (phases[dom] * 1e-3) / 1e9
     traffic = load_traffic(kname, cfg["workload"])
     roof = {"bound": "hbm", "kernel": kname + "_kernel", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": (traffic["bytes_per_launch"] if traffic else None),
-            "algorithmic_bytes_per_launch": ab[dom], "launch_ms": round(phases[dom], 4)}
+            "algorithmic_bytes_per_launch": ab[dom] // launches, "launch_ms": round(phases[dom] / launches, 4),
+            "launches": launches}
+    if traffic and traffic.get("measured_ms_per_launch"):
+        roof["traffic_gbs"] = round(traffic["bytes_per_launch"] / (roof["launch_ms"] * 1e-3) / 1e9, 1)
+
+    # the pivot column in both precisions (the same problem otherwise): iterations, time, the
+    # true residual and how far the mixed-precision column and diagonal are from the FP64 ones
+    # at identical counts (Eq. diag-comp: diag[v] - diag'[v] = 2 (x[v] - x'[v]) - (x[u] - x'[u]))
+    cmp = {}
+    xs = {}
+    for name, md in (("fp64", api.SOLVE_FP64), ("mixed", api.SOLVE_MIXED)):
+        q = api.Problem.from_buffer_copy(p)
+        q.solve_mode = md
+        x, r = api.solve_pivot_column(G, q, ws=ws)
+        xs[name] = x.double()
+        cmp[name] = {"ms": round(r["ms_solve"], 3), "iters": r["solve_iters"], "reliable_updates": r["solve_outer"],
+                     "relres": r["solve_relres"], "target": r["solve_tol"]}
+    dx = (xs["mixed"] - xs["fp64"])
+    cmp["mixed_vs_fp64_x_rel_inf"] = float(dx.abs().max() / xs["fp64"].abs().max())
+    dd = 2.0 * dx - dx[u]
+    dd[u] = dx[u]
+    cmp["mixed_vs_fp64_diag_rel_inf"] = float(dd.abs().max() / diag_t.abs().max())
+    cmp["mixed_speedup"] = round(cmp["fp64"]["ms"] / max(cmp["mixed"]["ms"], 1e-9), 3)
 
     out = {
         "metric": "spanning trees/sec + walk steps/sec; end-to-end diag(L†) time at ε=0.3",
@@ -413,6 +476,7 @@ def main():
         "solve_iters": reps[0]["solve_iters"], "solve_relres": reps[0]["solve_relres"],
         "roofline": roof,
         "centralities_ms": round(ms_central, 4),
+        "solve_compare": cmp,
     }
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -168,11 +168,14 @@ def tree_flow(u: int, parB, parent) -> np.ndarray:
 
 
 def trees(row_ptr, col, u: int, seed: int, tree_begin: int, tree_count: int,
-          want_parents: bool = True, want_counts: bool = True):
-    """Trees [tree_begin, tree_begin + tree_count).  Returns (parents or None, steps, counts or None)."""
+          want_parents: bool = True, want_counts: bool = True, parB=None):
+    """Trees [tree_begin, tree_begin + tree_count).  Returns (parents or None, steps, counts or None).
+    parB: the BFS parents of u if already computed (else the BFS runs here)."""
     rp, c = _csr(row_ptr, col)
     n = len(rp) - 1
-    _, parB, _ = bfs(rp, c, u)
+    if parB is None:
+        _, parB, _ = bfs(rp, c, u)
+    parB = np.ascontiguousarray(parB, dtype=np.int32)
     parents = np.zeros((tree_count, n), dtype=np.int32) if want_parents else None
     steps = np.zeros(tree_count, dtype=np.int64)
     counts = np.zeros(n, dtype=np.int64) if want_counts else None
@@ -182,6 +185,33 @@ def trees(row_ptr, col, u: int, seed: int, tree_begin: int, tree_count: int,
     if rc != OK:
         raise RuntimeError("oracle trees failed: %d" % rc)
     return parents, steps, counts
+
+
+def trees_threads(row_ptr, col, u: int, seed: int, tree_begin: int, tree_count: int, threads: int, parB=None):
+    """The trees of `trees` (steps and flow counts, no parents) split into `threads` contiguous
+    ranges, each run by the sequential C code on its own host thread (the foreign call releases
+    the interpreter lock).  Trees are independent and counts are integers, so the result is the
+    same as one sequential call.  Returns (steps, counts)."""
+    import threading
+
+    rp, c = _csr(row_ptr, col)
+    if parB is None:
+        _, parB, _ = bfs(rp, c, u)
+    threads = max(1, min(int(threads), int(tree_count))) if tree_count > 0 else 1
+    bounds = [tree_begin + (tree_count * i) // threads for i in range(threads + 1)]
+    out = [None] * threads
+
+    def run(i):
+        out[i] = trees(rp, c, u, seed, bounds[i], bounds[i + 1] - bounds[i], want_parents=False, parB=parB)
+
+    ts = [threading.Thread(target=run, args=(i,)) for i in range(threads)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    steps = np.concatenate([o[1] for o in out])
+    counts = np.sum([o[2] for o in out], axis=0).astype(np.int64)
+    return steps, counts
 
 
 def solve(row_ptr, col, u: int, tol: float = 1e-12, maxit: int = 100000):

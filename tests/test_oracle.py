@@ -313,6 +313,17 @@ def test_tree_flow_neighbours_and_bound():
         assert c[u] == 0
 
 
+def test_trees_threads_equal_one_sequential_call():
+    """The parallel-over-trees timing leg: trees split over host threads give the steps and
+    counts of one sequential call (also with more threads than trees)."""
+    g = gg.rmat(10, 8, 2)
+    u = oracle.max_degree_pivot(g.row_ptr)
+    _, st, want = oracle.trees(g.row_ptr, g.col, u, 9, 3, 37, want_parents=False)
+    for th in (1, 4, 64):
+        st2, got = oracle.trees_threads(g.row_ptr, g.col, u, 9, 3, 37, th)
+        assert (st2 == st).all() and (got == want).all()
+
+
 def test_trees_counts_additive():
     g = gg.grid2d(6)
     u = gg.grid_center_pivot(6)
