@@ -201,6 +201,24 @@ int ustd_solve_pivot_column(const ustd_problem *prob, void *d_ws, size_t ws_byte
 int ustd_diag_lpinv(const ustd_problem *prob, void *d_ws, size_t ws_bytes, double *d_diag,
                     int64_t *d_counts, ustd_report *rep, void *stream);
 
+/* ustd_diag_lpinv for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same computation,
+ * with no workspace argument.  Its workspace is a 64 MiB array of device memory inside the
+ * library (USTD_NOALLOC_SCRATCH_BYTES), which every GPU the library runs on holds from the
+ * library's load until the process ends; the call allocates nothing (no hipMalloc or
+ * hipFree, no HIP streams or events, no pinned host memory).  It runs every phase on
+ * `stream` (no side stream), solves with the one-workgroup engine, and takes as many trees
+ * per batch as fit the array (prob->trees_per_batch > 0 must fit as given).  A problem whose
+ * workspace does not fit even at one tree per batch returns USTD_ENOMEM.  Counts, walk
+ * steps and the diagonal equal those of ustd_diag_lpinv with solve_engine =
+ * USTD_ENGINE_WORKGROUP; rep->trees_per_batch gives the batch size used; phase times are
+ * not measured (0).  Every call on a GPU shares that GPU's array: calls that overlap in time
+ * on one GPU race and must not be made (the array is re-initialised by each call).
+ * Synchronises `stream`. */
+#define USTD_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ustd_diag_lpinv_noalloc(const ustd_problem *prob, double *d_diag, int64_t *d_counts, ustd_report *rep,
+                            void *stream);
+
 /* Workspace size for ustd_batch_diag_lpinv over probs[0 .. count-1] (host only). */
 int ustd_batch_workspace_bytes(const ustd_problem *probs, int32_t count, size_t *bytes);
 

@@ -61,7 +61,8 @@ class Report(ctypes.Structure):
 
 
 EXPORTS = ["ustd_workspace_bytes", "ustd_bfs", "ustd_sample_trees", "ustd_flow_counts", "ustd_tree_counts",
-           "ustd_solve_pivot_column", "ustd_diag_lpinv", "ustd_batch_workspace_bytes", "ustd_batch_diag_lpinv",
+           "ustd_solve_pivot_column", "ustd_diag_lpinv", "ustd_diag_lpinv_noalloc", "ustd_batch_workspace_bytes",
+           "ustd_batch_diag_lpinv",
            "ustd_edge_counts", "ustd_edge_sample_size", "ustd_centralities",
            "ustd_philox_words", "ustd_status_string", "ustd_last_error"]
 
@@ -84,6 +85,7 @@ def lib() -> ctypes.CDLL:
         L.ustd_tree_counts.argtypes = [PP, P, i64, P, ctypes.c_size_t, P, P]
         L.ustd_solve_pivot_column.argtypes = [PP, P, ctypes.c_size_t, P, PR, P]
         L.ustd_diag_lpinv.argtypes = [PP, P, ctypes.c_size_t, P, P, PR, P]
+        L.ustd_diag_lpinv_noalloc.argtypes = [PP, P, P, PR, P]
         L.ustd_batch_workspace_bytes.argtypes = [PP, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.ustd_batch_diag_lpinv.argtypes = [PP, i32, P, ctypes.c_size_t, P, P, PR, P]
         L.ustd_edge_counts.argtypes = [PP, i64, i64, P, ctypes.c_size_t, P, PR, P]
@@ -262,6 +264,23 @@ def diag_lpinv_p(g: Graph, p: Problem, ws: Workspace | None = None, want_counts:
     out = rep.as_dict()
     out["status"] = rc
     return diag, counts, out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def diag_lpinv_noalloc_p(g: Graph, p: Problem, diag: torch.Tensor, counts: torch.Tensor | None = None,
+                         allow_notconv: bool = False):
+    """ApproxDiagLpinv through the allocation-free entry point (the library's own static device
+    scratch, no workspace): the caller passes the outputs.  Returns the report."""
+    dev = g.row_ptr.device
+    assert diag.dtype == torch.float64 and diag.numel() == g.n and diag.is_contiguous()
+    rep = Report()
+    rc = lib().ustd_diag_lpinv_noalloc(ctypes.byref(p), _ptr(diag), _ptr(counts), ctypes.byref(rep), _stream(dev))
+    _check(rc, (OK, ENOTCONV) if allow_notconv else (OK,))
+    out = rep.as_dict()
+    out["status"] = rc
+    return out
 
 
 def diag_lpinv(row_ptr, col, pivot: int = -1, eps: float = 0.3, seed: int = 1, weight=None, **kw):

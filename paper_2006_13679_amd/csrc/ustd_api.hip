@@ -237,35 +237,55 @@ double solver_eta(const ustd_problem *p, int ecc) {
     return kappa * p->eps / (3.0 * std::sqrt(m * n * std::log(n)) * (2.0 * std::max(ecc, 1)));
 }
 
+// Calls of the allocation-free entry point create no HIP events (and no streams): timers then
+// read 0 and synchronise with the stream instead.
+thread_local bool g_no_events = false;
+struct NoEventsScope {
+    NoEventsScope() { g_no_events = true; }
+    ~NoEventsScope() { g_no_events = false; }
+};
+
 // start/stop events around queued work, read once the stream has been synchronised
 struct SpanTimer {
     hipEvent_t a = nullptr, b = nullptr;
     SpanTimer() {
+        if (g_no_events) return;
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
     }
-    void start(hipStream_t st) { (void)hipEventRecord(a, st); }
-    void stop(hipStream_t st) { (void)hipEventRecord(b, st); }
+    void start(hipStream_t st) {
+        if (a) (void)hipEventRecord(a, st);
+    }
+    void stop(hipStream_t st) {
+        if (b) (void)hipEventRecord(b, st);
+    }
     double ms() const {
         float m = 0.f;
-        (void)hipEventElapsedTime(&m, a, b);
+        if (a && b) (void)hipEventElapsedTime(&m, a, b);
         return (double)m;
     }
     ~SpanTimer() {
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
     }
 };
 
+// elapsed time of the work queued on a stream between construction and stop_ms(), which
+// synchronises the stream
 struct Timer {
     hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
     explicit Timer(hipStream_t s) : st(s) {
+        if (g_no_events) return;
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
         (void)hipEventRecord(a, st);
     }
     double stop_ms() {
+        if (!a || !b) {
+            (void)hipStreamSynchronize(st);
+            return 0.0;
+        }
         (void)hipEventRecord(b, st);
         (void)hipEventSynchronize(b);
         float ms = 0.f;
@@ -273,8 +293,8 @@ struct Timer {
         return (double)ms;
     }
     ~Timer() {
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
     }
 };
 
@@ -301,7 +321,9 @@ int side_stream(hipStream_t *out, int which = 0) {
 // an event without timing, destroyed with its scope
 struct SyncEvent {
     hipEvent_t e = nullptr;
-    SyncEvent() { (void)hipEventCreateWithFlags(&e, hipEventDisableTiming); }
+    SyncEvent() {
+        if (!g_no_events) (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    }
     ~SyncEvent() {
         if (e) (void)hipEventDestroy(e);
     }
@@ -505,6 +527,13 @@ int setup_graph(Ctx &c, ustd_report *rep);
 // on an error the host waits, so nothing is left writing the workspace.
 int setup(Ctx &c, ustd_report *rep) {
     if (!c.L.weighted) return setup_graph(c, rep);
+    if (g_no_events) {  // everything on the caller's stream
+        const ustd_problem *p = c.p;
+        HIP_TRY(launch_row_cumsum(c.L.n, c.L.nnz, c.rp32, p->d_weight, c.L.heavy_thresh, c.rows.heavy, c.rows.nheavy,
+                                  at<double>(c.ws, c.L.off_cw), at<double>(c.ws, c.L.off_wdeg),
+                                  at<int>(c.ws, c.L.off_guide), c.st));
+        return setup_graph(c, rep);
+    }
     hipStream_t side = nullptr;
     USTD_TRY(side_stream(&side));
     SyncEvent fork, join;
@@ -1080,6 +1109,63 @@ int solve_small_batch(std::vector<Ctx> &cs, const std::vector<int> &idx, const B
     return USTD_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// the allocation-free entry point's scratch: a file-scope device array that each GPU holds
+// from the library's load until the process ends.  Host code never uses the array's name
+// as an address: its device address is taken once per device with hipGetSymbolAddress.
+// ---------------------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = USTD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+int static_scratch(void **out) {
+    static std::mutex mu;
+    static std::vector<void *> ptrs;  // per device
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)ptrs.size() <= dev) ptrs.resize(dev + 1, nullptr);
+    if (!ptrs[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(USTD_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        if ((reinterpret_cast<uintptr_t>(ptr) & (kAlign - 1)) != 0)
+            return fail(USTD_EHIP, "static scratch is not 256-byte aligned");
+        ptrs[dev] = ptr;
+    }
+    *out = ptrs[dev];
+    return USTD_OK;
+}
+
+// the problem as the allocation-free entry point runs it: the one-workgroup solve engine and
+// the most trees per batch (at most kMaxTreesPerBatch) whose workspace fits the static scratch
+int fit_static(const ustd_problem *prob, ustd_problem *q, Plan *L) {
+    *q = *prob;
+    q->solve_engine = USTD_ENGINE_WORKGROUP;
+    if (prob->trees_per_batch > 0) {
+        *L = make_plan(q);
+        if ((size_t)L->total > kStaticScratchBytes)
+            return fail(USTD_ENOMEM, "the problem needs %lld bytes of scratch at %d trees per batch; the static "
+                                     "scratch holds %zu", L->total, prob->trees_per_batch, kStaticScratchBytes);
+        return USTD_OK;
+    }
+    q->trees_per_batch = 1;
+    *L = make_plan(q);
+    if ((size_t)L->total > kStaticScratchBytes)
+        return fail(USTD_ENOMEM, "the problem needs %lld bytes of scratch even at one tree per batch; the static "
+                                 "scratch holds %zu", L->total, kStaticScratchBytes);
+    int lo = 1, hi = kMaxTreesPerBatch;  // largest K whose plan fits
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        q->trees_per_batch = mid;
+        if ((size_t)make_plan(q).total <= kStaticScratchBytes) lo = mid;
+        else hi = mid - 1;
+    }
+    q->trees_per_batch = lo;
+    *L = make_plan(q);
+    return USTD_OK;
+}
+
 }  // namespace
 
 // =========================================================================================
@@ -1248,6 +1334,37 @@ int ustd_diag_lpinv(const ustd_problem *prob, void *d_ws, size_t ws_bytes, doubl
         r->ms_combine += tm.stop_ms();
     }
     r->ms_total = total.stop_ms();
+    return src;
+}
+
+int ustd_diag_lpinv_noalloc(const ustd_problem *prob, double *d_diag, int64_t *d_counts, ustd_report *rep,
+                            void *stream) {
+    g_err.clear();
+    USTD_TRY(check_problem(prob));
+    if (!d_diag) return fail(USTD_EINVAL, "d_diag is NULL");
+    ustd_problem q;
+    Plan L;
+    USTD_TRY(fit_static(prob, &q, &L));
+    void *ws = nullptr;
+    USTD_TRY(static_scratch(&ws));
+    NoEventsScope no_events;  // no HIP events or streams are created during this call
+    Ctx c;
+    USTD_TRY(begin_with(c, &q, L, ws, stream));
+    ustd_report local{};
+    ustd_report *r = rep ? rep : &local;
+    memset(r, 0, sizeof(*r));
+    USTD_TRY(setup(c, r));
+    const long long tau = problem_tau(c);
+    r->tau = tau;
+    long long *counts = d_counts ? (long long *)d_counts : at<long long>(c.ws, c.L.off_counts);
+    HIP_TRY(hipMemsetAsync(counts, 0, (size_t)c.L.n * 8, c.st));
+    // everything on the caller's stream: the trees, then the pivot column, then the combination
+    USTD_TRY(run_trees(c, 0, tau, counts, r));
+    double *x = at<double>(c.ws, c.L.off_x64);
+    const int src = solve_column(c, x, r);
+    if (src != USTD_OK && src != USTD_ENOTCONV) return src;
+    HIP_TRY(launch_combine(c.L.n, c.pivot, count_scale(c, tau), counts, x, d_diag, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
     return src;
 }
 
