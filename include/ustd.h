@@ -258,6 +258,21 @@ int ustd_edge_counts(const ustd_problem *prob, int64_t tree_begin, int64_t tree_
  * delta <= 0 selecting 1/n.  Host only. */
 int ustd_edge_sample_size(int64_t n, int64_t m, double eps, double delta, int64_t *q);
 
+/* Edge measures from spanning-edge counts (Kirchhoff index appendix, denominator of the
+ * Sherman-Morrison form of the Kirchhoff edge centrality C^Delta_theta(e)): with
+ * lev(e) = c(e) / q, the fraction of the q sampled trees that contain e (an estimate of the
+ * leverage w(e) r(e), the probability that a tree drawn with probability proportional to its
+ * weight contains e), d_r[e] = lev(e) / w(e) estimates the effective resistance r(e) and
+ * d_denom[e] = 1 - (1 - theta) lev(e) the denominator 1 - (1 - theta) w(e) r(e), both in FP64
+ * in that order of operations.  d_counts is the int64[nnz] output of ustd_edge_counts
+ * (counts at the entries (a, b), a < b); both outputs (double[nnz], nullable) get the edge's
+ * value at both of its entries.  d_row_ptr int64[n+1], d_col int32[nnz] as in ustd_problem,
+ * d_weight nullable (unit weights).  q >= 1; theta in (0, 1).  Enqueued on `stream`; does not
+ * synchronise. */
+int ustd_edge_resistances(int64_t n, int64_t nnz, const int64_t *d_row_ptr, const int32_t *d_col,
+                          const double *d_weight, const int64_t *d_counts, int64_t q, double theta, double *d_r,
+                          double *d_denom, void *stream);
+
 /* Vertex measures that depend only on the diagonal d = diag(L^+) (section on electrical
  * closeness, Eq. elec-farness; Lemma on normalized random-walk betweenness; Kirchhoff
  * index appendix): tr = sum_v d[v]; farness[v] = n d[v] + tr; closeness[v] = (n-1) /

@@ -420,6 +420,25 @@ def edge_counts(row_ptr, col, parents, u: int) -> np.ndarray:
     return counts
 
 
+def edge_resistances(row_ptr, col, counts, q, theta: float, w=None):
+    """Edge measures from spanning-edge counts (Kirchhoff index appendix): lev(e) = c(e) / q, the
+    fraction of the q trees containing e, estimates the leverage w(e) r(e); r(e) = lev / w(e);
+    the denominator of the Sherman-Morrison form of C^Delta_theta(e) is 1 - (1 - theta) w(e) r(e)
+    = 1 - (1 - theta) lev.  counts is per CSR entry, at the entries (a, b) with a < b (as
+    edge_counts returns them; a float array of exact leverages times q is accepted too).
+    Returns (r, denom) per CSR entry, the edge's value at both of its entries."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    cols = c.astype(np.int64)
+    key = rows * n + cols
+    cnt = np.asarray(counts)
+    upper_slot = np.where(rows < cols, np.arange(len(cols)), np.searchsorted(key, cols * n + rows))
+    lev = cnt[upper_slot].astype(np.float64) / float(q)
+    ww = np.ones(len(cols)) if w is None else np.asarray(w, dtype=np.float64)
+    return lev / ww, 1.0 - (1.0 - theta) * lev
+
+
 def sweep_pivot(row_ptr, col, sweeps: int = 10) -> tuple:
     """Pivot of low eccentricity by repeated BFS sweeps (engineering appendix, after Magnien et
     al.'s double sweep): BFS from a first source, then from the vertex farthest from it, and

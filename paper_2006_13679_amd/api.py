@@ -63,7 +63,7 @@ class Report(ctypes.Structure):
 EXPORTS = ["ustd_workspace_bytes", "ustd_bfs", "ustd_sample_trees", "ustd_flow_counts", "ustd_tree_counts",
            "ustd_solve_pivot_column", "ustd_diag_lpinv", "ustd_diag_lpinv_noalloc", "ustd_batch_workspace_bytes",
            "ustd_batch_diag_lpinv",
-           "ustd_edge_counts", "ustd_edge_sample_size", "ustd_centralities",
+           "ustd_edge_counts", "ustd_edge_sample_size", "ustd_edge_resistances", "ustd_centralities",
            "ustd_philox_words", "ustd_status_string", "ustd_last_error"]
 
 _lib = None
@@ -90,6 +90,7 @@ def lib() -> ctypes.CDLL:
         L.ustd_batch_diag_lpinv.argtypes = [PP, i32, P, ctypes.c_size_t, P, P, PR, P]
         L.ustd_edge_counts.argtypes = [PP, i64, i64, P, ctypes.c_size_t, P, PR, P]
         L.ustd_edge_sample_size.argtypes = [i64, i64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(i64)]
+        L.ustd_edge_resistances.argtypes = [i64, i64, P, P, P, P, i64, ctypes.c_double, P, P, P]
         L.ustd_centralities.argtypes = [i64, P, P, P, P, P, P]
         L.ustd_philox_words.argtypes = [u64, i64, i32, i64, i64, P, P]
         for name in EXPORTS[:-2]:
@@ -332,6 +333,19 @@ def edge_sample_size(n: int, m: int, eps: float, delta: float = 0.0) -> int:
     q = ctypes.c_int64(0)
     _check(lib().ustd_edge_sample_size(n, m, eps, delta, ctypes.byref(q)))
     return int(q.value)
+
+
+def edge_resistances(g: Graph, counts: torch.Tensor, q: int, theta: float = 0.5):
+    """Effective resistance and Kirchhoff-edge denominator 1 - (1 - theta) w(e) r(e) of every
+    edge from spanning-edge counts of q trees (ustd_edge_resistances).  Returns (r, denom),
+    float64[nnz] each, the edge's value at both of its CSR entries."""
+    dev = g.row_ptr.device
+    assert counts.dtype == torch.int64 and counts.numel() == g.nnz and counts.is_contiguous()
+    r = torch.empty(g.nnz, dtype=torch.float64, device=dev)
+    den = torch.empty_like(r)
+    _check(lib().ustd_edge_resistances(g.n, g.nnz, _ptr(g.row_ptr), _ptr(g.col), _ptr(g.weight), _ptr(counts), q,
+                                       theta, _ptr(r), _ptr(den), _stream(dev)))
+    return r, den
 
 
 def centralities(diag: torch.Tensor) -> dict:

@@ -1665,6 +1665,21 @@ int ustd_edge_sample_size(int64_t n, int64_t m, double eps, double delta, int64_
     return USTD_OK;
 }
 
+int ustd_edge_resistances(int64_t n, int64_t nnz, const int64_t *d_row_ptr, const int32_t *d_col,
+                          const double *d_weight, const int64_t *d_counts, int64_t q, double theta, double *d_r,
+                          double *d_denom, void *stream) {
+    g_err.clear();
+    if (n < 2 || n >= (1ll << 30) - 1 || nnz < 2 || nnz >= (1ll << 31))
+        return fail(USTD_EINVAL, "n = %lld, nnz = %lld out of range", (long long)n, (long long)nnz);
+    if (!d_row_ptr || !d_col || !d_counts) return fail(USTD_EINVAL, "row_ptr / col / counts is NULL");
+    if (q < 1) return fail(USTD_EINVAL, "q must be >= 1");
+    if (!(theta > 0.0 && theta < 1.0)) return fail(USTD_EINVAL, "theta must lie in (0,1)");
+    HIP_TRY(launch_edge_resistance((int)n, nnz, (const long long *)d_row_ptr, d_col, d_weight,
+                                   (const long long *)d_counts, (double)q, theta, d_r, d_denom,
+                                   (hipStream_t)stream));
+    return USTD_OK;
+}
+
 int ustd_centralities(int64_t n, const double *d_diag, double *d_farness, double *d_closeness, double *d_nrwb,
                       double *d_scalars, void *stream) {
     g_err.clear();

@@ -1657,6 +1657,45 @@ __global__ __launch_bounds__(256) void edge_fold_kernel(int n, long long nnz, co
     counts[e] = 0;
 }
 
+// Edge measures from spanning-edge counts (Kirchhoff index appendix): thread per CSR entry
+// e = (a, b); the count sits at the entry (min, max) of the edge (the mirror entry (b, a) is
+// found by binary search in row b); lev = c / q, r = lev / w(e), denom = 1 - (1 - theta) lev.
+__global__ __launch_bounds__(256) void edge_resistance_kernel(int n, long long nnz, const long long *__restrict__ rp,
+                                                              const int *__restrict__ col,
+                                                              const double *__restrict__ w,
+                                                              const long long *__restrict__ counts, double q,
+                                                              double theta, double *__restrict__ r,
+                                                              double *__restrict__ denom) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int lo = 0, hi = n;  // the row a: the largest a with rp[a] <= e
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rp[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    const int a = lo, b = col[e];
+    long long c = counts[e];
+    if (b < a) {  // the count is at the mirror entry (b, a)
+        long long l = rp[b], h = rp[b + 1];
+        c = 0;
+        while (l < h) {
+            const long long mid = (l + h) >> 1;
+            const int cm = col[mid];
+            if (cm == a) {
+                c = counts[mid];
+                break;
+            }
+            if (cm < a) l = mid + 1;
+            else h = mid;
+        }
+    }
+    // each operation rounded on its own (no fused multiply-add), as the definition reads
+    const double lev = __ddiv_rn((double)c, q);
+    if (r) r[e] = __ddiv_rn(lev, w ? w[e] : 1.0);
+    if (denom) denom[e] = __dsub_rn(1.0, __dmul_rn(__dsub_rn(1.0, theta), lev));
+}
+
 // Final fill (Algorithm 1; Eq. diag-comp): diag[u] = x[u], diag[v] = R[v]/tau - x[u] + 2 x[v]
 // ======================================================================================
 // Weighted graphs (Section "Generalizations").  Set-up only: the running conductance sums
@@ -2039,6 +2078,13 @@ hipError_t launch_fill_i64(long long n, long long *a, long long v, hipStream_t s
 }
 hipError_t launch_add_i64(long long n, const long long *a, long long *b, hipStream_t st) {
     if (n > 0) add_i64_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, a, b);
+    return hipGetLastError();
+}
+hipError_t launch_edge_resistance(int n, long long nnz, const long long *rp, const int *col, const double *w,
+                                  const long long *counts, double q, double theta, double *r, double *denom,
+                                  hipStream_t st) {
+    if (nnz > 0)
+        edge_resistance_kernel<<<blocks_for(nnz, 256), 256, 0, st>>>(n, nnz, rp, col, w, counts, q, theta, r, denom);
     return hipGetLastError();
 }
 hipError_t launch_combine(int n, int u, double den, const long long *counts, const double *x, double *diag,

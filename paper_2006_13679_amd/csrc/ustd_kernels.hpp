@@ -228,6 +228,9 @@ hipError_t launch_project(int n, double *x, const double *mean_src, int grid, hi
 // a[0..n) = v; b[0..n) += a[0..n) (int64)
 hipError_t launch_fill_i64(long long n, long long *a, long long v, hipStream_t st);
 hipError_t launch_add_i64(long long n, const long long *a, long long *b, hipStream_t st);
+hipError_t launch_edge_resistance(int n, long long nnz, const long long *rp, const int *col, const double *w,
+                                  const long long *counts, double q, double theta, double *r, double *denom,
+                                  hipStream_t st);
 hipError_t launch_combine(int n, int u, double den, const long long *counts, const double *x, double *diag,
                           hipStream_t st);
 hipError_t launch_philox_words(uint32_t key0, uint32_t key1, long long t, int s, long long k0, long long count,

@@ -506,3 +506,23 @@ def test_tree_counts_rejects_non_trees(gpu):
     _, parB, _ = oracle.bfs(g.row_ptr, g.col, u)
     want = 7 + sum(oracle.tree_flow(u, parB, t) for t in good)
     assert (counts.cpu().numpy() == want).all()
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_edge_resistances_match_oracle(gpu, weighted):
+    """Effective resistances and Kirchhoff-edge denominators from the GPU's spanning-edge counts
+    equal the oracle's from the same counts, bit for bit (each operation rounded once), at both
+    entries of every edge."""
+    for g, u in [(gg.rmat(11, 12, 2), -1), (gg.grid2d(15), 112)]:
+        w = gg.edge_weights(g, 4, "uniform", 1.0, 4.0) if weighted else None
+        G = api.Graph.from_host(g.row_ptr, g.col, weight=w)
+        uu = u if u >= 0 else oracle.max_degree_pivot(g.row_ptr)
+        q = 200
+        say("edge resistances", g.name, weighted)
+        counts, _ = api.edge_counts(G, api.problem(G, pivot=uu, seed=6, trees_per_batch=64), 0, q)
+        for theta in (0.25, 0.9):
+            r, den = api.edge_resistances(G, counts, q, theta)
+            want_r, want_d = oracle.edge_resistances(g.row_ptr, g.col, counts.cpu().numpy(), q, theta, w=w)
+            assert (r.cpu().numpy() == want_r).all() and (den.cpu().numpy() == want_d).all()
+    with pytest.raises(api.UstdError):
+        api.edge_resistances(G, counts, q, 1.0)

@@ -504,6 +504,43 @@ def test_edge_counts_on_tree_graph_and_sampled_trees():
     assert np.abs(est - R[rows[sel], h.col[sel]]).max() <= 0.05
 
 
+@pytest.mark.parametrize("name", ["K4", "grid3", "pendant_cycle", "K23"])
+def test_edge_resistances_and_kirchhoff_denominator(name):
+    """Over all spanning trees, count / #trees is every edge's effective resistance (Kirchhoff),
+    and with these the denominator 1 - (1 - theta) w(e) r(e) makes the Sherman-Morrison form of
+    the Kirchhoff edge centrality, n (1 - theta) w(e) |L+ b_e|^2 / denom, equal n times the change
+    of tr(L+) when e is down-weighted to theta w(e) (dense pseudoinverses), unit and random
+    weights (exact leverages w(e) r(e) times the tree count standing in for the counts)."""
+    g = TINY[name]()
+    trees = brute.spanning_trees(g, 0)
+    N = len(trees)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    counts = oracle.edge_counts(g.row_ptr, g.col, np.stack(trees), 0)
+    P = brute.pinv(g)
+    r_exact = P[rows, rows] + P[g.col, g.col] - 2 * P[rows, g.col]
+    r, den = oracle.edge_resistances(g.row_ptr, g.col, counts, N, 0.4)
+    np.testing.assert_allclose(r, r_exact, atol=1e-12)
+    np.testing.assert_allclose(den, 1 - 0.6 * r_exact, atol=1e-12)
+    rng = np.random.default_rng(3)
+    for weighted in (False, True):
+        w = gg.edge_weights(g, 5, "uniform", 0.5, 3.0) if weighted else np.ones(len(g.col))
+        L = brute.laplacian_weighted(g, w) if weighted else brute.laplacian(g)
+        Pw = np.linalg.pinv(L)
+        lev = w * (Pw[rows, rows] + Pw[g.col, g.col] - 2 * Pw[rows, g.col])
+        q = 1000
+        for theta in (0.3, 0.8):
+            rr, dd = oracle.edge_resistances(g.row_ptr, g.col, lev * q, q, theta, w=w if weighted else None)
+            for e in rng.choice(np.flatnonzero(rows < g.col), size=3, replace=False):
+                a, b = rows[e], g.col[e]
+                be = np.zeros(g.n)
+                be[a], be[b] = 1.0, -1.0
+                Lt = L - (1 - theta) * w[e] * np.outer(be, be)
+                direct = g.n * (np.trace(np.linalg.pinv(Lt)) - np.trace(Pw))
+                sm = g.n * (1 - theta) * w[e] * np.sum((Pw @ be) ** 2) / dd[e]
+                assert sm == pytest.approx(direct, rel=1e-9), (name, weighted, theta, e)
+                assert rr[e] == pytest.approx(lev[e] / w[e], rel=1e-12)
+
+
 def test_edge_sample_size_worked_example():
     # n = 100, m = 250, eps = 0.5, delta = 1/n: ln(2*250*100) = ln(50000) = 10.8198; 2/0.25 = 8 -> 86.56 -> 87
     assert oracle.edge_sample_size(100, 250, 0.5) == 87
@@ -548,3 +585,24 @@ def test_sweep_pivot_bounds_are_lower_bounds():
             want = np.maximum(want, D[src])
             src = int(np.flatnonzero(D[src] == D[src].max())[0])
         assert (bound == want).all() and piv == int(np.argmin(want))
+
+
+def test_oracle_clean_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The oracle's C code, built with gcc's AddressSanitizer and UndefinedBehaviorSanitizer (host
+    code only), runs every step once on small graphs with a cut vertex: no invalid access, leak or
+    undefined behaviour is reported."""
+    import shutil
+    import subprocess
+
+    if not shutil.which("gcc"):
+        pytest.skip("gcc is not available")
+    src = os.path.join(os.path.dirname(oracle.__file__), "ustd_oracle.c")
+    drv = os.path.join(os.path.dirname(oracle.__file__), "sanitize_driver.c")
+    exe = tmp_path / "orc_san"
+    flags = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g", "-O1"]
+    subprocess.check_call(["gcc", "-std=c11", *flags, src, drv, "-o", str(exe), "-lm"])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    out = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "ok" in out.stdout and "runtime error" not in out.stderr and "ERROR:" not in out.stderr
