@@ -90,6 +90,12 @@ def lib():
         L.ustd_oracle_diag_lpinv_weighted.argtypes = [i64, P, P, P, i32, dbl, dbl, dbl, u64, i64, dbl, i64,
                                                       P, P, P, P, P, P, P]
         L.ustd_oracle_diag_lpinv_weighted.restype = ctypes.c_int
+        L.ustd_oracle_blocks.argtypes = [i64, P, P, P]
+        L.ustd_oracle_blocks.restype = i64
+        L.ustd_oracle_wilson_blocks.argtypes = [i64, P, P, i32, P, i64, P, u64, i64, P]
+        L.ustd_oracle_wilson_blocks.restype = i64
+        L.ustd_oracle_trees_blocks.argtypes = [i64, P, P, i32, P, u64, i64, i64, P, P, P]
+        L.ustd_oracle_trees_blocks.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -212,6 +218,49 @@ def trees_threads(row_ptr, col, u: int, seed: int, tree_begin: int, tree_count: 
     steps = np.concatenate([o[1] for o in out])
     counts = np.sum([o[2] for o in out], axis=0).astype(np.int64)
     return steps, counts
+
+
+def blocks(row_ptr, col):
+    """Biconnected components of the edges (Tarjan): (eblock int32[nnz], the same id at both
+    entries of an edge, and the number of blocks)."""
+    rp, c = _csr(row_ptr, col)
+    eb = np.zeros(len(c), dtype=np.int32)
+    nb = int(lib().ustd_oracle_blocks(len(rp) - 1, _p(rp), _p(c), _p(eb)))
+    if nb < 0:
+        raise RuntimeError("oracle blocks: out of memory")
+    return eb, nb
+
+
+def wilson_blocks(row_ptr, col, u: int, seed: int, t: int):
+    """One UST rooted at u by Wilson's algorithm per biconnected component (the engineering
+    appendix's variant).  Returns (parent int32[n], walk steps)."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    eb, nb = blocks(rp, c)
+    dist, _, _ = bfs(rp, c, u)
+    parent = np.zeros(n, dtype=np.int32)
+    steps = int(lib().ustd_oracle_wilson_blocks(n, _p(rp), _p(c), u, _p(eb), nb, _p(dist), seed, t, _p(parent)))
+    if steps < 0:
+        raise RuntimeError("oracle wilson_blocks: out of memory")
+    return parent, steps
+
+
+def trees_blocks(row_ptr, col, u: int, seed: int, tree_begin: int, tree_count: int,
+                 want_parents: bool = True, want_counts: bool = True):
+    """Trees [tree_begin, +tree_count) of the per-block variant.  Returns (parents or None, steps,
+    counts or None); counts by Algorithm 2 on the joined trees."""
+    rp, c = _csr(row_ptr, col)
+    n = len(rp) - 1
+    _, parB, _ = bfs(rp, c, u)
+    parents = np.zeros((tree_count, n), dtype=np.int32) if want_parents else None
+    steps = np.zeros(tree_count, dtype=np.int64)
+    counts = np.zeros(n, dtype=np.int64) if want_counts else None
+    rc = lib().ustd_oracle_trees_blocks(n, _p(rp), _p(c), u, _p(parB), seed, tree_begin, tree_count,
+                                        _p(parents) if parents is not None else None, _p(steps),
+                                        _p(counts) if counts is not None else None)
+    if rc != OK:
+        raise RuntimeError("oracle trees_blocks failed: %d" % rc)
+    return parents, steps, counts
 
 
 def solve(row_ptr, col, u: int, tol: float = 1e-12, maxit: int = 100000):

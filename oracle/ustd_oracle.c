@@ -325,6 +325,227 @@ int ustd_oracle_trees(int64_t n, const int64_t *rp, const int32_t *col, int32_t 
 }
 
 /* ------------------------------------------------------------------------------------
+ * Wilson's algorithm per biconnected component (engineering appendix, after Hayashi et al.):
+ * compute the biconnected components (blocks) of G, run Wilson's algorithm in each block
+ * with a vertex of maximal degree as its root, and join the block trees into a spanning tree
+ * of G.  Every spanning tree of G is one spanning tree per block and vice versa, so drawing
+ * each block's tree uniformly and independently draws a uniform spanning tree of G.
+ *
+ * Readings (the appendix gives the idea only):
+ *  - a block's root is the vertex of largest degree inside the block (the graph the block's
+ *    walks run on), the smallest ID among equal degrees;
+ *  - inside a block, starts are taken in ascending vertex order and the walk at x moves to
+ *    neighbour floor(w * deg_B(x) / 2^32) of x's ascending adjacency inside the block;
+ *  - a cut vertex starts one walk in each block it is not the root of, so walks are keyed by
+ *    the CSR position e(v, B) of v's first edge inside B (unique per vertex and block) in
+ *    place of the vertex: step k of that walk takes word (k mod 4) of Philox4x32-10 with
+ *    counter (k / 4, e(v, B), tree lo, tree hi), so the blocks' draws are independent;
+ *  - joined rooted at u: each block's tree is re-rooted at the block's vertex closest to u
+ *    (u itself, or the cut vertex through which every path from the block to u passes), and
+ *    every vertex v != u takes its parent from the one block in which it is not that vertex.
+ * ---------------------------------------------------------------------------------- */
+
+/* position of w in the ascending row of v, or -1 */
+static int64_t row_find(const int64_t *rp, const int32_t *col, int32_t v, int32_t w)
+{
+    int64_t lo = rp[v], hi = rp[v + 1];
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (col[mid] == w) return mid;
+        if (col[mid] < w) lo = mid + 1; else hi = mid;
+    }
+    return -1;
+}
+
+/* Blocks of the edges by Tarjan's depth-first search with an edge stack (iterative).  Two
+ * edges share a block iff some simple cycle contains both; an edge on no cycle (a bridge) is a
+ * block of its own.  eblock[e] (per CSR entry, the same at both entries of an edge) gets ids
+ * 0 .. nb-1 in the order the blocks are completed.  Returns nb (-1 if out of memory). */
+int64_t ustd_oracle_blocks(int64_t n, const int64_t *rp, const int32_t *col, int32_t *eblock)
+{
+    int64_t nnz = rp[n];
+    int64_t *disc = malloc(sizeof(int64_t) * n), *low = malloc(sizeof(int64_t) * n);
+    int64_t *cur = malloc(sizeof(int64_t) * n), *pe = malloc(sizeof(int64_t) * n);
+    int32_t *vst = malloc(sizeof(int32_t) * n);
+    int64_t *est = malloc(sizeof(int64_t) * (nnz / 2 + 1));
+    if (!disc || !low || !cur || !pe || !vst || !est) {
+        free(disc); free(low); free(cur); free(pe); free(vst); free(est);
+        return -1;
+    }
+    for (int64_t v = 0; v < n; ++v) disc[v] = -1;
+    for (int64_t e = 0; e < nnz; ++e) eblock[e] = -1;
+    int64_t clock = 0, nb = 0, vtop = 0, etop = 0;
+    for (int32_t r = 0; r < n; ++r) {
+        if (disc[r] >= 0) continue;
+        disc[r] = low[r] = clock++;
+        cur[r] = rp[r];
+        pe[r] = -1;
+        vst[vtop++] = r;
+        while (vtop > 0) {
+            int32_t v = vst[vtop - 1];
+            if (cur[v] < rp[v + 1]) {
+                int64_t e = cur[v]++;
+                int32_t w = col[e];
+                if (disc[w] < 0) {               /* tree edge */
+                    disc[w] = low[w] = clock++;
+                    cur[w] = rp[w];
+                    pe[w] = e;
+                    est[etop++] = e;
+                    vst[vtop++] = w;
+                } else if (disc[w] < disc[v] && (vtop < 2 || w != vst[vtop - 2])) {
+                    /* an edge back to an ancestor other than the tree parent (the vertex below v
+                     * on the stack; the graph is simple) */
+                    est[etop++] = e;
+                    if (disc[w] < low[v]) low[v] = disc[w];
+                }
+            } else {
+                --vtop;
+                if (vtop == 0) break;
+                int32_t p = vst[vtop - 1];
+                if (low[v] < low[p]) low[p] = low[v];
+                if (low[v] >= disc[p]) {         /* p separates v's subtree: one block */
+                    int64_t f;
+                    do {
+                        f = est[--etop];
+                        int64_t lo2 = 0, hi2 = n;  /* the row a of entry f */
+                        while (hi2 - lo2 > 1) {
+                            int64_t mid = (lo2 + hi2) / 2;
+                            if (rp[mid] <= f) lo2 = mid; else hi2 = mid;
+                        }
+                        int32_t a = (int32_t)lo2;
+                        eblock[f] = (int32_t)nb;
+                        eblock[row_find(rp, col, col[f], a)] = (int32_t)nb;
+                    } while (f != pe[v]);
+                    ++nb;
+                }
+            }
+        }
+    }
+    free(disc); free(low); free(cur); free(pe); free(vst); free(est);
+    return nb;
+}
+
+/* One spanning tree by Wilson's algorithm per block (readings above).  eblock and nb from
+ * ustd_oracle_blocks, dist from the BFS of u.  parent[u] = -1.  Returns the walk steps (the
+ * sum over the blocks), -1 if out of memory. */
+int64_t ustd_oracle_wilson_blocks(int64_t n, const int64_t *rp, const int32_t *col, int32_t u,
+                                  const int32_t *eblock, int64_t nb, const int32_t *dist, uint64_t seed,
+                                  int64_t t, int32_t *parent)
+{
+    int64_t nnz = rp[n];
+    /* entries grouped by block, each block's in CSR order (so by row, then neighbour) */
+    int64_t *bstart = calloc((size_t)(nb + 1), sizeof(int64_t));
+    int64_t *ent = malloc(sizeof(int64_t) * (nnz > 0 ? nnz : 1));
+    int64_t *fill = malloc(sizeof(int64_t) * (nb > 0 ? nb : 1));
+    int32_t *loc = malloc(sizeof(int32_t) * n);          /* vertex -> index inside the block */
+    int32_t *vx = malloc(sizeof(int32_t) * n);           /* block vertices, ascending */
+    int64_t *ad0 = malloc(sizeof(int64_t) * n);          /* first of the vertex's entries in ent */
+    int32_t *dg = malloc(sizeof(int32_t) * n);           /* its degree inside the block */
+    int32_t *nxt = malloc(sizeof(int32_t) * n), *bpar = malloc(sizeof(int32_t) * n);
+    uint8_t *in = malloc(n);
+    if (!bstart || !ent || !fill || !loc || !vx || !ad0 || !dg || !nxt || !bpar || !in) {
+        free(bstart); free(ent); free(fill); free(loc); free(vx); free(ad0); free(dg); free(nxt); free(bpar);
+        free(in);
+        return -1;
+    }
+    for (int64_t e = 0; e < nnz; ++e) bstart[eblock[e] + 1]++;
+    for (int64_t b = 0; b < nb; ++b) bstart[b + 1] += bstart[b];
+    for (int64_t b = 0; b < nb; ++b) fill[b] = bstart[b];
+    for (int64_t e = 0; e < nnz; ++e) ent[fill[eblock[e]]++] = e;
+    for (int64_t v = 0; v < n; ++v) { loc[v] = -1; parent[v] = -1; }
+    int64_t steps = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        /* the block's vertices (ascending), their first entries and degrees inside it */
+        int32_t nv = 0;
+        for (int64_t i = bstart[b]; i < bstart[b + 1]; ++i) {
+            int64_t e = ent[i];
+            int64_t lo2 = 0, hi2 = n;               /* the row of entry e */
+            while (hi2 - lo2 > 1) {
+                int64_t mid = (lo2 + hi2) / 2;
+                if (rp[mid] <= e) lo2 = mid; else hi2 = mid;
+            }
+            int32_t v = (int32_t)lo2;
+            if (nv == 0 || vx[nv - 1] != v) {
+                vx[nv] = v;
+                ad0[nv] = i;
+                dg[nv] = 0;
+                loc[v] = nv;
+                ++nv;
+            }
+            dg[nv - 1]++;
+        }
+        /* root: largest degree inside the block, smallest ID among equal ones */
+        int32_t root = 0;
+        for (int32_t i = 1; i < nv; ++i)
+            if (dg[i] > dg[root]) root = i;
+        for (int32_t i = 0; i < nv; ++i) { in[i] = 0; bpar[i] = -1; }
+        in[root] = 1;
+        for (int32_t i = 0; i < nv; ++i) {      /* starts in ascending vertex order */
+            if (in[i]) continue;
+            int32_t key = (int32_t)ent[ad0[i]];   /* e(v, B): v's first edge inside the block */
+            int32_t x = i;
+            int64_t k = 0;
+            while (!in[x]) {
+                uint32_t w = ustd_oracle_walk_word(seed, t, key, k);
+                uint64_t j = ((uint64_t)w * (uint64_t)dg[x]) >> 32;
+                nxt[x] = loc[col[ent[ad0[x] + (int64_t)j]]];
+                x = nxt[x];
+                ++k;
+            }
+            steps += k;
+            for (x = i; !in[x]; x = nxt[x]) {
+                in[x] = 1;
+                bpar[x] = nxt[x];
+            }
+        }
+        /* re-root at the block's vertex closest to u, then each vertex but that one takes its
+         * parent from this block */
+        int32_t c = 0;
+        for (int32_t i = 1; i < nv; ++i)
+            if (dist[vx[i]] < dist[vx[c]]) c = i;
+        int32_t prev = -1, x = c;
+        while (x >= 0) {
+            int32_t up = bpar[x];
+            bpar[x] = prev;
+            prev = x;
+            x = up;
+        }
+        for (int32_t i = 0; i < nv; ++i) {
+            if (i != c) parent[vx[i]] = vx[bpar[i]];
+            loc[vx[i]] = -1;
+        }
+    }
+    parent[u] = -1;
+    free(bstart); free(ent); free(fill); free(loc); free(vx); free(ad0); free(dg); free(nxt); free(bpar); free(in);
+    return steps;
+}
+
+/* Trees tree_begin .. +tree_count-1 of the per-block variant: parents (tree_count x n,
+ * nullable), steps (nullable), flow counts accumulated into counts (nullable; Algorithm 2 on
+ * the joined tree). */
+int ustd_oracle_trees_blocks(int64_t n, const int64_t *rp, const int32_t *col, int32_t u, const int32_t *parB,
+                             uint64_t seed, int64_t tree_begin, int64_t tree_count, int32_t *parents,
+                             int64_t *steps, int64_t *counts)
+{
+    int32_t *eblock = malloc(sizeof(int32_t) * (rp[n] > 0 ? rp[n] : 1));
+    int32_t *dist = malloc(sizeof(int32_t) * n), *pb = malloc(sizeof(int32_t) * n);
+    int32_t *parent = malloc(sizeof(int32_t) * n);
+    if (!eblock || !dist || !pb || !parent) { free(eblock); free(dist); free(pb); free(parent); return ORC_ENOMEM; }
+    int64_t nb = ustd_oracle_blocks(n, rp, col, eblock);
+    ustd_oracle_bfs(n, rp, col, u, dist, pb);
+    int rc = nb < 0 ? ORC_ENOMEM : ORC_OK;
+    for (int64_t i = 0; i < tree_count && rc == ORC_OK; ++i) {
+        int64_t s = ustd_oracle_wilson_blocks(n, rp, col, u, eblock, nb, dist, seed, tree_begin + i, parent);
+        if (s < 0) { rc = ORC_ENOMEM; break; }
+        if (steps) steps[i] = s;
+        if (parents) memcpy(parents + i * n, parent, sizeof(int32_t) * n);
+        if (counts) rc = ustd_oracle_tree_flow(n, u, parB, parent, counts);
+    }
+    free(eblock); free(dist); free(pb); free(parent);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------
  * Pivot column of L^+ (Section "Overview", step 1; Algorithm 1, linear system):
  * solve L x = e_u - (1/n) 1 with x orthogonal to 1, which is column u of L^+.  The
  * paper uses conjugate gradients with a diagonal preconditioner.  Plain FP64 Jacobi-PCG

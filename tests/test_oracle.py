@@ -273,6 +273,126 @@ def test_wilson_edge_marginals_and_expected_steps():
 
 
 # -------------------------------------------------------------------------------------
+# Wilson's algorithm per biconnected component (engineering appendix)
+# -------------------------------------------------------------------------------------
+CUT = {
+    "pendant_cycle": lambda: TINY["pendant_cycle"](),
+    "bowtie": lambda: gg.from_edges(5, [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (4, 2)]),
+    "two_squares_bridge": lambda: gg.from_edges(8, [(0, 1), (1, 2), (2, 3), (3, 0), (3, 4), (4, 5), (5, 6),
+                                                    (6, 7), (7, 4)]),
+    "K4_tail": lambda: gg.from_edges(7, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3), (3, 4), (4, 5), (4, 6)]),
+}
+
+
+def _blocks_by_cycles(g):
+    """Blocks by their definition: two edges share a block iff a simple cycle contains both
+    (enumerated by depth-first search on the tiny graph); an edge on no cycle is alone."""
+    edges = [tuple(e) for e in brute.edges_of(g)]
+    idx = {e: i for i, e in enumerate(edges)}
+    par = list(range(len(edges)))
+
+    def find(x):
+        while par[x] != x:
+            x = par[x]
+        return x
+
+    adj = {v: [int(w) for w in g.col[g.row_ptr[v]:g.row_ptr[v + 1]]] for v in range(g.n)}
+
+    def key(a, b):
+        return idx[(min(a, b), max(a, b))]
+
+    def dfs(start, v, path, seen):
+        for w in adj[v]:
+            if w == start and len(path) >= 3:
+                cyc = [key(path[i], path[i + 1]) for i in range(len(path) - 1)] + [key(v, start)]
+                for e in cyc[1:]:
+                    par[find(e)] = find(cyc[0])
+            elif w not in seen and w > start:
+                seen.add(w)
+                dfs(start, w, path + [w], seen)
+                seen.discard(w)
+
+    for s0 in range(g.n):
+        dfs(s0, s0, [s0], {s0})
+    return [find(i) for i in range(len(edges))], edges
+
+
+@pytest.mark.parametrize("name", list(CUT) + ["K4", "C5", "grid3", "tree", "gnp"])
+def test_blocks_match_cycle_definition(name):
+    g = CUT[name]() if name in CUT else (TINY[name]() if name in TINY else
+                                         gg.random_tree(9, 4) if name == "tree" else gg.random_connected(9, 0.3, 2))
+    eb, nb = oracle.blocks(g.row_ptr, g.col)
+    lab, edges = _blocks_by_cycles(g)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    pos = {(int(a), int(b)): i for i, (a, b) in enumerate(zip(rows, g.col))}
+    got = [int(eb[pos[(a, b)]]) for a, b in edges]
+    assert all(eb[pos[(a, b)]] == eb[pos[(b, a)]] for a, b in edges)  # both entries of an edge
+    # the same partition of the edges
+    pairs_got = {(i, j) for i in range(len(edges)) for j in range(len(edges)) if got[i] == got[j]}
+    pairs_want = {(i, j) for i in range(len(edges)) for j in range(len(edges)) if lab[i] == lab[j]}
+    assert pairs_got == pairs_want
+    assert nb == len(set(lab))
+
+
+@pytest.mark.parametrize("name", list(CUT) + ["K4", "grid3"])
+def test_wilson_blocks_uniform_chisquare(name):
+    """Per-block trees joined at the cut vertices are uniform over the spanning trees of G."""
+    g = CUT[name]() if name in CUT else TINY[name]()
+    for u in (0, g.n - 1):
+        all_trees = brute.spanning_trees(g, u)
+        N = len(all_trees)
+        assert N == brute.matrix_tree_count(g)
+        index = {brute.tree_key(p): i for i, p in enumerate(all_trees)}
+        samples = max(100 * N, 3000)
+        parents, steps, _ = oracle.trees_blocks(g.row_ptr, g.col, u, 13, 0, samples, want_counts=False)
+        counts = np.zeros(N, dtype=np.int64)
+        for p in parents:
+            counts[index[brute.tree_key(p)]] += 1
+        _, pval = stats.chisquare(counts)
+        assert pval > 1e-4, (name, u, pval)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_wilson_blocks_tree_invariants_and_tree_graphs(seed):
+    """Spanning trees rooted at u on sparse random graphs; on a tree graph every block is a bridge,
+    so each walk is one step (n - 1 in all) and the tree is the graph itself."""
+    g = gg.random_connected(60, 0.04, seed)
+    u = oracle.max_degree_pivot(g.row_ptr)
+    parents, steps, _ = oracle.trees_blocks(g.row_ptr, g.col, u, seed, 0, 20, want_counts=False)
+    for p in parents:
+        brute.check_tree(g, p, u)
+    t = gg.random_tree(40, seed)
+    parents, steps, _ = oracle.trees_blocks(t.row_ptr, t.col, 5, seed, 0, 5, want_counts=False)
+    assert (steps == t.n - 1).all()
+    want = brute.rooted_parents(t.n, brute.edges_of(t), 5)
+    assert (parents == want).all()
+
+
+def test_wilson_blocks_expected_steps():
+    """Walks stay inside their block: the expected steps are sum over the blocks B of
+    sum_{v in B} deg_B(v) r(r_B, v), r_B the vertex of largest degree inside B (smallest ID on
+    ties), r the effective resistance of G (equal to that of B between two of its vertices)."""
+    g = CUT["K4_tail"]()
+    g2 = gg.from_edges(9, [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (4, 5), (5, 3), (5, 6), (6, 7), (7, 8), (8, 6),
+                           (1, 7)])
+    for gr, u in ((g, 6), (g2, 4)):
+        T = 8000
+        _, steps, _ = oracle.trees_blocks(gr.row_ptr, gr.col, u, 21, 0, T, want_parents=False, want_counts=False)
+        eb, nb = oracle.blocks(gr.row_ptr, gr.col)
+        P = brute.pinv(gr)
+        rows = np.repeat(np.arange(gr.n), np.diff(gr.row_ptr))
+        expect = 0.0
+        for b in range(nb):
+            sel = eb == b
+            verts = sorted(set(rows[sel].tolist()))
+            degb = {v: int(np.sum(rows[sel] == v)) for v in verts}
+            root = min(verts, key=lambda v: (-degb[v], v))
+            expect += sum(degb[v] * (P[root, root] + P[v, v] - 2 * P[root, v]) for v in verts)
+        se = steps.std() / math.sqrt(T)
+        assert abs(steps.mean() - expect) < 5 * se, (steps.mean(), expect)
+
+
+# -------------------------------------------------------------------------------------
 # Aggregation (Algorithm 2): exact expectation by enumeration, closed cases
 # -------------------------------------------------------------------------------------
 @pytest.mark.parametrize("name", list(TINY))
