@@ -37,7 +37,7 @@ WORKLOADS = {
     "batch64": dict(kind="batch", count=64, tau_cap=4096),
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2006_13679_amd", "csrc", f)
-                  for f in ("ustd_kernels.hip", "ustd_solve.hip", "ustd_kernels.hpp", "ustd_device.hpp")]
+                  for f in ("ustd_kernels.hip", "ustd_solve.hip", "ustd_blocks.hip", "ustd_kernels.hpp", "ustd_device.hpp")]
 
 
 def kernel_source_digest() -> str:

@@ -65,6 +65,21 @@ enum {
                                   device-side done flag */
 };
 
+/* How each tree is sampled.  Both draw uniform spanning trees rooted at the pivot; they consume
+ * the random words differently, so the trees (and counts) of one seed differ between them.
+ *  - PLAIN: Wilson's algorithm on G rooted at u, starts in ascending vertex order, the walk from
+ *    s keyed by (step / 4, s, tree);
+ *  - BLOCKS (engineering appendix, after Hayashi et al.): Wilson's algorithm in each biconnected
+ *    component B of G, rooted at B's vertex of largest degree inside B (smallest ID on ties),
+ *    starts in ascending vertex order, the walk confined to B's edges and keyed by
+ *    (step / 4, e(v, B), tree) with e(v, B) the CSR position of v's first edge inside B; the
+ *    block trees are re-rooted at each block's vertex closest to u and joined.  Weighted
+ *    problems and batches take PLAIN only. */
+enum {
+    USTD_WILSON_PLAIN = 0,
+    USTD_WILSON_BLOCKS = 1
+};
+
 /* One problem instance: the inputs of ApproxDiagLpinv(G, u, eps, delta) (Algorithm 1)
  * plus the solver split kappa and the random seed. */
 typedef struct ustd_problem {
@@ -107,7 +122,7 @@ typedef struct ustd_problem {
      * ustd_batch_diag_lpinv takes weighted and unweighted members together. */
     const double *d_weight;
     int32_t solve_engine;     /* USTD_ENGINE_AUTO, USTD_ENGINE_WORKGROUP or USTD_ENGINE_MULTI (below) */
-    int32_t reserved_;        /* must be 0 */
+    int32_t wilson_variant;   /* USTD_WILSON_PLAIN or USTD_WILSON_BLOCKS (below) */
 } ustd_problem;
 
 /* Filled by the calls that take it (nullable); times from HIP events on `stream`. */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libustd.so")
 OK, EINVAL, EGRAPH, ENOMEM, EHIP, ENOTCONV = 0, 1, 2, 3, 4, 5
 SOLVE_FP64, SOLVE_MIXED = 0, 1
 ENGINE_AUTO, ENGINE_WORKGROUP, ENGINE_MULTI = 0, 1, 2
+WILSON_PLAIN, WILSON_BLOCKS = 0, 1
 
 
 class UstdError(RuntimeError):
@@ -38,7 +39,7 @@ class Problem(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("tau_override", ctypes.c_int64),
         ("solve_tol", ctypes.c_double), ("solve_maxit", ctypes.c_int32),
         ("validate", ctypes.c_int32), ("trees_per_batch", ctypes.c_int32), ("tau_cap", ctypes.c_int32),
-        ("d_weight", ctypes.c_void_p), ("solve_engine", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+        ("d_weight", ctypes.c_void_p), ("solve_engine", ctypes.c_int32), ("wilson_variant", ctypes.c_int32),
     ]
 
 
@@ -144,7 +145,7 @@ class Graph:
 def problem(g: Graph, pivot: int = -1, eps: float = 0.3, seed: int = 1, delta: float = 0.0, kappa: float = 0.0,
             tau_override: int = 0, solve_mode: int = SOLVE_FP64, solve_tol: float = 0.0, solve_maxit: int = 0,
             validate: bool = False, trees_per_batch: int = 0, tau_cap: int = 0,
-            solve_engine: int = ENGINE_AUTO) -> Problem:
+            solve_engine: int = ENGINE_AUTO, wilson_variant: int = WILSON_PLAIN) -> Problem:
     assert g.row_ptr.dtype == torch.int64 and g.col.dtype == torch.int32
     assert g.row_ptr.is_cuda and g.col.is_cuda and g.row_ptr.is_contiguous() and g.col.is_contiguous()
     w = g.weight
@@ -154,7 +155,8 @@ def problem(g: Graph, pivot: int = -1, eps: float = 0.3, seed: int = 1, delta: f
                    solve_mode=solve_mode, eps=eps, delta=delta, kappa=kappa, seed=seed & 0xFFFFFFFFFFFFFFFF,
                    tau_override=tau_override, solve_tol=solve_tol, solve_maxit=solve_maxit,
                    validate=1 if validate else 0, trees_per_batch=trees_per_batch, tau_cap=tau_cap,
-                   d_weight=w.data_ptr() if w is not None else None, solve_engine=solve_engine)
+                   d_weight=w.data_ptr() if w is not None else None, solve_engine=solve_engine,
+                   wilson_variant=wilson_variant)
 
 
 def with_engine(p: Problem, engine: int) -> Problem:

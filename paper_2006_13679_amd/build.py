@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libustd.so")
-SOURCES = ["ustd_kernels.hip", "ustd_solve.hip", "ustd_api.hip"]
+SOURCES = ["ustd_kernels.hip", "ustd_solve.hip", "ustd_blocks.hip", "ustd_api.hip"]
 ARCH = os.environ.get("USTD_OFFLOAD_ARCH", "gfx950")
 
 

@@ -68,6 +68,7 @@ struct Misc {                      // small zero-initialised block at the front 
     unsigned long long best_degree;
     unsigned long long rho_max_bits;  // weighted: the largest B-path resistance, as double bits
     unsigned long long walk_totals[2];  // walk steps and draws of a run of batches
+    int nslots, nroots, ntops, scan_total;  // per-block variant: slots of G*, block roots and tops
     SolveScalars sc;
     double sums[4];
 };
@@ -80,6 +81,14 @@ struct Plan {
     long long off_misc, off_rp32, off_col16, off_dist, off_parB, off_bint, off_bflag, off_vrow, off_edge, off_heavy, off_bcount, off_counts, off_steps,
         off_draws, off_rec, off_path, off_scr, off_part, off_x64, off_r64, off_z64, off_p64, off_q64,
         off_res64, off_x32, off_r32, off_z32, off_p32, off_q32, off_cw, off_guide, off_wdeg, off_wB, off_F;
+    // Wilson per biconnected component: the block-split graph G* (at most 2n slots) and its
+    // sampler layout, decided for the upper bound of slots
+    bool bv, s_lds, s_col16, s_edges;
+    int s_nmax, s_nwords;
+    long long s_rec_stride;
+    long long off_bc_lo, off_bc_hi, off_uf, off_fpar, off_ftop, off_spar, off_stop, off_rkey, off_eblk, off_flag,
+        off_sid, off_svtx, off_skey, off_sblk, off_sdeg, off_rps, off_cur, off_scol, off_scol16, off_sbflag,
+        off_rflag, off_rpos, off_roots, off_tops, off_tiles, off_svrow, off_sedge, off_srec;
     long long total;
 };
 
@@ -102,7 +111,10 @@ int check_problem(const ustd_problem *p) {
         return fail(USTD_EINVAL, "unknown solve_mode %d", p->solve_mode);
     if (p->solve_engine < USTD_ENGINE_AUTO || p->solve_engine > USTD_ENGINE_MULTI)
         return fail(USTD_EINVAL, "unknown solve_engine %d", p->solve_engine);
-    if (p->reserved_ != 0) return fail(USTD_EINVAL, "reserved field must be 0");
+    if (p->wilson_variant != USTD_WILSON_PLAIN && p->wilson_variant != USTD_WILSON_BLOCKS)
+        return fail(USTD_EINVAL, "unknown wilson_variant %d", p->wilson_variant);
+    if (p->wilson_variant == USTD_WILSON_BLOCKS && p->d_weight)
+        return fail(USTD_EINVAL, "the per-block Wilson variant takes unit weights only");
     if (p->trees_per_batch > kMaxTreesPerBatch)
         return fail(USTD_EINVAL, "trees_per_batch %d exceeds %d", p->trees_per_batch, kMaxTreesPerBatch);
     return USTD_OK;
@@ -130,9 +142,19 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true, bool force_edges =
     // can each fill the GPU (kPoolMinTrees trees), they are sampled on two streams, so one
     // batch's tail and its Algorithm 2 overlap the next batch; smaller pools would leave
     // every batch short of the resident sampler slots, so the budget stays one pool.
-    const long long per_tree = L.rec_stride * 8 + 16;
+    L.bv = p->wilson_variant == USTD_WILSON_BLOCKS;
+    if (L.bv) {
+        L.s_nmax = 2 * L.n;
+        L.s_nwords = (L.s_nmax + 31) / 32;
+        L.s_lds = L.s_nwords <= kLdsBitsMaxWords;
+        L.s_col16 = L.s_nmax <= 65536;
+        L.s_edges = !L.s_lds;
+        L.s_rec_stride = align_up((long long)L.s_nmax * 8) / 8;
+        L.edges = false;  // the sampler runs on G*, not on G
+    }
+    const long long per_tree = L.rec_stride * 8 + 16 + (L.bv ? L.s_rec_stride * 8 : 0);
     const long long per_slot = kSamplerPathSlot * 4;
-    L.pools = (with_trees && !L.lds_bits && p->trees_per_batch <= 0 &&
+    L.pools = (with_trees && !L.bv && !L.lds_bits && p->trees_per_batch <= 0 &&
                kDefaultBudget / (per_tree + per_slot) >= 2 * kPoolMinTrees)
                   ? 2
                   : 1;
@@ -187,6 +209,37 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true, bool force_edges =
     L.off_wdeg = take(L.weighted ? n * 8 : 0);
     L.off_wB = take(L.weighted ? n * 8 : 0);
     L.off_F = take(L.weighted ? n * 8 : 0);
+    // the per-block variant: blocks of G, the slots of G* and its CSR, roots and tops, the
+    // sampler's view of G*, and G*'s tree records (the joined trees go to the records above)
+    const long long bn = L.bv ? n : 0, bnnz = L.bv ? (long long)L.nnz : 0, bs = L.bv ? L.s_nmax : 0;
+    L.off_bc_lo = take(bn * 4);
+    L.off_bc_hi = take(bn * 4);
+    L.off_uf = take(bn * 4);
+    L.off_fpar = take(bn * 4);
+    L.off_ftop = take(bn * 4);
+    L.off_spar = take(bn * 4);
+    L.off_stop = take(bn * 4);
+    L.off_rkey = take(bn * 8);
+    L.off_eblk = take(bnnz * 4);
+    L.off_flag = take(bnnz * 4);
+    L.off_sid = take(L.bv ? (bnnz + 1) * 4 : 0);
+    L.off_svtx = take(bs * 4);
+    L.off_skey = take(bs * 4);
+    L.off_sblk = take(bs * 4);
+    L.off_sdeg = take(bs * 4);
+    L.off_rps = take(L.bv ? (bs + 1) * 4 : 0);
+    L.off_cur = take(bs * 4);
+    L.off_scol = take(bnnz * 4);
+    L.off_scol16 = take(L.bv && L.s_col16 ? bnnz * 2 : 0);
+    L.off_sbflag = take(bs * 4);
+    L.off_rflag = take(bs * 4);
+    L.off_rpos = take(L.bv ? (bs + 1) * 4 : 0);
+    L.off_roots = take(bn * 4);
+    L.off_tops = take(bn * 4);
+    L.off_tiles = take(L.bv ? (std::max(bnnz, bs) / 1024 + 2) * 4 : 0);
+    L.off_svrow = take(L.bv && L.s_edges ? bs * 16 : 0);
+    L.off_sedge = take(L.bv && L.s_edges ? bnnz * 16 : 0);
+    L.off_srec = take(L.bv ? (long long)L.pools * L.K * L.s_rec_stride * 8 : 0);
     L.total = o;
     return L;
 }
@@ -341,6 +394,7 @@ struct Ctx {
     double rho_max = 0.0;  // weighted: largest B-path resistance
     long long tau = 0;     // weighted: the problem's tau (fixes the shift)
     int shift = 0;         // weighted: fixed-point shift k of the counts
+    int nslots = 0, nblocks = 0;  // per-block variant: slots of G*, blocks of G
 };
 
 // tau of the problem set up in c
@@ -525,8 +579,13 @@ int setup_graph(Ctx &c, ustd_report *rep);
 // weighted graph the running row sums and the step guide (needed from sampling on) are
 // computed on the side stream meanwhile; the caller's stream waits for them on success, and
 // on an error the host waits, so nothing is left writing the workspace.
+int setup_blocks(Ctx &c);
+
 int setup(Ctx &c, ustd_report *rep) {
-    if (!c.L.weighted) return setup_graph(c, rep);
+    if (!c.L.weighted) {
+        USTD_TRY(setup_graph(c, rep));
+        return c.L.bv ? setup_blocks(c) : USTD_OK;
+    }
     if (g_no_events) {  // everything on the caller's stream
         const ustd_problem *p = c.p;
         HIP_TRY(launch_row_cumsum(c.L.n, c.L.nnz, c.rp32, p->d_weight, c.L.heavy_thresh, c.rows.heavy, c.rows.nheavy,
@@ -626,6 +685,65 @@ int setup_graph(Ctx &c, ustd_report *rep) {
     return USTD_OK;
 }
 
+// The per-block variant's set-up, after B_u: blocks, the slots and CSR of G*, the block roots
+// and tops, and the sampler's view of G*.  Two readbacks (the slot count, then the root and top
+// counts); synchronises the stream.
+int setup_blocks(Ctx &c) {
+    const Plan &L = c.L;
+    const int n = L.n, u = c.pivot;
+    const long long nnz = L.nnz;
+    void *ws = c.ws;
+    hipStream_t st = c.st;
+    int *lo = at<int>(ws, L.off_bc_lo), *hi = at<int>(ws, L.off_bc_hi), *uf = at<int>(ws, L.off_uf);
+    int *fpar = at<int>(ws, L.off_fpar), *ftop = at<int>(ws, L.off_ftop);
+    int *spar = at<int>(ws, L.off_spar), *stop = at<int>(ws, L.off_stop);
+    int *eblk = at<int>(ws, L.off_eblk), *flag = at<int>(ws, L.off_flag), *sid = at<int>(ws, L.off_sid);
+    int *vtx = at<int>(ws, L.off_svtx), *skey = at<int>(ws, L.off_skey), *sblk = at<int>(ws, L.off_sblk);
+    int *sdeg = at<int>(ws, L.off_sdeg), *rps = at<int>(ws, L.off_rps), *cur = at<int>(ws, L.off_cur);
+    int *scol = at<int>(ws, L.off_scol), *rflag = at<int>(ws, L.off_rflag), *rpos = at<int>(ws, L.off_rpos);
+    int *roots = at<int>(ws, L.off_roots), *tops = at<int>(ws, L.off_tops), *tiles = at<int>(ws, L.off_tiles);
+    const int *parB = at<int>(ws, L.off_parB), *dist = at<int>(ws, L.off_dist);
+    const int2 *bint = at<int2>(ws, L.off_bint);
+    HIP_TRY(launch_bc_blocks(c.rows, L.G, u, c.ecc, dist, parB, bint, lo, hi, uf, st));
+    HIP_TRY(launch_fill_i32(n, fpar, INT32_MAX, st));
+    HIP_TRY(launch_fill_i32(n, ftop, INT32_MAX, st));
+    HIP_TRY(launch_bc_entries(n, nnz, u, c.rp32, c.p->d_col, parB, bint, uf, eblk, fpar, ftop, flag, st));
+    HIP_TRY(launch_scan_excl(flag, sid, nnz, tiles, &c.misc->nslots, st));
+    HIP_TRY(launch_fill_i32(L.s_nmax, sdeg, 0, st));
+    HIP_TRY(launch_fill_i32(L.s_nmax, cur, 0, st));
+    HIP_TRY(hipMemsetAsync(at<void>(ws, L.off_rkey), 0, (size_t)n * 8, st));
+    HIP_TRY(launch_bc_slots(n, nnz, u, c.rp32, flag, sid, eblk, uf, vtx, skey, sblk, spar, stop, sdeg, st));
+    int ns = 0;
+    HIP_TRY(hipMemcpyAsync(&ns, &c.misc->nslots, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ns < n || ns > L.s_nmax) return fail(USTD_EHIP, "block split: %d slots for %d vertices", ns, n);
+    HIP_TRY(launch_scan_excl(sdeg, rps, ns, tiles, &c.misc->scan_total, st));
+    HIP_TRY(launch_bc_columns(n, u, c.rp32, c.p->d_col, eblk, uf, spar, stop, rps, cur, scol, st));
+    HIP_TRY(launch_bc_roots(ns, rps, vtx, sblk, at<unsigned long long>(ws, L.off_rkey), rflag, st));
+    HIP_TRY(launch_scan_excl(rflag, rpos, ns, tiles, &c.misc->nroots, st));
+    HIP_TRY(launch_bc_compact(ns, rflag, rpos, roots, st));
+    HIP_TRY(launch_bc_top_flags(ns, sblk, stop, rflag, st));
+    HIP_TRY(launch_scan_excl(rflag, rpos, ns, tiles, &c.misc->ntops, st));
+    HIP_TRY(launch_bc_compact(ns, rflag, rpos, tops, st));
+    // the sampler's view of G*: no B_u flags (no marks), 16-bit columns or edge entries
+    int *sbflag = at<int>(ws, L.off_sbflag);
+    HIP_TRY(launch_fill_i32(ns, sbflag, 0, st));
+    if (L.s_col16) HIP_TRY(launch_col_to_u16(nnz, scol, at<unsigned short>(ws, L.off_scol16), st));
+    if (L.s_edges) {
+        HIP_TRY(launch_vertex_rows(ns, rps, sbflag, at<int4>(ws, L.off_svrow), st));
+        HIP_TRY(launch_edge_rows(nnz, scol, at<int4>(ws, L.off_svrow), at<int4>(ws, L.off_sedge), st));
+    }
+    int cnt[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&cnt[0], &c.misc->nroots, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&cnt[1], &c.misc->ntops, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (cnt[0] != cnt[1] || cnt[0] < 1 || ns != n + cnt[0] - 1)
+        return fail(USTD_EHIP, "block split: %d roots, %d tops, %d slots for %d vertices", cnt[0], cnt[1], ns, n);
+    c.nslots = ns;
+    c.nblocks = cnt[0];
+    return USTD_OK;
+}
+
 WilsonGraph wilson_graph(const Ctx &c) {
     WilsonGraph g{};
     g.n = c.L.n;
@@ -651,9 +769,52 @@ long long *pool_draws(const Ctx &c, int pool) { return at<long long>(c.ws, c.L.o
 
 // trees tree_begin .. +ntrees-1 into the record slots 0 .. ntrees-1 of a pool (ntrees <= K),
 // on stream st
+// the per-block variant: trees on G* (several roots, keyed starts) into G*'s records, then the
+// block trees joined into records of spanning trees of G in the pool's records
+int sample_batch_blocks(Ctx &c, long long tree_begin, int ntrees, long long *steps, long long *draws, int pool,
+                        hipStream_t st) {
+    const Plan &L = c.L;
+    const int ns = c.nslots;
+    WilsonArgs a{};
+    WilsonGraph &g = a.g;
+    g.n = ns;
+    g.u = -1;
+    g.nwords = (ns + 31) / 32;
+    g.rob = std::min(kSamplerRobMax, next_pow2(std::max(ns, 2)));
+    g.rp = at<int>(c.ws, L.off_rps);
+    g.colv = L.s_col16 ? (const void *)at<unsigned short>(c.ws, L.off_scol16) : (const void *)at<int>(c.ws, L.off_scol);
+    g.bflag = at<int>(c.ws, L.off_sbflag);
+    g.vrow = L.s_edges ? at<int4>(c.ws, L.off_svrow) : nullptr;
+    g.edge = L.s_edges ? at<int4>(c.ws, L.off_sedge) : nullptr;
+    g.key0 = (uint32_t)(c.p->seed & 0xFFFFFFFFull);
+    g.key1 = (uint32_t)(c.p->seed >> 32);
+    a.ntiles = ntrees;
+    a.tree_begin = tree_begin;
+    int2 *srec = at<int2>(c.ws, L.off_srec) + (long long)pool * L.K * L.s_rec_stride;
+    a.rec = srec;
+    a.rec_stride = L.s_rec_stride;
+    a.path = at<int>(c.ws, L.off_path) + (long long)pool * L.slots * kSamplerPathSlot;
+    a.queue = &c.misc->queue[pool];
+    a.steps = steps;
+    a.draws = draws;
+    a.roots = at<int>(c.ws, L.off_roots);
+    a.nroots = c.nblocks;
+    a.skey = at<int>(c.ws, L.off_skey);
+    int blocks = std::min(ntrees, L.slots);
+    const int resident = wilson_resident_blocks(L.s_lds, L.s_col16, false, g.nwords, true);
+    if (resident > 0) blocks = std::min(blocks, resident);
+    HIP_TRY(hipMemsetAsync(&c.misc->queue[pool], 0, sizeof(int), st));
+    HIP_TRY(launch_wilson(a, blocks, L.s_lds, L.s_col16, false, g.nwords, st, 0, true));
+    HIP_TRY(launch_bc_join(L.n, c.pivot, ntrees, c.nblocks, ns, at<int>(c.ws, L.off_tops), at<int>(c.ws, L.off_spar),
+                           at<int>(c.ws, L.off_svtx), srec, L.s_rec_stride, pool_rec(c, pool), L.rec_stride,
+                           at<int>(c.ws, L.off_bflag), st));
+    return USTD_OK;
+}
+
 int sample_batch(Ctx &c, long long tree_begin, int ntrees, long long *steps, long long *draws, int pool = 0,
                  hipStream_t st = nullptr) {
     if (!st) st = c.st;
+    if (c.L.bv) return sample_batch_blocks(c, tree_begin, ntrees, steps, draws, pool, st);
     WilsonArgs a{};
     a.g = wilson_graph(c);
     a.ntiles = ntrees;
@@ -976,6 +1137,8 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
             const std::string m = g_err;
             return fail(rc, "problem %d: %s", i, m.c_str());
         }
+        if (probs[i].wilson_variant != USTD_WILSON_PLAIN)
+            return fail(USTD_EINVAL, "problem %d: a batch samples with the plain Wilson variant only", i);
         B.lds_bits = B.lds_bits && make_plan(&probs[i], false).lds_bits;
     }
     // one sampler variant serves every member: without the LDS bitmap all need edge entries

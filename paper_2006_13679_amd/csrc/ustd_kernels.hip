@@ -475,7 +475,7 @@ __device__ void retrace_commit(const TreeState<LDS> &bits, int *recw, const int 
 template <typename CT, bool WT>
 __device__ long long walk_next_wave(const TreeState<true> &bits, int *recw, const int *__restrict__ rp,
                                     const CT *__restrict__ col, const double *__restrict__ cw,
-                                    const int *__restrict__ guide, int s0, int x0, long long k0, uint32_t tlo,
+                                    const int *__restrict__ guide, uint32_t wkey, int x0, long long k0, uint32_t tlo,
                                     uint32_t thi, uint32_t key0, uint32_t key1, uint32_t *wbuf) {
     const int lane = threadIdx.x;
     long long k = k0;  // wave-uniform between word blocks
@@ -486,7 +486,7 @@ __device__ long long walk_next_wave(const TreeState<true> &bits, int *recw, cons
     }
     for (;;) {
         const long long b0 = k >> 2;
-        const uint4 ph = philox4x32_10(make_uint4((uint32_t)(b0 + lane), (uint32_t)s0, tlo, thi), key0, key1);
+        const uint4 ph = philox4x32_10(make_uint4((uint32_t)(b0 + lane), wkey, tlo, thi), key0, key1);
         wbuf[4 * lane] = ph.x;
         wbuf[4 * lane + 1] = ph.y;
         wbuf[4 * lane + 2] = ph.z;
@@ -528,15 +528,15 @@ template <bool LDS, typename CT, bool WT>
 __device__ long long rewalk_commit(const TreeState<LDS> &bits, int *recw, const int *__restrict__ rp,
                                    const CT *__restrict__ col, const int4 *__restrict__ edge,
                                    const int4 *__restrict__ vrow, const double *__restrict__ cw,
-                                   const int *__restrict__ guide, const int *__restrict__ bflag, int s0, int x0,
-                                   long long k0, uint32_t tlo, uint32_t thi, uint32_t key0, uint32_t key1) {
+                                   const int *__restrict__ guide, const int *__restrict__ bflag, int s0, uint32_t wkey,
+                                   int x0, long long k0, uint32_t tlo, uint32_t thi, uint32_t key0, uint32_t key1) {
     int xw = x0;
     long long k = k0;
-    uint4 ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
+    uint4 ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), wkey, tlo, thi), key0, key1);
     if constexpr (LDS) {
         int r0 = rp[x0], r1 = rp[x0 + 1];
         for (;;) {
-            if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
+            if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), wkey, tlo, thi), key0, key1);
             const int q = (int)(k & 3);
             const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
             const int y = (int)col[r0 + step_index<WT>(w, r0, r1, cw, guide)];
@@ -561,7 +561,7 @@ __device__ long long rewalk_commit(const TreeState<LDS> &bits, int *recw, const 
     for (;;) {
         const int y = e.x;
         ++k;
-        if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s0, tlo, thi), key0, key1);
+        if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), wkey, tlo, thi), key0, key1);
         const int q = (int)(k & 3);
         const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
         const int4 en = edge[e.y + step_index<WT>(w, e.y, e.z, cw, guide)];  // step k from y
@@ -582,7 +582,7 @@ __device__ __forceinline__ T sel4(int c, T a0, T a1, T a2, T a3) {
 
 }  // namespace
 
-template <bool LDS, typename CT, bool WT, bool GL = false>
+template <bool LDS, typename CT, bool WT, bool GL = false, bool BV = false>
 __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     // Reorder buffer.  Vertex IDs take the column type (16 bits when n <= 65536), so that
     // with the tree bitmap a block of R-MAT scale 16 fits 18 to a CU.  A recorded step
@@ -674,7 +674,13 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     }
     for (int i = lane; i < 2 * kHashSlots; i += kWave) htab[i] = kWave;
     wave_sync();
-    if (lane == 0) {
+    if constexpr (BV) {  // several roots (one per block of the block-split graph)
+        for (int i = lane; i < a.nroots; i += kWave) {
+            const int r = a.roots[i];
+            bits.set(r);
+            rec[r] = make_int2(-1, r);
+        }
+    } else if (lane == 0) {
         bits.set(u);
         rec[u] = make_int2(-1, u);
     }
@@ -682,7 +688,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
 
     int head = 0, tail = 0, cursor = 0;  // wave-uniform
     int mode = 0;                        // 0 idle, 1 speculative walk
-    int my_e = 0, x = 0, s = 0, k = 0, r0 = 0, r1 = 0, fx = 0, pbits = 0;
+    int my_e = 0, x = 0, s = 0, sk = 0, k = 0, r0 = 0, r1 = 0, fx = 0, pbits = 0;
     uint4 ph = make_uint4(0, 0, 0, 0);
     long long steps = 0, draws = 0;
 
@@ -730,6 +736,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             if (mode == 0 && rank < got) {
                 my_e = tail + rank;
                 s = mys;
+                if constexpr (BV) sk = a.skey[s];
                 x = s;
                 k = 0;
                 mode = 1;
@@ -748,7 +755,8 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
 
         // ---------------------------------------------------------------- one walk step
         if (mode == 1) {
-            if ((k & 3) == 0) ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)s, tlo, thi), g.key0, g.key1);
+            if ((k & 3) == 0)
+                ph = philox4x32_10(make_uint4((uint32_t)(k >> 2), (uint32_t)(BV ? sk : s), tlo, thi), g.key0, g.key1);
             const int q = k & 3;
             const uint32_t w = q == 0 ? ph.x : (q == 1 ? ph.y : (q == 2 ? ph.z : ph.w));
             // y, its B_u flag and its row bounds.  With the tree bitmap in LDS (small graphs,
@@ -812,6 +820,8 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 const int sl = head & robm;
                 const int s0 = (int)rob_s[sl];
                 if (!bits.test(s0)) {
+                    uint32_t wk0 = (uint32_t)s0;  // the walk's Philox key
+                    if constexpr (BV) wk0 = (uint32_t)a.skey[s0];
                     if (hs == kContinue) wait_global();  // recorded steps stored by another lane
                     int xs = s0;
                     const long long k0 = hs == kContinue ? kPath : 0;
@@ -828,15 +838,15 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                     if constexpr (GL) {
                         // the conflict tables (all free now) hold the walk's Philox words meanwhile
                         xs = __shfl(xs, 0, kWave);
-                        kk = walk_next_wave<CT, WT>(bits, recw, rp, col, cw, guide, s0, xs, k0, tlo, thi, g.key0,
+                        kk = walk_next_wave<CT, WT>(bits, recw, rp, col, cw, guide, wk0, xs, k0, tlo, thi, g.key0,
                                                     g.key1, reinterpret_cast<uint32_t *>(htab));
                         for (int i = lane; i < 4 * kWave; i += kWave) htab[i] = kWave;
                         wave_sync();
                         if (lane == 0) retrace_commit<true>(bits, recw, bflag, s0);
                     } else {
                         if (lane == 0)
-                            kk = rewalk_commit<LDS, CT, WT>(bits, recw, rp, col, edge, vrow, cw, guide, bflag, s0, xs,
-                                                            k0, tlo, thi, g.key0, g.key1);
+                            kk = rewalk_commit<LDS, CT, WT>(bits, recw, rp, col, edge, vrow, cw, guide, bflag, s0, wk0,
+                                                            xs, k0, tlo, thi, g.key0, g.key1);
                     }
                     if (lane == 0) {
                         steps += kk;
@@ -1690,10 +1700,14 @@ __global__ __launch_bounds__(256) void edge_resistance_kernel(int n, long long n
             else h = mid;
         }
     }
-    // each operation rounded on its own (no fused multiply-add), as the definition reads
-    const double lev = __ddiv_rn((double)c, q);
-    if (r) r[e] = __ddiv_rn(lev, w ? w[e] : 1.0);
-    if (denom) denom[e] = __dsub_rn(1.0, __dmul_rn(__dsub_rn(1.0, theta), lev));
+    {
+        // each operation rounded on its own, as the definition reads: no contraction into a fused
+        // multiply-add
+#pragma clang fp contract(off)
+        const double lev = (double)c / q;
+        if (r) r[e] = lev / (w ? w[e] : 1.0);
+        if (denom) denom[e] = 1.0 - (1.0 - theta) * lev;
+    }
 }
 
 // Final fill (Algorithm 1; Eq. diag-comp): diag[u] = x[u], diag[v] = R[v]/tau - x[u] + 2 x[v]
@@ -1943,17 +1957,23 @@ hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t 
     count_unreached_kernel<<<blocks_for(n, 256), 256, 0, st>>>(n, dist, err);
     return hipGetLastError();
 }
-template <bool LDS, typename CT, bool WT>
+template <bool LDS, typename CT, bool WT, bool BV = false>
 int resident_of(size_t dyn, int *per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wilson_kernel<LDS, CT, WT>, 64, dyn) == hipSuccess;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wilson_kernel<LDS, CT, WT, false, BV>, 64, dyn) ==
+           hipSuccess;
 }
-int wilson_resident_blocks(bool lds_bits, bool col16, bool weighted, int nwords) {
+int wilson_resident_blocks(bool lds_bits, bool col16, bool weighted, int nwords, bool block_split) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     const size_t dyn = lds_bits ? (size_t)nwords * 4 : 0;
     int ok;
-    if (lds_bits) {
+    if (block_split) {
+        if (lds_bits) ok = col16 ? resident_of<true, unsigned short, false, true>(dyn, &per_cu)
+                                 : resident_of<true, int, false, true>(dyn, &per_cu);
+        else ok = col16 ? resident_of<false, unsigned short, false, true>(0, &per_cu)
+                        : resident_of<false, int, false, true>(0, &per_cu);
+    } else if (lds_bits) {
         if (col16) ok = weighted ? resident_of<true, unsigned short, true>(dyn, &per_cu)
                                  : resident_of<true, unsigned short, false>(dyn, &per_cu);
         else ok = weighted ? resident_of<true, int, true>(dyn, &per_cu) : resident_of<true, int, false>(dyn, &per_cu);
@@ -1986,12 +2006,14 @@ int wilson_resident_blocks_graph_lds(int nwords, long long graph_bytes) {
     return std::max(0, std::min(per_cu, by_lds)) * std::max(1, cus);
 }
 template <bool LDS, typename CT>
-void launch_wilson_t(const WilsonArgs &a, int blocks, bool weighted, size_t dyn, hipStream_t st) {
-    if (weighted) wilson_kernel<LDS, CT, true><<<blocks, 64, dyn, st>>>(a);
+void launch_wilson_t(const WilsonArgs &a, int blocks, bool weighted, bool bv, size_t dyn, hipStream_t st) {
+    if (bv) wilson_kernel<LDS, CT, false, false, true><<<blocks, 64, dyn, st>>>(a);
+    else if (weighted) wilson_kernel<LDS, CT, true><<<blocks, 64, dyn, st>>>(a);
     else wilson_kernel<LDS, CT, false><<<blocks, 64, dyn, st>>>(a);
 }
 hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool col16, bool weighted, int nwords,
-                         hipStream_t st, long long graph_lds_bytes) {
+                         hipStream_t st, long long graph_lds_bytes, bool block_split) {
+    if (block_split && (weighted || a.tiles || graph_lds_bytes > 0)) return hipErrorInvalidValue;
     if (graph_lds_bytes > 0) {
         if (!lds_bits || !col16 || weighted || a.tiles) return hipErrorInvalidValue;
         wilson_kernel<true, unsigned short, false, true>
@@ -2000,11 +2022,11 @@ hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool co
     }
     if (lds_bits) {
         const size_t dyn = (size_t)nwords * 4;
-        if (col16) launch_wilson_t<true, unsigned short>(a, blocks, weighted, dyn, st);
-        else launch_wilson_t<true, int>(a, blocks, weighted, dyn, st);
+        if (col16) launch_wilson_t<true, unsigned short>(a, blocks, weighted, block_split, dyn, st);
+        else launch_wilson_t<true, int>(a, blocks, weighted, block_split, dyn, st);
     } else {
-        if (col16) launch_wilson_t<false, unsigned short>(a, blocks, weighted, 0, st);
-        else launch_wilson_t<false, int>(a, blocks, weighted, 0, st);
+        if (col16) launch_wilson_t<false, unsigned short>(a, blocks, weighted, block_split, 0, st);
+        else launch_wilson_t<false, int>(a, blocks, weighted, block_split, 0, st);
     }
     return hipGetLastError();
 }

@@ -54,6 +54,12 @@ struct WilsonArgs {
     int *queue;                 // tile counter, zero at launch
     long long *steps;           // [ntiles], nullable
     long long *draws;           // [ntiles], nullable
+    // single-graph launches on the block-split graph (Wilson per biconnected component): every
+    // block's root starts in the tree (roots[0..nroots), in place of the single root g.u), and
+    // the walk from s is keyed by skey[s] in place of s
+    const int *roots;
+    const int *skey;
+    int nroots;
 };
 
 struct IntervalArgs {
@@ -172,15 +178,16 @@ int solve_grid(const RowMap &m, int G);
 int vec_grid(int n);
 hipError_t launch_count_unreached(int n, const int *dist, int *err, hipStream_t st);
 // resident blocks of one sampler launch on the current device (occupancy x compute units)
-int wilson_resident_blocks(bool lds_bits, bool col16, bool weighted, int nwords);
+int wilson_resident_blocks(bool lds_bits, bool col16, bool weighted, int nwords, bool block_split = false);
 // Small unweighted graphs (16-bit columns, LDS tree bitmap) may keep the graph in LDS as well:
 // its bytes there (row pointers, B_u flags, columns), and the resident blocks of such a
 // launch by the LDS residency measured on gfx950 (two 80 KB halves, 256-byte units).
 long long wilson_graph_lds_bytes(int n, long long nnz);
 int wilson_resident_blocks_graph_lds(int nwords, long long graph_bytes);
 // graph_lds_bytes > 0 (single-graph launches only): the graph-in-LDS variant
+// block_split: the block-split graph of the per-block variant (several roots, keyed starts)
 hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool col16, bool weighted, int nwords,
-                         hipStream_t st, long long graph_lds_bytes = 0);
+                         hipStream_t st, long long graph_lds_bytes = 0, bool block_split = false);
 // weighted graphs: running row sums and row totals; weight checks; B_u edge conductances,
 // B-path resistances (max into *rmax_bits, as the bits of a non-negative double); F
 hipError_t launch_sum_walks(int cnt, const long long *steps, const long long *draws, unsigned long long *totals,
@@ -225,6 +232,31 @@ hipError_t launch_residual64(const RowMap &m, int G, int u, const double *x, dou
                              hipStream_t st);
 // x -= mean_src[0] / n
 hipError_t launch_project(int n, double *x, const double *mean_src, int grid, hipStream_t st);
+// Wilson per biconnected component (ustd_blocks.hip): exclusive scan of int counts (out[n] =
+// total, also written to *total; sums holds (n / 1024 + 2) ints); the blocks of G from B_u
+// (lo, hi, uf: int[n]); per entry its block and the first entries of each (vertex, block);
+// the slots of G*; G*'s columns; block roots and tops; and, per batch of trees, the join of the
+// block trees (records of G* in recs) into records of spanning trees of G (rec)
+hipError_t launch_scan_excl(const int *in, int *out, long long n, int *sums, int *total, hipStream_t st);
+hipError_t launch_fill_i32(long long n, int *a, int v, hipStream_t st);
+hipError_t launch_bc_blocks(const RowMap &m, int G, int u, int ecc, const int *dist, const int *parB,
+                            const int2 *bint, int *lo, int *hi, int *uf, hipStream_t st);
+hipError_t launch_bc_entries(int n, long long nnz, int u, const int *rp, const int *col, const int *parB,
+                             const int2 *bint, const int *uf, int *eblk, int *firstPar, int *firstTop, int *flag,
+                             hipStream_t st);
+hipError_t launch_bc_slots(int n, long long nnz, int u, const int *rp, const int *flag, const int *sid,
+                           const int *eblk, const int *uf, int *vtx, int *skey, int *sblk, int *slotPar, int *slotTop,
+                           int *deg, hipStream_t st);
+hipError_t launch_bc_columns(int n, int u, const int *rp, const int *col, const int *eblk, const int *uf,
+                             const int *slotPar, const int *slotTop, const int *rps, int *cursor, int *cols,
+                             hipStream_t st);
+hipError_t launch_bc_roots(int nslots, const int *rps, const int *vtx, const int *sblk, unsigned long long *key,
+                           int *flag, hipStream_t st);
+hipError_t launch_bc_top_flags(int nslots, const int *sblk, const int *slotTop, int *flag, hipStream_t st);
+hipError_t launch_bc_compact(int nslots, const int *flag, const int *pos, int *list, hipStream_t st);
+hipError_t launch_bc_join(int n, int u, int ntrees, int ntop, int nslots, const int *tops, const int *slotPar,
+                          const int *vtx, int2 *recs, long long sstride, int2 *rec, long long stride,
+                          const int *bflag, hipStream_t st);
 // a[0..n) = v; b[0..n) += a[0..n) (int64)
 hipError_t launch_fill_i64(long long n, long long *a, long long v, hipStream_t st);
 hipError_t launch_add_i64(long long n, const long long *a, long long *b, hipStream_t st);
