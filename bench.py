@@ -156,8 +156,11 @@ def cpu_baseline(g, u, tau, seed, budget_s: float, w=None):
 
 
 def run_batch(args):
-    """Config of 64 mixed graphs (32 R-MAT, 32 grids) with tau capped at 4096, through the
-    batched entry point; one step = one ustd_batch_diag_lpinv call over all members."""
+    """Config of 64 mixed graphs (32 R-MAT, 32 grids) with tau capped at 4096.  The schedule is
+    tuned (ustd_batch_autotune; cached in the JSON file USTD_TUNE_CACHE names, when set), one
+    execution of the planned batch is captured in a HIP graph, and one step = one replay of that
+    graph: the whole estimator for all members (set-up, sampling, Algorithm 2, solves,
+    combination).  The one-shot batch call and per-graph FP64 calls are timed beside it."""
     import numpy as np
     import torch
 
@@ -174,23 +177,48 @@ def run_batch(args):
     ws = api.Workspace(dev)
     print("bench: batch of %d graphs, n total %d" % (len(members), sum(m["graph"].n for m in members)),
           file=sys.stderr, flush=True)
-    for i in range(args.warmup):
-        api.batch_diag_lpinv(graphs, probs, ws=ws, want_counts=False)
-        print("bench: warmup %d done" % i, file=sys.stderr, flush=True)
+    # the one-shot call (plan, one eager execution, reports), for reference
+    api.batch_diag_lpinv(graphs, probs, ws=ws, want_counts=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    reps = None
+    d_ref, _, reps_ref = api.batch_diag_lpinv(graphs, probs, ws=ws, want_counts=False)
+    torch.cuda.synchronize()
+    ms_one_shot = (time.perf_counter() - t0) * 1e3
+    print("bench: one-shot batch %.1f ms" % ms_one_shot, file=sys.stderr, flush=True)
+
+    tt = time.perf_counter()
+    sched, tuned_ms, hit = api.batch_autotune(graphs, probs, ws=ws, cache_path=os.environ.get("USTD_TUNE_CACHE"),
+                                              graph=True)
+    tune_s = time.perf_counter() - tt
+    print("bench: tuned schedule %s (%.1f ms, %s) in %.1f s" % (sched.as_dict(), tuned_ms,
+                                                               "cached" if hit else "timed", tune_s),
+          file=sys.stderr, flush=True)
+    tp = time.perf_counter()
+    plan = api.BatchPlan(graphs, probs, ws=ws, schedule=sched, want_counts=False)
+    ms_plan = (time.perf_counter() - tp) * 1e3
+    plan.execute()  # eager execution: phase times
+    reps_eager = plan.reports()
+    plan.capture()
+    for i in range(args.warmup):
+        plan.replay()
+        torch.cuda.synchronize()
+        print("bench: warmup replay %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     for i in range(args.steps):
-        _, _, reps = api.batch_diag_lpinv(graphs, probs, ws=ws, want_counts=False)
+        plan.replay()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall * 1e3 / args.steps
-    print("bench: %d timed steps in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
+    print("bench: %d timed graph replays in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
+    reps = plan.reports()
+    for i in range(len(members)):  # the replayed graph gives the one-shot call's results
+        assert torch.equal(plan.diags[i], d_ref[i]) and reps[i]["walk_steps"] == reps_ref[i]["walk_steps"], i
     tau = sum(r["tau"] for r in reps)
     steps = sum(r["walk_steps"] for r in reps)
-    ms_sample, ms_ag = reps[0]["ms_sample"], reps[0]["ms_aggregate"]
-    ms_solve = sum(r["ms_solve"] for r in reps)
-    ms_bfs = sum(r["ms_bfs"] for r in reps)
+    ms_sample, ms_ag = reps_eager[0]["ms_sample"], reps_eager[0]["ms_aggregate"]
+    ms_solve = sum(r["ms_solve"] for r in reps_eager)
+    ms_bfs = sum(r["ms_bfs"] for r in reps_eager)
     # the same members one call each, FP64 solve (the plain per-graph form), one pass
     pws = api.Workspace(dev)
     torch.cuda.synchronize()
@@ -214,17 +242,23 @@ def run_batch(args):
         "dtype": "int32+fp64" if mode == api.SOLVE_FP64 else "int32+fp32/fp64", "data": "synthetic",
         "config": {"workload": "batch-%d-mixed-rmat10to16-grid16to256-taucap%d" % (w["count"], w["tau_cap"]),
                    "members": w["count"], "tau_total": tau, "n_total": sum(m["graph"].n for m in members),
-                   "eps": 0.3, "solve": args.solve},
+                   "eps": 0.3, "solve": args.solve, "step": "one replay of the captured HIP graph"},
+        "tuned_schedule": sched.as_dict(),
+        "tuner": {"from_cache": hit, "ms_per_execution": round(tuned_ms, 3), "tuning_s": round(tune_s, 2)},
+        "plan_ms": round(ms_plan, 2),
+        "one_shot_ms": round(ms_one_shot, 3),
         "walk_steps_per_s": round(steps / (ms_sample * 1e-3), 1),
         "sampling_trees_per_s": round(tau / (ms_sample * 1e-3), 1),
-        "e2e_ms": round(reps[0]["ms_total"], 4),
-        "phase_ms": {"setup_bfs": ms_bfs, "sample": ms_sample, "aggregate": ms_ag, "solve": ms_solve},
+        "e2e_ms_eager": round(reps_eager[0]["ms_total"], 4),
+        "phase_ms_eager": {"setup_bfs_at_plan": ms_bfs, "sample": ms_sample, "aggregate": ms_ag,
+                           "solve": ms_solve},
         "pool_fills": reps[0]["n_batches"], "walk_steps": steps,
         "per_graph_fp64_ms": round(ms_single, 3), "batched_speedup_vs_per_graph_fp64": round(ms_single / ms_step, 3),
         "roofline": {"bound": "hbm", "kernel": "wilson_kernel", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
                      "algorithmic_bytes_per_launch": ab, "launch_ms": round(ms_sample, 4)},
     }
+    plan.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(members, reps, args.cpu_budget)
     print(json.dumps(out), flush=True)
@@ -335,6 +369,11 @@ def main():
                          "(pivot = -2: the smallest eccentricity bound after ten BFS sweeps, found on the device)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant", default="plain", choices=["plain", "blocks"],
+                    help="Wilson variant of the timed leg: plain (rooted at the pivot), or blocks (one walk "
+                         "per biconnected component of the graph, joined at the cut vertices)")
+    ap.add_argument("--no-variant-compare", action="store_true",
+                    help="skip the one-run comparison of the two Wilson variants")
     ap.add_argument("--task", default="diag", choices=["diag", "edges"],
                     help="diag: diag(L+) (default); edges: spanning-edge counts of q = ceil(2 eps^-2 ln(2m/delta)) "
                          "trees, the effective resistance of every edge")
@@ -386,8 +425,11 @@ def main():
     if args.pivot == "sweep":
         u = -2  # chosen on the device in every call (its BFS sweeps are part of the timed set-up)
         cfg = dict(cfg, workload=cfg["workload"] + "-sweep-pivot")
+    variant = api.WILSON_BLOCKS if args.variant == "blocks" else api.WILSON_PLAIN
+    if variant == api.WILSON_BLOCKS:
+        cfg = dict(cfg, workload=cfg["workload"] + "-blocks")
     p = api.problem(G, pivot=u, eps=0.3, seed=1, tau_override=tau_override, solve_mode=mode, solve_tol=1e-12,
-                    trees_per_batch=args.trees_per_batch)
+                    trees_per_batch=args.trees_per_batch, wilson_variant=variant)
     ws = api.Workspace(dev)
     print("bench: %s n=%d m=%d pivot=%d" % (cfg["workload"], g.n, g.m, u), file=sys.stderr, flush=True)
 
@@ -456,6 +498,29 @@ def main():
     cmp["mixed_vs_fp64_diag_rel_inf"] = float(dd.abs().max() / diag_t.abs().max())
     cmp["mixed_speedup"] = round(cmp["fp64"]["ms"] / max(cmp["mixed"]["ms"], 1e-9), 3)
 
+    # the other Wilson variant, one warm and one timed run of the same problem: sampling time and
+    # walk steps beside the timed leg's (the per-component walks take fewer steps; the estimate
+    # they give differs from the timed leg's by the sampling error only)
+    vcmp = None
+    if not args.no_variant_compare and w is None:
+        other = api.WILSON_PLAIN if variant == api.WILSON_BLOCKS else api.WILSON_BLOCKS
+        q = api.Problem.from_buffer_copy(p)
+        q.wilson_variant = other
+        api.diag_lpinv_p(G, q, ws=ws, want_counts=False)
+        torch.cuda.synchronize()
+        tv = time.perf_counter()
+        _, _, ro = api.diag_lpinv_p(G, q, ws=ws, want_counts=False)
+        torch.cuda.synchronize()
+        wall_o = (time.perf_counter() - tv) * 1e3
+        names = {api.WILSON_PLAIN: "plain", api.WILSON_BLOCKS: "blocks"}
+        vcmp = {names[variant]: {"ms_sample": round(ms_sample, 3), "walk_steps": steps, "ms_step": round(ms_step, 3),
+                                 "sampling_trees_per_s": round(tau / (ms_sample * 1e-3), 1)},
+                names[other]: {"ms_sample": round(ro["ms_sample"], 3), "walk_steps": ro["walk_steps"],
+                               "ms_step": round(wall_o, 3),
+                               "sampling_trees_per_s": round(tau / (ro["ms_sample"] * 1e-3), 1)}}
+        vcmp["blocks_sample_speedup"] = round(vcmp["plain"]["ms_sample"] / max(vcmp["blocks"]["ms_sample"], 1e-9), 3)
+        vcmp["blocks_step_ratio"] = round(vcmp["blocks"]["walk_steps"] / max(vcmp["plain"]["walk_steps"], 1), 4)
+
     out = {
         "metric": "spanning trees/sec + walk steps/sec; end-to-end diag(L†) time at ε=0.3",
         "value": round(tau / (ms_step * 1e-3), 2),
@@ -466,7 +531,7 @@ def main():
         "dtype": "int32+fp64" if mode == api.SOLVE_FP64 else "int32+fp32/fp64",
         "data": "synthetic",
         "config": dict(cfg, n=g.n, m=g.m, pivot=u, ecc=reps[0]["ecc"], eps=0.3, tau=tau, seed=1,
-                       solve=args.solve, trees_per_batch=reps[0]["trees_per_batch"]),
+                       solve=args.solve, trees_per_batch=reps[0]["trees_per_batch"], wilson_variant=args.variant),
         "walk_steps_per_s": round(steps / (ms_sample * 1e-3), 1),
         "sampling_trees_per_s": round(tau / (ms_sample * 1e-3), 1),
         "e2e_ms": round(med("ms_total"), 4),
@@ -478,6 +543,8 @@ def main():
         "centralities_ms": round(ms_central, 4),
         "solve_compare": cmp,
     }
+    if vcmp:
+        out["wilson_variant_compare"] = vcmp
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, u, tau, 1, args.cpu_budget, w)

@@ -255,6 +255,95 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
                           double *const *d_diags, int64_t *const *d_counts, ustd_report *reps,
                           void *stream);
 
+/* ---- planned batches: set up once, execute many times, capture in a HIP graph ----
+ *
+ * ustd_batch_diag_lpinv above runs a plan once.  A plan splits the call in two: creation does
+ * everything that needs the host (argument and graph checks, pivots, the BFS trees' depths and
+ * so tau, the schedule of (member, tree) tiles over pool fills), and execution only enqueues
+ * kernels on the stream and the library's side streams: no host wait, copy or memory set, so
+ * an execution can be captured in a HIP graph and replayed.  Every execution recomputes the
+ * whole estimator from the graphs (CSR views, BFS trees, sampling, Algorithm 2, solves,
+ * combination) and gives results bit-identical to ustd_batch_diag_lpinv and to single calls;
+ * the graphs' CSR arrays (and weights) must not change while the plan lives.  Trees are keyed
+ * by (seed, tree, start), so no schedule changes any result. */
+
+/* Schedule of a planned batch's launches (zero-initialised = the defaults). */
+typedef struct {
+    int32_t group_fills;  /* sampler group (one persistent launch) of about this many GPU-fills of trees
+                             (resident sampler waves); 0 = 2; -1 = the whole pool fill in one launch */
+    int32_t agg_chunk;    /* trees per Algorithm 2 thread: 0 = by eccentricity (4 from ecc 8 on, else 8),
+                             or 4 or 8 */
+    int32_t layout;       /* USTD_LAYOUT_AUTO or USTD_LAYOUT_RECORDS (below) */
+    int32_t branches;     /* 0 or 1: sampler groups alternate between two streams and Algorithm 2 runs on a
+                             third; 2 .. 4: the members are split into this many independent chains (by
+                             estimated work), each one persistent sampler launch on its share of the
+                             GPU's resident waves followed by its Algorithm 2 on the same stream
+                             (group_fills is then unused) */
+    int64_t fill_trees;   /* trees resident at once (one pool fill) at most; 0 = as many as the
+                             workspace's record pool holds, up to 2^20 */
+} ustd_batch_schedule;
+
+enum {
+    USTD_LAYOUT_AUTO = 0,    /* sampler tree state in an LDS bitmap when every member fits it */
+    USTD_LAYOUT_RECORDS = 1  /* tree state in the tree records and per-edge entries, for every member */
+};
+
+typedef struct ustd_batch_plan ustd_batch_plan; /* opaque */
+
+/* Creates a plan for probs[0 .. count-1] on the workspace d_ws (ustd_batch_workspace_bytes
+ * bytes, kept by the plan until it is destroyed) with schedule `sched` (nullable: defaults).
+ * Runs the members' set-up on `stream` (synchronises it) and allocates the plan's own device
+ * memory for the tile schedule (24 bytes per tree plus a few hundred bytes per member).  The
+ * problems are copied; their device arrays must stay valid.  Errors as ustd_batch_diag_lpinv
+ * ("problem i: ..."); *plan is NULL on error. */
+int ustd_batch_plan_create(const ustd_problem *probs, int32_t count, void *d_ws, size_t ws_bytes,
+                           const ustd_batch_schedule *sched, ustd_batch_plan **plan, void *stream);
+
+/* Enqueues one execution of the plan on `stream`: diag of member i into d_diags[i]
+ * (double[n_i]); d_counts as in ustd_batch_diag_lpinv.  Returns without waiting.  Executions of
+ * one plan must not overlap (they share the workspace).  When `stream` is capturing, phase
+ * timers are left out and members that asked for USTD_ENGINE_MULTI are refused (that engine
+ * is driven from the host); otherwise ustd_batch_plan_reports gives the phase times. */
+int ustd_batch_plan_execute(ustd_batch_plan *plan, double *const *d_diags, int64_t *const *d_counts,
+                            void *stream);
+
+/* Per-member reports of the plan's last execution (or graph launch): synchronises `stream`
+ * (the one it ran on) and reads walk totals and solve results from the device; ms_sample,
+ * ms_aggregate, ms_solve, ms_combine and ms_total are those of the last eager execution (0
+ * after a graph launch), ms_bfs is the set-up at creation.  `reps`: `count` entries.
+ * Returns USTD_ENOTCONV (after filling every report) when a member's solve ended above its
+ * target. */
+int ustd_batch_plan_reports(ustd_batch_plan *plan, ustd_report *reps, void *stream);
+
+/* The schedule a plan runs with (defaults filled in). */
+int ustd_batch_plan_schedule(const ustd_batch_plan *plan, ustd_batch_schedule *out);
+
+/* Frees the plan's device memory (synchronises the device). */
+int ustd_batch_plan_destroy(ustd_batch_plan *plan);
+
+/* Captures one execution of the plan (ustd_batch_plan_execute with these outputs) into an
+ * instantiated HIP graph, *graph = its hipGraphExec_t.  Capture runs on a stream of the
+ * library's.  USTD_EINVAL when a member uses USTD_ENGINE_MULTI. */
+int ustd_batch_graph_create(ustd_batch_plan *plan, double *const *d_diags, int64_t *const *d_counts, void **graph);
+/* Launches a captured execution on `stream` (returns without waiting). */
+int ustd_batch_graph_launch(void *graph, void *stream);
+int ustd_batch_graph_destroy(void *graph);
+
+/* Autotuner of a batch's schedule (dynamic load balancing, parallel implementation appendix):
+ * times executions of plans over branches {alternating groups, 2, 3, 4 chains}, group_fills
+ * {1, 2, 4, whole fill}, agg_chunk {by eccentricity, 4, 8}, layout {auto, records} and fill_trees
+ * {all, half}, one dimension at a time from the defaults, and returns the fastest in *best (its
+ * time per execution in *best_ms, nullable).  graph != 0 times replays of each plan's captured
+ * HIP graph (the way a repeated batch runs), else eager executions.
+ * cache_path (nullable: the environment variable USTD_TUNE_CACHE, none when unset) names a JSON
+ * file of tuned schedules keyed by the batch's shape (members' n, nnz, tau, eccentricity,
+ * weightedness), the timing mode and the device (architecture, compute units): a hit returns the stored
+ * schedule without timing (*from_cache = 1, nullable), a miss adds the result to the file.
+ * Synchronises `stream`; the workspace as for ustd_batch_plan_create. */
+int ustd_batch_autotune(const ustd_problem *probs, int32_t count, void *d_ws, size_t ws_bytes,
+                        const char *cache_path, int32_t graph, ustd_batch_schedule *best, double *best_ms,
+                        int32_t *from_cache, void *stream);
+
 /* Spanning-edge counts (Kirchhoff index appendix: counting, for each edge, the sampled USTs
  * it appears in; count / #trees estimates the edge's effective resistance r(e), which is
  * also the probability that a uniform spanning tree contains e).  Trees tree_begin ..

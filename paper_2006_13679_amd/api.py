@@ -19,6 +19,7 @@ OK, EINVAL, EGRAPH, ENOMEM, EHIP, ENOTCONV = 0, 1, 2, 3, 4, 5
 SOLVE_FP64, SOLVE_MIXED = 0, 1
 ENGINE_AUTO, ENGINE_WORKGROUP, ENGINE_MULTI = 0, 1, 2
 WILSON_PLAIN, WILSON_BLOCKS = 0, 1
+LAYOUT_AUTO, LAYOUT_RECORDS = 0, 1
 
 
 class UstdError(RuntimeError):
@@ -61,9 +62,22 @@ class Report(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Schedule(ctypes.Structure):
+    """ustd_batch_schedule: launch schedule of a planned batch (zeros = defaults)."""
+    _fields_ = [
+        ("group_fills", ctypes.c_int32), ("agg_chunk", ctypes.c_int32), ("layout", ctypes.c_int32),
+        ("branches", ctypes.c_int32), ("fill_trees", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 EXPORTS = ["ustd_workspace_bytes", "ustd_bfs", "ustd_sample_trees", "ustd_flow_counts", "ustd_tree_counts",
            "ustd_solve_pivot_column", "ustd_diag_lpinv", "ustd_diag_lpinv_noalloc", "ustd_batch_workspace_bytes",
-           "ustd_batch_diag_lpinv",
+           "ustd_batch_diag_lpinv", "ustd_batch_plan_create", "ustd_batch_plan_execute", "ustd_batch_plan_reports",
+           "ustd_batch_plan_schedule", "ustd_batch_plan_destroy", "ustd_batch_graph_create", "ustd_batch_graph_launch",
+           "ustd_batch_graph_destroy", "ustd_batch_autotune",
            "ustd_edge_counts", "ustd_edge_sample_size", "ustd_edge_resistances", "ustd_centralities",
            "ustd_philox_words", "ustd_status_string", "ustd_last_error"]
 
@@ -89,6 +103,17 @@ def lib() -> ctypes.CDLL:
         L.ustd_diag_lpinv_noalloc.argtypes = [PP, P, P, PR, P]
         L.ustd_batch_workspace_bytes.argtypes = [PP, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.ustd_batch_diag_lpinv.argtypes = [PP, i32, P, ctypes.c_size_t, P, P, PR, P]
+        PS = ctypes.POINTER(Schedule)
+        L.ustd_batch_plan_create.argtypes = [PP, i32, P, ctypes.c_size_t, PS, ctypes.POINTER(P), P]
+        L.ustd_batch_plan_execute.argtypes = [P, P, P, P]
+        L.ustd_batch_plan_reports.argtypes = [P, PR, P]
+        L.ustd_batch_plan_schedule.argtypes = [P, PS]
+        L.ustd_batch_plan_destroy.argtypes = [P]
+        L.ustd_batch_graph_create.argtypes = [P, P, P, ctypes.POINTER(P)]
+        L.ustd_batch_graph_launch.argtypes = [P, P]
+        L.ustd_batch_graph_destroy.argtypes = [P]
+        L.ustd_batch_autotune.argtypes = [PP, i32, P, ctypes.c_size_t, ctypes.c_char_p, i32, PS,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), P]
         L.ustd_edge_counts.argtypes = [PP, i64, i64, P, ctypes.c_size_t, P, PR, P]
         L.ustd_edge_sample_size.argtypes = [i64, i64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(i64)]
         L.ustd_edge_resistances.argtypes = [i64, i64, P, P, P, P, i64, ctypes.c_double, P, P, P]
@@ -315,6 +340,94 @@ def batch_diag_lpinv(graphs: list, probs: list, ws: Workspace | None = None, wan
     rc = lib().ustd_batch_diag_lpinv(arr, count, _ptr(buf), buf.numel(), dptr, cptr, reps, _stream(dev))
     _check(rc, (OK, ENOTCONV) if allow_notconv else (OK,))
     return diags, counts, [r.as_dict() for r in reps]
+
+
+def _batch_ws(graphs: list, probs: list, ws: Workspace | None):
+    count = len(probs)
+    assert count == len(graphs) and count > 0
+    dev = graphs[0].row_ptr.device
+    arr = (Problem * count)(*probs)
+    b = ctypes.c_size_t(0)
+    _check(lib().ustd_batch_workspace_bytes(arr, count, ctypes.byref(b)))
+    if ws is None:
+        ws = _default_ws.setdefault(dev, Workspace(dev))
+    return arr, ws.get(int(b.value)), dev
+
+
+class BatchPlan:
+    """A planned batch (ustd_batch_plan_*): set up once, then executed eagerly or through a
+    captured HIP graph.  Owns its output tensors; the workspace buffer is held until close()."""
+
+    def __init__(self, graphs: list, probs: list, ws: Workspace | None = None, schedule: Schedule | None = None,
+                 want_counts: bool = True):
+        arr, buf, dev = _batch_ws(graphs, probs, ws)
+        self.count, self.dev, self._buf, self._graphs = len(probs), dev, buf, list(graphs)
+        self.diags = [torch.empty(g.n, dtype=torch.float64, device=dev) for g in graphs]
+        self.counts = [torch.empty(g.n, dtype=torch.int64, device=dev) for g in graphs] if want_counts else None
+        self._dptr = (ctypes.c_void_p * self.count)(*[d.data_ptr() for d in self.diags])
+        self._cptr = (ctypes.c_void_p * self.count)(*[c.data_ptr() for c in self.counts]) if want_counts else None
+        h = ctypes.c_void_p(None)
+        _check(lib().ustd_batch_plan_create(arr, self.count, _ptr(buf), buf.numel(),
+                                            ctypes.byref(schedule) if schedule is not None else None,
+                                            ctypes.byref(h), _stream(dev)))
+        self._h = h
+        self._graph = None
+
+    def schedule(self) -> dict:
+        s = Schedule()
+        _check(lib().ustd_batch_plan_schedule(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def execute(self):
+        _check(lib().ustd_batch_plan_execute(self._h, self._dptr, self._cptr, _stream(self.dev)))
+
+    def capture(self):
+        """Captures one execution into a HIP graph (replaced if one exists)."""
+        if self._graph is not None:
+            _check(lib().ustd_batch_graph_destroy(self._graph))
+            self._graph = None
+        g = ctypes.c_void_p(None)
+        _check(lib().ustd_batch_graph_create(self._h, self._dptr, self._cptr, ctypes.byref(g)))
+        self._graph = g
+
+    def replay(self):
+        assert self._graph is not None, "capture() first"
+        _check(lib().ustd_batch_graph_launch(self._graph, _stream(self.dev)))
+
+    def reports(self, allow_notconv: bool = False) -> list:
+        reps = (Report * self.count)()
+        rc = lib().ustd_batch_plan_reports(self._h, reps, _stream(self.dev))
+        _check(rc, (OK, ENOTCONV) if allow_notconv else (OK,))
+        return [r.as_dict() for r in reps]
+
+    def close(self):
+        if self._graph is not None:
+            lib().ustd_batch_graph_destroy(self._graph)
+            self._graph = None
+        if self._h:
+            torch.cuda.synchronize(self.dev)
+            lib().ustd_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_autotune(graphs: list, probs: list, ws: Workspace | None = None, cache_path: str | None = None,
+                   graph: bool = True):
+    """Tuned schedule of a batch (ustd_batch_autotune), timing graph replays (graph=True) or eager
+    executions.  Returns (Schedule, ms per execution, whether it came from the cache)."""
+    arr, buf, dev = _batch_ws(graphs, probs, ws)
+    best = Schedule()
+    ms = ctypes.c_double(0.0)
+    hit = ctypes.c_int32(0)
+    _check(lib().ustd_batch_autotune(arr, len(probs), _ptr(buf), buf.numel(),
+                                     cache_path.encode() if cache_path else None, 1 if graph else 0, ctypes.byref(best),
+                                     ctypes.byref(ms), ctypes.byref(hit), _stream(dev)))
+    return best, float(ms.value), bool(hit.value)
 
 
 def edge_counts(g: Graph, p: Problem, tree_begin: int, tree_count: int, counts: torch.Tensor | None = None,

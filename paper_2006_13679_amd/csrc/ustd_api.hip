@@ -354,9 +354,10 @@ struct Timer {
 // Extra streams per device (default priority, not blocking on the null stream): stream 0
 // runs the pivot-column solve (and a weighted graph's row sums) while the trees are sampled
 // on the caller's stream; stream 1 runs the second tree pool of a large graph (and every
-// other sampler group of a batch); stream 2 runs a batch's Algorithm 2.  Created on first
-// use and kept until the process ends.
-constexpr int kSideStreams = 3;
+// other sampler group of a batch); stream 2 runs a batch's Algorithm 2; streams 1 to 3 run
+// the chains of a batch split into branches.  Created on first use and kept until the
+// process ends.
+constexpr int kSideStreams = 4;
 int side_stream(hipStream_t *out, int which = 0) {
     static std::mutex mu;
     static std::vector<hipStream_t> streams;
@@ -1116,6 +1117,7 @@ int solve_column(Ctx &c, double *x_out, ustd_report *rep) {
 // pool fill.
 // ---------------------------------------------------------------------------------------
 constexpr long long kMaxBatchTiles = 1ll << 20;
+constexpr int kMaxBranches = 4;
 
 struct BatchPlan {
     std::vector<Plan> g;
@@ -1123,14 +1125,33 @@ struct BatchPlan {
     bool lds_bits = true, col16 = true;
     int nwords_max = 0, slots = 0;
     long long rec_pool = 0, max_tiles = 0;
-    long long off_queue = 0, off_rec = 0, off_path = 0, off_steps = 0, off_draws = 0, off_tiles = 0,
-              off_graphs = 0, off_jobs = 0, off_jobs32 = 0, total = 0;
+    long long off_queue = 0, off_rec = 0, off_path = 0, off_steps = 0, off_draws = 0, total = 0;
 };
 
-int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
+// the schedule with its defaults filled in, and its checks
+ustd_batch_schedule schedule_of(const ustd_batch_schedule *s) {
+    ustd_batch_schedule r{};
+    if (s) r = *s;
+    if (r.group_fills == 0) r.group_fills = kBatchGroupFills;
+    if (r.branches == 1) r.branches = 0;
+    return r;
+}
+int check_schedule(const ustd_batch_schedule &s) {
+    if (s.group_fills < -1) return fail(USTD_EINVAL, "group_fills %d (> 0, 0 or -1)", s.group_fills);
+    if (s.agg_chunk != 0 && s.agg_chunk != kAggChunk && s.agg_chunk != kAggChunkLarge)
+        return fail(USTD_EINVAL, "agg_chunk %d (0, %d or %d)", s.agg_chunk, kAggChunkLarge, kAggChunk);
+    if (s.layout != USTD_LAYOUT_AUTO && s.layout != USTD_LAYOUT_RECORDS)
+        return fail(USTD_EINVAL, "layout %d", s.layout);
+    if (s.fill_trees < 0) return fail(USTD_EINVAL, "fill_trees %lld < 0", (long long)s.fill_trees);
+    if (s.branches < 0 || s.branches > kMaxBranches) return fail(USTD_EINVAL, "branches %d (0 .. %d)", s.branches, kMaxBranches);
+    return USTD_OK;
+}
+
+int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B, const ustd_batch_schedule &S) {
     if (!probs || count <= 0) return fail(USTD_EINVAL, "empty batch");
     long long o = 0, want_rec = 0, min_rec = 0, want_tiles = 0;
     bool bounded = true;
+    B.lds_bits = S.layout == USTD_LAYOUT_AUTO;
     for (int i = 0; i < count; ++i) {
         const int rc = check_problem(&probs[i]);
         if (rc != USTD_OK) {
@@ -1162,8 +1183,9 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
         }
     }
     B.max_tiles = std::max(1ll, std::min(bounded ? want_tiles : kMaxBatchTiles, kMaxBatchTiles));
+    if (S.fill_trees > 0) B.max_tiles = std::min<long long>(B.max_tiles, S.fill_trees);
     B.slots = (int)std::min<long long>(kSamplerMaxBlocks, B.max_tiles);
-    const long long slot_bytes = 2 * (long long)B.slots * kSamplerPathSlot * 4;
+    const long long slot_bytes = 2 * (long long)kSamplerMaxBlocks * kSamplerPathSlot * 4;
     long long pool = std::max(kDefaultBudget - slot_bytes, min_rec);
     if (bounded) pool = std::min(pool, std::max(want_rec, min_rec));
     B.rec_pool = align_up(pool);
@@ -1172,16 +1194,23 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B) {
         o += align_up(bytes);
         return at;
     };
-    B.off_queue = take(2 * sizeof(int));
+    B.off_queue = take(kMaxBranches * sizeof(int));
     B.off_rec = take(B.rec_pool);
-    B.off_path = take(2 * (long long)B.slots * kSamplerPathSlot * 4);  // two launches per fill
-    B.off_steps = take(B.max_tiles * 8);
-    B.off_draws = take(B.max_tiles * 8);
-    B.off_tiles = take(B.max_tiles * (long long)sizeof(WilsonTile));
-    B.off_graphs = take((long long)count * (long long)sizeof(WilsonGraph));
-    B.off_jobs = take((long long)count * (long long)sizeof(SolveJob<double>));
-    B.off_jobs32 = take((long long)count * (long long)sizeof(SolveJob<float>));
+    B.off_path = take(2 * (long long)kSamplerMaxBlocks * kSamplerPathSlot * 4);  // two launches per fill
+    B.off_steps = take(std::min(bounded ? want_tiles : kMaxBatchTiles, kMaxBatchTiles) * 8);
+    B.off_draws = take(std::min(bounded ? want_tiles : kMaxBatchTiles, kMaxBatchTiles) * 8);
     B.total = o;
+    return USTD_OK;
+}
+
+// the workspace of a batch: enough for every schedule (the records layout needs edge entries)
+int batch_workspace(const ustd_problem *probs, int count, long long *bytes) {
+    BatchPlan a, b;
+    ustd_batch_schedule s = schedule_of(nullptr);
+    USTD_TRY(make_batch_plan(probs, count, a, s));
+    s.layout = USTD_LAYOUT_RECORDS;
+    USTD_TRY(make_batch_plan(probs, count, b, s));
+    *bytes = std::max(a.total, b.total);
     return USTD_OK;
 }
 
@@ -1191,27 +1220,256 @@ int member(int i, int rc) {
     return fail(rc, "problem %d: %s", i, m.c_str());
 }
 
-// One-workgroup pivot-column solves of the batch members listed in `idx` on `st`: one launch
-// per precision and row-group size with a workgroup per member (the same kernel body, stopping
-// rule, projection and final residual as a single call with the one-workgroup engine, so the
-// results are bit-identical to it).  Each member's ms_solve is an equal share of the batched
-// solve's time.  A member that does not converge sets *status to USTD_ENOTCONV (its message
-// names it).
-int solve_small_batch(std::vector<Ctx> &cs, const std::vector<int> &idx, const BatchPlan &B, void *d_ws,
-                      hipStream_t st, ustd_report *R, int *status) {
+// the pieces of a planned batch: a run of tiles of one pool fill sampled by one persistent
+// launch (a group), the members' trees in it (segments, for Algorithm 2), and the fills
+struct BatchSeg {
+    int graph;
+    long long ntrees, rec_off;
+};
+struct BatchGroup {
+    int t0, cnt;  // tiles of the fill
+    bool weighted;
+    int branch;  // chain of a batch split into branches, else -1
+    std::vector<BatchSeg> segs;
+};
+struct BatchFill {
+    long long tile0;  // first tile in the plan's tile table
+    int ntiles;
+    std::vector<BatchGroup> groups;
+};
+
+// Re-enqueues a member's set-up with the pivot and eccentricity its plan found (no host round
+// trip): the CSR views and heavy-row list, the BFS tree B_u (ecc levels), its intervals and
+// marks, the sampler's edge entries, and a weighted graph's row sums, B-path resistances and
+// edge factors at the planned fixed-point shift.  The kernels are deterministic, so the
+// workspace ends as the plan's set-up left it.
+int setup_replay(Ctx &c) {
+    const ustd_problem *p = c.p;
+    const Plan &L = c.L;
+    const int n = L.n;
+    hipStream_t st = c.st;
+    void *ws = c.ws;
+    HIP_TRY(launch_rp_to_i32(n, (const long long *)p->d_row_ptr, c.rp32, st));
+    if (L.col16) HIP_TRY(launch_col_to_u16(L.nnz, p->d_col, at<unsigned short>(ws, L.off_col16), st));
+    HIP_TRY(launch_heavy_list(n, c.rp32, L.heavy_thresh, at<int>(ws, L.off_bcount), at<int>(ws, L.off_heavy),
+                              &c.misc->nheavy, st));
+    if (L.weighted)
+        HIP_TRY(launch_row_cumsum(n, L.nnz, c.rp32, p->d_weight, L.heavy_thresh, c.rows.heavy, c.rows.nheavy,
+                                  at<double>(ws, L.off_cw), at<double>(ws, L.off_wdeg), at<int>(ws, L.off_guide), st));
+    int *dist = at<int>(ws, L.off_dist), *parB = at<int>(ws, L.off_parB);
+    if (n <= kSmallSolveMaxN) {
+        HIP_TRY(launch_setup_small(c.rows, L.G, c.pivot, dist, parB, at<int>(ws, L.off_scr), at<int2>(ws, L.off_bint),
+                                   at<int>(ws, L.off_bflag), c.misc->setup_out, st));
+    } else {
+        HIP_TRY(launch_bfs_init(n, c.pivot, dist, parB, st));
+        for (int d = 0; d < c.ecc; ++d)
+            HIP_TRY(launch_bfs_level(c.rows, L.G, d, dist, parB, &c.misc->bfs_found[0], nullptr, st));
+        HIP_TRY(launch_b_intervals(n, c.pivot, c.ecc, dist, parB, at<int>(ws, L.off_scr), at<int2>(ws, L.off_bint),
+                                   at<int>(ws, L.off_bflag), st));
+    }
+    if (L.edges) {
+        HIP_TRY(launch_vertex_rows(n, c.rp32, at<int>(ws, L.off_bflag), at<int4>(ws, L.off_vrow), st));
+        HIP_TRY(launch_edge_rows(L.nnz, p->d_col, at<int4>(ws, L.off_vrow), at<int4>(ws, L.off_edge), st));
+    }
+    if (L.weighted) {
+        double *wB = at<double>(ws, L.off_wB);
+        HIP_TRY(launch_fill_i64(1, reinterpret_cast<long long *>(&c.misc->rho_max_bits), 0, st));
+        HIP_TRY(launch_bpath(n, c.pivot, c.rp32, p->d_col, p->d_weight, parB, wB, &c.misc->rho_max_bits, st));
+        HIP_TRY(launch_fixed_weights(n, c.pivot, wB, c.shift, at<long long>(ws, L.off_F), st));
+    }
+    return USTD_OK;
+}
+
+}  // namespace
+
+// A batch set up once and executed by kernel launches only.
+struct ustd_batch_plan {
+    int count = 0, device = 0;
+    std::vector<ustd_problem> probs;  // copies; the contexts point here
+    BatchPlan B;
+    ustd_batch_schedule sched{};
+    void *ws = nullptr;
+    std::vector<Ctx> cs;
+    std::vector<long long> tau;
+    std::vector<ustd_report> setup_rep;  // what the set-up fixed, per member
+    std::vector<BatchFill> fills;
+    long long largest = 0;  // tiles of the largest fill
+    int resident = 0, resident_w = 0;
+    // pivot-column solves: one-workgroup members by (precision, row-group size) runs, the
+    // others (multi-kernel engine, host-driven)
+    std::vector<int> small, big;
+    std::vector<std::pair<int, int>> runs64, runs32;  // (row-group size, jobs), in launch order
+    std::vector<double> tols;
+    std::vector<ustd_report> big_rep;  // solve fields of the host-driven members, last execution
+    std::vector<int> big_rc;
+    // the plan's device memory: tiles of every fill, graph table, solve jobs, walk totals
+    char *dmem = nullptr;
+    WilsonTile *d_tiles = nullptr;
+    WilsonGraph *d_graphs = nullptr;
+    SolveJob<double> *d_j64 = nullptr;
+    SolveJob<float> *d_j32 = nullptr;
+    unsigned long long *d_totals = nullptr;
+    // timers of the last eager execution
+    bool timed = false;
+    std::vector<std::unique_ptr<SpanTimer>> ts, ta;
+    std::unique_ptr<SpanTimer> t_solve, t_combine, t_total;
+    ~ustd_batch_plan() {
+        if (dmem) (void)hipFree(dmem);
+    }
+};
+
+namespace {
+
+// Set-up of every member (with host readbacks: validation, pivot, eccentricity, tau), the
+// schedule of tiles over pool fills and sampler groups, the solve jobs, and the plan's device
+// memory.  A pool fill takes members in order (unweighted before weighted, then decreasing
+// eccentricity: the longest B-paths, so the costliest Algorithm 2, first) as far as the
+// record pool and fill_trees allow; a fill is split into groups of whole members of about
+// group_fills GPU-fills of trees (one persistent launch each, one kind per launch), each
+// group's tiles by decreasing graph size (the longest trees start first), a member's trees in
+// order.
+int batch_plan_create(const ustd_problem *probs, int count, void *d_ws, size_t ws_bytes,
+                      const ustd_batch_schedule *sched, std::unique_ptr<ustd_batch_plan> &out, hipStream_t st) {
+    auto P = std::make_unique<ustd_batch_plan>();
+    P->sched = schedule_of(sched);
+    USTD_TRY(check_schedule(P->sched));
+    BatchPlan &B = P->B;
+    USTD_TRY(make_batch_plan(probs, count, B, P->sched));
+    USTD_TRY(check_ws(d_ws, ws_bytes, B.total));
+    HIP_TRY(hipGetDevice(&P->device));
+    P->count = count;
+    P->probs.assign(probs, probs + count);
+    P->ws = d_ws;
+    P->cs.resize(count);
+    P->tau.assign(count, 0);
+    P->setup_rep.assign(count, ustd_report{});
+    P->big_rep.assign(count, ustd_report{});
+    P->big_rc.assign(count, USTD_OK);
+    P->tols.assign(count, 0.0);
+    std::vector<WilsonGraph> gt(count);
+    for (int i = 0; i < count; ++i) {
+        void *wsi = static_cast<char *>(d_ws) + B.base[i];
+        Ctx &c = P->cs[i];
+        USTD_TRY(member(i, begin_with(c, &P->probs[i], B.g[i], wsi, st)));
+        Timer tm(st);
+        USTD_TRY(member(i, setup(c, &P->setup_rep[i])));
+        P->setup_rep[i].ms_bfs = tm.stop_ms();
+        P->tau[i] = problem_tau(c);
+        P->setup_rep[i].tau = P->tau[i];
+        gt[i] = wilson_graph(c);
+        gt[i].colv = B.col16 ? (const void *)at<unsigned short>(wsi, B.g[i].off_col16) : (const void *)probs[i].d_col;
+    }
+    HIP_TRY(hipStreamSynchronize(st));  // a weighted member's side-stream set-up is joined into st
+
+    // fills and groups
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (B.g[a].weighted != B.g[b].weighted) return !B.g[a].weighted;
+        const Ctx &ca = P->cs[a], &cb = P->cs[b];
+        return ca.ecc != cb.ecc ? ca.ecc > cb.ecc : B.g[a].n > B.g[b].n;
+    });
+    P->resident = wilson_resident_blocks(B.lds_bits, B.col16, false, B.nwords_max);
+    P->resident_w = wilson_resident_blocks(B.lds_bits, B.col16, true, B.nwords_max);
+    const long long group_trees =
+        P->sched.group_fills > 0 ? (long long)P->sched.group_fills * std::max(P->resident, 1) : LLONG_MAX;
+    std::vector<WilsonTile> tiles;
+    std::vector<long long> next(count, 0);
+    for (;;) {
+        std::vector<std::pair<int, long long>> part;  // members of this fill, with their tree counts
+        long long used = 0, ntiles = 0;
+        for (int gi : order) {
+            const long long left = P->tau[gi] - next[gi];
+            if (left <= 0) continue;
+            const long long rb = B.g[gi].rec_stride * 8;
+            const long long fit = std::min((B.rec_pool - used) / rb, B.max_tiles - ntiles);
+            const long long lim = probs[gi].trees_per_batch > 0 ? probs[gi].trees_per_batch : left;
+            const long long take = std::min(std::min(left, fit), lim);
+            if (take <= 0) break;
+            part.emplace_back(gi, take);
+            used += take * rb;
+            ntiles += take;
+        }
+        if (part.empty()) break;
+        BatchFill F{(long long)tiles.size(), 0, {}};
+        long long rec_used = 0;
+        // the fill's members in launch groups: runs of `order` (alternating groups), or each
+        // branch's members of one kind (branches; members to the least loaded branch, largest
+        // estimated work first: tau (n ecc + nnz), walks and Algorithm 2)
+        std::vector<std::pair<int, std::vector<std::pair<int, long long>>>> runs;  // (branch, members)
+        if (P->sched.branches >= 2) {
+            const int nb = P->sched.branches;
+            std::vector<std::pair<double, size_t>> work;
+            for (size_t k = 0; k < part.size(); ++k) {
+                const Plan &L = B.g[part[k].first];
+                work.emplace_back((double)part[k].second *
+                                      ((double)L.n * (double)std::max(P->cs[part[k].first].ecc, 1) + (double)L.nnz),
+                                  k);
+            }
+            std::stable_sort(work.begin(), work.end(),
+                             [](const std::pair<double, size_t> &a, const std::pair<double, size_t> &b) {
+                                 return a.first > b.first;
+                             });
+            std::vector<double> load(nb, 0.0);
+            std::vector<std::vector<std::pair<int, long long>>> br(2 * nb);  // (branch, kind)
+            for (auto &wk : work) {
+                const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                load[b] += wk.first;
+                br[2 * b + (B.g[part[wk.second].first].weighted ? 1 : 0)].push_back(part[wk.second]);
+            }
+            for (int b = 0; b < 2 * nb; ++b)
+                if (!br[b].empty()) runs.emplace_back(b / 2, br[b]);
+        } else {
+            for (size_t k = 0; k < part.size();) {
+                size_t e = k;
+                long long cnt = 0;
+                const bool wk = B.g[part[k].first].weighted;
+                while (e < part.size() && (e == k || cnt < group_trees) && B.g[part[e].first].weighted == wk)
+                    cnt += part[e++].second;
+                runs.emplace_back(-1, std::vector<std::pair<int, long long>>(part.begin() + k, part.begin() + e));
+                k = e;
+            }
+        }
+        for (auto &run : runs) {
+            std::vector<std::pair<int, long long>> &mem = run.second;
+            std::stable_sort(mem.begin(), mem.end(), [&](const std::pair<int, long long> &x,
+                                                         const std::pair<int, long long> &y) {
+                return B.g[x.first].n > B.g[y.first].n;
+            });
+            BatchGroup G{(int)(tiles.size() - F.tile0), 0, B.g[mem[0].first].weighted, run.first, {}};
+            for (auto &pr : mem) {
+                const int gi = pr.first;
+                const long long take = pr.second;
+                G.segs.push_back(BatchSeg{gi, take, rec_used / 8});
+                for (long long j = 0; j < take; ++j)
+                    tiles.push_back(WilsonTile{next[gi] + j, rec_used / 8 + j * B.g[gi].rec_stride, gi, 0});
+                rec_used += take * B.g[gi].rec_stride * 8;
+                next[gi] += take;
+            }
+            G.cnt = (int)(tiles.size() - F.tile0) - G.t0;
+            F.groups.push_back(std::move(G));
+        }
+        F.ntiles = (int)(tiles.size() - F.tile0);
+        P->largest = std::max<long long>(P->largest, F.ntiles);
+        P->fills.push_back(std::move(F));
+    }
+
+    // solves: members on the one-workgroup engine (all by default) in one launch per precision
+    // and row-group size, a workgroup each; the others by the host-driven multi-kernel loop
     std::vector<SolveJob<double>> j64;
     std::vector<SolveJob<float>> j32;
-    std::vector<std::pair<int, int>> runs64, runs32;  // (row-group size, jobs) in launch order
-    std::vector<double> tols(cs.size(), 0.0);
+    for (int i = 0; i < count; ++i) {
+        P->tols[i] = solve_target(&P->probs[i], P->cs[i].ecc);
+        (one_workgroup(&P->probs[i], B.g[i].n, true) ? P->small : P->big).push_back(i);
+    }
     for (int mixed = 0; mixed < 2; ++mixed)
         for (int G : {4, 8, 16, 32}) {
             int cnt = 0;
-            for (int i : idx) {
-                Ctx &c = cs[i];
+            for (int i : P->small) {
+                Ctx &c = P->cs[i];
                 const bool mx = c.p->solve_mode == USTD_SOLVE_MIXED;
                 if (c.L.G != G || (int)mx != mixed) continue;
-                const double tol = solve_target(c.p, c.ecc);
-                tols[i] = tol;
+                const double tol = P->tols[i];
                 const int maxit = c.p->solve_maxit > 0 ? c.p->solve_maxit : 20000;
                 double *x = at<double>(c.ws, B.g[i].off_x64);
                 if (mx) j32.push_back(SolveJob<float>{solve_args<float>(c, c.ws, c.L, x), c.rows, tol * tol,
@@ -1220,55 +1478,385 @@ int solve_small_batch(std::vector<Ctx> &cs, const std::vector<int> &idx, const B
                                                     solve_delta2(c.p), maxit});
                 ++cnt;
             }
-            if (cnt) (mixed ? runs32 : runs64).emplace_back(G, cnt);
+            if (cnt) (mixed ? P->runs32 : P->runs64).emplace_back(G, cnt);
         }
-    if (j64.size() + j32.size() != idx.size()) return fail(USTD_EINVAL, "unexpected row-group size in a batched solve");
-    SolveJob<double> *d64 = at<SolveJob<double>>(d_ws, B.off_jobs);
-    SolveJob<float> *d32 = at<SolveJob<float>>(d_ws, B.off_jobs32);
-    Timer tm(st);
+    if (j64.size() + j32.size() != P->small.size())
+        return fail(USTD_EINVAL, "unexpected row-group size in a batched solve");
+
+    // device memory of the plan
+    const long long b_tiles = align_up((long long)std::max<size_t>(tiles.size(), 1) * sizeof(WilsonTile));
+    const long long b_graphs = align_up((long long)count * sizeof(WilsonGraph));
+    const long long b_j64 = align_up((long long)std::max<size_t>(j64.size(), 1) * sizeof(SolveJob<double>));
+    const long long b_j32 = align_up((long long)std::max<size_t>(j32.size(), 1) * sizeof(SolveJob<float>));
+    const long long b_tot = align_up((long long)count * 2 * sizeof(unsigned long long));
+    if (hipMalloc((void **)&P->dmem, (size_t)(b_tiles + b_graphs + b_j64 + b_j32 + b_tot)) != hipSuccess) {
+        (void)hipGetLastError();
+        P->dmem = nullptr;
+        return fail(USTD_ENOMEM, "plan memory of %lld bytes", b_tiles + b_graphs + b_j64 + b_j32 + b_tot);
+    }
+    P->d_tiles = reinterpret_cast<WilsonTile *>(P->dmem);
+    P->d_graphs = reinterpret_cast<WilsonGraph *>(P->dmem + b_tiles);
+    P->d_j64 = reinterpret_cast<SolveJob<double> *>(P->dmem + b_tiles + b_graphs);
+    P->d_j32 = reinterpret_cast<SolveJob<float> *>(P->dmem + b_tiles + b_graphs + b_j64);
+    P->d_totals = reinterpret_cast<unsigned long long *>(P->dmem + b_tiles + b_graphs + b_j64 + b_j32);
+    if (!tiles.empty())
+        HIP_TRY(hipMemcpy(P->d_tiles, tiles.data(), sizeof(WilsonTile) * tiles.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(P->d_graphs, gt.data(), sizeof(WilsonGraph) * (size_t)count, hipMemcpyHostToDevice));
     if (!j64.empty())
-        HIP_TRY(hipMemcpyAsync(d64, j64.data(), sizeof(SolveJob<double>) * j64.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpy(P->d_j64, j64.data(), sizeof(SolveJob<double>) * j64.size(), hipMemcpyHostToDevice));
     if (!j32.empty())
-        HIP_TRY(hipMemcpyAsync(d32, j32.data(), sizeof(SolveJob<float>) * j32.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpy(P->d_j32, j32.data(), sizeof(SolveJob<float>) * j32.size(), hipMemcpyHostToDevice));
+    out = std::move(P);
+    return USTD_OK;
+}
+
+// the one-workgroup solves, then every such member's projection and final residual, on st
+int enqueue_small_solves(ustd_batch_plan &P, std::vector<Ctx> &cs, hipStream_t st) {
     int off = 0;
-    for (auto &r : runs64) {
-        HIP_TRY(launch_solve_small_batch<double>(d64 + off, r.second, r.first, st));
+    for (auto &r : P.runs64) {
+        HIP_TRY(launch_solve_small_batch<double>(P.d_j64 + off, r.second, r.first, st));
         off += r.second;
     }
     off = 0;
-    for (auto &r : runs32) {
-        HIP_TRY(launch_solve_small_batch<float>(d32 + off, r.second, r.first, st));
+    for (auto &r : P.runs32) {
+        HIP_TRY(launch_solve_small_batch<float>(P.d_j32 + off, r.second, r.first, st));
         off += r.second;
     }
-    for (int i : idx) {
+    for (int i : P.small) {
         Ctx &c = cs[i];
-        double *x64 = at<double>(c.ws, B.g[i].off_x64);
+        double *x64 = at<double>(c.ws, P.B.g[i].off_x64);
         double *part = at<double>(c.ws, c.L.off_part) + 3 * kMaxSolveGrid;
         double *sums = c.misc->sums;
         HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, sums, st));
         HIP_TRY(launch_project(c.L.n, x64, sums + 2, vec_grid(c.L.n), st));
         HIP_TRY(launch_residual64(c.rows, c.L.G, c.pivot, x64, nullptr, part, sums, st));
     }
-    const double ms = tm.stop_ms();  // synchronises st
-    for (int i : idx) {
+    return USTD_OK;
+}
+
+// One execution: the members' set-up replayed on st; then, beside each other, the solves on
+// side stream 0, the sampler groups alternating between st and side stream 1 and each
+// group's Algorithm 2 on side stream 2; a pool fill starts once the previous one's groups
+// and Algorithm 2 are done (they share the record pool); all streams join st before the
+// combination.  No host wait unless a member uses the host-driven solve engine (eager only).
+int batch_plan_execute(ustd_batch_plan &P, double *const *d_diags, int64_t *const *d_counts, hipStream_t st) {
+    if (!d_diags) return fail(USTD_EINVAL, "d_diags is NULL");
+    for (int i = 0; i < P.count; ++i)
+        if (!d_diags[i]) return fail(USTD_EINVAL, "d_diags[%d] is NULL", i);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != P.device) return fail(USTD_EINVAL, "plan made on device %d, current device %d", P.device, dev);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cap));
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    if (capturing && !P.big.empty())
+        return fail(USTD_EINVAL, "problem %d uses the multi-kernel solve engine, which the host drives: it cannot be "
+                                 "captured", P.big[0]);
+    const bool timed = !capturing && !g_no_events;
+    P.timed = timed;
+    P.ts.clear();
+    P.ta.clear();
+    P.t_solve.reset();
+    P.t_combine.reset();
+    P.t_total.reset();
+    if (timed) {
+        P.t_solve.reset(new SpanTimer());
+        P.t_combine.reset(new SpanTimer());
+        P.t_total.reset(new SpanTimer());
+        P.t_total->start(st);
+    }
+    const BatchPlan &B = P.B;
+    std::vector<Ctx> cs = P.cs;
+    std::vector<long long *> counts(P.count);
+    for (int i = 0; i < P.count; ++i) {
         Ctx &c = cs[i];
+        c.st = st;
+        counts[i] = (d_counts && d_counts[i]) ? (long long *)d_counts[i] : at<long long>(c.ws, B.g[i].off_counts);
+        USTD_TRY(member(i, setup_replay(c)));
+        HIP_TRY(launch_fill_i64(B.g[i].n, counts[i], 0, st));
+    }
+    HIP_TRY(launch_fill_i64(2ll * P.count, reinterpret_cast<long long *>(P.d_totals), 0, st));
+
+    hipStream_t side = nullptr, samp1 = nullptr, aggq = nullptr, br3 = nullptr;
+    USTD_TRY(side_stream(&side, 0));
+    USTD_TRY(side_stream(&samp1, 1));
+    USTD_TRY(side_stream(&aggq, 2));
+    USTD_TRY(side_stream(&br3, 3));
+    const int nbr = P.sched.branches;
+    const hipStream_t br[kMaxBranches] = {st, samp1, aggq, br3};  // the chains of branch mode
+    std::vector<std::unique_ptr<SyncEvent>> evs;  // kept until every wait on them is queued
+    auto event = [&](hipStream_t s) -> hipEvent_t {
+        evs.emplace_back(new SyncEvent());
+        hipEvent_t e = evs.back()->e;
+        if (e && hipEventRecord(e, s) != hipSuccess) return nullptr;
+        return e;
+    };
+    auto wait = [&](hipStream_t s, hipEvent_t e) { return e && hipStreamWaitEvent(s, e, 0) == hipSuccess; };
+    hipEvent_t fork = event(st);
+    if (!wait(side, fork) || !wait(samp1, fork) || !wait(aggq, fork) || (nbr >= 4 && !wait(br3, fork)))
+        return fail(USTD_EHIP, "forking the batch streams failed");
+    if (timed) P.t_solve->start(side);
+    USTD_TRY(enqueue_small_solves(P, cs, side));
+
+    int2 *pool = at<int2>(P.ws, B.off_rec);
+    long long *steps = at<long long>(P.ws, B.off_steps), *draws = at<long long>(P.ws, B.off_draws);
+    int *queue = at<int>(P.ws, B.off_queue);
+    for (size_t f = 0; f < P.fills.size(); ++f) {
+        const BatchFill &F = P.fills[f];
+        if (f > 0) {  // the previous fill's groups and Algorithm 2 are done with the record pool
+            if (!wait(st, event(samp1)) || !wait(st, event(aggq)) || (nbr >= 4 && !wait(st, event(br3))))
+                return fail(USTD_EHIP, "joining a pool fill failed");
+            hipEvent_t ready = event(st);
+            if (!wait(samp1, ready) || !wait(aggq, ready) || (nbr >= 4 && !wait(br3, ready)))
+                return fail(USTD_EHIP, "starting a pool fill failed");
+        }
+        for (size_t gidx = 0; gidx < F.groups.size(); ++gidx) {
+            const BatchGroup &G = F.groups[gidx];
+            // alternating groups: streams st / 1, sampler scratch and tile counter by parity;
+            // branches: the branch's stream, scratch and counter (Algorithm 2 on that stream)
+            const int pool2 = G.branch >= 0 ? G.branch : (int)(gidx & 1);
+            hipStream_t s = G.branch >= 0 ? br[G.branch] : (pool2 ? samp1 : st);
+            hipStream_t sa = G.branch >= 0 ? s : aggq;
+            WilsonArgs a{};
+            a.graphs = P.d_graphs;
+            a.tiles = P.d_tiles + F.tile0 + G.t0;
+            a.ntiles = G.cnt;
+            a.rec = pool;
+            // sampler path slots: kSamplerMaxBlocks per stream of alternating groups; a branch's
+            // launch has at most kSamplerMaxBlocks / branches blocks and takes that share
+            const long long slot0 = G.branch >= 0 ? (long long)G.branch * (kSamplerMaxBlocks / nbr)
+                                                  : (long long)pool2 * kSamplerMaxBlocks;
+            a.path = at<int>(P.ws, B.off_path) + slot0 * kSamplerPathSlot;
+            a.queue = queue + pool2;
+            a.steps = steps + G.t0;
+            a.draws = draws + G.t0;
+            const int res = G.weighted ? P.resident_w : P.resident;
+            int blocks = std::min(G.cnt, B.slots);
+            if (res > 0) blocks = std::min(blocks, res);
+            if (G.branch >= 0) blocks = std::max(1, std::min(blocks, std::min(res > 0 ? res : kSamplerMaxBlocks,
+                                                                                  kSamplerMaxBlocks) / nbr));
+            if (timed) {
+                P.ts.emplace_back(new SpanTimer());
+                P.ts.back()->start(s);
+            }
+            HIP_TRY(launch_fill_i32(1, queue + pool2, 0, s));
+            HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, G.weighted, B.nwords_max, s));
+            if (timed) P.ts.back()->stop(s);
+            HIP_TRY(launch_tile_walks(G.cnt, a.tiles, a.steps, a.draws, P.d_totals, s));
+            if (sa != s && !wait(sa, event(s)))
+                return fail(USTD_EHIP, "ordering Algorithm 2 after a sampler group failed");
+            if (timed) {
+                P.ta.emplace_back(new SpanTimer());
+                P.ta.back()->start(sa);
+            }
+            for (const BatchSeg &sg : G.segs) {
+                const Ctx &c = cs[sg.graph];
+                const Plan &L = B.g[sg.graph];
+                AggregateArgs aa{};
+                aa.n = L.n;
+                aa.u = c.pivot;
+                aa.ntrees = (int)sg.ntrees;
+                aa.parB = at<int>(c.ws, L.off_parB);
+                aa.bint = at<int2>(c.ws, L.off_bint);
+                aa.rec = pool + sg.rec_off;
+                aa.rec_stride = L.rec_stride;
+                aa.counts = counts[sg.graph];
+                aa.F = L.weighted ? at<long long>(c.ws, L.off_F) : nullptr;
+                aa.chunk = P.sched.agg_chunk > 0 ? P.sched.agg_chunk : agg_chunk(c.ecc);
+                HIP_TRY(launch_aggregate(aa, sa));
+            }
+            if (timed) P.ta.back()->stop(sa);
+        }
+    }
+    // members on the host-driven engine: every fill is queued, the GPU samples meanwhile
+    for (int i : P.big) {
+        Ctx ci = cs[i];
+        ci.st = side;
+        ustd_report r{};
+        const int rc = solve_column(ci, at<double>(ci.ws, B.g[i].off_x64), &r);
+        if (rc != USTD_OK && rc != USTD_ENOTCONV) {
+            (void)hipStreamSynchronize(side);
+            return member(i, rc);
+        }
+        P.big_rep[i] = r;
+        P.big_rc[i] = rc;
+    }
+    if (timed) P.t_solve->stop(side);
+    if (!wait(st, event(side)) || !wait(st, event(samp1)) || !wait(st, event(aggq)) ||
+        (nbr >= 4 && !wait(st, event(br3))))
+        return fail(USTD_EHIP, "joining the batch streams failed");
+    if (timed) P.t_combine->start(st);
+    for (int i = 0; i < P.count; ++i)
+        HIP_TRY(launch_combine(B.g[i].n, cs[i].pivot, count_scale(cs[i], P.tau[i]), counts[i],
+                               at<double>(cs[i].ws, B.g[i].off_x64), d_diags[i], st));
+    if (timed) {
+        P.t_combine->stop(st);
+        P.t_total->stop(st);
+    }
+    return USTD_OK;
+}
+
+// reports of the last execution; synchronises st
+int batch_plan_reports(ustd_batch_plan &P, ustd_report *R, hipStream_t st) {
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<unsigned long long> tot(2 * (size_t)P.count);
+    HIP_TRY(hipMemcpy(tot.data(), P.d_totals, sizeof(unsigned long long) * tot.size(), hipMemcpyDeviceToHost));
+    double ms_s = 0, ms_a = 0;
+    for (auto &t : P.ts) ms_s += t->ms();
+    for (auto &t : P.ta) ms_a += t->ms();
+    const double ms_solve = P.timed && P.t_solve ? P.t_solve->ms() : 0.0;
+    const double ms_comb = P.timed && P.t_combine ? P.t_combine->ms() : 0.0;
+    const double ms_tot = P.timed && P.t_total ? P.t_total->ms() : 0.0;
+    int status = USTD_OK;
+    for (int i = 0; i < P.count; ++i) {
+        ustd_report &r = R[i];
+        r = P.setup_rep[i];
+        r.walk_steps = (long long)tot[2 * i];
+        r.walk_draws = (long long)tot[2 * i + 1];
+        r.n_batches = (int32_t)P.fills.size();
+        r.trees_per_batch = (int32_t)P.largest;
+        r.ms_sample = ms_s;
+        r.ms_aggregate = ms_a;
+        r.ms_combine = ms_comb / (double)P.count;
+        r.ms_total = ms_tot;
+        r.solve_tol = P.tols[i];
+        if (std::find(P.big.begin(), P.big.end(), i) != P.big.end()) {
+            const ustd_report &b = P.big_rep[i];
+            r.solve_iters = b.solve_iters;
+            r.solve_outer = b.solve_outer;
+            r.solve_relres = b.solve_relres;
+            r.solve_converged = b.solve_converged;
+            r.ms_solve = b.ms_solve;
+            if (P.big_rc[i] != USTD_OK && status == USTD_OK)
+                status = member(i, fail(P.big_rc[i], "solve stopped at relative residual %.3e (target %.3e)",
+                                        b.solve_relres, P.tols[i]));
+            continue;
+        }
+        const Ctx &c = P.cs[i];
         SolveScalars sc{};
         double hs[4];
         HIP_TRY(hipMemcpy(&sc, &c.misc->sc, sizeof(sc), hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(hs, c.misc->sums, sizeof(hs), hipMemcpyDeviceToHost));
         const double bnorm = std::sqrt((double)(c.L.n - 1) / (double)c.L.n);
         const double relres = std::sqrt(std::max(hs[1], 0.0)) / bnorm;
-        const bool conv = relres <= tols[i];
-        R[i].solve_iters += sc.iter;
-        R[i].solve_outer += sc.updates;
-        R[i].solve_relres = relres;
-        R[i].solve_tol = tols[i];
-        R[i].solve_converged = conv ? 1 : 0;
-        R[i].ms_solve += ms / (double)idx.size();
-        if (!conv)
-            *status = member(i, fail(USTD_ENOTCONV, "solve stopped at relative residual %.3e (target %.3e)", relres,
-                                     tols[i]));
+        const bool conv = relres <= P.tols[i];
+        r.solve_iters = sc.iter;
+        r.solve_outer = sc.updates;
+        r.solve_relres = relres;
+        r.solve_converged = conv ? 1 : 0;
+        r.ms_solve = P.small.empty() ? 0.0 : ms_solve / (double)P.small.size();
+        if (!conv && status == USTD_OK)
+            status = member(i, fail(USTD_ENOTCONV, "solve stopped at relative residual %.3e (target %.3e)", relres,
+                                    P.tols[i]));
     }
+    return status;
+}
+
+// ---------------------------------------------------------------------------------------
+// autotuner cache: a JSON object of schedules keyed by the batch's shape and the device,
+// one entry per line, {"key": {"group_fills": g, "agg_chunk": c, "layout": l, "branches": b, "fill_trees": f,
+// "ms": t}}
+// ---------------------------------------------------------------------------------------
+struct TuneEntry {
+    ustd_batch_schedule s{};
+    double ms = 0.0;
+};
+
+bool json_number(const std::string &obj, const char *name, double *v) {
+    const std::string k = std::string("\"") + name + "\"";
+    const size_t at_ = obj.find(k);
+    if (at_ == std::string::npos) return false;
+    size_t c = obj.find(':', at_ + k.size());
+    if (c == std::string::npos) return false;
+    char *end = nullptr;
+    const double x = std::strtod(obj.c_str() + c + 1, &end);
+    if (end == obj.c_str() + c + 1) return false;
+    *v = x;
+    return true;
+}
+
+// entries of the cache file (missing or unreadable: none); malformed entries are skipped
+std::vector<std::pair<std::string, TuneEntry>> read_tune_cache(const std::string &path) {
+    std::vector<std::pair<std::string, TuneEntry>> out;
+    FILE *f = std::fopen(path.c_str(), "rb");
+    if (!f) return out;
+    std::string text;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, k);
+    std::fclose(f);
+    size_t pos = 0;
+    for (;;) {
+        const size_t q0 = text.find('"', pos);
+        if (q0 == std::string::npos) break;
+        const size_t q1 = text.find('"', q0 + 1);
+        if (q1 == std::string::npos) break;
+        const size_t b0 = text.find('{', q1);
+        const size_t b1 = b0 == std::string::npos ? b0 : text.find('}', b0);
+        if (b1 == std::string::npos) break;
+        const std::string key = text.substr(q0 + 1, q1 - q0 - 1), obj = text.substr(b0, b1 - b0 + 1);
+        pos = b1 + 1;
+        double g = 0, c = 0, l = 0, ft = 0, ms = 0, nb = 0;
+        if (!json_number(obj, "group_fills", &g) || !json_number(obj, "agg_chunk", &c) ||
+            !json_number(obj, "layout", &l) || !json_number(obj, "fill_trees", &ft))
+            continue;
+        json_number(obj, "ms", &ms);
+        json_number(obj, "branches", &nb);
+        TuneEntry e;
+        e.s.branches = (int32_t)nb;
+        e.s.group_fills = (int32_t)g;
+        e.s.agg_chunk = (int32_t)c;
+        e.s.layout = (int32_t)l;
+        e.s.fill_trees = (int64_t)ft;
+        e.ms = ms;
+        out.emplace_back(key, e);
+    }
+    return out;
+}
+
+int write_tune_cache(const std::string &path, const std::vector<std::pair<std::string, TuneEntry>> &entries) {
+    const std::string tmp = path + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return fail(USTD_EINVAL, "cannot write the tuning cache %s", tmp.c_str());
+    std::fprintf(f, "{\n");
+    for (size_t i = 0; i < entries.size(); ++i) {
+        const TuneEntry &e = entries[i].second;
+        std::fprintf(f, "  \"%s\": {\"group_fills\": %d, \"agg_chunk\": %d, \"layout\": %d, \"branches\": %d, "
+                        "\"fill_trees\": %lld, \"ms\": %.3f}%s\n",
+                     entries[i].first.c_str(), e.s.group_fills, e.s.agg_chunk, e.s.layout, e.s.branches,
+                     (long long)e.s.fill_trees, e.ms, i + 1 < entries.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0)
+        return fail(USTD_EINVAL, "cannot write the tuning cache %s", path.c_str());
+    return USTD_OK;
+}
+
+// the cache key: device architecture and compute units, then each member's n, nnz, tau, ecc
+// and weightedness, hashed (FNV-1a, 64 bits)
+int tune_key(const ustd_batch_plan &P, std::string *key) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    std::string d;
+    char buf[128];
+    for (int i = 0; i < P.count; ++i) {
+        std::snprintf(buf, sizeof(buf), "%lld,%lld,%lld,%d,%d;", (long long)P.probs[i].n, (long long)P.probs[i].nnz,
+                      P.tau[i], P.cs[i].ecc, P.B.g[i].weighted ? 1 : 0);
+        d += buf;
+    }
+    unsigned long long h = 1469598103934665603ull;
+    for (unsigned char ch : d) {
+        h ^= ch;
+        h *= 1099511628211ull;
+    }
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    std::snprintf(buf, sizeof(buf), "%s-cu%d-m%d-%016llx", arch.c_str(), prop.multiProcessorCount, P.count, h);
+    *key = buf;
     return USTD_OK;
 }
 
@@ -1534,264 +2122,256 @@ int ustd_diag_lpinv_noalloc(const ustd_problem *prob, double *d_diag, int64_t *d
 int ustd_batch_workspace_bytes(const ustd_problem *probs, int32_t count, size_t *bytes) {
     g_err.clear();
     if (!bytes) return fail(USTD_EINVAL, "bytes is NULL");
-    BatchPlan B;
-    USTD_TRY(make_batch_plan(probs, count, B));
-    *bytes = (size_t)B.total;
+    long long b = 0;
+    USTD_TRY(batch_workspace(probs, count, &b));
+    *bytes = (size_t)b;
     return USTD_OK;
 }
 
 int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, size_t ws_bytes,
                           double *const *d_diags, int64_t *const *d_counts, ustd_report *reps, void *stream) {
     g_err.clear();
-    BatchPlan B;
-    USTD_TRY(make_batch_plan(probs, count, B));
-    USTD_TRY(check_ws(d_ws, ws_bytes, B.total));
     if (!d_diags) return fail(USTD_EINVAL, "d_diags is NULL");
     for (int i = 0; i < count; ++i)
         if (!d_diags[i]) return fail(USTD_EINVAL, "d_diags[%d] is NULL", i);
     hipStream_t st = (hipStream_t)stream;
+    std::unique_ptr<ustd_batch_plan> P;
+    Timer total(st);
+    USTD_TRY(batch_plan_create(probs, count, d_ws, ws_bytes, nullptr, P, st));
+    const int rc = batch_plan_execute(*P, d_diags, d_counts, st);
+    if (rc != USTD_OK) {
+        (void)hipStreamSynchronize(st);
+        return rc;
+    }
     std::vector<ustd_report> local(count);
     ustd_report *R = reps ? reps : local.data();
-    memset(R, 0, sizeof(ustd_report) * (size_t)count);
-    Timer total(st);
-
-    // per member: preparation, BFS tree B_u, tau, zeroed counts
-    std::vector<Ctx> cs(count);
-    std::vector<long long> tau(count), next(count, 0);
-    std::vector<long long *> counts(count);
-    std::vector<WilsonGraph> gt(count);
-    for (int i = 0; i < count; ++i) {
-        void *wsi = static_cast<char *>(d_ws) + B.base[i];
-        USTD_TRY(member(i, begin_with(cs[i], &probs[i], B.g[i], wsi, stream)));
-        USTD_TRY(member(i, setup(cs[i], &R[i])));
-        tau[i] = problem_tau(cs[i]);
-        R[i].tau = tau[i];
-        counts[i] = (d_counts && d_counts[i]) ? (long long *)d_counts[i] : at<long long>(wsi, B.g[i].off_counts);
-        HIP_TRY(hipMemsetAsync(counts[i], 0, (size_t)B.g[i].n * 8, st));
-        gt[i] = wilson_graph(cs[i]);
-        gt[i].colv = B.col16 ? (const void *)at<unsigned short>(wsi, B.g[i].off_col16) : (const void *)probs[i].d_col;
-    }
-    WilsonGraph *d_graphs = at<WilsonGraph>(d_ws, B.off_graphs);
-    WilsonTile *d_tiles = at<WilsonTile>(d_ws, B.off_tiles);
-    int2 *pool = at<int2>(d_ws, B.off_rec);
-    long long *steps = at<long long>(d_ws, B.off_steps), *draws = at<long long>(d_ws, B.off_draws);
-    int *queue = at<int>(d_ws, B.off_queue);
-    HIP_TRY(hipMemcpyAsync(d_graphs, gt.data(), sizeof(WilsonGraph) * (size_t)count, hipMemcpyHostToDevice, st));
-
-    // A pool fill is sampled in groups of about kBatchGroupFills GPU-fills of trees, unweighted
-    // members before weighted ones (a group holds one kind: one sampler variant per launch),
-    // each kind in order of decreasing eccentricity (the longest B-paths, so the costliest Algorithm 2,
-    // first).  Groups alternate between the caller's stream and side stream 1, so one group's
-    // tail overlaps the next; each group's Algorithm 2 runs on side stream 2 once that group
-    // is sampled, beside the later groups' sampling.  Within a group, tiles go by decreasing
-    // graph size (the longest trees start first), each member's trees in order.
-    std::vector<int> order(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (B.g[a].weighted != B.g[b].weighted) return !B.g[a].weighted;  // one kind per group
-        return cs[a].ecc != cs[b].ecc ? cs[a].ecc > cs[b].ecc : B.g[a].n > B.g[b].n;
-    });
-    struct Seg {
-        int graph;
-        long long ntrees, rec_off;
-    };
-    std::vector<WilsonTile> tiles;
-    std::vector<long long> hs, hd;
-    double ms_s = 0, ms_a = 0;
-    int fills = 0;
-    long long largest = 0;
-    const int resident = wilson_resident_blocks(B.lds_bits, B.col16, false, B.nwords_max);
-    const int resident_w = wilson_resident_blocks(B.lds_bits, B.col16, true, B.nwords_max);
-    const long long group_trees = (long long)kBatchGroupFills * std::max(resident, 1);
-
-    // The members' pivot-column solves run on side stream 0 while the first pool fill is
-    // sampled (each solve touches only its member's solve vectors).
-    hipStream_t side = nullptr, samp1 = nullptr, aggq = nullptr;
-    USTD_TRY(side_stream(&side, 0));
-    USTD_TRY(side_stream(&samp1, 1));
-    USTD_TRY(side_stream(&aggq, 2));
-    SyncEvent fork, join;
-    if (!fork.e || !join.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
-    HIP_TRY(hipEventRecord(fork.e, st));
-    HIP_TRY(hipStreamWaitEvent(side, fork.e, 0));
-    int status = USTD_OK, hard = USTD_OK;
-    bool solved = false;
-    auto solve_all = [&]() {
-        solved = true;
-        // members on the one-workgroup engine (all of them by default): one launch per precision
-        // and row-group size with a workgroup per member, so their solves run side by side; then
-        // each member's projection and final residual, one synchronisation and the readbacks
-        std::vector<int> small;
-        for (int i = 0; i < count; ++i)
-            if (one_workgroup(&probs[i], B.g[i].n, true)) small.push_back(i);
-        if (!small.empty()) {
-            const int rc = solve_small_batch(cs, small, B, d_ws, side, R, &status);
-            if (rc != USTD_OK) {
-                hard = rc;
-                (void)hipStreamSynchronize(side);
-                return;
-            }
-        }
-        for (int i = 0; i < count; ++i) {
-            if (std::find(small.begin(), small.end(), i) != small.end()) continue;
-            Ctx ci = cs[i];
-            ci.st = side;
-            const int src = solve_column(ci, at<double>(cs[i].ws, B.g[i].off_x64), &R[i]);
-            if (src == USTD_ENOTCONV) {
-                status = member(i, src);
-            } else if (src != USTD_OK) {
-                hard = member(i, src);
-                (void)hipStreamSynchronize(side);
-                return;
-            }
-        }
-    };
-    for (;;) {
-        // members taking part in this fill, in `order`, with their tree counts
-        std::vector<std::pair<int, long long>> part;
-        long long used = 0, ntiles = 0;  // bytes of the record pool, tiles
-        for (int gi : order) {
-            const long long left = tau[gi] - next[gi];
-            if (left <= 0) continue;
-            const long long rb = B.g[gi].rec_stride * 8;
-            const long long fit = std::min((B.rec_pool - used) / rb, B.max_tiles - ntiles);
-            const long long lim = probs[gi].trees_per_batch > 0 ? probs[gi].trees_per_batch : left;
-            const long long take = std::min(std::min(left, fit), lim);
-            if (take <= 0) break;
-            part.emplace_back(gi, take);
-            used += take * rb;
-            ntiles += take;
-        }
-        if (part.empty()) break;
-        // groups of whole members, each reaching group_trees trees (the last one may not)
-        std::vector<std::vector<Seg>> groups;
-        std::vector<int> gstart;  // first tile of each group
-        tiles.clear();
-        long long rec_used = 0;
-        std::vector<char> gweighted;  // each group is all weighted or all unweighted (one kernel)
-        for (size_t k = 0; k < part.size();) {
-            size_t e = k;
-            long long cnt = 0;
-            const bool wk = B.g[part[k].first].weighted;
-            while (e < part.size() && (e == k || cnt < group_trees) && B.g[part[e].first].weighted == wk)
-                cnt += part[e++].second;
-            gweighted.push_back(wk ? 1 : 0);
-            std::vector<std::pair<int, long long>> mem(part.begin() + k, part.begin() + e);
-            std::stable_sort(mem.begin(), mem.end(), [&](const std::pair<int, long long> &x,
-                                                         const std::pair<int, long long> &y) {
-                return B.g[x.first].n > B.g[y.first].n;
-            });
-            gstart.push_back((int)tiles.size());
-            groups.emplace_back();
-            for (auto &pr : mem) {
-                const int gi = pr.first;
-                const long long take = pr.second;
-                groups.back().push_back(Seg{gi, take, rec_used / 8});
-                for (long long j = 0; j < take; ++j)
-                    tiles.push_back(WilsonTile{next[gi] + j, rec_used / 8 + j * B.g[gi].rec_stride, gi, 0});
-                rec_used += take * B.g[gi].rec_stride * 8;
-                next[gi] += take;
-            }
-            k = e;
-        }
-        gstart.push_back((int)tiles.size());
-        const int nt = (int)tiles.size();
-        largest = std::max<long long>(largest, nt);
-        HIP_TRY(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(WilsonTile) * tiles.size(), hipMemcpyHostToDevice, st));
-        SyncEvent ready;
-        if (!ready.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
-        HIP_TRY(hipEventRecord(ready.e, st));
-        HIP_TRY(hipStreamWaitEvent(samp1, ready.e, 0));
-        HIP_TRY(hipStreamWaitEvent(aggq, ready.e, 0));
-        const size_t ng = groups.size();
-        std::vector<std::unique_ptr<SpanTimer>> ts, ta;
-        std::vector<std::unique_ptr<SyncEvent>> sampled;
-        for (size_t gidx = 0; gidx < ng; ++gidx) {
-            const int pool2 = (int)(gidx & 1);
-            hipStream_t s = pool2 ? samp1 : st;
-            const int t0 = gstart[gidx], cnt = gstart[gidx + 1] - gstart[gidx];
-            WilsonArgs a{};
-            a.graphs = d_graphs;
-            a.tiles = d_tiles + t0;
-            a.ntiles = cnt;
-            a.rec = pool;
-            a.path = at<int>(d_ws, B.off_path) + (long long)pool2 * B.slots * kSamplerPathSlot;
-            a.queue = queue + pool2;
-            a.steps = steps + t0;
-            a.draws = draws + t0;
-            const bool wt = gweighted[gidx] != 0;
-            const int res = wt ? resident_w : resident;
-            int blocks = std::min(cnt, B.slots);
-            if (res > 0) blocks = std::min(blocks, res);
-            ts.emplace_back(new SpanTimer());
-            ta.emplace_back(new SpanTimer());
-            sampled.emplace_back(new SyncEvent());
-            if (!sampled.back()->e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
-            ts.back()->start(s);
-            HIP_TRY(hipMemsetAsync(queue + pool2, 0, sizeof(int), s));
-            HIP_TRY(launch_wilson(a, blocks, B.lds_bits, B.col16, wt, B.nwords_max, s));
-            ts.back()->stop(s);
-            HIP_TRY(hipEventRecord(sampled.back()->e, s));
-            HIP_TRY(hipStreamWaitEvent(aggq, sampled.back()->e, 0));
-            ta.back()->start(aggq);
-            for (const Seg &sg : groups[gidx]) {
-                AggregateArgs aa{};
-                aa.n = B.g[sg.graph].n;
-                aa.u = cs[sg.graph].pivot;
-                aa.ntrees = (int)sg.ntrees;
-                aa.parB = at<int>(cs[sg.graph].ws, B.g[sg.graph].off_parB);
-                aa.bint = at<int2>(cs[sg.graph].ws, B.g[sg.graph].off_bint);
-                aa.rec = pool + sg.rec_off;
-                aa.rec_stride = B.g[sg.graph].rec_stride;
-                aa.counts = counts[sg.graph];
-                aa.F = B.g[sg.graph].weighted ? at<long long>(cs[sg.graph].ws, B.g[sg.graph].off_F) : nullptr;
-                aa.chunk = agg_chunk(cs[sg.graph].ecc);
-                HIP_TRY(launch_aggregate(aa, aggq));
-            }
-            ta.back()->stop(aggq);
-        }
-        SyncEvent s1done, aggdone;
-        if (!s1done.e || !aggdone.e) return fail(USTD_EHIP, "hipEventCreateWithFlags failed");
-        HIP_TRY(hipEventRecord(s1done.e, samp1));
-        HIP_TRY(hipEventRecord(aggdone.e, aggq));
-        HIP_TRY(hipStreamWaitEvent(st, s1done.e, 0));
-        HIP_TRY(hipStreamWaitEvent(st, aggdone.e, 0));
-        // before the copies: a copy into pageable host memory blocks the host until it is done
-        if (!solved) solve_all();
-        hs.resize(nt);
-        hd.resize(nt);
-        HIP_TRY(hipMemcpyAsync(hs.data(), steps, sizeof(long long) * (size_t)nt, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(hd.data(), draws, sizeof(long long) * (size_t)nt, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        for (size_t gidx = 0; gidx < ng; ++gidx) {
-            ms_s += ts[gidx]->ms();
-            ms_a += ta[gidx]->ms();
-        }
-        for (int j = 0; j < nt; ++j) {
-            R[tiles[j].graph].walk_steps += hs[j];
-            R[tiles[j].graph].walk_draws += hd[j];
-        }
-        ++fills;
-    }
-
-    // per member: combination, once the solves are in
-    if (!solved) solve_all();
-    if (hard != USTD_OK) return hard;
-    HIP_TRY(hipEventRecord(join.e, side));
-    HIP_TRY(hipStreamWaitEvent(st, join.e, 0));
-    for (int i = 0; i < count; ++i) {
-        R[i].n_batches = fills;
-        R[i].trees_per_batch = (int32_t)largest;
-        R[i].ms_sample = ms_s;
-        R[i].ms_aggregate = ms_a;
-        double *x = at<double>(cs[i].ws, B.g[i].off_x64);
-        Timer tm(st);
-        HIP_TRY(launch_combine(B.g[i].n, cs[i].pivot, count_scale(cs[i], tau[i]), counts[i], x, d_diags[i], st));
-        R[i].ms_combine += tm.stop_ms();
-    }
+    const int status = batch_plan_reports(*P, R, st);
     const double ms = total.stop_ms();
     for (int i = 0; i < count; ++i) R[i].ms_total = ms;
     return status;
+}
+
+int ustd_batch_plan_create(const ustd_problem *probs, int32_t count, void *d_ws, size_t ws_bytes,
+                           const ustd_batch_schedule *sched, ustd_batch_plan **plan, void *stream) {
+    g_err.clear();
+    if (!plan) return fail(USTD_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    std::unique_ptr<ustd_batch_plan> P;
+    const int rc = batch_plan_create(probs, count, d_ws, ws_bytes, sched, P, (hipStream_t)stream);
+    if (rc != USTD_OK) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        return rc;
+    }
+    *plan = P.release();
+    return USTD_OK;
+}
+
+int ustd_batch_plan_execute(ustd_batch_plan *plan, double *const *d_diags, int64_t *const *d_counts, void *stream) {
+    g_err.clear();
+    if (!plan) return fail(USTD_EINVAL, "plan is NULL");
+    return batch_plan_execute(*plan, d_diags, d_counts, (hipStream_t)stream);
+}
+
+int ustd_batch_plan_reports(ustd_batch_plan *plan, ustd_report *reps, void *stream) {
+    g_err.clear();
+    if (!plan || !reps) return fail(USTD_EINVAL, "plan or reps is NULL");
+    return batch_plan_reports(*plan, reps, (hipStream_t)stream);
+}
+
+int ustd_batch_plan_schedule(const ustd_batch_plan *plan, ustd_batch_schedule *out) {
+    g_err.clear();
+    if (!plan || !out) return fail(USTD_EINVAL, "plan or out is NULL");
+    *out = plan->sched;
+    return USTD_OK;
+}
+
+int ustd_batch_plan_destroy(ustd_batch_plan *plan) {
+    g_err.clear();
+    delete plan;
+    return USTD_OK;
+}
+
+int ustd_batch_graph_create(ustd_batch_plan *plan, double *const *d_diags, int64_t *const *d_counts, void **graph) {
+    g_err.clear();
+    if (!plan || !graph) return fail(USTD_EINVAL, "plan or graph is NULL");
+    *graph = nullptr;
+    if (!plan->big.empty())
+        return fail(USTD_EINVAL, "problem %d uses the multi-kernel solve engine, which the host drives: it cannot be "
+                                 "captured", plan->big[0]);
+    hipStream_t s = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return fail(USTD_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    const int rc = batch_plan_execute(*plan, d_diags, d_counts, s);
+    const std::string err = g_err;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    (void)hipStreamDestroy(s);
+    if (rc != USTD_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != USTD_OK) return fail(rc, "%s", err.c_str());
+        return fail(USTD_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(USTD_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    *graph = ex;
+    return USTD_OK;
+}
+
+int ustd_batch_graph_launch(void *graph, void *stream) {
+    g_err.clear();
+    if (!graph) return fail(USTD_EINVAL, "graph is NULL");
+    HIP_TRY(hipGraphLaunch((hipGraphExec_t)graph, (hipStream_t)stream));
+    return USTD_OK;
+}
+
+int ustd_batch_graph_destroy(void *graph) {
+    g_err.clear();
+    if (graph) HIP_TRY(hipGraphExecDestroy((hipGraphExec_t)graph));
+    return USTD_OK;
+}
+
+int ustd_batch_autotune(const ustd_problem *probs, int32_t count, void *d_ws, size_t ws_bytes, const char *cache_path,
+                        int32_t graph, ustd_batch_schedule *best, double *best_ms, int32_t *from_cache, void *stream) {
+    g_err.clear();
+    if (!best) return fail(USTD_EINVAL, "best is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if (from_cache) *from_cache = 0;
+    std::unique_ptr<ustd_batch_plan> P;
+    USTD_TRY(batch_plan_create(probs, count, d_ws, ws_bytes, nullptr, P, st));
+    if (graph && !P->big.empty())
+        return fail(USTD_EINVAL, "problem %d uses the multi-kernel solve engine: its batches cannot be captured",
+                    P->big[0]);
+    std::string key;
+    USTD_TRY(tune_key(*P, &key));
+    key += graph ? "-graph" : "-eager";
+    const char *env = std::getenv("USTD_TUNE_CACHE");
+    const std::string path = cache_path ? cache_path : (env ? env : "");
+    std::vector<std::pair<std::string, TuneEntry>> cache;
+    if (!path.empty()) {
+        cache = read_tune_cache(path);
+        for (auto &kv : cache)
+            if (kv.first == key && check_schedule(kv.second.s) == USTD_OK) {
+                *best = schedule_of(&kv.second.s);
+                if (best_ms) *best_ms = kv.second.ms;
+                if (from_cache) *from_cache = 1;
+                g_err.clear();
+                return USTD_OK;
+            }
+        g_err.clear();
+    }
+    // outputs for the timed executions
+    long long ntot = 0;
+    for (int i = 0; i < count; ++i) ntot += probs[i].n;
+    double *dd = nullptr;
+    if (hipMalloc((void **)&dd, (size_t)ntot * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(USTD_ENOMEM, "tuning outputs of %lld doubles", ntot);
+    }
+    std::unique_ptr<double, void (*)(double *)> hold(dd, [](double *p) { (void)hipFree(p); });
+    std::vector<double *> diags(count);
+    for (int i = 0, o = 0; i < count; o += (int)probs[i].n, ++i) diags[i] = dd + o;
+    std::vector<ustd_report> reps(count);
+    // one execution of the plan (eager, or a replay of its captured graph), timed by events
+    auto time_plan = [&](ustd_batch_plan &Q, double *ms) -> int {
+        hipGraphExec_t ex = nullptr;
+        if (graph) {
+            void *gx = nullptr;
+            USTD_TRY(ustd_batch_graph_create(&Q, diags.data(), nullptr, &gx));
+            ex = (hipGraphExec_t)gx;
+        }
+        hipEvent_t a = nullptr, b = nullptr;
+        int rc = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess
+                     ? USTD_OK
+                     : fail(USTD_EHIP, "hipEventCreate failed");
+        if (rc == USTD_OK && hipEventRecord(a, st) != hipSuccess) rc = fail(USTD_EHIP, "hipEventRecord failed");
+        if (rc == USTD_OK)
+            rc = ex ? (hipGraphLaunch(ex, st) == hipSuccess ? USTD_OK : fail(USTD_EHIP, "hipGraphLaunch failed"))
+                    : batch_plan_execute(Q, diags.data(), nullptr, st);
+        if (rc == USTD_OK && hipEventRecord(b, st) != hipSuccess) rc = fail(USTD_EHIP, "hipEventRecord failed");
+        (void)hipStreamSynchronize(st);
+        float m = 0.f;
+        if (rc == USTD_OK && hipEventElapsedTime(&m, a, b) != hipSuccess) rc = fail(USTD_EHIP, "hipEventElapsedTime failed");
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        if (ex) (void)hipGraphExecDestroy(ex);
+        if (rc != USTD_OK) return rc;
+        rc = batch_plan_reports(Q, reps.data(), st);
+        if (rc != USTD_OK && rc != USTD_ENOTCONV) return rc;
+        *ms = (double)m;
+        return USTD_OK;
+    };
+    double ms0 = 0.0;
+    USTD_TRY(time_plan(*P, &ms0));  // warm-up: code objects and caches
+    USTD_TRY(time_plan(*P, &ms0));
+    P.reset();
+    ustd_batch_schedule cur = schedule_of(nullptr);
+    double cur_ms = ms0;
+    auto try_one = [&](ustd_batch_schedule cand) -> int {
+        std::unique_ptr<ustd_batch_plan> Q;
+        USTD_TRY(batch_plan_create(probs, count, d_ws, ws_bytes, &cand, Q, st));
+        double ms = 0.0;
+        USTD_TRY(time_plan(*Q, &ms));
+        if (ms < cur_ms) {
+            cur_ms = ms;
+            cur = Q->sched;
+        }
+        return USTD_OK;
+    };
+    // one dimension at a time, from the defaults, each value against the best so far
+    for (int b : {2, 3, 4}) {
+        ustd_batch_schedule c = cur;
+        c.branches = b;
+        USTD_TRY(try_one(c));
+    }
+    for (int g : {1, 4, -1}) {
+        if (cur.branches >= 2) break;  // the chains of branch mode have no groups
+        ustd_batch_schedule c = cur;
+        c.group_fills = g;
+        if (c.group_fills != cur.group_fills) USTD_TRY(try_one(c));
+    }
+    for (int ch : {kAggChunkLarge, kAggChunk}) {
+        ustd_batch_schedule c = cur;
+        c.agg_chunk = ch;
+        USTD_TRY(try_one(c));
+    }
+    {
+        ustd_batch_schedule c = cur;
+        c.layout = USTD_LAYOUT_RECORDS;
+        USTD_TRY(try_one(c));
+    }
+    {  // half the largest pool fill: more fills, less of the record pool
+        std::unique_ptr<ustd_batch_plan> Q;
+        USTD_TRY(batch_plan_create(probs, count, d_ws, ws_bytes, &cur, Q, st));
+        const long long largest = Q->largest;
+        Q.reset();
+        if (largest > 1) {
+            ustd_batch_schedule c = cur;
+            c.fill_trees = (largest + 1) / 2;
+            USTD_TRY(try_one(c));
+        }
+    }
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    if (!path.empty()) {
+        TuneEntry e;
+        e.s = cur;
+        e.ms = cur_ms;
+        bool found = false;
+        for (auto &kv : cache)
+            if (kv.first == key) {
+                kv.second = e;
+                found = true;
+            }
+        if (!found) cache.emplace_back(key, e);
+        USTD_TRY(write_tune_cache(path, cache));
+    }
+    return USTD_OK;
 }
 
 int ustd_edge_counts(const ustd_problem *prob, int64_t tree_begin, int64_t tree_count, void *d_ws, size_t ws_bytes,

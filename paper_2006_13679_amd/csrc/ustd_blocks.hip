@@ -428,14 +428,62 @@ __global__ void bc_map_parents_kernel(int n, int u, int ntrees, const int *__res
 }
 
 // the {nba | marks} half of each vertex's record for Algorithm 2, from the parents: the marks
-// of v and its tree edge, and the nearest marked strict ancestor (u if none), found by walking
-// up the parents
+// of v and its tree edge, and the nearest marked strict ancestor nba(v) (u if none).  A vertex
+// y is marked when its own tree edge (y, parent(y)) is an edge of B_u.
 __device__ __forceinline__ int bf_parent_b(int f) { return (int)((unsigned)f & 0x7FFFFFFFu) - 1; }
 __device__ __forceinline__ int marks_of(int x, int fx, int px, int fpx) {
     const unsigned fwd = px == bf_parent_b(fx), bwd = bf_parent_b(fpx) == x;
     const unsigned m = ((unsigned)fx >> 31) & (fwd | bwd);
     return (int)((m << 31) | ((m & fwd) << 30));
 }
+
+// nba by pointer jumping, in place in the record's second word: jw(v) = J | done << 31, where J
+// is an ancestor of v such that every vertex from parent(v) up to J is unmarked and not u
+// (not done), or J = nba(v) (done).  Start: J = parent(v), done when parent(v) is u or marked.
+// A step replaces jw(v) by jw(J): nba(v) = nba(J) when J is unmarked, and the path covered
+// doubles.  Any value of jw(J) that another thread has stored keeps the invariant, so the
+// steps run concurrently without ordering; the words are single 32-bit loads and stores.
+constexpr unsigned kJumpDone = 0x80000000u;
+
+__global__ void bc_nba_init_kernel(int n, int u, int ntrees, const int *__restrict__ bflag, int2 *__restrict__ rec,
+                                   long long stride) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * ntrees) return;
+    const long long t = i / n;
+    const int v = (int)(i - t * n);
+    int *r = reinterpret_cast<int *>(rec + t * stride);
+    const int pv = v == u ? -1 : r[2 * v];
+    unsigned jw;
+    if (pv < 0 || pv >= n || pv == u) {  // out-of-range never for a joined tree; keeps accesses in bounds
+        jw = (unsigned)u | kJumpDone;
+    } else {
+        const int ppv = r[2 * pv];
+        const bool marked = ppv >= 0 && ppv < n && marks_of(pv, bflag[pv], ppv, bflag[ppv]) != 0;
+        jw = (unsigned)pv | (marked ? kJumpDone : 0u);
+    }
+    r[2 * v + 1] = (int)jw;
+}
+
+__global__ void bc_nba_jump_kernel(int n, int ntrees, int2 *__restrict__ rec, long long stride) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * ntrees) return;
+    const long long t = i / n;
+    const int v = (int)(i - t * n);
+    int *r = reinterpret_cast<int *>(rec + t * stride);
+    unsigned jw = __hip_atomic_load(r + 2 * v + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // each step moves J at least one vertex up the tree: at most n steps
+    for (int steps = 0; !(jw & kJumpDone) && steps < n; ++steps) {
+        const int x = (int)(jw & ~kJumpDone);
+        if (x >= n) {
+            jw = kJumpDone;  // never for a joined tree
+            break;
+        }
+        jw = __hip_atomic_load(r + 2 * x + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(r + 2 * v + 1, (int)jw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// the final record word: nba(v) | marks of v
 __global__ void bc_records_kernel(int n, int u, int ntrees, const int *__restrict__ bflag, int2 *__restrict__ rec,
                                   long long stride) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -448,21 +496,10 @@ __global__ void bc_records_kernel(int n, int u, int ntrees, const int *__restric
         return;
     }
     const int pv = r[2 * v];
-    if (pv < 0 || pv >= n) {  // never for a joined tree; keeps every access in bounds
-        r[2 * v + 1] = u;
-        return;
-    }
-    const int mv = marks_of(v, bflag[v], pv, bflag[pv]);
-    int y = pv;
-    for (int steps = 0; y != u && steps < n; ++steps) {  // up a tree: at most its depth
-        const int py = r[2 * y];
-        if (py < 0 || py >= n) {
-            y = u;
-            break;
-        }
-        if (marks_of(y, bflag[y], py, bflag[py])) break;
-        y = py;
-    }
+    const unsigned jw = (unsigned)r[2 * v + 1];
+    int y = (int)(jw & ~kJumpDone);
+    if (!(jw & kJumpDone) || y >= n) y = u;  // never for a joined tree
+    const int mv = pv >= 0 && pv < n ? marks_of(v, bflag[v], pv, bflag[pv]) : 0;
     r[2 * v + 1] = y | mv;
 }
 
@@ -538,6 +575,8 @@ hipError_t launch_bc_join(int n, int u, int ntrees, int ntop, int nslots, const 
                                                                             sstride);
     bc_map_parents_kernel<<<bgrid((long long)n * ntrees, 256), 256, 0, st>>>(n, u, ntrees, slotPar, vtx, recs,
                                                                              sstride, rec, stride);
+    bc_nba_init_kernel<<<bgrid((long long)n * ntrees, 256), 256, 0, st>>>(n, u, ntrees, bflag, rec, stride);
+    bc_nba_jump_kernel<<<bgrid((long long)n * ntrees, 256), 256, 0, st>>>(n, ntrees, rec, stride);
     bc_records_kernel<<<bgrid((long long)n * ntrees, 256), 256, 0, st>>>(n, u, ntrees, bflag, rec, stride);
     return hipGetLastError();
 }

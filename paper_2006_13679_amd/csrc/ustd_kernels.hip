@@ -1882,6 +1882,18 @@ __global__ __launch_bounds__(256) void sum_walks_kernel(int cnt, const long long
     }
 }
 
+// walk steps and draws of a batch's tiles added to their member's totals (totals[2 g], totals[2 g + 1])
+__global__ __launch_bounds__(256) void tile_walks_kernel(int cnt, const WilsonTile *__restrict__ tiles,
+                                                         const long long *__restrict__ steps,
+                                                         const long long *__restrict__ draws,
+                                                         unsigned long long *__restrict__ totals) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int g = tiles[i].graph;
+    atomicAdd(&totals[2 * g], (unsigned long long)steps[i]);
+    atomicAdd(&totals[2 * g + 1], (unsigned long long)draws[i]);
+}
+
 // den = tau, or tau 2^k for the fixed-point counts of a weighted graph
 __global__ void combine_kernel(int n, int u, double den, const long long *__restrict__ counts,
                                const double *__restrict__ x, double *__restrict__ diag) {
@@ -2117,6 +2129,11 @@ hipError_t launch_combine(int n, int u, double den, const long long *counts, con
 hipError_t launch_sum_walks(int cnt, const long long *steps, const long long *draws, unsigned long long *totals,
                             hipStream_t st) {
     sum_walks_kernel<<<1, 256, 0, st>>>(cnt, steps, draws, totals);
+    return hipGetLastError();
+}
+hipError_t launch_tile_walks(int cnt, const WilsonTile *tiles, const long long *steps, const long long *draws,
+                             unsigned long long *totals, hipStream_t st) {
+    if (cnt > 0) tile_walks_kernel<<<blocks_for(cnt, 256), 256, 0, st>>>(cnt, tiles, steps, draws, totals);
     return hipGetLastError();
 }
 hipError_t launch_row_cumsum(int n, int nnz, const int *rp, const double *w, int heavy_thresh, const int *heavy,

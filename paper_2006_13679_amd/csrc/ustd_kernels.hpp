@@ -188,6 +188,9 @@ int wilson_resident_blocks_graph_lds(int nwords, long long graph_bytes);
 // block_split: the block-split graph of the per-block variant (several roots, keyed starts)
 hipError_t launch_wilson(const WilsonArgs &a, int blocks, bool lds_bits, bool col16, bool weighted, int nwords,
                          hipStream_t st, long long graph_lds_bytes = 0, bool block_split = false);
+// per-member walk totals of a batch: totals[2 g] += steps[i], totals[2 g + 1] += draws[i], g = tiles[i].graph
+hipError_t launch_tile_walks(int cnt, const WilsonTile *tiles, const long long *steps, const long long *draws,
+                             unsigned long long *totals, hipStream_t st);
 // weighted graphs: running row sums and row totals; weight checks; B_u edge conductances,
 // B-path resistances (max into *rmax_bits, as the bits of a non-negative double); F
 hipError_t launch_sum_walks(int cnt, const long long *steps, const long long *draws, unsigned long long *totals,

@@ -83,7 +83,7 @@ def test_struct_layouts_match_header(tmp_path):
     include/ustd.h prints them)."""
     import subprocess
 
-    fields = {"ustd_problem": api.Problem, "ustd_report": api.Report}
+    fields = {"ustd_problem": api.Problem, "ustd_report": api.Report, "ustd_batch_schedule": api.Schedule}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "ustd.h"', "int main(void) {"]
     for cname, cls in fields.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
