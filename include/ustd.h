@@ -271,8 +271,8 @@ int ustd_batch_diag_lpinv(const ustd_problem *probs, int32_t count, void *d_ws, 
 typedef struct {
     int32_t group_fills;  /* sampler group (one persistent launch) of about this many GPU-fills of trees
                              (resident sampler waves); 0 = 2; -1 = the whole pool fill in one launch */
-    int32_t agg_chunk;    /* trees per Algorithm 2 thread: 0 = by eccentricity (4 from ecc 8 on, else 8),
-                             or 4 or 8 */
+    int32_t agg_chunk;    /* trees per Algorithm 2 thread, walked in lockstep: 0 = by eccentricity (4 from
+                             ecc 8 on, else 8), or 4 or 8 */
     int32_t layout;       /* USTD_LAYOUT_AUTO or USTD_LAYOUT_RECORDS (below) */
     int32_t branches;     /* 0 or 1: sampler groups alternate between two streams and Algorithm 2 runs on a
                              third; 2 .. 4: the members are split into this many independent chains (by

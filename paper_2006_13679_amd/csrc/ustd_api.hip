@@ -846,6 +846,8 @@ int sample_batch(Ctx &c, long long tree_begin, int ntrees, long long *steps, lon
 // of Algorithm 2 time with 4, R-MAT 16 loses 6%).
 constexpr int kAggDeepEcc = 8;
 int agg_chunk(int ecc) { return ecc >= kAggDeepEcc ? kAggChunkLarge : kAggChunk; }
+// the form of Algorithm 2: a schedule's fixed chunk, else by eccentricity
+void agg_form(AggregateArgs &aa, int ecc, int sched_chunk) { aa.chunk = sched_chunk > 0 ? sched_chunk : agg_chunk(ecc); }
 
 // Algorithm 2 over `cnt` resident trees (records of a pool), on stream st
 int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag, int pool = 0, hipStream_t st = nullptr) {
@@ -860,7 +862,7 @@ int aggregate_trees(Ctx &c, int cnt, long long *counts, double *ms_ag, int pool 
     aa.rec_stride = c.L.rec_stride;
     aa.counts = counts;
     aa.F = c.L.weighted ? at<long long>(c.ws, c.L.off_F) : nullptr;
-    aa.chunk = agg_chunk(c.ecc);
+    agg_form(aa, c.ecc, 0);
     Timer tm(st);
     HIP_TRY(launch_aggregate(aa, st));
     if (ms_ag) *ms_ag += tm.stop_ms();
@@ -1662,7 +1664,7 @@ int batch_plan_execute(ustd_batch_plan &P, double *const *d_diags, int64_t *cons
                 aa.rec_stride = L.rec_stride;
                 aa.counts = counts[sg.graph];
                 aa.F = L.weighted ? at<long long>(c.ws, L.off_F) : nullptr;
-                aa.chunk = P.sched.agg_chunk > 0 ? P.sched.agg_chunk : agg_chunk(c.ecc);
+                agg_form(aa, c.ecc, P.sched.agg_chunk);
                 HIP_TRY(launch_aggregate(aa, sa));
             }
             if (timed) P.ta.back()->stop(sa);
