@@ -131,7 +131,7 @@ Plan make_plan(const ustd_problem *p, bool with_trees = true, bool force_edges =
     L.col16 = L.n <= 65536;  // 16-bit column copy for the sampler (half the cache footprint)
     L.edges = !L.lds_bits || force_edges;
     L.weighted = p->d_weight != nullptr;
-    L.rob = std::min(kSamplerRobMax, next_pow2(std::max(L.n, 2)));
+    L.rob = std::min(L.lds_bits && !force_edges ? kSamplerRobLds : kSamplerRobMax, next_pow2(std::max(L.n, 2)));
     const double avg = (double)L.nnz / (double)L.n;
     L.G = avg <= 6.0 ? 4 : (avg <= 16.0 ? 8 : (avg <= 48.0 ? 16 : 32));
     L.heavy_thresh = 32 * L.G;
@@ -781,7 +781,7 @@ int sample_batch_blocks(Ctx &c, long long tree_begin, int ntrees, long long *ste
     g.n = ns;
     g.u = -1;
     g.nwords = (ns + 31) / 32;
-    g.rob = std::min(kSamplerRobMax, next_pow2(std::max(ns, 2)));
+    g.rob = std::min(L.s_lds ? kSamplerRobLds : kSamplerRobMax, next_pow2(std::max(ns, 2)));
     g.rp = at<int>(c.ws, L.off_rps);
     g.colv = L.s_col16 ? (const void *)at<unsigned short>(c.ws, L.off_scol16) : (const void *)at<int>(c.ws, L.off_scol);
     g.bflag = at<int>(c.ws, L.off_sbflag);

@@ -242,7 +242,11 @@ __global__ void count_unreached_kernel(int n, const int *__restrict__ dist, int 
 // ======================================================================================
 namespace {
 
-constexpr int kRobMax = kSamplerRobMax;  // reorder-buffer entries (LDS)
+// reorder-buffer entries (LDS): with the tree bitmap in LDS the sampler's occupancy is bound by
+// LDS (64 entries); with the tree state in the records it is bound by registers, and 128 entries
+// let the lanes run further ahead of a long walk at the head
+template <bool LDS>
+constexpr int rob_cap() { return LDS ? kSamplerRobLds : kSamplerRobMax; }
 constexpr int kPathLds = 5;              // recorded steps kept in LDS per entry (x_1..x_5)
 constexpr int kPath = 255;               // recorded steps per speculative walk (x_1..x_255)
 static_assert(kPath - kPathLds == kSamplerPathGlobal, "path split");
@@ -587,12 +591,17 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     // Reorder buffer.  Vertex IDs take the column type (16 bits when n <= 65536), so that
     // with the tree bitmap a block of R-MAT scale 16 fits 18 to a CU.  A recorded step
     // keeps the vertex and the step's edge bits (below), not the vertex's B_u flag word.
+    constexpr int kRobMax = rob_cap<LDS>();
     extern __shared__ uint32_t lds_bits[];
     __shared__ CT rob_s[kRobMax], rob_cv[kRobMax];
     __shared__ short rob_k[kRobMax];
     __shared__ unsigned short rob_pb[kRobMax];  // edge bits of steps 1..kPathLds, 2 bits each
     __shared__ CT rob_p[kRobMax][kPathLds];
     __shared__ int htab[2 * kHashSlots];
+    // tree state in the records: the free-vertex words of the last scanned window (a window of
+    // 64 allocation words is read once, not once per allocation round)
+    __shared__ uint32_t win_fb[LDS ? 1 : kWave];
+    __shared__ int win_base;  // first word of that window, -1 before the first read
     int *const hslot = htab;                     // first conflict table
     int *const hslot2 = htab + kHashSlots;       // second conflict table
     int *const br = htab;  // a long walk's branch (vertex | edge bits << 30) shares the tables'
@@ -647,7 +656,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
     }
     const int n = g.n;
     const int nwords = g.nwords;
-    const int rob = g.rob;  // power of two <= kRobMax
+    const int rob = min(g.rob, kRobMax);  // power of two
     const int robm = rob - 1;
     const uint32_t tlo = (uint32_t)(unsigned long long)t, thi = (uint32_t)((unsigned long long)t >> 32);
     int *recw = reinterpret_cast<int *>(rec);  // recw[2x] = parent (Next while walking)
@@ -673,6 +682,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
         wait_global();
     }
     for (int i = lane; i < 2 * kHashSlots; i += kWave) htab[i] = kWave;
+    if (lane == 0) __hip_atomic_store(&win_base, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     wave_sync();
     if constexpr (BV) {  // several roots (one per block of the block-split graph)
         for (int i = lane; i < a.nroots; i += kWave) {
@@ -703,13 +713,35 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
         const int rank = __popcll(idle & lanemask_lt());
         int got = 0, mys = 0;
         while (got < want && cursor < n) {
-            const int wbase = cursor >> kWShift;
-            const int wi = wbase + lane;
+            // With the tree state in the records, the window's words are read once and kept in
+            // LDS while the cursor stays inside it.  A vertex that joined the tree since the
+            // read still shows as free: it is allocated, and its walk finds it in the tree after
+            // one step and ends without a commit (as the sequential algorithm skips it).
+            int wbase = cursor >> kWShift;
             uint32_t fb = 0u;
+            if constexpr (LDS) {
+                if (wbase + lane < nw) fb = ~bits.word(wbase + lane, n);
+            } else {
+                // win_base is written by lane 0 and read by every lane: atomic accesses
+                const int wb = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(&win_base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT));
+                if (wb >= 0 && wbase < wb + kWave) {
+                    wbase = wb;
+                } else {
+                    win_fb[lane] = wbase + lane < nw ? ~bits.word(wbase + lane, n) : 0u;
+                    if (lane == 0) __hip_atomic_store(&win_base, wbase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    wave_sync();
+                }
+                fb = win_fb[lane];  // this lane's own word
+            }
+            const int wi = wbase + lane;
             if (wi < nw) {
-                fb = ~bits.word(wi, n) & (kW == 32 ? ~0u : (1u << kW) - 1u);
-                if (lane == 0) fb &= ~0u << (cursor & (kW - 1));
+                fb &= (kW == 32 ? ~0u : (1u << kW) - 1u);
+                const int d = cursor - (wi << kWShift);  // vertices of this word before the cursor
+                if (d > 0) fb = d >= kW ? 0u : fb & (~0u << d);
                 if (wi == nw - 1 && (n & (kW - 1))) fb &= (1u << (n & (kW - 1))) - 1u;
+            } else {
+                fb = 0u;
             }
             const int c = __popc(fb);
             const int incl = wave_scan_dpp(c);
@@ -726,7 +758,7 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
             if (mode == 0 && j >= 0 && j < min(total, need)) mys = ((wbase + L) << kWShift) + select_bit(wL, j - eL);
             if (total >= need) {
                 got = want;
-                cursor = __shfl(mys, select_bit64(idle, want - 1), kWave) + 1;
+                cursor = __builtin_amdgcn_readfirstlane(__shfl(mys, select_bit64(idle, want - 1), kWave) + 1);
             } else {
                 got += total;
                 cursor = (wbase + kWave) << kWShift;
@@ -740,9 +772,16 @@ __global__ __launch_bounds__(64) void wilson_kernel(WilsonArgs a) {
                 x = s;
                 k = 0;
                 mode = 1;
-                r0 = rp[s];
-                r1 = rp[s + 1];
-                fx = bflag[s];
+                if constexpr (LDS) {
+                    r0 = rp[s];
+                    r1 = rp[s + 1];
+                    fx = bflag[s];
+                } else {  // the vertex entry {row begin, row end, B_u flag}: one load
+                    const int4 vr = vrow[s];
+                    r0 = vr.x;
+                    r1 = vr.y;
+                    fx = vr.z;
+                }
                 pbits = 0;
                 const int sl = my_e & robm;
                 rob_s[sl] = (CT)s;

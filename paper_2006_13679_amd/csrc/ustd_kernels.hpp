@@ -98,7 +98,8 @@ struct EdgeCountArgs {
     long long *counts;          // [nnz], accumulated
 };
 
-constexpr int kSamplerRobMax = 64;       // reorder-buffer entries of the sampler
+constexpr int kSamplerRobMax = 128;      // reorder-buffer entries of the sampler (tree state in the records)
+constexpr int kSamplerRobLds = 64;       // reorder-buffer entries with the tree bitmap in LDS
 constexpr int kSamplerPathGlobal = 250;  // recorded steps per entry kept in global memory
 constexpr long long kSamplerPathSlot = (long long)kSamplerRobMax * kSamplerPathGlobal;  // ints per block
 constexpr int kSamplerMaxBlocks = 8192;  // resident sampler blocks (path slots)
