@@ -187,8 +187,11 @@ def run_batch(args):
     print("bench: one-shot batch %.1f ms" % ms_one_shot, file=sys.stderr, flush=True)
 
     tt = time.perf_counter()
-    sched, tuned_ms, hit = api.batch_autotune(graphs, probs, ws=ws, cache_path=os.environ.get("USTD_TUNE_CACHE"),
-                                              graph=True)
+    if args.no_tune:
+        sched, tuned_ms, hit = api.Schedule(), 0.0, False
+    else:
+        sched, tuned_ms, hit = api.batch_autotune(graphs, probs, ws=ws, cache_path=os.environ.get("USTD_TUNE_CACHE"),
+                                                  graph=True)
     tune_s = time.perf_counter() - tt
     print("bench: tuned schedule %s (%.1f ms, %s) in %.1f s" % (sched.as_dict(), tuned_ms,
                                                                "cached" if hit else "timed", tune_s),
@@ -244,7 +247,8 @@ def run_batch(args):
                    "members": w["count"], "tau_total": tau, "n_total": sum(m["graph"].n for m in members),
                    "eps": 0.3, "solve": args.solve, "step": "one replay of the captured HIP graph"},
         "tuned_schedule": sched.as_dict(),
-        "tuner": {"from_cache": hit, "ms_per_execution": round(tuned_ms, 3), "tuning_s": round(tune_s, 2)},
+        "tuner": ({"from_cache": hit, "ms_per_graph_replay": round(tuned_ms, 3), "tuning_s": round(tune_s, 2)}
+                  if not args.no_tune else "off: default schedule"),
         "plan_ms": round(ms_plan, 2),
         "one_shot_ms": round(ms_one_shot, 3),
         "walk_steps_per_s": round(steps / (ms_sample * 1e-3), 1),
@@ -372,6 +376,8 @@ def main():
     ap.add_argument("--variant", default="plain", choices=["plain", "blocks"],
                     help="Wilson variant of the timed leg: plain (rooted at the pivot), or blocks (one walk "
                          "per biconnected component of the graph, joined at the cut vertices)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch workload: replay the default schedule (no autotuning)")
     ap.add_argument("--no-variant-compare", action="store_true",
                     help="skip the one-run comparison of the two Wilson variants")
     ap.add_argument("--task", default="diag", choices=["diag", "edges"],
@@ -535,8 +541,11 @@ def main():
         "walk_steps_per_s": round(steps / (ms_sample * 1e-3), 1),
         "sampling_trees_per_s": round(tau / (ms_sample * 1e-3), 1),
         "e2e_ms": round(med("ms_total"), 4),
+        # sample and aggregate sum each batch's launch spans (two pools overlap); the solve runs on a
+        # side stream beside the sampling, so its span is wall time, not kernel time (solve_compare
+        # has the solve alone)
         "phase_ms": {"setup_bfs": med("ms_bfs"), "sample": ms_sample, "aggregate": ms_ag,
-                     "solve": med("ms_solve"), "combine": med("ms_combine")},
+                     "solve_span_overlapped": med("ms_solve"), "combine": med("ms_combine")},
         "walk_steps": steps, "walk_draws": reps[0]["walk_draws"],
         "solve_iters": reps[0]["solve_iters"], "solve_relres": reps[0]["solve_relres"],
         "roofline": roof,
