@@ -25,6 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# VALU issue peak: one wave64 instruction per SIMD every 4 cycles (16-lane SIMDs for 32-bit
+# integer work), 256 CUs x 4 SIMDs at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 WORKLOADS = {
     "rmat16": dict(kind="rmat", scale=16, ef=16, seed=1),
     # weighted graphs (Section "Generalizations"): R-MAT 16 with conductances uniform in [1, 4)
@@ -484,6 +487,15 @@ def main():
             "launches": launches}
     if traffic and traffic.get("measured_ms_per_launch"):
         roof["traffic_gbs"] = round(traffic["bytes_per_launch"] / (roof["launch_ms"] * 1e-3) / 1e9, 1)
+    # instruction-issue roofline of the same kernel: VALU wave instructions per launch (rocprofv3
+    # SQ_INSTS_VALU of the current kernels) over this run's mean launch time
+    issue = None
+    if traffic and traffic.get("valu_wave_insts_per_launch"):
+        v = traffic["valu_wave_insts_per_launch"]
+        rate = v / (roof["launch_ms"] * 1e-3)
+        issue = {"bound": "valu_issue", "kernel": kname + "_kernel", "achieved": round(rate, 1), "peak": VALU_ISSUE_PEAK,
+                 "unit": "wave64 VALU instructions/s", "frac": round(rate / VALU_ISSUE_PEAK, 4),
+                 "valu_per_walk_step": round(v / max(steps / launches, 1), 3)}
 
     # the pivot column in both precisions (the same problem otherwise): iterations, time, the
     # true residual and how far the mixed-precision column and diagonal are from the FP64 ones
@@ -549,6 +561,7 @@ def main():
         "walk_steps": steps, "walk_draws": reps[0]["walk_draws"],
         "solve_iters": reps[0]["solve_iters"], "solve_relres": reps[0]["solve_relres"],
         "roofline": roof,
+        "issue_roofline": issue,
         "centralities_ms": round(ms_central, 4),
         "solve_compare": cmp,
     }
