@@ -318,15 +318,19 @@ int ustd_batch_plan_reports(ustd_batch_plan *plan, ustd_report *reps, void *stre
 /* The schedule a plan runs with (defaults filled in). */
 int ustd_batch_plan_schedule(const ustd_batch_plan *plan, ustd_batch_schedule *out);
 
-/* Frees the plan's device memory (synchronises the device). */
+/* Frees the plan's device memory (synchronises the device).  USTD_EINVAL (nothing freed) while a
+ * graph captured from the plan is alive: destroy the graphs first. */
 int ustd_batch_plan_destroy(ustd_batch_plan *plan);
 
 /* Captures one execution of the plan (ustd_batch_plan_execute with these outputs) into an
- * instantiated HIP graph, *graph = its hipGraphExec_t.  Capture runs on a stream of the
- * library's.  USTD_EINVAL when a member uses USTD_ENGINE_MULTI. */
+ * instantiated HIP graph; *graph = an opaque handle.  Capture runs on a stream of the library's.
+ * The graph uses the plan's device memory, the workspace and the outputs, which must outlive
+ * it.  USTD_EINVAL when a member uses USTD_ENGINE_MULTI. */
 int ustd_batch_graph_create(ustd_batch_plan *plan, double *const *d_diags, int64_t *const *d_counts, void **graph);
-/* Launches a captured execution on `stream` (returns without waiting). */
+/* Launches a captured execution on `stream` (returns without waiting).  Launches of graphs of
+ * one plan, and its executions, must not overlap. */
 int ustd_batch_graph_launch(void *graph, void *stream);
+/* Destroys a captured graph (synchronises the device). */
 int ustd_batch_graph_destroy(void *graph);
 
 /* Autotuner of a batch's schedule (dynamic load balancing, parallel implementation appendix):

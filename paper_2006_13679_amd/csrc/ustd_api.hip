@@ -1311,6 +1311,8 @@ struct ustd_batch_plan {
     SolveJob<double> *d_j64 = nullptr;
     SolveJob<float> *d_j32 = nullptr;
     unsigned long long *d_totals = nullptr;
+    // captured graphs of this plan still alive (they use the plan's device memory)
+    int live_graphs = 0;
     // timers of the last eager execution
     bool timed = false;
     std::vector<std::unique_ptr<SpanTimer>> ts, ta;
@@ -1321,6 +1323,12 @@ struct ustd_batch_plan {
 };
 
 namespace {
+
+// an instantiated capture of one execution, and the plan whose memory it uses
+struct BatchGraph {
+    hipGraphExec_t ex;
+    ustd_batch_plan *plan;
+};
 
 // Set-up of every member (with host readbacks: validation, pivot, eccentricity, tau), the
 // schedule of tiles over pool fills and sampler groups, the solve jobs, and the plan's device
@@ -2189,6 +2197,10 @@ int ustd_batch_plan_schedule(const ustd_batch_plan *plan, ustd_batch_schedule *o
 
 int ustd_batch_plan_destroy(ustd_batch_plan *plan) {
     g_err.clear();
+    if (plan && plan->live_graphs > 0)
+        return fail(USTD_EINVAL, "%d captured graph(s) of this plan are still alive: destroy them first",
+                    plan->live_graphs);
+    if (plan) (void)hipDeviceSynchronize();  // no execution still reads the plan's memory
     delete plan;
     return USTD_OK;
 }
@@ -2221,20 +2233,27 @@ int ustd_batch_graph_create(ustd_batch_plan *plan, double *const *d_diags, int64
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(USTD_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    *graph = ex;
+    *graph = new BatchGraph{ex, plan};
+    ++plan->live_graphs;
     return USTD_OK;
 }
 
 int ustd_batch_graph_launch(void *graph, void *stream) {
     g_err.clear();
     if (!graph) return fail(USTD_EINVAL, "graph is NULL");
-    HIP_TRY(hipGraphLaunch((hipGraphExec_t)graph, (hipStream_t)stream));
+    HIP_TRY(hipGraphLaunch(static_cast<BatchGraph *>(graph)->ex, (hipStream_t)stream));
     return USTD_OK;
 }
 
 int ustd_batch_graph_destroy(void *graph) {
     g_err.clear();
-    if (graph) HIP_TRY(hipGraphExecDestroy((hipGraphExec_t)graph));
+    if (!graph) return USTD_OK;
+    BatchGraph *bg = static_cast<BatchGraph *>(graph);
+    (void)hipDeviceSynchronize();  // no launch of it still running
+    const hipError_t e = hipGraphExecDestroy(bg->ex);
+    --bg->plan->live_graphs;
+    delete bg;
+    if (e != hipSuccess) return fail(USTD_EHIP, "hipGraphExecDestroy: %s", hipGetErrorString(e));
     return USTD_OK;
 }
 
@@ -2281,11 +2300,11 @@ int ustd_batch_autotune(const ustd_problem *probs, int32_t count, void *d_ws, si
     std::vector<ustd_report> reps(count);
     // one execution of the plan (eager, or a replay of its captured graph), timed by events
     auto time_plan = [&](ustd_batch_plan &Q, double *ms) -> int {
+        void *gx = nullptr;
         hipGraphExec_t ex = nullptr;
         if (graph) {
-            void *gx = nullptr;
             USTD_TRY(ustd_batch_graph_create(&Q, diags.data(), nullptr, &gx));
-            ex = (hipGraphExec_t)gx;
+            ex = static_cast<BatchGraph *>(gx)->ex;
         }
         hipEvent_t a = nullptr, b = nullptr;
         int rc = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess
@@ -2301,7 +2320,7 @@ int ustd_batch_autotune(const ustd_problem *probs, int32_t count, void *d_ws, si
         if (rc == USTD_OK && hipEventElapsedTime(&m, a, b) != hipSuccess) rc = fail(USTD_EHIP, "hipEventElapsedTime failed");
         if (a) (void)hipEventDestroy(a);
         if (b) (void)hipEventDestroy(b);
-        if (ex) (void)hipGraphExecDestroy(ex);
+        if (gx) (void)ustd_batch_graph_destroy(gx);
         if (rc != USTD_OK) return rc;
         rc = batch_plan_reports(Q, reps.data(), st);
         if (rc != USTD_OK && rc != USTD_ENOTCONV) return rc;

@@ -153,6 +153,20 @@ def test_graph_replays_match_eager(batch):
         plan.close()
 
 
+def test_plan_outlives_its_graphs(batch):
+    """A plan is not destroyed while a graph captured from it is alive (the graph uses its memory)."""
+    mem, graphs, probs, diags, counts, reps = batch
+    plan = api.BatchPlan(graphs[:3], probs[:3], ws=api.Workspace(graphs[0].row_ptr.device))
+    plan.capture()
+    rc = api.lib().ustd_batch_plan_destroy(plan._h)
+    assert rc == api.EINVAL
+    plan.replay()  # still valid
+    r2 = plan.reports()
+    for i in range(3):
+        assert torch.equal(plan.counts[i], counts[i]), i
+    plan.close()  # the graph first, then the plan
+
+
 def test_graph_refuses_host_driven_solve(batch):
     mem, graphs, probs, diags, counts, reps = batch
     probs2 = list(probs)
