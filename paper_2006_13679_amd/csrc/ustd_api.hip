@@ -1127,6 +1127,7 @@ struct BatchPlan {
     bool lds_bits = true, col16 = true;
     int nwords_max = 0, slots = 0;
     long long rec_pool = 0, max_tiles = 0;
+    long long path_slots = 0;  // sampler path slots per launch stream (blocks of one launch at most)
     long long off_queue = 0, off_rec = 0, off_path = 0, off_steps = 0, off_draws = 0, total = 0;
 };
 
@@ -1187,7 +1188,11 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B, const us
     B.max_tiles = std::max(1ll, std::min(bounded ? want_tiles : kMaxBatchTiles, kMaxBatchTiles));
     if (S.fill_trees > 0) B.max_tiles = std::min<long long>(B.max_tiles, S.fill_trees);
     B.slots = (int)std::min<long long>(kSamplerMaxBlocks, B.max_tiles);
-    const long long slot_bytes = 2 * (long long)kSamplerMaxBlocks * kSamplerPathSlot * 4;
+    // path slots per launch stream, for any schedule: a launch never has more blocks than the
+    // batch has tiles, and each of up to kMaxBranches chains gets at least one slot
+    const long long tile_bound = std::min(bounded ? want_tiles : kMaxBatchTiles, kMaxBatchTiles);
+    B.path_slots = std::max<long long>(std::min<long long>(kSamplerMaxBlocks, tile_bound), kMaxBranches);
+    const long long slot_bytes = 2 * B.path_slots * kSamplerPathSlot * 4;
     long long pool = std::max(kDefaultBudget - slot_bytes, min_rec);
     if (bounded) pool = std::min(pool, std::max(want_rec, min_rec));
     B.rec_pool = align_up(pool);
@@ -1198,7 +1203,7 @@ int make_batch_plan(const ustd_problem *probs, int count, BatchPlan &B, const us
     };
     B.off_queue = take(kMaxBranches * sizeof(int));
     B.off_rec = take(B.rec_pool);
-    B.off_path = take(2 * (long long)kSamplerMaxBlocks * kSamplerPathSlot * 4);  // two launches per fill
+    B.off_path = take(2 * B.path_slots * kSamplerPathSlot * 4);  // two launch streams
     B.off_steps = take(std::min(bounded ? want_tiles : kMaxBatchTiles, kMaxBatchTiles) * 8);
     B.off_draws = take(std::min(bounded ? want_tiles : kMaxBatchTiles, kMaxBatchTiles) * 8);
     B.total = o;
@@ -1632,10 +1637,10 @@ int batch_plan_execute(ustd_batch_plan &P, double *const *d_diags, int64_t *cons
             a.tiles = P.d_tiles + F.tile0 + G.t0;
             a.ntiles = G.cnt;
             a.rec = pool;
-            // sampler path slots: kSamplerMaxBlocks per stream of alternating groups; a branch's
-            // launch has at most kSamplerMaxBlocks / branches blocks and takes that share
-            const long long slot0 = G.branch >= 0 ? (long long)G.branch * (kSamplerMaxBlocks / nbr)
-                                                  : (long long)pool2 * kSamplerMaxBlocks;
+            // sampler path slots: path_slots per stream of alternating groups; a branch's launch
+            // has at most path_slots / branches blocks and takes that share of the first stream's
+            const long long share = G.branch >= 0 ? B.path_slots / nbr : B.path_slots;
+            const long long slot0 = G.branch >= 0 ? (long long)G.branch * share : (long long)pool2 * B.path_slots;
             a.path = at<int>(P.ws, B.off_path) + slot0 * kSamplerPathSlot;
             a.queue = queue + pool2;
             a.steps = steps + G.t0;
@@ -1645,6 +1650,7 @@ int batch_plan_execute(ustd_batch_plan &P, double *const *d_diags, int64_t *cons
             if (res > 0) blocks = std::min(blocks, res);
             if (G.branch >= 0) blocks = std::max(1, std::min(blocks, std::min(res > 0 ? res : kSamplerMaxBlocks,
                                                                                   kSamplerMaxBlocks) / nbr));
+            blocks = (int)std::min<long long>(blocks, share);  // within the launch's path slots
             if (timed) {
                 P.ts.emplace_back(new SpanTimer());
                 P.ts.back()->start(s);
