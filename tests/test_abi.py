@@ -100,3 +100,40 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+@pytest.mark.parametrize("kw", [dict(group_fills=-2), dict(agg_chunk=5), dict(layout=2), dict(branches=5),
+                                dict(branches=-1), dict(fill_trees=-3)])
+def test_batch_plan_rejects_bad_schedules(kw):
+    """The schedule is checked before anything touches a device: USTD_EINVAL and no plan."""
+    arr = (api.Problem * 2)(_prob(), _prob(seed=2))
+    plan = ctypes.c_void_p(None)
+    rc = api.lib().ustd_batch_plan_create(arr, 2, ctypes.c_void_p(0x100000), 1 << 40,
+                                          ctypes.byref(api.Schedule(**kw)), ctypes.byref(plan), None)
+    assert rc == api.EINVAL and not plan.value
+    assert api.lib().ustd_last_error()
+
+
+def test_batch_plan_null_arguments():
+    L = api.lib()
+    assert L.ustd_batch_plan_create(None, 0, None, 0, None, None, None) == api.EINVAL
+    assert L.ustd_batch_plan_destroy(None) == api.OK
+    assert L.ustd_batch_graph_destroy(None) == api.OK
+    assert L.ustd_batch_graph_launch(None, None) == api.EINVAL
+    assert L.ustd_batch_plan_execute(None, None, None, None) == api.EINVAL
+    assert L.ustd_batch_plan_reports(None, None, None) == api.EINVAL
+    s = api.Schedule()
+    assert L.ustd_batch_plan_schedule(None, ctypes.byref(s)) == api.EINVAL
+    arr = (api.Problem * 1)(_prob())
+    assert L.ustd_batch_autotune(arr, 1, None, 0, None, 1, None, None, None, None) == api.EINVAL
+
+
+def test_batch_workspace_covers_every_layout():
+    """One workspace size serves every schedule: the records layout (edge entries for every
+    member) needs more than the LDS-bitmap layout for members that fit the bitmap."""
+    arr = (api.Problem * 2)(_prob(tau_cap=64), _prob(seed=2, tau_cap=64))
+    size = ctypes.c_size_t(0)
+    assert api.lib().ustd_batch_workspace_bytes(arr, 2, ctypes.byref(size)) == api.OK
+    single = api.workspace_bytes(_prob())
+    assert size.value > 2 * 3968 * 16  # edge entries of both members
+    assert size.value < 64 * single + (1 << 30)
