@@ -896,7 +896,8 @@ int edge_count_trees(Ctx &c, int cnt, long long *edge_counts, double *ms, int po
 // runs on the host once all batches are queued, before anything waits for them (work for
 // other streams).
 int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *counts, ustd_report *rep,
-              long long *edge_counts = nullptr, const std::function<void()> &overlap = nullptr) {
+              long long *edge_counts = nullptr, const std::function<void()> &overlap = nullptr,
+              hipEvent_t last_sampled = nullptr) {
     // equal batches: ceil(count / K) of them, none larger than K
     const long long nb = (tree_count + c.L.K - 1) / c.L.K;
     const long long per = nb > 0 ? (tree_count + nb - 1) / nb : 0;
@@ -924,6 +925,10 @@ int run_trees(Ctx &c, long long tree_begin, long long tree_count, long long *cou
         rc = sample_batch(c, tree_begin + b0, cnt, pool_steps(c, pool), pool_draws(c, pool), pool, s);
         if (rc != USTD_OK) break;
         ts.back()->stop(s);
+        if (last_sampled && b0 + per >= tree_count && hipEventRecord(last_sampled, s) != hipSuccess) {
+            rc = fail(USTD_EHIP, "hipEventRecord failed");
+            break;
+        }
         if (launch_sum_walks(cnt, pool_steps(c, pool), pool_draws(c, pool), totals, s) != hipSuccess) {
             rc = fail(USTD_EHIP, "walk totals launch failed");
             break;
@@ -2078,10 +2083,25 @@ int ustd_diag_lpinv(const ustd_problem *prob, void *d_ws, size_t ws_bytes, doubl
     cs.st = side;
     int src = USTD_EHIP;
     bool solved = false;
+    // Where the solve overlaps.  The LDS-bitmap sampler leaves registers for the solve's kernels
+    // beside it, so the solve runs during sampling.  The records sampler fills every SIMD's
+    // registers (96 x 5 waves): solve kernels issued beside it only get slots as its launches
+    // drain.  With two tree pools the launches of the two streams overlap and the solve fills
+    // their drain gaps, so it still starts at once.  With one pool the batches run back to back
+    // on one stream, and which of the solve and the first launch reached the CUs first changed
+    // the run time by 13% from call to call (R-MAT scale 22, 19 MB of records per tree): there
+    // the solve waits for the last sampler launch and runs beside the last batch's Algorithm 2.
+    SyncEvent sampled;
+    const bool after_sampling = !c.L.lds_bits && c.L.pools == 1 && sampled.e;
     const int trc = run_trees(c, 0, tau, counts, r, nullptr, [&]() {
+        if (after_sampling && hipStreamWaitEvent(side, sampled.e, 0) != hipSuccess) {
+            src = fail(USTD_EHIP, "hipStreamWaitEvent failed");
+            solved = true;
+            return;
+        }
         src = solve_column(cs, x, r);
         solved = true;
-    });
+    }, after_sampling ? sampled.e : nullptr);
     if (!solved) {
         if (trc != USTD_OK) return trc;  // failed before the first sampler launch
         src = solve_column(cs, x, r);
