@@ -388,6 +388,9 @@ def main():
                          "trees, the effective resistance of every edge")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device to device (calibrates HBM byte counters) and exit")
+    ap.add_argument("--gather-probe", type=int, default=0, metavar="MIB",
+                    help="only gather 2^24 random 4-byte words from a MIB-mebibyte array and exit (HBM bytes the "
+                         "counters report per random access)")
     args = ap.parse_args()
 
     if args.copy_probe:
@@ -400,6 +403,20 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": nbytes}), flush=True)
+        return
+
+    if args.gather_probe:
+        import torch
+
+        words = (args.gather_probe << 20) // 4
+        src = torch.arange(words, dtype=torch.int32, device="cuda:0")
+        g = torch.Generator(device="cuda:0").manual_seed(7)
+        idx = torch.randint(0, words, (1 << 24,), device="cuda:0", generator=g)
+        torch.cuda.synchronize()
+        out = src[idx]
+        torch.cuda.synchronize()
+        print(json.dumps({"gather_probe_words": 1 << 24, "array_bytes": words * 4, "check": int(out[:4].sum())}),
+              flush=True)
         return
 
     if args.gpus != 1:
