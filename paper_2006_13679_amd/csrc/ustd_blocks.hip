@@ -571,13 +571,21 @@ hipError_t launch_bc_join(int n, int u, int ntrees, int ntop, int nslots, const 
                           const int *vtx, int2 *recs, long long sstride, int2 *rec, long long stride,
                           const int *bflag, hipStream_t st) {
     if (ntrees <= 0) return hipSuccess;
-    bc_reroot_kernel<<<bgrid((long long)ntop * ntrees, 256), 256, 0, st>>>(ntop, tops, ntrees, nslots, recs,
-                                                                            sstride);
-    bc_map_parents_kernel<<<bgrid((long long)n * ntrees, 256), 256, 0, st>>>(n, u, ntrees, slotPar, vtx, recs,
-                                                                             sstride, rec, stride);
-    bc_nba_init_kernel<<<bgrid((long long)n * ntrees, 256), 256, 0, st>>>(n, u, ntrees, bflag, rec, stride);
-    bc_nba_jump_kernel<<<bgrid((long long)n * ntrees, 256), 256, 0, st>>>(n, ntrees, rec, stride);
-    bc_records_kernel<<<bgrid((long long)n * ntrees, 256), 256, 0, st>>>(n, u, ntrees, bflag, rec, stride);
+    // One work-item per (vertex, tree), and a dispatch counts its work-items in 32 bits: the
+    // trees go in chunks of at most 2^31 work-items per launch (each tree is independent).
+    const long long per = std::max<long long>({(long long)n, (long long)ntop, 1ll});
+    const int chunk = (int)std::max(1ll, std::min<long long>(ntrees, (1ll << 31) / per));
+    for (int t0 = 0; t0 < ntrees; t0 += chunk) {
+        const int nt = std::min(chunk, ntrees - t0);
+        int2 *rs = recs + (long long)t0 * sstride;
+        int2 *rr = rec + (long long)t0 * stride;
+        bc_reroot_kernel<<<bgrid((long long)ntop * nt, 256), 256, 0, st>>>(ntop, tops, nt, nslots, rs, sstride);
+        bc_map_parents_kernel<<<bgrid((long long)n * nt, 256), 256, 0, st>>>(n, u, nt, slotPar, vtx, rs, sstride,
+                                                                             rr, stride);
+        bc_nba_init_kernel<<<bgrid((long long)n * nt, 256), 256, 0, st>>>(n, u, nt, bflag, rr, stride);
+        bc_nba_jump_kernel<<<bgrid((long long)n * nt, 256), 256, 0, st>>>(n, nt, rr, stride);
+        bc_records_kernel<<<bgrid((long long)n * nt, 256), 256, 0, st>>>(n, u, nt, bflag, rr, stride);
+    }
     return hipGetLastError();
 }
 

@@ -1296,9 +1296,11 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
             const int2 rv = rec0[(long long)i * a.rec_stride + v];
             sum += (rv.x == pbv) ? fv : (Acc)0;
             x[i] = nba_of(rv.y);
+            if (x[i] >= a.n) x[i] = u;
         }
     }
-    for (;;) {
+    // a chain visits each T-ancestor at most once: n rounds bound it even on broken records
+    for (int round = 0; round < a.n; ++round) {
         int2 rx[CH], bx[CH];
         bool act = false;
 #pragma unroll
@@ -1328,6 +1330,7 @@ __global__ __launch_bounds__(256) void aggregate_kernel(AggregateArgs a) {
                     }
                 }
                 x[i] = nba_of(rx[i].y);
+                if (x[i] >= a.n) x[i] = u;  // never for sampled trees; keeps reads in bounds
             }
         }
     }
@@ -2086,7 +2089,13 @@ hipError_t launch_tree_records(const IntervalArgs &a, int ntrees, hipStream_t st
     return hipGetLastError();
 }
 hipError_t launch_extract_parents(int n, int ntrees, const int2 *rec, long long rec_stride, int *out, hipStream_t st) {
-    extract_parents_kernel<<<blocks_for((long long)n * ntrees, 256), 256, 0, st>>>(n, ntrees, rec, rec_stride, out);
+    // a dispatch counts its work-items in 32 bits: at most 2^31 (vertex, tree) items per launch
+    const int chunk = (int)std::max(1ll, std::min<long long>(ntrees, (1ll << 31) / std::max(n, 1)));
+    for (int t0 = 0; t0 < ntrees; t0 += chunk) {
+        const int nt = std::min(chunk, ntrees - t0);
+        extract_parents_kernel<<<blocks_for((long long)n * nt, 256), 256, 0, st>>>(
+            n, nt, rec + (long long)t0 * rec_stride, rec_stride, out + (long long)t0 * n);
+    }
     return hipGetLastError();
 }
 hipError_t launch_b_intervals(int n, int u, int ecc, const int *dist, const int *parB, int *scratch, int2 *bint,
